@@ -1,0 +1,255 @@
+"""ctypes wrapper around the FP64 C oracle (test infrastructure only).
+
+The C source follows the paper's step order: pull-stream (Eq. (1) and Eq. (4)
+left-hand sides), MRT collision of f (Eq. (2)) with the body force of Eq. (1),
+MRT collision of g (Eq. (4)), then the interface velocity of Eq. (6) and the
+phase switch.  This module only marshals arguments and exposes the state as
+numpy views.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import neumann
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def oracle_library_path() -> str:
+    return _LIB
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, IEEE semantics, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+               "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int),
+        ("ra", ctypes.c_double),
+        ("pr", ctypes.c_double),
+        ("ste", ctypes.c_double),
+        ("t_h", ctypes.c_double),
+        ("t_c", ctypes.c_double),
+        ("t_m", ctypes.c_double),
+        ("ma", ctypes.c_double),
+        ("alpha_in", ctypes.c_double),
+        ("s0", ctypes.c_double),
+        ("heating", ctypes.c_int),
+        ("flow", ctypes.c_int),
+        ("seed_profile", ctypes.c_int),
+        ("seed_lambda", ctypes.c_double),
+        ("periodic", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build_oracle()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        d, i, ll, vp = ctypes.c_double, ctypes.c_int, ctypes.c_longlong, ctypes.c_void_p
+        dp = P(d)
+        ip = P(i)
+        lib.orc_sizeof_params.restype = i
+        lib.orc_create.argtypes = [P(_Params)]
+        lib.orc_create.restype = vp
+        lib.orc_destroy.argtypes = [vp]
+        lib.orc_step.argtypes = [vp, ll]
+        lib.orc_liquid_fraction.argtypes = [vp]
+        lib.orc_liquid_fraction.restype = d
+        lib.orc_fields.argtypes = [vp, dp, dp, dp, dp, dp]
+        lib.orc_front_velocity.argtypes = [vp, dp]
+        for name in ("orc_f", "orc_g", "orc_s", "orc_th"):
+            getattr(lib, name).argtypes = [vp]
+            getattr(lib, name).restype = dp
+        for name in ("orc_steps", "orc_melted", "orc_frozen"):
+            getattr(lib, name).argtypes = [vp]
+            getattr(lib, name).restype = ll
+        lib.orc_derived.argtypes = [vp, dp]
+        lib.orc_tables.argtypes = [vp, ip, ip, dp, dp, ip, ip, dp, dp, dp, dp, dp, dp]
+        lib.orc_collide_f_cell.argtypes = [vp, dp, d, dp]
+        lib.orc_set_rates.argtypes = [vp, dp, dp]
+        lib.orc_equilibrium_moments.argtypes = [d, d, d, d, d, d, d, d, dp, dp]
+        lib.orc_guo_force.argtypes = [vp, d, d, d, d, d, d, dp]
+        assert lib.orc_sizeof_params() == ctypes.sizeof(_Params), "oracle params layout mismatch"
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+@dataclass
+class Derived:
+    nu: float
+    alpha: float
+    s_nu: float
+    q_j: float
+    q_e: float
+    gbeta: float
+    t0: float
+    latent: float
+    u0: float
+
+
+class OracleSim:
+    """One FP64 oracle simulation.
+
+    Parameters mirror the problem statement of the paper's section 1: cube of
+    edge ``n`` lattice units, hot wall at ``t_h``, cold wall at ``t_c``,
+    melting temperature ``t_m``, and the dimensionless groups ``ra``, ``pr``,
+    ``ste``.  ``heating`` 0 puts the hot wall at y=0 and the cold wall at y=n;
+    1 puts it at z=0 with every other wall adiabatic.  ``flow`` 0 freezes the
+    flow (energy distribution only).  ``periodic`` is a test mode: periodic
+    box, all liquid, no walls and no front.
+    """
+
+    def __init__(self, n, ra=1e4, pr=1.0, ste=0.1, t_h=1.0, t_c=0.0, t_m=0.0,
+                 ma=0.1, alpha=0.1, s0=1.0, heating=0, flow=1, seed_profile=0,
+                 periodic=False):
+        lib = _load()
+        lam = neumann.stefan_lambda(ste) if (seed_profile == 1 and ste > 0) else 0.0
+        self.params = _Params(int(n), float(ra), float(pr), float(ste), float(t_h),
+                              float(t_c), float(t_m), float(ma), float(alpha), float(s0),
+                              int(heating), int(flow), int(seed_profile), float(lam),
+                              int(bool(periodic)))
+        h = lib.orc_create(ctypes.byref(self.params))
+        if not h:
+            raise MemoryError("oracle allocation failed")
+        self._h = h
+        self._lib = lib
+        self.n = int(n)
+        self.ncell = self.n ** 3
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc_destroy(h)
+            self._h = None
+
+    # ---- state views (re-fetched each time: the step swaps buffers) ----
+    def _view(self, fn, count, shape):
+        ptr = fn(self._h)
+        return np.ctypeslib.as_array(ptr, shape=(count,)).reshape(shape)
+
+    @property
+    def f(self) -> np.ndarray:
+        n = self.n
+        return self._view(self._lib.orc_f, 19 * n ** 3, (19, n, n, n))
+
+    @property
+    def g(self) -> np.ndarray:
+        n = self.n
+        return self._view(self._lib.orc_g, 7 * n ** 3, (7, n, n, n))
+
+    @property
+    def s(self) -> np.ndarray:
+        n = self.n
+        return self._view(self._lib.orc_s, n * n, (n, n))
+
+    @property
+    def th(self) -> np.ndarray:
+        n = self.n
+        return self._view(self._lib.orc_th, n * n, (n, n))
+
+    # ---- stepping and outputs ----
+    def step(self, nsteps: int = 1) -> None:
+        self._lib.orc_step(self._h, int(nsteps))
+
+    @property
+    def steps(self) -> int:
+        return int(self._lib.orc_steps(self._h))
+
+    @property
+    def melted(self) -> int:
+        return int(self._lib.orc_melted(self._h))
+
+    def liquid_fraction(self) -> float:
+        return float(self._lib.orc_liquid_fraction(self._h))
+
+    def fields(self):
+        n = self.n
+        out = [np.zeros((n, n, n)) for _ in range(5)]
+        self._lib.orc_fields(self._h, *[_dp(a) for a in out])
+        T, ux, uy, uz, rho = out
+        return {"T": T, "u": np.stack([ux, uy, uz]), "rho": rho, "s": self.s.copy()}
+
+    def front_velocity(self) -> np.ndarray:
+        V = np.zeros((self.n, self.n))
+        self._lib.orc_front_velocity(self._h, _dp(V))
+        return V
+
+    def derived(self) -> Derived:
+        out = np.zeros(9)
+        self._lib.orc_derived(self._h, _dp(out))
+        return Derived(*[float(v) for v in out])
+
+    def tables(self) -> dict:
+        e19 = np.zeros((19, 3), dtype=np.int32)
+        e7 = np.zeros((7, 3), dtype=np.int32)
+        w19 = np.zeros(19)
+        w7 = np.zeros(7)
+        o19 = np.zeros(19, dtype=np.int32)
+        o7 = np.zeros(7, dtype=np.int32)
+        M = np.zeros((19, 19))
+        Minv = np.zeros((19, 19))
+        N = np.zeros((7, 7))
+        Ninv = np.zeros((7, 7))
+        S = np.zeros(19)
+        Q = np.zeros(7)
+        self._lib.orc_tables(self._h, _ip(e19), _ip(e7), _dp(w19), _dp(w7), _ip(o19),
+                             _ip(o7), _dp(M), _dp(Minv), _dp(N), _dp(Ninv), _dp(S), _dp(Q))
+        return dict(e19=e19, e7=e7, w19=w19, w7=w7, opp19=o19, opp7=o7, M=M, Minv=Minv,
+                    N=N, Ninv=Ninv, S=S, Q=Q)
+
+    def collide_f_cell(self, fin, T: float) -> np.ndarray:
+        fin = np.ascontiguousarray(fin, dtype=np.float64)
+        out = np.zeros(19)
+        self._lib.orc_collide_f_cell(self._h, _dp(fin), float(T), _dp(out))
+        return out
+
+    def set_rates(self, S=None, Q=None) -> None:
+        Sa = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
+        Qa = None if Q is None else np.ascontiguousarray(Q, dtype=np.float64)
+        self._lib.orc_set_rates(self._h, None if Sa is None else _dp(Sa),
+                                None if Qa is None else _dp(Qa))
+
+    def guo_force(self, u, F) -> np.ndarray:
+        out = np.zeros(19)
+        self._lib.orc_guo_force(self._h, *[float(v) for v in u], *[float(v) for v in F],
+                                _dp(out))
+        return out
+
+    @staticmethod
+    def equilibrium_moments(rho, j, T, u):
+        lib = _load()
+        m = np.zeros(19)
+        nn = np.zeros(7)
+        lib.orc_equilibrium_moments(float(rho), *[float(v) for v in j], float(T),
+                                    *[float(v) for v in u], _dp(m), _dp(nn))
+        return m, nn
