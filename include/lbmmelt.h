@@ -1,0 +1,188 @@
+/*
+ * lbmmelt — double-MRT lattice Boltzmann melting step on one MI355X (gfx950).
+ *
+ * C ABI of the library liblbmmelt.so.  Plain C99 types only; no exceptions
+ * cross this boundary.  Every function returns an lbm_status (0 = success);
+ * on failure lbm_last_error() returns a thread-local message.
+ *
+ * Method: Li, Yang & Zhang, "Lattice Boltzmann method simulation of 3-D
+ * melting using double MRT model with interfacial tracking method"
+ * (arXiv:1604.03478).  One time step is
+ *   1. pull-streaming of f (D3Q19, section 2 Eq. (1) and Eq. (3)) and of g
+ *      (D3Q7, Eq. (4) and Eq. (5)) with no-slip, thermal wall and front
+ *      boundary conditions,
+ *   2. the MRT collision of f (Eq. (2)) with a Boussinesq buoyancy force
+ *      (section 1, assumption 4) and the MRT collision of g (Eq. (4)),
+ *   3. the interfacial-tracking update of the solid-liquid front from the
+ *      interface energy balance, Eq. (6), which masks solid cells out of the
+ *      flow.
+ * Geometry (section 1): a cube of edge H = n lattice units; the hot wall at
+ * t_h, the opposite wall at t_c <= t_m, the other walls adiabatic, no slip
+ * on every wall, the solid initially at t_c.
+ *
+ * Layouts.  Cell (x, y, z) has linear index (z*n + y)*n + x (x fastest).
+ * The front s is one value per column along the melt axis: with
+ * LBM_HEAT_Y0 the melt axis is y and s is stored [z][x]; with LBM_HEAT_Z0
+ * the melt axis is z and s is stored [y][x].  A cell is liquid iff its
+ * centre coordinate along the melt axis (index + 1/2) is strictly below the
+ * front of its column.
+ *
+ * Threads and streams.  One context per host thread.  All device work of a
+ * context is enqueued on its stream (the caller's, or one the library owns);
+ * lbm_step only enqueues.  The functions that return host data
+ * (lbm_liquid_fraction, lbm_fields, lbm_get_populations, lbm_save_state,
+ * lbm_diagnostics) synchronize that stream.
+ */
+#ifndef LBMMELT_H
+#define LBMMELT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque; owns all of its device memory */
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* invalid argument or parameter                      */
+  LBM_ENOMEM = -2,    /* device or host allocation failed                   */
+  LBM_EDEVICE = -3,   /* HIP runtime or kernel launch error                 */
+  LBM_EUNSTABLE = -4, /* a non-finite value appeared; state is unusable      */
+  LBM_ESTATE = -5     /* call not valid in the context's current state       */
+} lbm_status;
+
+/* Storage precision of the distributions.  LBM_F64 and LBM_F32 collide in
+ * the storage type; the two 16-bit formats store the shifted populations
+ * (f_q - w_q*rho0 and g_q - w_q*T0) and collide in FP32.  The front and all
+ * reductions are FP64 in every mode. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_precision;
+
+typedef enum {
+  LBM_HEAT_Y0 = 0, /* hot wall y = 0, cold wall y = n (paper, section 1) */
+  LBM_HEAT_Z0 = 1  /* hot wall z = 0 (bottom heating), all others adiabatic */
+} lbm_heating;
+
+typedef struct {
+  int32_t n;        /* cells per edge, 4 <= n <= 1024                         */
+  double ra;        /* Rayleigh number (flow = 1), > 0                        */
+  double pr;        /* Prandtl number (flow = 1), > 0                         */
+  double ste;       /* Stefan number c_p (t_h - t_m)/h_sl >= 0; 0 = front fixed*/
+  double t_h;       /* hot-wall temperature                                   */
+  double t_c;       /* cold-wall and initial solid temperature, t_c <= t_m    */
+  double t_m;       /* melting temperature, t_m < t_h                         */
+  double ma;        /* Mach number, 0 < ma < 0.3 (section 3.2)                */
+  double alpha;     /* lattice thermal diffusivity, used only when flow == 0 */
+  double s0;        /* initial front position in lattice units, 0 <= s0 <= n  */
+  int32_t heating;  /* lbm_heating                                            */
+  int32_t flow;     /* 0: flow frozen (energy distribution only), 1: full    */
+  int32_t precision;/* lbm_precision                                          */
+  int32_t seed_profile; /* initial liquid temperature: 0 linear from t_h to t_m
+                           across the seed layer, 1 the Neumann profile whose
+                           front is at s0                                    */
+} lbm_params;
+
+/* Lattice units derived from the parameters (Eq. (7) time scale: the
+ * Fourier number is alpha * t / n^2). */
+typedef struct {
+  double u0;      /* buoyancy velocity scale Ma * c_s                       */
+  double nu;      /* kinematic viscosity                                    */
+  double alpha;   /* thermal diffusivity                                    */
+  double gbeta;   /* buoyancy coefficient g*beta (force = gbeta*(T - t0))   */
+  double t0;      /* reference temperature (t_h + t_c)/2                    */
+  double s_nu;    /* shear relaxation rate of f                            */
+  double q_j;     /* heat-flux relaxation rate of g                        */
+  double q_e;     /* remaining relaxation rate of g                        */
+} lbm_lattice;
+
+/* Create a context: validates *params, maps them to lattice units, allocates
+ * the double-buffered distributions in HBM and writes the initial state
+ * (f at rest, g at equilibrium of the seed temperature profile, front at
+ * s0).  hip_stream is a hipStream_t, or NULL for a stream the library
+ * creates and owns.  On success *out receives the context.
+ * Errors: LBM_EINVAL (bad parameter; e.g. n out of range, t_c > t_m,
+ * ma >= 0.3, derived viscous relaxation time <= 0.5 + 1e-3),
+ * LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_init(const lbm_params *params, void *hip_stream, lbm_ctx **out);
+
+/* Release every device and host resource of ctx (NULL is accepted). */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Enqueue nsteps >= 0 time steps (stream, collide, front update and phase
+ * switch; section 2, Eq. (1), (2), (4), (6)).  Asynchronous: the device
+ * instability flag is only read by the synchronizing queries.
+ * Errors: LBM_EINVAL (nsteps < 0), LBM_ESTATE (a query has reported
+ * LBM_EUNSTABLE and no lbm_load_state followed), LBM_EDEVICE. */
+int lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* Liquid fraction: sum of the column fronts over n^3, in FP64 (the quantity
+ * plotted against the Fourier number in the paper's Fig. 2 and Fig. 4(d)).
+ * Synchronizes.  Returns LBM_EUNSTABLE if a non-finite value was detected in
+ * any step so far. */
+int lbm_liquid_fraction(lbm_ctx *ctx, double *fl);
+
+/* Copy the macroscopic fields of the current state to host memory, in FP64.
+ * T and rho: n^3 values each; u: 3*n^3 values (u_x, u_y, u_z planes);
+ * s: n^2 values.  Any pointer may be NULL.  Solid cells report rho = 0 and
+ * u = 0.  u is the velocity the collision used (momentum plus half the
+ * force).  Synchronizes; LBM_EUNSTABLE as for lbm_liquid_fraction. */
+int lbm_fields(lbm_ctx *ctx, double *T, double *u, double *rho, double *s);
+
+/* Derived lattice parameters of the context. */
+int lbm_get_lattice(const lbm_ctx *ctx, lbm_lattice *out);
+
+/* Number of time steps taken since lbm_init (or restored by
+ * lbm_load_state). */
+int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
+
+/* Set the hot-wall temperature of every column (n^2 FP64 values, column
+ * layout of s).  th points to device memory if on_device != 0, else to host
+ * memory.  Takes effect from the next step; the initial seed profile always
+ * uses params->t_h.  Enqueued on the context stream. */
+int lbm_set_hot_wall(lbm_ctx *ctx, const double *th, int on_device);
+
+/* Overwrite the state with unshifted FP64 populations from host memory:
+ * f is 19*n^3 values in the velocity order of Eq. (3) ([q][z][y][x]; NULL
+ * when flow == 0), g is 7*n^3 values in the order of Eq. (5), s is n^2 front
+ * positions.  Values are rounded to the storage precision.  Synchronizes. */
+int lbm_set_populations(lbm_ctx *ctx, const double *f, const double *g,
+                        const double *s);
+
+/* Copy the current state out as unshifted FP64 populations (same layout as
+ * lbm_set_populations; any pointer may be NULL).  Synchronizes. */
+int lbm_get_populations(lbm_ctx *ctx, double *f, double *g, double *s);
+
+/* FP64 reductions of the current state.  out[0] liquid mass (sum of rho over
+ * liquid cells), out[1] thermal energy sum of (T - t_m) over all cells,
+ * out[2] sum of the fronts, out[3] cells melted since init, out[4] cells
+ * that changed from liquid to solid since init.  Synchronizes. */
+int lbm_diagnostics(lbm_ctx *ctx, double out[5]);
+
+/* Checkpoint.  With host_buf == NULL, *bytes receives the size needed.
+ * Otherwise the state (distributions in storage precision, front, counters,
+ * step) is copied into host_buf, which must hold *bytes bytes.
+ * lbm_load_state restores a blob made by a context with the same n,
+ * precision, flow and heating (else LBM_EINVAL), and clears the unstable
+ * flag.  Both synchronize. */
+int lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t *bytes);
+int lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Kernel timing for measurement.  While enabled (enable != 0), every step
+ * brackets its fused stream-collide kernel with a pair of HIP events on the
+ * context stream.  lbm_kernel_time synchronizes, returns the summed duration
+ * of those kernels in milliseconds and their count, and clears the record.
+ * Enabling adds two event records per step; leave it off when timing whole
+ * steps. */
+int lbm_kernel_timing(lbm_ctx *ctx, int enable);
+int lbm_kernel_time(lbm_ctx *ctx, double *ms, int64_t *launches);
+
+/* Thread-local message describing the last error of this thread. */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMMELT_H */

@@ -1,0 +1,586 @@
+// Host side of liblbmmelt: the C ABI declared in include/lbmmelt.h.
+//
+// Owns the device memory of one simulation (double-buffered SoA
+// distributions in HBM, the front, per-column counters), maps the physical
+// parameters of the problem statement (section 1 of Li, Yang & Zhang,
+// arXiv:1604.03478) to lattice units, and enqueues the gfx950 kernels on one
+// HIP stream.  Device work is asynchronous except where the header says a
+// call synchronizes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbm_internal.h"
+#include "lbmmelt.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+// Root of lam * exp(lam^2) * erf(lam) = Ste / sqrt(pi): the Neumann constant
+// of one-dimensional melting without subcooling (section 3.1 verification
+// case), by bisection.
+double neumann_constant(double ste) {
+  const double target = ste / std::sqrt(M_PI);
+  auto h = [&](double l) { return l * std::exp(l * l) * std::erf(l) - target; };
+  double lo = 0.0, hi = 1.0;
+  while (h(hi) < 0.0) hi *= 2.0;
+  for (int it = 0; it < 200 && hi - lo > 1e-16; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (h(mid) < 0.0 ? lo : hi) = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p{};
+  lbm_lattice lat{};
+  lbmk::KParams kp{};
+  int kind = 0;
+  size_t esz = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  void* f[2] = {nullptr, nullptr};
+  void* g[2] = {nullptr, nullptr};
+  int cur = 0;
+  double* s[2] = {nullptr, nullptr};
+  int scur = 0;
+  int* cnt = nullptr;
+  int* cmin = nullptr;
+  int* cmax = nullptr;
+  int* melted = nullptr;
+  int* frozen = nullptr;
+  int* flag = nullptr;
+  double* th = nullptr;
+  double* red = nullptr;
+  double* seedT = nullptr;
+  double* fields = nullptr;  // 5 * n^3 FP64 scratch for fields and diagnostics
+  int64_t step = 0;
+  bool unstable = false;  // a query saw the device flag; steps refused until load
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed kernels
+  size_t ev_used = 0;
+};
+
+namespace {
+
+void release(lbm_ctx* c) {
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  void* ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->s[0], c->s[1], c->cnt,  c->cmin,
+                  c->cmax, c->melted, c->frozen, c->flag, c->th,  c->red,  c->seedT, c->fields};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+int validate(const lbm_params* p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->n < 4 || p->n > 1024) return fail(LBM_EINVAL, "n = %d outside [4, 1024]", p->n);
+  if (p->precision < LBM_F64 || p->precision > LBM_BF16S)
+    return fail(LBM_EINVAL, "precision = %d is not an lbm_precision", p->precision);
+  const double bytes = std::pow((double)p->n, 3) * (double)lbmk::store_bytes(p->precision);
+  if (bytes > 4294967295.0)
+    return fail(LBM_EINVAL, "n = %d too large for this storage precision (one population "
+                "array must stay below 4 GiB)", p->n);
+  if (p->heating != LBM_HEAT_Y0 && p->heating != LBM_HEAT_Z0)
+    return fail(LBM_EINVAL, "heating = %d is not an lbm_heating", p->heating);
+  if (p->flow != 0 && p->flow != 1) return fail(LBM_EINVAL, "flow must be 0 or 1");
+  if (p->seed_profile != 0 && p->seed_profile != 1)
+    return fail(LBM_EINVAL, "seed_profile must be 0 or 1");
+  if (!(p->t_c <= p->t_m && p->t_m < p->t_h))
+    return fail(LBM_EINVAL, "temperatures must satisfy t_c <= t_m < t_h");
+  if (!(p->ste >= 0.0) || !std::isfinite(p->ste)) return fail(LBM_EINVAL, "ste must be >= 0");
+  if (p->seed_profile == 1 && !(p->ste > 0.0))
+    return fail(LBM_EINVAL, "the Neumann seed profile needs ste > 0");
+  if (!(p->ma > 0.0 && p->ma < 0.3)) return fail(LBM_EINVAL, "ma must lie in (0, 0.3)");
+  if (!(p->s0 >= 0.0 && p->s0 <= p->n)) return fail(LBM_EINVAL, "s0 must lie in [0, n]");
+  if (p->flow) {
+    if (!(p->ra > 0.0) || !(p->pr > 0.0) || !std::isfinite(p->ra) || !std::isfinite(p->pr))
+      return fail(LBM_EINVAL, "ra and pr must be positive");
+  } else if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) {
+    return fail(LBM_EINVAL, "alpha must be positive when flow == 0");
+  }
+  return LBM_OK;
+}
+
+// Lattice units: U0 = Ma c_s; nu = U0 H sqrt(Pr/Ra); alpha = U0 H / sqrt(Ra Pr);
+// g beta = U0^2 / (H (t_h - t_m)), so that Ra = g beta dT H^3 / (nu alpha),
+// and the Fourier number alpha t / H^2 equals Eq. (7).
+int derive(const lbm_params* p, lbm_lattice* L) {
+  const double n = p->n;
+  L->u0 = p->ma / std::sqrt(3.0);
+  if (p->flow) {
+    L->nu = L->u0 * n * std::sqrt(p->pr / p->ra);
+    L->alpha = L->u0 * n / std::sqrt(p->ra * p->pr);
+    L->gbeta = L->u0 * L->u0 / (n * (p->t_h - p->t_m));
+    L->s_nu = 1.0 / (3.0 * L->nu + 0.5);
+    if (!(3.0 * L->nu + 0.5 > 0.5 + 1e-3))
+      return fail(LBM_EINVAL, "viscous relaxation time %.6g too close to 1/2 (raise n or ma, "
+                  "or lower ra)", 3.0 * L->nu + 0.5);
+  } else {
+    L->nu = 0.0;
+    L->alpha = p->alpha;
+    L->gbeta = 0.0;
+    L->s_nu = 1.0;
+  }
+  L->t0 = 0.5 * (p->t_h + p->t_c);
+  L->q_j = 1.0 / (4.0 * L->alpha + 0.5);
+  L->q_e = 1.0 / (0.5 + 1.0 / (16.0 * L->alpha));
+  return LBM_OK;
+}
+
+int refresh_masks(lbm_ctx* c) {
+  HIP_TRY(lbmk::launch_counts(c->kp, c->s[c->scur], c->cnt, c->stream));
+  HIP_TRY(lbmk::launch_neighbourhood(c->kp, c->cnt, c->cmin, c->cmax, c->stream));
+  return LBM_OK;
+}
+
+int check_ctx(const lbm_ctx* c) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  return LBM_OK;
+}
+
+int check_unstable(lbm_ctx* c) {
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (flag) {
+    c->unstable = true;
+    return fail(LBM_EUNSTABLE, "a non-finite value appeared (step <= %lld)", (long long)c->step);
+  }
+  return LBM_OK;
+}
+
+int ensure_fields(lbm_ctx* c) {
+  if (!c->fields) {
+    const size_t nc = c->kp.ncell;
+    if (hipMalloc((void**)&c->fields, 5 * nc * sizeof(double)) != hipSuccess) {
+      c->fields = nullptr;
+      return fail(LBM_ENOMEM, "cannot allocate %zu bytes for field output",
+                  5 * nc * sizeof(double));
+    }
+  }
+  return LBM_OK;
+}
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return fail(LBM_ENOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+  }
+  return LBM_OK;
+}
+
+struct StateHeader {
+  char magic[8];
+  int32_t n, precision, flow, heating;
+  int64_t step;
+  uint64_t ncell;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err; }
+
+int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(params);
+  if (rc) return rc;
+  lbm_lattice L{};
+  rc = derive(params, &L);
+  if (rc) return rc;
+
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_ENOMEM, "host allocation failed");
+  c->p = *params;
+  c->lat = L;
+  c->kind = params->precision;
+  c->esz = lbmk::store_bytes(c->kind);
+  const int n = params->n;
+  const size_t nn = (size_t)n * n, nc = nn * n;
+  lbmk::KParams& k = c->kp;
+  k.n = n;
+  k.ncell = (uint32_t)nc;
+  k.melt_z = params->heating == LBM_HEAT_Z0;
+  k.flow = params->flow;
+  k.t0 = L.t0;
+  k.t_m = params->t_m;
+  k.t_c = params->t_c;
+  k.gbeta = L.gbeta;
+  k.s_nu = L.s_nu;
+  k.q_j = L.q_j;
+  k.q_e = L.q_e;
+  k.alpha = L.alpha;
+  k.ste = params->ste;
+  k.dT = params->t_h - params->t_m;
+
+  auto bail = [&](int code) {
+    release(c);
+    delete c;
+    return code;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(LBM_EDEVICE, "no HIP device"));
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    // blocking stream: ordered with work on the legacy default stream
+    if (hipStreamCreate(&c->stream) != hipSuccess)
+      return bail(fail(LBM_EDEVICE, "hipStreamCreate failed"));
+    c->own_stream = true;
+  }
+  if (params->flow) {
+    for (int b = 0; b < 2; ++b)
+      if (hipMalloc(&c->f[b], 19 * nc * c->esz) != hipSuccess) {
+        c->f[b] = nullptr;
+        return bail(fail(LBM_ENOMEM, "cannot allocate f (%zu bytes)", 19 * nc * c->esz));
+      }
+  }
+  for (int b = 0; b < 2; ++b)
+    if (hipMalloc(&c->g[b], 7 * nc * c->esz) != hipSuccess) {
+      c->g[b] = nullptr;
+      return bail(fail(LBM_ENOMEM, "cannot allocate g (%zu bytes)", 7 * nc * c->esz));
+    }
+  if ((rc = dalloc(&c->s[0], nn)) || (rc = dalloc(&c->s[1], nn)) || (rc = dalloc(&c->cnt, nn)) ||
+      (rc = dalloc(&c->cmin, nn)) || (rc = dalloc(&c->cmax, nn)) ||
+      (rc = dalloc(&c->melted, nn)) || (rc = dalloc(&c->frozen, nn)) ||
+      (rc = dalloc(&c->flag, 1)) || (rc = dalloc(&c->th, nn)) || (rc = dalloc(&c->red, 8)) ||
+      (rc = dalloc(&c->seedT, (size_t)n)))
+    return bail(rc);
+
+  // initial front, hot wall, seed temperature profile along the melt axis
+  std::vector<double> hs(nn, params->s0), ht(nn, params->t_h), seed(n, params->t_c);
+  double lam = 0.0, t_init = 0.0;
+  if (params->seed_profile == 1) {
+    lam = neumann_constant(params->ste);
+    t_init = (params->s0 / (2.0 * lam)) * (params->s0 / (2.0 * lam)) / L.alpha;
+  }
+  for (int a = 0; a < n; ++a) {
+    const double y = a + 0.5;
+    if (!(y < params->s0)) continue;
+    if (params->seed_profile == 1)
+      seed[a] = params->t_h - (params->t_h - params->t_m) *
+                                  std::erf(y / (2.0 * std::sqrt(L.alpha * t_init))) /
+                                  std::erf(lam);
+    else
+      seed[a] = params->t_h + (params->t_m - params->t_h) * y / params->s0;
+  }
+  auto dev = [&](int code) { return bail(code); };
+  if (hipMemcpyAsync(c->s[0], hs.data(), nn * sizeof(double), hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->th, ht.data(), nn * sizeof(double), hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->seedT, seed.data(), n * sizeof(double), hipMemcpyHostToDevice,
+                     c->stream) ||
+      hipMemsetAsync(c->melted, 0, nn * sizeof(int), c->stream) ||
+      hipMemsetAsync(c->frozen, 0, nn * sizeof(int), c->stream) ||
+      hipMemsetAsync(c->flag, 0, sizeof(int), c->stream))
+    return dev(fail(LBM_EDEVICE, "initial upload failed"));
+  if ((rc = refresh_masks(c))) return bail(rc);
+  if (lbmk::launch_init(c->kind, k, c->cnt, c->seedT, c->f[0], c->g[0], c->stream) != hipSuccess)
+    return bail(fail(LBM_EDEVICE, "init kernel launch failed"));
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(fail(LBM_EDEVICE, "initialisation failed on the device"));
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  release(c);
+  delete c;
+}
+
+int lbm_step(lbm_ctx* c, int64_t nsteps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+  if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
+  const lbmk::KParams& k = c->kp;
+  for (int64_t i = 0; i < nsteps; ++i) {
+    const int nx = c->cur ^ 1, sx = c->scur ^ 1;
+    if (c->timing) {
+      if (c->ev_used + 2 > c->ev.size()) {
+        for (int e = 0; e < 2; ++e) {
+          hipEvent_t h;
+          HIP_TRY(hipEventCreate(&h));
+          c->ev.push_back(h);
+        }
+      }
+      HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
+    }
+    HIP_TRY(lbmk::launch_stream_collide(c->kind, k, c->f[c->cur], c->f[nx], c->g[c->cur], c->g[nx],
+                                        c->cnt, c->cmin, c->cmax, c->s[c->scur], c->th, c->flag,
+                                        c->stream));
+    if (c->timing) {
+      HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+      c->ev_used += 2;
+    }
+    HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
+                               c->th, c->melted, c->frozen, c->flag, c->stream));
+    HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
+    c->cur = nx;
+    c->scur = sx;
+    c->step++;
+  }
+  return LBM_OK;
+}
+
+int lbm_liquid_fraction(lbm_ctx* c, double* fl) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!fl) return fail(LBM_EINVAL, "fl is NULL");
+  const int64_t nn = (int64_t)c->p.n * c->p.n;
+  HIP_TRY(lbmk::launch_sum(c->s[c->scur], nullptr, nullptr, nullptr, nn, c->red, c->stream));
+  double host[4];
+  HIP_TRY(hipMemcpyAsync(host, c->red, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if ((rc = check_unstable(c))) return rc;
+  *fl = host[0] / ((double)nn * c->p.n);
+  return LBM_OK;
+}
+
+int lbm_fields(lbm_ctx* c, double* T, double* u, double* rho, double* s) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if ((rc = ensure_fields(c))) return rc;
+  const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
+  double* d = c->fields;
+  HIP_TRY(lbmk::launch_fields(c->kind, c->kp, c->f[c->cur], c->g[c->cur], c->cnt, d, d + nc,
+                              d + 2 * nc, d + 3 * nc, d + 4 * nc, c->stream));
+  if (T) HIP_TRY(hipMemcpyAsync(T, d, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (u)
+    HIP_TRY(hipMemcpyAsync(u, d + nc, 3 * nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (rho)
+    HIP_TRY(hipMemcpyAsync(rho, d + 4 * nc, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (s)
+    HIP_TRY(hipMemcpyAsync(s, c->s[c->scur], nn * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  return check_unstable(c);
+}
+
+int lbm_get_lattice(const lbm_ctx* c, lbm_lattice* out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = c->lat;
+  return LBM_OK;
+}
+
+int lbm_get_step(const lbm_ctx* c, int64_t* step) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!step) return fail(LBM_EINVAL, "step is NULL");
+  *step = c->step;
+  return LBM_OK;
+}
+
+int lbm_set_hot_wall(lbm_ctx* c, const double* th, int on_device) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!th) return fail(LBM_EINVAL, "th is NULL");
+  const size_t nn = (size_t)c->p.n * c->p.n;
+  HIP_TRY(hipMemcpyAsync(c->th, th, nn * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  if (!on_device) HIP_TRY(hipStreamSynchronize(c->stream));  // host buffer may be reused
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx* c, const double* f, const double* g, const double* s) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->p.flow && !f) return fail(LBM_EINVAL, "f is required when flow == 1");
+  if (!g || !s) return fail(LBM_EINVAL, "g and s are required");
+  const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
+  double* tmp = nullptr;
+  if ((rc = dalloc(&tmp, (c->p.flow ? 19 : 7) * nc))) return rc;
+  auto done = [&](int code) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    return code;
+  };
+  if (c->p.flow) {
+    if (hipMemcpyAsync(tmp, f, 19 * nc * sizeof(double), hipMemcpyHostToDevice, c->stream) ||
+        lbmk::launch_to_storage(c->kind, c->kp, 19, tmp, c->f[c->cur], c->stream))
+      return done(fail(LBM_EDEVICE, "upload of f failed"));
+    if (hipStreamSynchronize(c->stream)) return done(fail(LBM_EDEVICE, "upload of f failed"));
+  }
+  if (hipMemcpyAsync(tmp, g, 7 * nc * sizeof(double), hipMemcpyHostToDevice, c->stream) ||
+      lbmk::launch_to_storage(c->kind, c->kp, 7, tmp, c->g[c->cur], c->stream) ||
+      hipMemcpyAsync(c->s[c->scur], s, nn * sizeof(double), hipMemcpyHostToDevice, c->stream))
+    return done(fail(LBM_EDEVICE, "upload of g or s failed"));
+  if ((rc = refresh_masks(c))) return done(rc);
+  return done(LBM_OK);
+}
+
+int lbm_get_populations(lbm_ctx* c, double* f, double* g, double* s) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
+  double* tmp = nullptr;
+  if ((f && c->p.flow) || g)
+    if ((rc = dalloc(&tmp, ((f && c->p.flow) ? 19 : 7) * nc))) return rc;
+  auto done = [&](int code) {
+    (void)hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    return code;
+  };
+  if (f && c->p.flow) {
+    if (lbmk::launch_from_storage(c->kind, c->kp, 19, c->f[c->cur], tmp, c->stream) ||
+        hipMemcpyAsync(f, tmp, 19 * nc * sizeof(double), hipMemcpyDeviceToHost, c->stream) ||
+        hipStreamSynchronize(c->stream))
+      return done(fail(LBM_EDEVICE, "download of f failed"));
+  }
+  if (g) {
+    if (lbmk::launch_from_storage(c->kind, c->kp, 7, c->g[c->cur], tmp, c->stream) ||
+        hipMemcpyAsync(g, tmp, 7 * nc * sizeof(double), hipMemcpyDeviceToHost, c->stream))
+      return done(fail(LBM_EDEVICE, "download of g failed"));
+  }
+  if (s && hipMemcpyAsync(s, c->s[c->scur], nn * sizeof(double), hipMemcpyDeviceToHost, c->stream))
+    return done(fail(LBM_EDEVICE, "download of s failed"));
+  return done(LBM_OK);
+}
+
+int lbm_diagnostics(lbm_ctx* c, double out[5]) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  if ((rc = ensure_fields(c))) return rc;
+  const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
+  double* d = c->fields;
+  HIP_TRY(lbmk::launch_fields(c->kind, c->kp, c->f[c->cur], c->g[c->cur], c->cnt, d, nullptr,
+                              nullptr, nullptr, d + 4 * nc, c->stream));
+  HIP_TRY(lbmk::launch_sum(d + 4 * nc, d, c->s[c->scur], nullptr, (int64_t)nc, c->red, c->stream));
+  HIP_TRY(lbmk::launch_sum_int(c->melted, (int64_t)nn, c->red + 4, c->stream));
+  HIP_TRY(lbmk::launch_sum_int(c->frozen, (int64_t)nn, c->red + 5, c->stream));
+  double h[8];
+  HIP_TRY(hipMemcpyAsync(h, c->red, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  out[0] = h[0];
+  out[1] = h[1] - (double)nc * c->p.t_m;
+  out[2] = h[2];
+  out[3] = h[4];
+  out[4] = h[5];
+  return check_unstable(c);
+}
+
+int lbm_save_state(lbm_ctx* c, void* host_buf, size_t* bytes) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
+  const size_t fb = c->p.flow ? 19 * nc * c->esz : 0, gb = 7 * nc * c->esz;
+  const size_t need = sizeof(StateHeader) + fb + gb + nn * (sizeof(double) + 2 * sizeof(int));
+  if (!host_buf) {
+    *bytes = need;
+    return LBM_OK;
+  }
+  if (*bytes < need) return fail(LBM_EINVAL, "buffer holds %zu bytes, %zu needed", *bytes, need);
+  StateHeader h{};
+  memcpy(h.magic, "LBMMELT1", 8);
+  h.n = c->p.n;
+  h.precision = c->p.precision;
+  h.flow = c->p.flow;
+  h.heating = c->p.heating;
+  h.step = c->step;
+  h.ncell = nc;
+  char* b = static_cast<char*>(host_buf);
+  memcpy(b, &h, sizeof(h));
+  b += sizeof(h);
+  if (fb) HIP_TRY(hipMemcpyAsync(b, c->f[c->cur], fb, hipMemcpyDeviceToHost, c->stream));
+  b += fb;
+  HIP_TRY(hipMemcpyAsync(b, c->g[c->cur], gb, hipMemcpyDeviceToHost, c->stream));
+  b += gb;
+  HIP_TRY(hipMemcpyAsync(b, c->s[c->scur], nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  b += nn * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(b, c->melted, nn * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  b += nn * sizeof(int);
+  HIP_TRY(hipMemcpyAsync(b, c->frozen, nn * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *bytes = need;
+  return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!host_buf) return fail(LBM_EINVAL, "host_buf is NULL");
+  const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
+  const size_t fb = c->p.flow ? 19 * nc * c->esz : 0, gb = 7 * nc * c->esz;
+  const size_t need = sizeof(StateHeader) + fb + gb + nn * (sizeof(double) + 2 * sizeof(int));
+  if (bytes < need) return fail(LBM_EINVAL, "state blob has %zu bytes, %zu needed", bytes, need);
+  StateHeader h;
+  memcpy(&h, host_buf, sizeof(h));
+  if (memcmp(h.magic, "LBMMELT1", 8) != 0) return fail(LBM_EINVAL, "not a state blob");
+  if (h.n != c->p.n || h.precision != c->p.precision || h.flow != c->p.flow ||
+      h.heating != c->p.heating || h.ncell != nc)
+    return fail(LBM_EINVAL, "state blob was made by an incompatible context");
+  const char* b = static_cast<const char*>(host_buf) + sizeof(h);
+  if (fb) HIP_TRY(hipMemcpyAsync(c->f[c->cur], b, fb, hipMemcpyHostToDevice, c->stream));
+  b += fb;
+  HIP_TRY(hipMemcpyAsync(c->g[c->cur], b, gb, hipMemcpyHostToDevice, c->stream));
+  b += gb;
+  HIP_TRY(hipMemcpyAsync(c->s[c->scur], b, nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  b += nn * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(c->melted, b, nn * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  b += nn * sizeof(int);
+  HIP_TRY(hipMemcpyAsync(c->frozen, b, nn * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+  if ((rc = refresh_masks(c))) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->step = h.step;
+  c->unstable = false;
+  return LBM_OK;
+}
+
+int lbm_kernel_timing(lbm_ctx* c, int enable) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  c->timing = enable != 0;
+  return LBM_OK;
+}
+
+int lbm_kernel_time(lbm_ctx* c, double* ms, int64_t* launches) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!ms || !launches) return fail(LBM_EINVAL, "ms and launches are required");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, c->ev[i], c->ev[i + 1]));
+    total += t;
+  }
+  *ms = total;
+  *launches = (int64_t)(c->ev_used / 2);
+  c->ev_used = 0;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal interface between the host context (lbm_capi.hip) and the gfx950
+// kernels (lbm_kernels.hip) of liblbmmelt.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmk {
+
+// Storage precisions (same numbering as lbm_precision in the public header).
+enum StoreKind { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
+
+// Everything a step kernel needs, in lattice units.  Distributions are
+// stored shifted: f_q - w_q * rho0 (rho0 = 1) and g_q - w_q * t0, so every
+// kernel works on deviations from the rest state.
+struct KParams {
+  int n;           // cells per edge
+  uint32_t ncell;  // n^3
+  int melt_z;      // 0: melt axis y (hot wall y=0, cold wall y=n); 1: axis z
+  int flow;        // 0: energy distribution only
+  double t0;       // reference temperature (storage shift and buoyancy)
+  double t_m;      // melting temperature (front Dirichlet value)
+  double t_c;      // cold-wall temperature (melt axis y only)
+  double gbeta;    // buoyancy: F_z = gbeta * (T - t0)
+  double s_nu;     // shear rate of the D3Q19 MRT
+  double q_j;      // heat-flux rate of the D3Q7 MRT
+  double q_e;      // rate of the remaining D3Q7 moments
+  double alpha;    // thermal diffusivity (front update)
+  double ste;      // Stefan number (front update)
+  double dT;       // nominal t_h - t_m (front update)
+};
+
+size_t store_bytes(int kind);
+
+// One fused stream + collide pass over all cells: reads (fs, gs), writes
+// (fd, gd).  cnt/cmin/cmax: liquid-cell count per column and its min / max
+// over the 3x3 column neighbourhood.  s: front per column.  th: hot-wall
+// temperature per column.  flag: set to 1 when a non-finite value appears.
+hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, void* fd,
+                                 const void* gs, void* gd, const int* cnt, const int* cmin,
+                                 const int* cmax, const double* s, const double* th, int* flag,
+                                 hipStream_t st);
+
+// Interface update (Eq. (6)) of every column from the post-collision g, then
+// the phase switch: s_new, cnt (in place), refill of f in newly liquid cells,
+// per-column melt / freeze counters.
+hipError_t launch_front(int kind, const KParams& P, const double* s_old, double* s_new,
+                        int* cnt, const void* g, void* f, const double* th, int* melted,
+                        int* frozen, int* flag, hipStream_t st);
+
+// cmin/cmax from cnt.
+hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
+                                hipStream_t st);
+
+// cnt from s.
+hipError_t launch_counts(const KParams& P, const double* s, int* cnt, hipStream_t st);
+
+// Initial state: f at rest, g at equilibrium of seedT[a] in liquid cells and
+// of t_c in solid cells.
+hipError_t launch_init(int kind, const KParams& P, const int* cnt, const double* seedT, void* f,
+                       void* g, hipStream_t st);
+
+// Macroscopic fields in FP64 (any output may be null).
+hipError_t launch_fields(int kind, const KParams& P, const void* f, const void* g, const int* cnt,
+                         double* T, double* ux, double* uy, double* uz, double* rho,
+                         hipStream_t st);
+
+// Conversion between unshifted FP64 populations and the shifted storage.
+// q_count = 19 (f) or 7 (g).
+hipError_t launch_to_storage(int kind, const KParams& P, int q_count, const double* src, void* dst,
+                             hipStream_t st);
+hipError_t launch_from_storage(int kind, const KParams& P, int q_count, const void* src,
+                               double* dst, hipStream_t st);
+
+// Deterministic FP64 sums (fixed order; no atomics).  out[k] = sum of
+// v_k[0..count).  Up to 4 vectors per launch (null vectors give 0).
+hipError_t launch_sum(const double* v0, const double* v1, const double* v2, const double* v3,
+                      int64_t count, double* out, hipStream_t st);
+hipError_t launch_sum_int(const int* v, int64_t count, double* out, hipStream_t st);
+
+}  // namespace lbmk

@@ -1,0 +1,882 @@
+// gfx950 kernels of the double-MRT lattice Boltzmann melting step.
+//
+// Method: Li, Yang & Zhang, arXiv:1604.03478, section 2.
+//   f: D3Q19 (Eq. (3) velocity order), Eq. (1) with the MRT collision of
+//      Eq. (2) and a Boussinesq body force (section 1, assumption 4).
+//   g: D3Q7 (Eq. (5) velocity order), Eq. (4).
+//   front: Eq. (6), one height per column along the melt axis.
+//
+// Design (MI355X):
+//   * SoA storage, x fastest; one thread per cell, 64 lanes of a wave along
+//     x, so every population load and store of a wave is one contiguous
+//     256 B (FP32) segment.  Pull streaming: each stored value is read once
+//     and written once per step (208 B per FP32 cell update).
+//   * Populations are stored shifted (f - w*rho0, g - w*t0) and the whole
+//     collision works on deviations, which keeps FP32 and 16-bit storage
+//     accurate.
+//   * The 19x19 and 7x7 moment transforms use the integer structure of the
+//     orthogonal bases (pairwise sums and differences), about 250 flops per
+//     cell instead of 1444 for a dense product; no MFMA (the transform is a
+//     tiny, sparse, per-cell integer matrix and the kernel is HBM bound).
+//   * A wave takes the fast path when every lane is away from the y/z walls
+//     and its 3x3x3 stencil lies in one phase; x walls are handled there by
+//     a rare masked reload.  Waves that touch the front or a y/z wall take
+//     the general path with per-link boundary handling.
+//   * Each population array is addressed as a wave-uniform base plus a 32-bit
+//     per-lane byte offset (global_load ... saddr form).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_internal.h"
+
+namespace lbmk {
+namespace {
+
+// --------------------------------------------------------------- storage
+template <typename Ts> struct Compute { using type = float; };
+template <> struct Compute<double> { using type = double; };
+
+template <typename Ts>
+__device__ __forceinline__ typename Compute<Ts>::type load(const Ts* __restrict__ base, uint32_t i) {
+  const Ts* p = reinterpret_cast<const Ts*>(reinterpret_cast<const char*>(base) +
+                                            (uint32_t)(i * (uint32_t)sizeof(Ts)));
+  return static_cast<typename Compute<Ts>::type>(*p);
+}
+
+template <typename Ts, typename C>
+__device__ __forceinline__ void store(Ts* __restrict__ base, uint32_t i, C v) {
+  Ts* p = reinterpret_cast<Ts*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(Ts)));
+  *p = static_cast<Ts>(v);
+}
+
+// --------------------------------------------------------------- lattices
+// D3Q19 in the order of Eq. (3).
+__host__ __device__ constexpr int ex19(int q) {
+  return (q == 1 || q == 7 || q == 9 || q == 11 || q == 13) ? 1
+       : (q == 2 || q == 8 || q == 10 || q == 12 || q == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int ey19(int q) {
+  return (q == 3 || q == 7 || q == 8 || q == 15 || q == 17) ? 1
+       : (q == 4 || q == 9 || q == 10 || q == 16 || q == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int ez19(int q) {
+  return (q == 5 || q == 11 || q == 12 || q == 15 || q == 16) ? 1
+       : (q == 6 || q == 13 || q == 14 || q == 17 || q == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp19(int q) {
+  return q == 0 ? 0 : (q <= 6 ? (q % 2 ? q + 1 : q - 1)
+                               : (q <= 10 ? 17 - q : (q <= 14 ? 25 - q : 33 - q)));
+}
+// D3Q7 in the order of Eq. (5).
+__host__ __device__ constexpr int ex7(int q) { return q == 1 ? 1 : (q == 2 ? -1 : 0); }
+__host__ __device__ constexpr int ey7(int q) { return q == 3 ? 1 : (q == 4 ? -1 : 0); }
+__host__ __device__ constexpr int ez7(int q) { return q == 5 ? 1 : (q == 6 ? -1 : 0); }
+__host__ __device__ constexpr int opp7(int q) { return q == 0 ? 0 : (q % 2 ? q + 1 : q - 1); }
+
+static_assert(ex19(opp19(7)) == -1 && ey19(opp19(7)) == -1, "opp19");
+static_assert(opp19(8) == 9 && opp19(11) == 14 && opp19(12) == 13 && opp19(15) == 18 &&
+              opp19(16) == 17, "opp19");
+
+constexpr double kW7Axis = 0.125;  // D3Q7 weight of the six moving directions
+constexpr double kW7Rest = 0.25;
+
+// --------------------------------------------------------------- collision
+template <typename C>
+struct Rates {
+  C sv, qj, qe, gb, t0;
+};
+
+// MRT collision of f (Eq. (2) with the force of Eq. (1)) and of g (Eq. (4))
+// on shifted populations, then the store.  Gravity is along z, so the force
+// has one component F_z = gbeta (T - t0).
+template <typename Ts, bool FLOW, typename C>
+__device__ __forceinline__ void collide_store(C (&f)[19], C (&g)[7], bool liquid,
+                                              Ts* __restrict__ fd, Ts* __restrict__ gd,
+                                              uint32_t self, uint32_t nc, const Rates<C>& r,
+                                              int* __restrict__ flag) {
+  C Tt = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);  // T - t0
+  C ux = C(0), uy = C(0), uz = C(0);
+  bool bad = !(fabs(Tt) < C(1e30));
+
+  if (FLOW && liquid) {
+    // ---- forward transform m = M f (orthogonal D3Q19 basis) ----
+    const C axp = f[1] + f[2], axm = f[1] - f[2];
+    const C ayp = f[3] + f[4], aym = f[3] - f[4];
+    const C azp = f[5] + f[6], azm = f[5] - f[6];
+    const C a78 = f[7] + f[8], b78 = f[7] - f[8], a910 = f[9] + f[10], b910 = f[9] - f[10];
+    const C Sxy = a78 + a910, Xxy = b78 + b910, Yxy = a78 - a910, Pxy = b78 - b910;
+    const C a1112 = f[11] + f[12], b1112 = f[11] - f[12];
+    const C a1314 = f[13] + f[14], b1314 = f[13] - f[14];
+    const C Sxz = a1112 + a1314, Xxz = b1112 + b1314, Zxz = a1112 - a1314, Pxz = b1112 - b1314;
+    const C a1516 = f[15] + f[16], b1516 = f[15] - f[16];
+    const C a1718 = f[17] + f[18], b1718 = f[17] - f[18];
+    const C Syz = a1516 + a1718, Yyz = b1516 + b1718, Zyz = a1516 - a1718, Pyz = b1516 - b1718;
+    const C A = axp + ayp + azp;
+    const C E = Sxy + Sxz + Syz;
+
+    const C drho = f[0] + A + E;
+    const C m1 = C(-30) * f[0] - C(11) * A + C(8) * E;
+    const C m2 = C(12) * f[0] - C(4) * A + E;
+    const C jx = axm + Xxy + Xxz;
+    const C m4 = C(-4) * axm + Xxy + Xxz;
+    const C jy = aym + Yxy + Yyz;
+    const C m6 = C(-4) * aym + Yxy + Yyz;
+    const C jz = azm + Zxz + Zyz;
+    const C m8 = C(-4) * azm + Zxz + Zyz;
+    const C Ed = Sxy + Sxz - C(2) * Syz;
+    const C m9 = C(2) * axp - ayp - azp + Ed;
+    const C m10 = C(-4) * axp + C(2) * ayp + C(2) * azp + Ed;
+    const C m11 = ayp - azp + Sxy - Sxz;
+    const C m12 = C(-2) * ayp + C(2) * azp + Sxy - Sxz;
+    const C m16 = Xxy - Xxz, m17 = Yyz - Yxy, m18 = Zxz - Zyz;
+
+    // ---- macroscopic, force, equilibria (incompressible, rho0 = 1) ----
+    const C Fz = r.gb * Tt;
+    ux = jx;
+    uy = jy;
+    uz = jz + C(0.5) * Fz;
+    const C usq = ux * ux + uy * uy + uz * uz;
+    const C uF = uz * Fz;
+    const C p9 = C(3) * ux * ux - usq;
+    const C p11 = uy * uy - uz * uz;
+
+    // ---- relaxation S (reading: d'Humieres et al. 2002 rates) ----
+    constexpr C s_e = C(1.19), s_eps = C(1.4), s_q = C(1.2), s_pi = C(1.4), s_m = C(1.98);
+    const C sv = r.sv;
+    const C hv = C(1) - C(0.5) * sv;
+    const C m1s = m1 - s_e * (m1 - (C(-11) * drho + C(19) * usq)) + (C(1) - C(0.5) * s_e) * C(38) * uF;
+    const C m2s = m2 - s_eps * (m2 - (C(3) * drho - C(5.5) * usq)) + (C(1) - C(0.5) * s_eps) * C(-11) * uF;
+    const C m4s = m4 - s_q * (m4 + C(2.0 / 3.0) * ux);
+    const C m6s = m6 - s_q * (m6 + C(2.0 / 3.0) * uy);
+    const C m8s = m8 - s_q * (m8 + C(2.0 / 3.0) * uz) + (C(1) - C(0.5) * s_q) * C(-2.0 / 3.0) * Fz;
+    const C m7s = jz + Fz;
+    const C m9s = m9 - sv * (m9 - p9) + hv * C(-2) * uF;
+    const C m10s = m10 - s_pi * (m10 + C(0.5) * p9) + (C(1) - C(0.5) * s_pi) * uF;
+    const C m11s = m11 - sv * (m11 - p11) + hv * C(-2) * uF;
+    const C m12s = m12 - s_pi * (m12 + C(0.5) * p11) + (C(1) - C(0.5) * s_pi) * uF;
+    const C m13s = Pxy - sv * (Pxy - ux * uy);
+    const C m14s = Pyz - sv * (Pyz - uy * uz) + hv * uy * Fz;
+    const C m15s = Pxz - sv * (Pxz - ux * uz) + hv * ux * Fz;
+    const C km = C(1) - s_m;
+
+    // ---- inverse transform f = M^T D^-1 m* ----
+    const C a0 = drho * C(1.0 / 19.0);
+    const C a1 = m1s * C(1.0 / 2394.0);
+    const C a2 = m2s * C(1.0 / 252.0);
+    const C a3 = jx * C(0.1), a5 = jy * C(0.1), a7 = m7s * C(0.1);
+    const C a4 = m4s * C(1.0 / 40.0), a6 = m6s * C(1.0 / 40.0), a8 = m8s * C(1.0 / 40.0);
+    const C a9 = m9s * C(1.0 / 36.0), a10 = m10s * C(1.0 / 72.0);
+    const C a11 = m11s * C(1.0 / 12.0), a12 = m12s * C(1.0 / 24.0);
+    const C a13 = m13s * C(0.25), a14 = m14s * C(0.25), a15 = m15s * C(0.25);
+    const C a16 = km * m16 * C(0.125), a17 = km * m17 * C(0.125), a18 = km * m18 * C(0.125);
+
+    const C Aax = a0 - C(11) * a1 - C(4) * a2;
+    const C Aed = a0 + C(8) * a1 + a2;
+    C o[19];
+    o[0] = a0 - C(30) * a1 + C(12) * a2;
+    {
+      const C c = Aax + C(2) * a9 - C(4) * a10, d = a3 - C(4) * a4;
+      o[1] = c + d;
+      o[2] = c - d;
+    }
+    {
+      const C c = Aax - a9 + C(2) * a10 + a11 - C(2) * a12, d = a5 - C(4) * a6;
+      o[3] = c + d;
+      o[4] = c - d;
+    }
+    {
+      const C c = Aax - a9 + C(2) * a10 - a11 + C(2) * a12, d = a7 - C(4) * a8;
+      o[5] = c + d;
+      o[6] = c - d;
+    }
+    {  // xy edges 7..10
+      const C b = Aed + a9 + a10 + a11 + a12, X = a3 + a4 + a16, Y = a5 + a6 - a17;
+      o[7] = b + X + Y + a13;
+      o[8] = b - X + Y - a13;
+      o[9] = b + X - Y - a13;
+      o[10] = b - X - Y + a13;
+    }
+    {  // xz edges 11..14
+      const C b = Aed + a9 + a10 - a11 - a12, X = a3 + a4 - a16, Z = a7 + a8 + a18;
+      o[11] = b + X + Z + a15;
+      o[12] = b - X + Z - a15;
+      o[13] = b + X - Z - a15;
+      o[14] = b - X - Z + a15;
+    }
+    {  // yz edges 15..18
+      const C b = Aed - C(2) * a9 - C(2) * a10, Y = a5 + a6 + a17, Z = a7 + a8 - a18;
+      o[15] = b + Y + Z + a14;
+      o[16] = b - Y + Z - a14;
+      o[17] = b + Y - Z - a14;
+      o[18] = b - Y - Z + a14;
+    }
+#pragma unroll
+    for (int q = 0; q < 19; ++q) store(fd + (size_t)q * nc, self, o[q]);
+    bad = bad || !(fabs(drho) < C(1e30));
+  }
+
+  // ---- D3Q7 MRT collision of g (Eq. (4)), c_sT^2 = 1/4 ----
+  {
+    const C T = Tt + r.t0;
+    const C px = g[1] + g[2], py = g[3] + g[4], pz = g[5] + g[6];
+    const C n1 = g[1] - g[2], n2 = g[3] - g[4], n3 = g[5] - g[6];
+    const C n4 = C(6) * g[0] - (px + py + pz);
+    const C n5 = C(2) * px - py - pz;
+    const C n6 = py - pz;
+    const C n1s = n1 - r.qj * (n1 - ux * T);
+    const C n2s = n2 - r.qj * (n2 - uy * T);
+    const C n3s = n3 - r.qj * (n3 - uz * T);
+    const C n4s = n4 - r.qe * (n4 - C(0.75) * Tt);
+    const C ke = C(1) - r.qe;
+    const C b0 = Tt * C(1.0 / 7.0);
+    const C b1 = C(0.5) * n1s, b2 = C(0.5) * n2s, b3 = C(0.5) * n3s;
+    const C b4 = n4s * C(1.0 / 42.0), b5 = ke * n5 * C(1.0 / 12.0), b6 = ke * n6 * C(0.25);
+    const C c1 = b0 - b4 + C(2) * b5;
+    const C c3 = b0 - b4 - b5 + b6;
+    const C c5 = b0 - b4 - b5 - b6;
+    store(gd, self, b0 + C(6) * b4);
+    store(gd + (size_t)1 * nc, self, c1 + b1);
+    store(gd + (size_t)2 * nc, self, c1 - b1);
+    store(gd + (size_t)3 * nc, self, c3 + b2);
+    store(gd + (size_t)4 * nc, self, c3 - b2);
+    store(gd + (size_t)5 * nc, self, c5 + b3);
+    store(gd + (size_t)6 * nc, self, c5 - b3);
+  }
+  if (bad) *flag = 1;
+}
+
+// --------------------------------------------------------------- step kernel
+template <typename Ts, bool FLOW, bool MZ>
+__global__ __launch_bounds__(256) void k_stream_collide(
+    const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
+    Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
+    const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
+    int* __restrict__ flag, KParams P) {
+  using C = typename Compute<Ts>::type;
+  const int n = P.n;
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= n || y >= n) return;
+  const uint32_t nc = P.ncell;
+  const uint32_t nn = (uint32_t)n * (uint32_t)n;
+  const uint32_t self = (uint32_t)z * nn + (uint32_t)y * (uint32_t)n + (uint32_t)x;
+  const int a = MZ ? z : y;  // coordinate along the melt axis
+  const int o = MZ ? y : z;  // the other lateral coordinate
+  const int col = o * n + x;
+  const int cc = cnt[col];
+  const bool liquid = a < cc;
+  const bool interior = (y > 0) & (y < n - 1) & (z > 0) & (z < n - 1);
+  const bool all_liq = (a + 1) < cmin[col];
+  const bool all_sol = (a - 1) >= cmax[col];
+  const bool fast = interior & (all_liq | all_sol);
+
+  Rates<C> r;
+  r.sv = (C)P.s_nu;
+  r.qj = (C)P.q_j;
+  r.qe = (C)P.q_e;
+  r.gb = (C)P.gbeta;
+  r.t0 = (C)P.t0;
+
+  C f[19], g[7];
+
+  if (__all(fast)) {
+    // ---------- fast path: one phase, only x walls possible ----------
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const int ex = ex7(q);
+      const int off = ex + ey7(q) * n + ez7(q) * (int)nn;
+      const Ts* bq = gs + (size_t)q * nc;
+      if (ex == 0) {
+        g[q] = load(bq, self - off);
+      } else {
+        const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
+        C v = load(bq, wall ? self : self - off);
+        if (wall) v = load(gs + (size_t)opp7(q) * nc, self);  // adiabatic x wall
+        g[q] = v;
+      }
+    }
+    if (FLOW && liquid) {
+#pragma unroll
+      for (int q = 0; q < 19; ++q) {
+        const int ex = ex19(q);
+        const int off = ex + ey19(q) * n + ez19(q) * (int)nn;
+        const Ts* bq = fs + (size_t)q * nc;
+        if (ex == 0) {
+          f[q] = load(bq, self - off);
+        } else {
+          const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
+          C v = load(bq, wall ? self : self - off);
+          if (wall) v = load(fs + (size_t)opp19(q) * nc, self);  // no-slip x wall
+          f[q] = v;
+        }
+      }
+    }
+  } else {
+    // ---------- general path: walls and the front, link by link ----------
+    const double s_self = s[col];
+    const C wTm = C(kW7Axis) * (C)(P.t_m - P.t0);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const int ex = ex7(q), ey = ey7(q), ez = ez7(q), p = opp7(q);
+      const int sx = x - ex, sy = y - ey, sz = z - ez;
+      const Ts* bq = gs + (size_t)q * nc;
+      const Ts* bp = gs + (size_t)p * nc;
+      C v;
+      if ((unsigned)sx >= (unsigned)n || (unsigned)sy >= (unsigned)n || (unsigned)sz >= (unsigned)n) {
+        // thermal wall: Dirichlet (anti-bounce-back) or adiabatic (bounce-back)
+        const int sa = MZ ? sz : sy;
+        const C gp = load(bp, self);
+        if (sa < 0) {
+          v = -gp + C(2.0 * kW7Axis) * (C)(th[col] - P.t0);
+        } else if (!MZ && sa >= n) {
+          v = -gp + C(2.0 * kW7Axis) * (C)(P.t_c - P.t0);
+        } else {
+          v = gp;
+        }
+      } else {
+        const int sa = MZ ? sz : sy, so = MZ ? sy : sz;
+        const int scol = so * n + sx;
+        const bool src_liq = sa < cnt[scol];
+        const uint32_t src = self - (uint32_t)(ex + ey * n + ez * (int)nn);
+        if (src_liq == liquid) {
+          v = load(bq, src);
+        } else {
+          // interpolated anti-bounce-back at the front (wall value t_m)
+          const bool along = MZ ? (ez != 0) : (ey != 0);
+          double d;
+          if (along) {
+            d = fabs(s_self - (a + 0.5));
+          } else {
+            d = ((a + 0.5) - s_self) / (s[scol] - s_self);
+          }
+          const C dl = (C)d;
+          const C gp = load(bp, self);
+          if (d < 0.5) {
+            const int bx = x + ex, by = y + ey, bz = z + ez;
+            bool behind = (unsigned)bx < (unsigned)n && (unsigned)by < (unsigned)n &&
+                          (unsigned)bz < (unsigned)n;
+            if (behind) {
+              const int ba = MZ ? bz : by, bo = MZ ? by : bz;
+              behind = (ba < cnt[bo * n + bx]) == liquid;
+            }
+            if (behind) {
+              const uint32_t bidx = self + (uint32_t)(ex + ey * n + ez * (int)nn);
+              v = -(C(2) * dl * gp + (C(1) - C(2) * dl) * load(bp, bidx)) + C(2) * wTm;
+            } else {
+              v = -gp + C(2) * wTm;
+            }
+          } else {
+            const C inv2d = C(1) / (C(2) * dl);
+            v = -gp * inv2d + (C(2) * dl - C(1)) * inv2d * load(bq, self) + wTm / dl;
+          }
+        }
+      }
+      g[q] = v;
+    }
+    if (FLOW && liquid) {
+#pragma unroll
+      for (int q = 0; q < 19; ++q) {
+        const int ex = ex19(q), ey = ey19(q), ez = ez19(q);
+        const int sx = x - ex, sy = y - ey, sz = z - ez;
+        bool ok = (unsigned)sx < (unsigned)n && (unsigned)sy < (unsigned)n &&
+                  (unsigned)sz < (unsigned)n;
+        if (ok) {
+          const int sa = MZ ? sz : sy, so = MZ ? sy : sz;
+          ok = sa < cnt[so * n + sx];
+        }
+        // halfway bounce-back from walls and solid cells
+        const uint32_t src = self - (uint32_t)(ex + ey * n + ez * (int)nn);
+        f[q] = ok ? load(fs + (size_t)q * nc, src) : load(fs + (size_t)opp19(q) * nc, self);
+      }
+    }
+  }
+  collide_store<Ts, FLOW>(f, g, liquid, fd, gd, self, nc, r, flag);
+}
+
+// --------------------------------------------------------------- front update
+// Gradient of the one-sided quadratic through (0, tm), (xi0, T0v), (xi1, T1v)
+// at xi = 0; with one node, the chord slope.
+__device__ __forceinline__ double one_sided(int k, double xi0, double T0v, double xi1, double T1v,
+                                            double tm) {
+  if (k >= 2)
+    return ((T0v - tm) * xi1 * xi1 - (T1v - tm) * xi0 * xi0) / (xi0 * xi1 * (xi1 - xi0));
+  if (k == 1 && xi0 > 0.0) return (T0v - tm) / xi0;
+  return 0.0;
+}
+
+template <typename Ts, bool MZ>
+__device__ __forceinline__ double cell_T(const Ts* __restrict__ g, uint32_t nc, uint32_t cell,
+                                         double t0) {
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) acc += (double)load(g + (size_t)q * nc, cell);
+  return acc + t0;
+}
+
+__device__ __forceinline__ int count_liquid(double sv, int n) {
+  // number of a in [0, n) with a + 1/2 < s (exact: s - 1/2 is exact in FP64)
+  double c = ceil(sv - 0.5);
+  if (!(c > 0.0)) return 0;
+  if (c > (double)n) return n;
+  return (int)c;
+}
+
+template <typename Ts, bool FLOW, bool MZ>
+__global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
+                                               double* __restrict__ s_new, int* __restrict__ cnt,
+                                               const Ts* __restrict__ g, Ts* __restrict__ f,
+                                               const double* __restrict__ th,
+                                               int* __restrict__ melted, int* __restrict__ frozen,
+                                               int* __restrict__ flag, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = blockIdx.y;
+  if (x >= n) return;
+  const int col = o * n + x;
+  const uint32_t nc = P.ncell;
+  const uint32_t nn = (uint32_t)n * (uint32_t)n;
+  auto cell = [&](int a) -> uint32_t {
+    return MZ ? (uint32_t)a * nn + (uint32_t)o * n + x : (uint32_t)o * nn + (uint32_t)a * n + x;
+  };
+  const double sc = s_old[col];
+  const int c0 = cnt[col];
+
+  // liquid side: nodes with distance >= 1/2 from the front, then the hot wall
+  double xi0 = 0, T0v = 0, xi1 = 0, T1v = 0;
+  int k = 0;
+  for (int a = c0 - 1; a >= 0 && k < 2; --a) {
+    const double d = sc - (a + 0.5);
+    if (d >= 0.5) {
+      const double T = cell_T<Ts, MZ>(g, nc, cell(a), P.t0);
+      if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
+      ++k;
+    }
+  }
+  if (k < 2) {
+    if (k == 0) { xi0 = sc; T0v = th[col]; } else { xi1 = sc; T1v = th[col]; }
+    ++k;
+  }
+  const double Gl = -one_sided(k, xi0, T0v, xi1, T1v, P.t_m);
+
+  // solid side: nodes beyond the front, then the cold wall (melt axis y)
+  k = 0;
+  for (int a = c0; a < n && k < 2; ++a) {
+    const double d = (a + 0.5) - sc;
+    if (d >= 0.5) {
+      const double T = cell_T<Ts, MZ>(g, nc, cell(a), P.t0);
+      if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
+      ++k;
+    }
+  }
+  if (k < 2 && !MZ) {
+    if (k == 0) { xi0 = n - sc; T0v = P.t_c; } else { xi1 = n - sc; T1v = P.t_c; }
+    ++k;
+  }
+  const double Gs = one_sided(k, xi0, T0v, xi1, T1v, P.t_m);
+
+  // front slopes by central differences, mirrored at the walls
+  const double sxp = s_old[o * n + (x + 1 < n ? x + 1 : x)];
+  const double sxm = s_old[o * n + (x > 0 ? x - 1 : x)];
+  const double sop = s_old[(o + 1 < n ? o + 1 : o) * n + x];
+  const double som = s_old[(o > 0 ? o - 1 : o) * n + x];
+  const double dsx = 0.5 * (sxp - sxm), dso = 0.5 * (sop - som);
+  const double V = (1.0 + dsx * dsx + dso * dso) * P.alpha * P.ste * (Gs - Gl) / P.dT;
+  double sn = sc + V;
+  if (!(sn == sn)) *flag = 1;
+  sn = sn < 0.0 ? 0.0 : (sn > (double)n ? (double)n : sn);
+  s_new[col] = sn;
+
+  // phase switch: newly liquid cells start from the rest state of f
+  const int c1 = count_liquid(sn, n);
+  if (FLOW) {
+    for (int a = c0; a < c1; ++a) {
+      const uint32_t i = cell(a);
+#pragma unroll
+      for (int q = 0; q < 19; ++q) store(f + (size_t)q * nc, i, 0.0f);
+    }
+  }
+  if (c1 > c0) melted[col] += c1 - c0;
+  if (c1 < c0) frozen[col] += c0 - c1;
+  cnt[col] = c1;
+}
+
+__global__ void k_counts(const double* __restrict__ s, int* __restrict__ cnt, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * n) cnt[i] = count_liquid(s[i], n);
+}
+
+__global__ void k_neighbourhood(const int* __restrict__ cnt, int* __restrict__ cmin,
+                                int* __restrict__ cmax, int n) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = blockIdx.y;
+  if (x >= n) return;
+  int lo = 0x7fffffff, hi = -1;
+  for (int d_o = -1; d_o <= 1; ++d_o) {
+    const int oo = o + d_o;
+    if (oo < 0 || oo >= n) continue;
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int xx = x + dx;
+      if (xx < 0 || xx >= n) continue;
+      const int c = cnt[oo * n + xx];
+      lo = c < lo ? c : lo;
+      hi = c > hi ? c : hi;
+    }
+  }
+  cmin[o * n + x] = lo;
+  cmax[o * n + x] = hi;
+}
+
+// --------------------------------------------------------------- init, fields
+template <typename Ts, bool MZ>
+__global__ void k_init(const int* __restrict__ cnt, const double* __restrict__ seedT,
+                       Ts* __restrict__ f, Ts* __restrict__ g, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, z = blockIdx.z;
+  if (x >= n) return;
+  const uint32_t nc = P.ncell;
+  const uint32_t i = ((uint32_t)z * n + y) * n + x;
+  const int a = MZ ? z : y, o = MZ ? y : z;
+  const bool liquid = a < cnt[o * n + x];
+  const double Tt = (liquid ? seedT[a] : P.t_c) - P.t0;
+  store(g, i, kW7Rest * Tt);
+  for (int q = 1; q < 7; ++q) store(g + (size_t)q * nc, i, kW7Axis * Tt);
+  if (P.flow)
+    for (int q = 0; q < 19; ++q) store(f + (size_t)q * nc, i, 0.0);
+}
+
+template <typename Ts, bool MZ>
+__global__ void k_fields(const Ts* __restrict__ f, const Ts* __restrict__ g,
+                         const int* __restrict__ cnt, double* __restrict__ T,
+                         double* __restrict__ ux, double* __restrict__ uy,
+                         double* __restrict__ uz, double* __restrict__ rho, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, z = blockIdx.z;
+  if (x >= n) return;
+  const uint32_t nc = P.ncell;
+  const uint32_t i = ((uint32_t)z * n + y) * n + x;
+  const int a = MZ ? z : y, o = MZ ? y : z;
+  const bool liquid = a < cnt[o * n + x];
+  double Tt = 0.0;
+  for (int q = 0; q < 7; ++q) Tt += (double)load(g + (size_t)q * nc, i);
+  double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  if (P.flow && liquid) {
+    double d = 0.0;
+    for (int q = 0; q < 19; ++q) {
+      const double v = (double)load(f + (size_t)q * nc, i);
+      d += v;
+      jx += ex19(q) * v;
+      jy += ey19(q) * v;
+      jz += ez19(q) * v;
+    }
+    r = 1.0 + d;
+    jz -= 0.5 * P.gbeta * Tt;
+  }
+  if (T) T[i] = Tt + P.t0;
+  if (rho) rho[i] = r;
+  if (ux) ux[i] = jx;
+  if (uy) uy[i] = jy;
+  if (uz) uz[i] = jz;
+}
+
+// --------------------------------------------------------------- conversions
+__device__ __forceinline__ double weight(int qcount, int q) {
+  if (qcount == 7) return q == 0 ? kW7Rest : kW7Axis;
+  const int e2 = ex19(q) * ex19(q) + ey19(q) * ey19(q) + ez19(q) * ez19(q);
+  return e2 == 0 ? 1.0 / 3.0 : (e2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+template <typename Ts>
+__global__ void k_to_storage(const double* __restrict__ src, Ts* __restrict__ dst, int qcount,
+                             KParams P) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t total = (uint64_t)qcount * P.ncell;
+  if (i >= total) return;
+  const int q = (int)(i / P.ncell);
+  const double shift = weight(qcount, q) * (qcount == 7 ? P.t0 : 1.0);
+  dst[i] = static_cast<Ts>(src[i] - shift);
+}
+
+template <typename Ts>
+__global__ void k_from_storage(const Ts* __restrict__ src, double* __restrict__ dst, int qcount,
+                               KParams P) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t total = (uint64_t)qcount * P.ncell;
+  if (i >= total) return;
+  const int q = (int)(i / P.ncell);
+  const double shift = weight(qcount, q) * (qcount == 7 ? P.t0 : 1.0);
+  dst[i] = (double)static_cast<typename Compute<Ts>::type>(src[i]) + shift;
+}
+
+// --------------------------------------------------------------- reductions
+constexpr int kSumThreads = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // deterministic: fixed shuffle tree inside the wave, fixed order across waves
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kSumThreads / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kSumThreads) void k_sum4(const double* __restrict__ v0,
+                                                      const double* __restrict__ v1,
+                                                      const double* __restrict__ v2,
+                                                      const double* __restrict__ v3,
+                                                      int64_t count, double* __restrict__ out) {
+  __shared__ double sh[kSumThreads / 64];
+  const double* vs[4] = {v0, v1, v2, v3};
+  for (int k = 0; k < 4; ++k) {
+    const double* v = vs[k];
+    double acc = 0.0;
+    if (v)
+      for (int64_t i = threadIdx.x; i < count; i += kSumThreads) acc += v[i];
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[k] = t;
+  }
+}
+
+__global__ __launch_bounds__(kSumThreads) void k_sum_int(const int* __restrict__ v, int64_t count,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[kSumThreads / 64];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += kSumThreads) acc += (double)v[i];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+// --------------------------------------------------------------- dispatch
+template <typename Ts>
+hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* gs, void* gd,
+                       const int* cnt, const int* cmin, const int* cmax, const double* s,
+                       const double* th, int* flag, hipStream_t st) {
+  dim3 block(64, 4, 1);
+  dim3 grid((P.n + 63) / 64, (P.n + 3) / 4, P.n);
+  auto F = static_cast<const Ts*>(fs);
+  auto Fd = static_cast<Ts*>(fd);
+  auto G = static_cast<const Ts*>(gs);
+  auto Gd = static_cast<Ts*>(gd);
+  if (P.flow) {
+    if (P.melt_z)
+      hipLaunchKernelGGL((k_stream_collide<Ts, true, true>), grid, block, 0, st, F, Fd, G, Gd, cnt,
+                         cmin, cmax, s, th, flag, P);
+    else
+      hipLaunchKernelGGL((k_stream_collide<Ts, true, false>), grid, block, 0, st, F, Fd, G, Gd, cnt,
+                         cmin, cmax, s, th, flag, P);
+  } else {
+    if (P.melt_z)
+      hipLaunchKernelGGL((k_stream_collide<Ts, false, true>), grid, block, 0, st, F, Fd, G, Gd, cnt,
+                         cmin, cmax, s, th, flag, P);
+    else
+      hipLaunchKernelGGL((k_stream_collide<Ts, false, false>), grid, block, 0, st, F, Fd, G, Gd,
+                         cnt, cmin, cmax, s, th, flag, P);
+  }
+  return hipGetLastError();
+}
+
+template <typename Ts>
+hipError_t front_dispatch(const KParams& P, const double* s_old, double* s_new, int* cnt,
+                          const void* g, void* f, const double* th, int* melted, int* frozen,
+                          int* flag, hipStream_t st) {
+  dim3 block(64, 1, 1);
+  dim3 grid((P.n + 63) / 64, P.n, 1);
+  auto G = static_cast<const Ts*>(g);
+  auto F = static_cast<Ts*>(f);
+  if (P.flow) {
+    if (P.melt_z)
+      hipLaunchKernelGGL((k_front<Ts, true, true>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
+                         melted, frozen, flag, P);
+    else
+      hipLaunchKernelGGL((k_front<Ts, true, false>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
+                         melted, frozen, flag, P);
+  } else {
+    if (P.melt_z)
+      hipLaunchKernelGGL((k_front<Ts, false, true>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
+                         melted, frozen, flag, P);
+    else
+      hipLaunchKernelGGL((k_front<Ts, false, false>), grid, block, 0, st, s_old, s_new, cnt, G, F,
+                         th, melted, frozen, flag, P);
+  }
+  return hipGetLastError();
+}
+
+template <typename Ts>
+hipError_t init_dispatch(const KParams& P, const int* cnt, const double* seedT, void* f, void* g,
+                         hipStream_t st) {
+  dim3 block(64, 1, 1);
+  dim3 grid((P.n + 63) / 64, P.n, P.n);
+  if (P.melt_z)
+    hipLaunchKernelGGL((k_init<Ts, true>), grid, block, 0, st, cnt, seedT, static_cast<Ts*>(f),
+                       static_cast<Ts*>(g), P);
+  else
+    hipLaunchKernelGGL((k_init<Ts, false>), grid, block, 0, st, cnt, seedT, static_cast<Ts*>(f),
+                       static_cast<Ts*>(g), P);
+  return hipGetLastError();
+}
+
+template <typename Ts>
+hipError_t fields_dispatch(const KParams& P, const void* f, const void* g, const int* cnt,
+                           double* T, double* ux, double* uy, double* uz, double* rho,
+                           hipStream_t st) {
+  dim3 block(64, 1, 1);
+  dim3 grid((P.n + 63) / 64, P.n, P.n);
+  if (P.melt_z)
+    hipLaunchKernelGGL((k_fields<Ts, true>), grid, block, 0, st, static_cast<const Ts*>(f),
+                       static_cast<const Ts*>(g), cnt, T, ux, uy, uz, rho, P);
+  else
+    hipLaunchKernelGGL((k_fields<Ts, false>), grid, block, 0, st, static_cast<const Ts*>(f),
+                       static_cast<const Ts*>(g), cnt, T, ux, uy, uz, rho, P);
+  return hipGetLastError();
+}
+
+template <typename Ts>
+hipError_t conv_dispatch(bool to_storage, const KParams& P, int qcount, const void* src,
+                         void* dst, hipStream_t st) {
+  const uint64_t total = (uint64_t)qcount * P.ncell;
+  dim3 block(256, 1, 1);
+  dim3 grid((unsigned)((total + 255) / 256), 1, 1);
+  if (to_storage)
+    hipLaunchKernelGGL((k_to_storage<Ts>), grid, block, 0, st, static_cast<const double*>(src),
+                       static_cast<Ts*>(dst), qcount, P);
+  else
+    hipLaunchKernelGGL((k_from_storage<Ts>), grid, block, 0, st, static_cast<const Ts*>(src),
+                       static_cast<double*>(dst), qcount, P);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define LBMK_DISPATCH(kind, call)            \
+  switch (kind) {                            \
+    case kF64: return call<double>;          \
+    case kF32: return call<float>;           \
+    case kF16S: return call<_Float16>;       \
+    case kBF16S: return call<__bf16>;        \
+    default: return hipErrorInvalidValue;    \
+  }
+
+size_t store_bytes(int kind) {
+  switch (kind) {
+    case kF64: return 8;
+    case kF32: return 4;
+    case kF16S:
+    case kBF16S: return 2;
+    default: return 0;
+  }
+}
+
+hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, void* fd,
+                                 const void* gs, void* gd, const int* cnt, const int* cmin,
+                                 const int* cmax, const double* s, const double* th, int* flag,
+                                 hipStream_t st) {
+#define CALL(T) sc_dispatch<T>(P, fs, fd, gs, gd, cnt, cmin, cmax, s, th, flag, st)
+  switch (kind) {
+    case kF64: return CALL(double);
+    case kF32: return CALL(float);
+    case kF16S: return CALL(_Float16);
+    case kBF16S: return CALL(__bf16);
+    default: return hipErrorInvalidValue;
+  }
+#undef CALL
+}
+
+hipError_t launch_front(int kind, const KParams& P, const double* s_old, double* s_new, int* cnt,
+                        const void* g, void* f, const double* th, int* melted, int* frozen,
+                        int* flag, hipStream_t st) {
+#define CALL(T) front_dispatch<T>(P, s_old, s_new, cnt, g, f, th, melted, frozen, flag, st)
+  switch (kind) {
+    case kF64: return CALL(double);
+    case kF32: return CALL(float);
+    case kF16S: return CALL(_Float16);
+    case kBF16S: return CALL(__bf16);
+    default: return hipErrorInvalidValue;
+  }
+#undef CALL
+}
+
+hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
+                                hipStream_t st) {
+  dim3 block(64, 1, 1);
+  dim3 grid((P.n + 63) / 64, P.n, 1);
+  hipLaunchKernelGGL(k_neighbourhood, grid, block, 0, st, cnt, cmin, cmax, P.n);
+  return hipGetLastError();
+}
+
+hipError_t launch_counts(const KParams& P, const double* s, int* cnt, hipStream_t st) {
+  const int total = P.n * P.n;
+  hipLaunchKernelGGL(k_counts, dim3((total + 255) / 256), dim3(256), 0, st, s, cnt, P.n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int kind, const KParams& P, const int* cnt, const double* seedT, void* f,
+                       void* g, hipStream_t st) {
+#define CALL(T) init_dispatch<T>(P, cnt, seedT, f, g, st)
+  switch (kind) {
+    case kF64: return CALL(double);
+    case kF32: return CALL(float);
+    case kF16S: return CALL(_Float16);
+    case kBF16S: return CALL(__bf16);
+    default: return hipErrorInvalidValue;
+  }
+#undef CALL
+}
+
+hipError_t launch_fields(int kind, const KParams& P, const void* f, const void* g, const int* cnt,
+                         double* T, double* ux, double* uy, double* uz, double* rho,
+                         hipStream_t st) {
+#define CALL(T_) fields_dispatch<T_>(P, f, g, cnt, T, ux, uy, uz, rho, st)
+  switch (kind) {
+    case kF64: return CALL(double);
+    case kF32: return CALL(float);
+    case kF16S: return CALL(_Float16);
+    case kBF16S: return CALL(__bf16);
+    default: return hipErrorInvalidValue;
+  }
+#undef CALL
+}
+
+hipError_t launch_to_storage(int kind, const KParams& P, int q_count, const double* src, void* dst,
+                             hipStream_t st) {
+#define CALL(T) conv_dispatch<T>(true, P, q_count, src, dst, st)
+  switch (kind) {
+    case kF64: return CALL(double);
+    case kF32: return CALL(float);
+    case kF16S: return CALL(_Float16);
+    case kBF16S: return CALL(__bf16);
+    default: return hipErrorInvalidValue;
+  }
+#undef CALL
+}
+
+hipError_t launch_from_storage(int kind, const KParams& P, int q_count, const void* src,
+                               double* dst, hipStream_t st) {
+#define CALL(T) conv_dispatch<T>(false, P, q_count, src, dst, st)
+  switch (kind) {
+    case kF64: return CALL(double);
+    case kF32: return CALL(float);
+    case kF16S: return CALL(_Float16);
+    case kBF16S: return CALL(__bf16);
+    default: return hipErrorInvalidValue;
+  }
+#undef CALL
+}
+
+hipError_t launch_sum(const double* v0, const double* v1, const double* v2, const double* v3,
+                      int64_t count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum4, dim3(1), dim3(kSumThreads), 0, st, v0, v1, v2, v3, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_int(const int* v, int64_t count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_int, dim3(1), dim3(kSumThreads), 0, st, v, count, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbmk

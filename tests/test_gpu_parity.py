@@ -1,0 +1,148 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Both sides start from the same parameters and build their initial state
+independently; every comparison is element by element over the whole field
+at sizes that span several 64-wide x tiles and 4-row y tiles with ragged
+tails.  Tolerances: FP64 storage at round-off; FP32 storage within
+max|dT| <= 1e-5 and relative liquid-fraction error <= 1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import OracleSim
+
+pytestmark = pytest.mark.gpu
+
+HEAT = {"y0": 0, "z0": 1}
+
+
+def make_pair(steps=0, **kw):
+    from paper_1604_03478_amd import Config, Sim
+    cfg = Config(**kw)
+    orc = OracleSim(cfg.n, ra=cfg.ra, pr=cfg.pr, ste=cfg.ste, t_h=cfg.t_h, t_c=cfg.t_c,
+                    t_m=cfg.t_m, ma=cfg.ma, alpha=cfg.alpha, s0=cfg.s0,
+                    heating=HEAT[cfg.heating], flow=cfg.flow, seed_profile=cfg.seed_profile)
+    gpu = Sim(cfg)
+    if steps:
+        orc.step(steps)
+        gpu.step(steps)
+    return orc, gpu
+
+
+def diffs(orc, gpu):
+    Fo, Fg = orc.fields(), gpu.fields()
+    liq = Fo["rho"] > 0
+    return {
+        "T": np.abs(Fo["T"] - Fg["T"]).max(),
+        "s": np.abs(Fo["s"] - Fg["s"]).max(),
+        "u": np.abs(Fo["u"] - Fg["u"]).max(),
+        "rho": np.abs(Fo["rho"] - Fg["rho"]).max(),
+        "mask": int(np.sum(liq != (Fg["rho"] > 0))),
+        "fl_rel": abs(orc.liquid_fraction() - gpu.liquid_fraction()) / max(orc.liquid_fraction(), 1e-300),
+    }
+
+
+def test_initial_state_matches():
+    for prec in ("f64", "f32"):
+        orc, gpu = make_pair(n=20, flow=0, ste=0.1, s0=3.4, alpha=0.1, seed_profile=1,
+                             precision=prec)
+        d = diffs(orc, gpu)
+        assert d["T"] < (1e-15 if prec == "f64" else 1e-7), d
+        assert d["s"] == 0.0
+
+
+@pytest.mark.parametrize("prec,tol_T,tol_s", [("f64", 1e-12, 1e-12), ("f32", 1e-5, 1e-5)])
+def test_conduction_melting_24(prec, tol_T, tol_s):
+    """Conduction-controlled melting, 24^3, D3Q7 only, Ste = 0.1, 2000
+    steps, Neumann seed (the paper's verification case, section 3.1)."""
+    orc, gpu = make_pair(2000, n=24, flow=0, ste=0.1, s0=1.0, alpha=0.1, seed_profile=1,
+                         precision=prec)
+    d = diffs(orc, gpu)
+    assert d["T"] <= tol_T and d["s"] <= tol_s and d["mask"] == 0, d
+    assert d["fl_rel"] <= (1e-13 if prec == "f64" else 1e-6), d
+
+
+@pytest.mark.parametrize("heating,s0", [("y0", 23.3), ("z0", 10.6)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_convection_melting_70(heating, s0, prec):
+    """Full double MRT with buoyancy and a moving front, 70^3 (two x tiles,
+    ragged y tiles), 150 steps."""
+    orc, gpu = make_pair(150, n=70, ra=1e5, pr=1.0, ste=0.5, s0=s0, heating=heating,
+                         precision=prec)
+    d = diffs(orc, gpu)
+    assert d["mask"] == 0, d
+    if prec == "f64":
+        assert d["T"] < 1e-12 and d["s"] < 1e-12 and d["u"] < 1e-14 and d["rho"] < 1e-13, d
+    else:
+        assert d["T"] <= 1e-5 and d["fl_rel"] <= 1e-6, d
+        assert d["u"] <= 1e-6 and d["rho"] <= 1e-6, d
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_one_step_from_developed_state(prec):
+    """Run the oracle into a developed convecting state with a curved front,
+    hand the same state to both sides, take one step, compare."""
+    from paper_1604_03478_amd import Config, Sim
+    n = 36
+    kw = dict(n=n, ra=1e5, pr=1.0, ste=1.0, s0=9.7)
+    orc = OracleSim(n, ra=1e5, pr=1.0, ste=1.0, s0=9.7)
+    orc.step(400)
+    gpu = Sim(Config(**kw, precision=prec))
+    gpu.set_populations(orc.f.copy(), orc.g.copy(), orc.s.copy())
+    assert np.ptp(orc.s) > 0.02  # the front is not flat
+    d0 = diffs(orc, gpu)
+    assert d0["mask"] == 0
+    orc.step(1)
+    gpu.step(1)
+    d = diffs(orc, gpu)
+    if prec == "f64":
+        assert d["T"] < 1e-14 and d["s"] < 1e-14 and d["u"] < 1e-16 and d["rho"] < 1e-15, d
+    else:
+        assert d["T"] < 1e-6 and d["s"] < 1e-7 and d["u"] < 1e-8, d
+
+
+@pytest.mark.parametrize("n,s0", [(4, 1.5), (5, 0.0), (9, 9.0), (7, 3.5)])
+def test_edge_sizes_and_fronts(n, s0):
+    """Minimum size, ragged tiles, all-solid and all-liquid boxes, a front
+    exactly on a cell face."""
+    orc, gpu = make_pair(60, n=n, ra=1e3, pr=1.0, ste=0.5, s0=s0, precision="f64")
+    d = diffs(orc, gpu)
+    assert d["mask"] == 0 and d["T"] < 1e-13 and d["s"] < 1e-13 and d["u"] < 1e-15, d
+
+
+def test_runs_are_bitwise_deterministic():
+    from paper_1604_03478_amd import Config, Sim
+    out = []
+    for _ in range(2):
+        g = Sim(Config(n=40, ra=1e5, pr=1.0, ste=0.5, s0=11.2, precision="f32"))
+        g.step(120)
+        out.append(g.get_populations())
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_save_load_resume_is_bitwise():
+    from paper_1604_03478_amd import Config, Sim
+    cfg = Config(n=24, ra=1e5, pr=1.0, ste=0.5, s0=6.3, precision="f32")
+    a = Sim(cfg)
+    a.step(80)
+    ref = a.get_populations()
+    b = Sim(cfg)
+    b.step(40)
+    blob = b.save_state()
+    c = Sim(cfg)
+    c.load_state(blob)
+    assert c.steps == 40
+    c.step(40)
+    for x, y in zip(ref, c.get_populations()):
+        assert np.array_equal(x, y)
+
+
+def test_mass_conservation_on_gpu():
+    from paper_1604_03478_amd import Config, Sim
+    g = Sim(Config(n=32, ra=1e5, pr=1.0, ste=1.0, s0=4.2, precision="f64"))
+    m0 = g.diagnostics()["mass"]
+    g.step(200)
+    d = g.diagnostics()
+    assert d["melted"] > 0
+    assert abs(d["mass"] - (m0 + d["melted"])) < 1e-9
