@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Throughput of the double-MRT melting step on one MI355X.
+
+Metric: double-MRT MLUPS (million lattice-cell updates per second) and HBM
+GB/s at 256^3, FP32 distributions, with the 16-bit shifted-storage path
+reported beside it.
+
+Workload (the timed step): one full step of the method - fused pull-stream +
+MRT collide of f (D3Q19, Boussinesq force) and g (D3Q7), the interface
+update of Eq. (6), the phase switch and the neighbourhood masks - on the
+256^3 side-heated cavity (Ra = 1e5, Pr = 1, Ste = 0.1) in its all-liquid
+state (front at the far wall), so that every cell runs the full double MRT
+and moves 208 B (FP32).  The melting state of the same configuration
+(front near the heated wall) is timed as well and reported separately.
+
+Output: one JSON line (see the contract in the repository notes).  The
+roofline object uses the stream-collide kernel's average duration measured
+live with HIP events on the stream it runs on; `traffic` comes from the
+rocprofv3 counter summary under profiles/ when it was taken on the current
+kernel source (else null).
+
+Modes:
+  (default)       the benchmark line
+  --mode profile  a short run of the FP32 workload only (for rocprofv3)
+  --mode copy     a plain device copy of known size (counter calibration)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_CELL = {"f32": 208, "f16s": 104, "bf16s": 104, "f64": 416}
+KERNEL_SRC = os.path.join(ROOT, "paper_1604_03478_amd", "csrc", "lbm_kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stream_collide_f32_256_counters.md")
+
+
+def workload_config(n: int, precision: str, all_liquid: bool):
+    from paper_1604_03478_amd import Config
+    return Config(n=n, ra=1e5, pr=1.0, ste=0.1, t_h=1.0, t_c=0.0, t_m=0.0, ma=0.1,
+                  s0=float(n) if all_liquid else 1.0, heating="y0", flow=1,
+                  precision=precision)
+
+
+def time_steps(sim, stream, steps: int):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per step
+
+
+def kernel_ms(sim, steps: int):
+    sim.kernel_timing(True)
+    sim.step(steps)
+    ms, launches = sim.kernel_time()
+    sim.kernel_timing(False)
+    return ms / launches
+
+
+def measure(n, precision, all_liquid, steps, warmup, stream):
+    from paper_1604_03478_amd import Sim
+    sim = Sim(workload_config(n, precision, all_liquid), stream=stream)
+    sim.step(warmup)
+    ms = time_steps(sim, stream, steps)
+    kms = kernel_ms(sim, max(10, min(steps, 200)))
+    fl = sim.liquid_fraction()
+    sim.close()
+    return ms, kms, fl
+
+
+def traffic_from_profile(n: int):
+    """HBM bytes per stream-collide launch from the committed counter summary,
+    if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    text = open(TRAFFIC_SUMMARY).read()
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    m = re.search(r"kernel-source-sha256:\s*([0-9a-f]{64})", text)
+    t = re.search(r"hbm-bytes-per-launch:\s*([0-9.eE+]+)", text)
+    nn = re.search(r"lattice:\s*(\d+)", text)
+    if not (m and t and nn) or m.group(1) != src_hash or int(nn.group(1)) != n:
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(n: int, steps: int):
+    """The FP64 oracle, as it stands, on this host's cores: a bounded sample
+    of the same workload (a few steps of the all-liquid 256^3 state)."""
+    from oracle import OracleSim
+    from oracle.oracle import build_oracle
+    build_oracle()
+    orc = OracleSim(n, ra=1e5, pr=1.0, ste=0.1, t_h=1.0, t_c=0.0, t_m=0.0, ma=0.1,
+                    s0=float(n), heating=0, flow=1)
+    orc.step(1)  # first touch of the buffers
+    t0 = time.perf_counter()
+    orc.step(steps)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n ** 3 * steps / el / 1e6, "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps} steps of the {n}^3 all-liquid double-MRT state "
+                      f"({n ** 3 * steps / 1e6:.1f}M FP64 cell updates, {el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--mode", choices=["bench", "profile", "copy"], default="bench")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU slab decomposition is a design, not an implementation.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+
+    if args.mode == "copy":
+        nbytes = 2 << 30
+        with torch.cuda.stream(stream):
+            src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(5):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                dst.copy_(src)
+            e1.record(stream)
+            torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "ms": ms, "GBps": 2 * nbytes / ms / 1e6}), flush=True)
+        return
+
+    if args.mode == "profile":
+        from paper_1604_03478_amd import Sim
+        sim = Sim(workload_config(args.n, "f32", True), stream=stream)
+        sim.step(args.warmup)
+        ms = time_steps(sim, stream, args.steps)
+        print(json.dumps({"mode": "profile", "n": args.n, "steps": args.steps,
+                          "ms_per_step": ms}), flush=True)
+        return
+
+    n, K, W = args.n, args.steps, args.warmup
+    print(f"bench: {n}^3 all-liquid FP32, {W} warmup + {K} timed steps", file=sys.stderr,
+          flush=True)
+    ms, kms, fl = measure(n, "f32", True, K, W, stream)
+    mlups = n ** 3 / (ms * 1e-3) / 1e6
+    achieved = BYTES_PER_CELL["f32"] * n ** 3 / (kms * 1e-3) / 1e9
+    traffic = traffic_from_profile(n)
+
+    print("bench: 16-bit shifted storage and the melting state", file=sys.stderr, flush=True)
+    ms16, kms16, _ = measure(n, "f16s", True, K, W, stream)
+    msm, kmsm, flm = measure(n, "f32", False, K, W, stream)
+
+    line = {
+        "metric": "double-MRT MLUPS & HBM GB/s at 256^3; FP16-store vs FP32 at equal error",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"convection melting {n}^3, side-heated (hot y=0), Ra=1e5, Pr=1, "
+                        "Ste=0.1, full double MRT (D3Q19 f + D3Q7 g), all-liquid state",
+            "n": n, "cells": n ** 3, "liquid_fraction": round(fl, 6),
+            "storage": "fp32 shifted", "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_stream_collide<float>",
+            "kernel_ms": round(kms, 5),
+            "bytes_per_cell": BYTES_PER_CELL["f32"],
+        },
+        "fp16s": {
+            "value": round(n ** 3 / (ms16 * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(ms16, 5), "kernel_ms": round(kms16, 5),
+            "achieved_GBps": round(BYTES_PER_CELL["f16s"] * n ** 3 / (kms16 * 1e-3) / 1e9, 1),
+            "bytes_per_cell": BYTES_PER_CELL["f16s"],
+        },
+        "melting_state": {
+            "value": round(n ** 3 / (msm * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "liquid_fraction": round(flm, 6), "ms_per_step": round(msm, 5),
+            "note": "front near the heated wall: solid cells move only g (56 B)",
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -230,6 +230,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   lbmk::KParams& k = c->kp;
   k.n = n;
   k.ncell = (uint32_t)nc;
+  k.qstride = lbmk::population_stride((uint32_t)nc, c->kind);
   k.melt_z = params->heating == LBM_HEAT_Z0;
   k.flow = params->flow;
   k.t0 = L.t0;
@@ -257,17 +258,18 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
       return bail(fail(LBM_EDEVICE, "hipStreamCreate failed"));
     c->own_stream = true;
   }
+  const size_t qs = k.qstride;
   if (params->flow) {
     for (int b = 0; b < 2; ++b)
-      if (hipMalloc(&c->f[b], 19 * nc * c->esz) != hipSuccess) {
+      if (hipMalloc(&c->f[b], 19 * qs * c->esz) != hipSuccess) {
         c->f[b] = nullptr;
-        return bail(fail(LBM_ENOMEM, "cannot allocate f (%zu bytes)", 19 * nc * c->esz));
+        return bail(fail(LBM_ENOMEM, "cannot allocate f (%zu bytes)", 19 * qs * c->esz));
       }
   }
   for (int b = 0; b < 2; ++b)
-    if (hipMalloc(&c->g[b], 7 * nc * c->esz) != hipSuccess) {
+    if (hipMalloc(&c->g[b], 7 * qs * c->esz) != hipSuccess) {
       c->g[b] = nullptr;
-      return bail(fail(LBM_ENOMEM, "cannot allocate g (%zu bytes)", 7 * nc * c->esz));
+      return bail(fail(LBM_ENOMEM, "cannot allocate g (%zu bytes)", 7 * qs * c->esz));
     }
   if ((rc = dalloc(&c->s[0], nn)) || (rc = dalloc(&c->s[1], nn)) || (rc = dalloc(&c->cnt, nn)) ||
       (rc = dalloc(&c->cmin, nn)) || (rc = dalloc(&c->cmax, nn)) ||
@@ -358,9 +360,9 @@ int lbm_liquid_fraction(lbm_ctx* c, double* fl) {
   if (rc) return rc;
   if (!fl) return fail(LBM_EINVAL, "fl is NULL");
   const int64_t nn = (int64_t)c->p.n * c->p.n;
-  HIP_TRY(lbmk::launch_sum(c->s[c->scur], nullptr, nullptr, nullptr, nn, c->red, c->stream));
-  double host[4];
-  HIP_TRY(hipMemcpyAsync(host, c->red, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(lbmk::launch_sum(c->s[c->scur], nn, c->red, c->stream));
+  double host[1];
+  HIP_TRY(hipMemcpyAsync(host, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if ((rc = check_unstable(c))) return rc;
   *fl = host[0] / ((double)nn * c->p.n);
   return LBM_OK;
@@ -476,7 +478,10 @@ int lbm_diagnostics(lbm_ctx* c, double out[5]) {
   double* d = c->fields;
   HIP_TRY(lbmk::launch_fields(c->kind, c->kp, c->f[c->cur], c->g[c->cur], c->cnt, d, nullptr,
                               nullptr, nullptr, d + 4 * nc, c->stream));
-  HIP_TRY(lbmk::launch_sum(d + 4 * nc, d, c->s[c->scur], nullptr, (int64_t)nc, c->red, c->stream));
+  // each reduction over its own array length: rho and T have n^3 values, s has n^2
+  HIP_TRY(lbmk::launch_sum(d + 4 * nc, (int64_t)nc, c->red + 0, c->stream));
+  HIP_TRY(lbmk::launch_sum(d, (int64_t)nc, c->red + 1, c->stream));
+  HIP_TRY(lbmk::launch_sum(c->s[c->scur], (int64_t)nn, c->red + 2, c->stream));
   HIP_TRY(lbmk::launch_sum_int(c->melted, (int64_t)nn, c->red + 4, c->stream));
   HIP_TRY(lbmk::launch_sum_int(c->frozen, (int64_t)nn, c->red + 5, c->stream));
   double h[8];
@@ -513,9 +518,14 @@ int lbm_save_state(lbm_ctx* c, void* host_buf, size_t* bytes) {
   char* b = static_cast<char*>(host_buf);
   memcpy(b, &h, sizeof(h));
   b += sizeof(h);
-  if (fb) HIP_TRY(hipMemcpyAsync(b, c->f[c->cur], fb, hipMemcpyDeviceToHost, c->stream));
+  const size_t pb = nc * c->esz, sb = c->kp.qstride * c->esz;  // bytes per population
+  for (size_t q = 0; fb && q < 19; ++q)
+    HIP_TRY(hipMemcpyAsync(b + q * pb, static_cast<char*>(c->f[c->cur]) + q * sb, pb,
+                           hipMemcpyDeviceToHost, c->stream));
   b += fb;
-  HIP_TRY(hipMemcpyAsync(b, c->g[c->cur], gb, hipMemcpyDeviceToHost, c->stream));
+  for (size_t q = 0; q < 7; ++q)
+    HIP_TRY(hipMemcpyAsync(b + q * pb, static_cast<char*>(c->g[c->cur]) + q * sb, pb,
+                           hipMemcpyDeviceToHost, c->stream));
   b += gb;
   HIP_TRY(hipMemcpyAsync(b, c->s[c->scur], nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   b += nn * sizeof(double);
@@ -542,9 +552,14 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes) {
       h.heating != c->p.heating || h.ncell != nc)
     return fail(LBM_EINVAL, "state blob was made by an incompatible context");
   const char* b = static_cast<const char*>(host_buf) + sizeof(h);
-  if (fb) HIP_TRY(hipMemcpyAsync(c->f[c->cur], b, fb, hipMemcpyHostToDevice, c->stream));
+  const size_t pb = nc * c->esz, sb = c->kp.qstride * c->esz;  // bytes per population
+  for (size_t q = 0; fb && q < 19; ++q)
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(c->f[c->cur]) + q * sb, b + q * pb, pb,
+                           hipMemcpyHostToDevice, c->stream));
   b += fb;
-  HIP_TRY(hipMemcpyAsync(c->g[c->cur], b, gb, hipMemcpyHostToDevice, c->stream));
+  for (size_t q = 0; q < 7; ++q)
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(c->g[c->cur]) + q * sb, b + q * pb, pb,
+                           hipMemcpyHostToDevice, c->stream));
   b += gb;
   HIP_TRY(hipMemcpyAsync(c->s[c->scur], b, nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
   b += nn * sizeof(double);

@@ -16,6 +16,7 @@ enum StoreKind { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
 struct KParams {
   int n;           // cells per edge
   uint32_t ncell;  // n^3
+  uint64_t qstride;  // elements between consecutive population arrays (>= ncell)
   int melt_z;      // 0: melt axis y (hot wall y=0, cold wall y=n); 1: axis z
   int flow;        // 0: energy distribution only
   double t0;       // reference temperature (storage shift and buoyancy)
@@ -31,6 +32,11 @@ struct KParams {
 };
 
 size_t store_bytes(int kind);
+
+// Population-array stride for n^3 cells: n^3 plus a pad that keeps the arrays
+// of different directions from starting at the same offset modulo large
+// powers of two.
+uint64_t population_stride(uint32_t ncell, int kind);
 
 // One fused stream + collide pass over all cells: reads (fs, gs), writes
 // (fd, gd).  cnt/cmin/cmax: liquid-cell count per column and its min / max
@@ -72,10 +78,9 @@ hipError_t launch_to_storage(int kind, const KParams& P, int q_count, const doub
 hipError_t launch_from_storage(int kind, const KParams& P, int q_count, const void* src,
                                double* dst, hipStream_t st);
 
-// Deterministic FP64 sums (fixed order; no atomics).  out[k] = sum of
-// v_k[0..count).  Up to 4 vectors per launch (null vectors give 0).
-hipError_t launch_sum(const double* v0, const double* v1, const double* v2, const double* v3,
-                      int64_t count, double* out, hipStream_t st);
+// Deterministic FP64 sum (fixed order; no atomics) of v[0..count) into
+// out[0].  count must not exceed the number of elements v points to.
+hipError_t launch_sum(const double* v, int64_t count, double* out, hipStream_t st);
 hipError_t launch_sum_int(const int* v, int64_t count, double* out, hipStream_t st);
 
 }  // namespace lbmk

@@ -19,15 +19,21 @@
 //     cell instead of 1444 for a dense product; no MFMA (the transform is a
 //     tiny, sparse, per-cell integer matrix and the kernel is HBM bound).
 //   * A wave takes the fast path when every lane is away from the y/z walls
-//     and its 3x3x3 stencil lies in one phase; x walls are handled there by
-//     a rare masked reload.  Waves that touch the front or a y/z wall take
-//     the general path with per-link boundary handling.
-//   * Each population array is addressed as a wave-uniform base plus a 32-bit
-//     per-lane byte offset (global_load ... saddr form).
+//     and its 3x3x3 stencil lies in one phase; x walls are handled there by a
+//     per-lane address select, so all 26 loads of a cell are issued before
+//     the first wait.  Waves that touch the front or a y/z wall take the
+//     general path with per-link boundary handling.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "lbm_internal.h"
+
+#ifndef LBM_LOAD
+#define LBM_LOAD(p) (*(p))
+#endif
+#ifndef LBM_POP_PAD_BYTES
+#define LBM_POP_PAD_BYTES 4352
+#endif
 
 namespace lbmk {
 namespace {
@@ -47,6 +53,14 @@ template <typename Ts, typename C>
 __device__ __forceinline__ void store(Ts* __restrict__ base, uint32_t i, C v) {
   Ts* p = reinterpret_cast<Ts*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(Ts)));
   *p = static_cast<Ts>(v);
+}
+
+// Stores of the step kernel: written once, read only in the next step, so
+// they bypass the caches (non-temporal).
+template <typename Ts, typename C>
+__device__ __forceinline__ void store_stream(Ts* __restrict__ base, uint32_t i, C v) {
+  Ts* p = reinterpret_cast<Ts*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(Ts)));
+  __builtin_nontemporal_store(static_cast<Ts>(v), p);
 }
 
 // --------------------------------------------------------------- lattices
@@ -87,13 +101,11 @@ struct Rates {
 };
 
 // MRT collision of f (Eq. (2) with the force of Eq. (1)) and of g (Eq. (4))
-// on shifted populations, then the store.  Gravity is along z, so the force
-// has one component F_z = gbeta (T - t0).
-template <typename Ts, bool FLOW, typename C>
-__device__ __forceinline__ void collide_store(C (&f)[19], C (&g)[7], bool liquid,
-                                              Ts* __restrict__ fd, Ts* __restrict__ gd,
-                                              uint32_t self, uint32_t nc, const Rates<C>& r,
-                                              int* __restrict__ flag) {
+// on shifted populations, in place (f is left untouched in solid cells).
+// Gravity is along z, so the force has one component F_z = gbeta (T - t0).
+// Returns true when a non-finite value appeared.
+template <bool FLOW, typename C>
+__device__ __forceinline__ bool collide(C (&f)[19], C (&g)[7], bool liquid, const Rates<C>& r) {
   C Tt = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);  // T - t0
   C ux = C(0), uy = C(0), uz = C(0);
   bool bad = !(fabs(Tt) < C(1e30));
@@ -211,7 +223,7 @@ __device__ __forceinline__ void collide_store(C (&f)[19], C (&g)[7], bool liquid
       o[18] = b - Y - Z + a14;
     }
 #pragma unroll
-    for (int q = 0; q < 19; ++q) store(fd + (size_t)q * nc, self, o[q]);
+    for (int q = 0; q < 19; ++q) f[q] = o[q];
     bad = bad || !(fabs(drho) < C(1e30));
   }
 
@@ -234,31 +246,29 @@ __device__ __forceinline__ void collide_store(C (&f)[19], C (&g)[7], bool liquid
     const C c1 = b0 - b4 + C(2) * b5;
     const C c3 = b0 - b4 - b5 + b6;
     const C c5 = b0 - b4 - b5 - b6;
-    store(gd, self, b0 + C(6) * b4);
-    store(gd + (size_t)1 * nc, self, c1 + b1);
-    store(gd + (size_t)2 * nc, self, c1 - b1);
-    store(gd + (size_t)3 * nc, self, c3 + b2);
-    store(gd + (size_t)4 * nc, self, c3 - b2);
-    store(gd + (size_t)5 * nc, self, c5 + b3);
-    store(gd + (size_t)6 * nc, self, c5 - b3);
+    g[0] = b0 + C(6) * b4;
+    g[1] = c1 + b1;
+    g[2] = c1 - b1;
+    g[3] = c3 + b2;
+    g[4] = c3 - b2;
+    g[5] = c5 + b3;
+    g[6] = c5 - b3;
   }
-  if (bad) *flag = 1;
+  return bad;
 }
 
 // --------------------------------------------------------------- step kernel
+// One cell of the fused step: pull-stream f and g, collide, store.
 template <typename Ts, bool FLOW, bool MZ>
-__global__ __launch_bounds__(256) void k_stream_collide(
-    const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
-    Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
-    const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
-    int* __restrict__ flag, KParams P) {
+__device__ __forceinline__ void update_cell(
+    int x, int y, int z, const Ts* __restrict__ fs, Ts* __restrict__ fd,
+    const Ts* __restrict__ gs, Ts* __restrict__ gd, const int* __restrict__ cnt,
+    const int* __restrict__ cmin, const int* __restrict__ cmax, const double* __restrict__ s,
+    const double* __restrict__ th, int* __restrict__ flag, const KParams& P) {
   using C = typename Compute<Ts>::type;
   const int n = P.n;
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  const int z = blockIdx.z;
   if (x >= n || y >= n) return;
-  const uint32_t nc = P.ncell;
+  const size_t qs = P.qstride;
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
   const uint32_t self = (uint32_t)z * nn + (uint32_t)y * (uint32_t)n + (uint32_t)x;
   const int a = MZ ? z : y;  // coordinate along the melt axis
@@ -286,14 +296,15 @@ __global__ __launch_bounds__(256) void k_stream_collide(
     for (int q = 0; q < 7; ++q) {
       const int ex = ex7(q);
       const int off = ex + ey7(q) * n + ez7(q) * (int)nn;
-      const Ts* bq = gs + (size_t)q * nc;
+      const Ts* bq = gs + (size_t)q * qs;
       if (ex == 0) {
-        g[q] = load(bq, self - off);
+        g[q] = static_cast<C>(LBM_LOAD(bq + (self - off)));
       } else {
+        // adiabatic x wall: bounce-back, chosen by a per-lane address select
+        // (no branch, so the loads of all directions stay in flight together)
         const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
-        C v = load(bq, wall ? self : self - off);
-        if (wall) v = load(gs + (size_t)opp7(q) * nc, self);  // adiabatic x wall
-        g[q] = v;
+        const Ts* p = wall ? gs + (size_t)opp7(q) * qs + self : bq + (self - off);
+        g[q] = static_cast<C>(LBM_LOAD(p));
       }
     }
     if (FLOW && liquid) {
@@ -301,14 +312,14 @@ __global__ __launch_bounds__(256) void k_stream_collide(
       for (int q = 0; q < 19; ++q) {
         const int ex = ex19(q);
         const int off = ex + ey19(q) * n + ez19(q) * (int)nn;
-        const Ts* bq = fs + (size_t)q * nc;
+        const Ts* bq = fs + (size_t)q * qs;
         if (ex == 0) {
-          f[q] = load(bq, self - off);
+          f[q] = static_cast<C>(LBM_LOAD(bq + (self - off)));
         } else {
+          // no-slip x wall: halfway bounce-back by a per-lane address select
           const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
-          C v = load(bq, wall ? self : self - off);
-          if (wall) v = load(fs + (size_t)opp19(q) * nc, self);  // no-slip x wall
-          f[q] = v;
+          const Ts* p = wall ? fs + (size_t)opp19(q) * qs + self : bq + (self - off);
+          f[q] = static_cast<C>(LBM_LOAD(p));
         }
       }
     }
@@ -320,8 +331,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(
     for (int q = 0; q < 7; ++q) {
       const int ex = ex7(q), ey = ey7(q), ez = ez7(q), p = opp7(q);
       const int sx = x - ex, sy = y - ey, sz = z - ez;
-      const Ts* bq = gs + (size_t)q * nc;
-      const Ts* bp = gs + (size_t)p * nc;
+      const Ts* bq = gs + (size_t)q * qs;
+      const Ts* bp = gs + (size_t)p * qs;
       C v;
       if ((unsigned)sx >= (unsigned)n || (unsigned)sy >= (unsigned)n || (unsigned)sz >= (unsigned)n) {
         // thermal wall: Dirichlet (anti-bounce-back) or adiabatic (bounce-back)
@@ -385,13 +396,221 @@ __global__ __launch_bounds__(256) void k_stream_collide(
           const int sa = MZ ? sz : sy, so = MZ ? sy : sz;
           ok = sa < cnt[so * n + sx];
         }
-        // halfway bounce-back from walls and solid cells
+        // halfway bounce-back from walls and solid cells (address select)
         const uint32_t src = self - (uint32_t)(ex + ey * n + ez * (int)nn);
-        f[q] = ok ? load(fs + (size_t)q * nc, src) : load(fs + (size_t)opp19(q) * nc, self);
+        const Ts* p = ok ? fs + (size_t)q * qs + src : fs + (size_t)opp19(q) * qs + self;
+        f[q] = static_cast<C>(*p);
       }
     }
   }
-  collide_store<Ts, FLOW>(f, g, liquid, fd, gd, self, nc, r, flag);
+  if (collide<FLOW>(f, g, liquid, r)) *flag = 1;
+  if (FLOW && liquid) {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) store_stream(fd + (size_t)q * qs, self, f[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 7; ++q) store_stream(gd + (size_t)q * qs, self, g[q]);
+}
+
+// Rows of cells along y handled one after another by each thread.
+#ifndef LBM_ROWS_PER_THREAD
+#define LBM_ROWS_PER_THREAD 1
+#endif
+constexpr int kRows = LBM_ROWS_PER_THREAD;
+
+template <typename Ts, bool FLOW, bool MZ>
+__global__ __launch_bounds__(512) void k_stream_collide(
+    const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
+    Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
+    const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
+    int* __restrict__ flag, KParams P) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y0 = (blockIdx.y * blockDim.y + threadIdx.y) * kRows;
+  const int z = blockIdx.z;
+  for (int k = 0; k < kRows; ++k)
+    update_cell<Ts, FLOW, MZ>(x, y0 + k, z, fs, fd, gs, gd, cnt, cmin, cmax, s, th, flag, P);
+}
+
+// --------------------------------------------------------------- row-wave step kernel
+// One wave per 64*VW consecutive cells of an x row; each lane owns VW
+// consecutive cells.  Every population is read as one aligned VW-wide vector
+// per lane from its source row; the +-1 shift in x of the x-moving
+// directions comes from the neighbouring lane (wave shuffle), and only the
+// two segment-edge lanes read one extra value from memory (bounce-back at
+// an x wall, or the first cell of the next segment).  Waves that are not in
+// the bulk of one phase fall back to the per-cell path, 64 cells at a time.
+template <typename T, int W>
+using vec_t = T __attribute__((ext_vector_type(W)));
+
+template <typename Ts, int VW, bool FLOW, bool MZ>
+__global__ __launch_bounds__(256) void k_stream_collide_rows(
+    const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
+    Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
+    const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
+    int* __restrict__ flag, KParams P) {
+  using C = typename Compute<Ts>::type;
+  using V = vec_t<Ts, VW>;
+  using VI = vec_t<int, VW>;
+  const int n = P.n;
+  const int lane = threadIdx.x;          // blockDim.x == 64: one wave per segment
+  const int xw = blockIdx.x * (64 * VW);  // first cell of the segment
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (y >= n) return;  // whole wave
+  const int x0 = xw + lane * VW;
+  const size_t qs = P.qstride;
+  const uint32_t nn = (uint32_t)n * (uint32_t)n;
+  const uint32_t self0 = (uint32_t)z * nn + (uint32_t)y * (uint32_t)n + (uint32_t)x0;
+  const int a = MZ ? z : y;
+  const int o = MZ ? y : z;
+  const int col0 = o * n + x0;
+
+  const VI mn = *reinterpret_cast<const VI*>(cmin + col0);
+  const VI mx = *reinterpret_cast<const VI*>(cmax + col0);
+  bool all_liq = true, all_sol = true;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) {
+    all_liq = all_liq && (a + 1) < mn[k];
+    all_sol = all_sol && (a - 1) >= mx[k];
+  }
+  const bool interior = (y > 0) & (y < n - 1) & (z > 0) & (z < n - 1);
+  if (!__all(interior & (all_liq | all_sol))) {
+    for (int k = 0; k < VW; ++k)
+      update_cell<Ts, FLOW, MZ>(xw + 64 * k + lane, y, z, fs, fd, gs, gd, cnt, cmin, cmax, s, th,
+                                flag, P);
+    return;
+  }
+  const bool liquid = all_liq;
+  const bool left_edge = lane == 0, right_edge = lane == 63;
+
+  Rates<C> r;
+  r.sv = (C)P.s_nu;
+  r.qj = (C)P.q_j;
+  r.qe = (C)P.q_e;
+  r.gb = (C)P.gbeta;
+  r.t0 = (C)P.t0;
+
+  // ---- loads: one aligned vector per direction, from its source row ----
+  C gv[7][VW];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const int roff = ey7(q) * n + ez7(q) * (int)nn;
+    const V v = *reinterpret_cast<const V*>(gs + (size_t)q * qs + (self0 - roff));
+#pragma unroll
+    for (int k = 0; k < VW; ++k) gv[q][k] = static_cast<C>(v[k]);
+  }
+  C fv[19][VW];
+  if (FLOW && liquid) {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      const int roff = ey19(q) * n + ez19(q) * (int)nn;
+      const V v = *reinterpret_cast<const V*>(fs + (size_t)q * qs + (self0 - roff));
+#pragma unroll
+      for (int k = 0; k < VW; ++k) fv[q][k] = static_cast<C>(v[k]);
+    }
+  }
+  // segment-edge values of the x-moving directions (bounce-back at x walls:
+  // adiabatic for g, no-slip for f; otherwise the neighbouring segment)
+  C gL = C(0), gR = C(0);
+  C fL[5] = {C(0), C(0), C(0), C(0), C(0)}, fR[5] = {C(0), C(0), C(0), C(0), C(0)};
+  if (left_edge) {  // directions with e_x = +1 pull from x0 - 1
+    const bool wall = xw == 0;
+    gL = wall ? static_cast<C>(gs[(size_t)opp7(1) * qs + self0])
+              : static_cast<C>(gs[(size_t)1 * qs + self0 - 1]);
+    if (FLOW && liquid) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        const int q = i == 0 ? 1 : 5 + 2 * i;  // 1, 7, 9, 11, 13
+        const int off = 1 + ey19(q) * n + ez19(q) * (int)nn;
+        fL[i] = wall ? static_cast<C>(fs[(size_t)opp19(q) * qs + self0])
+                     : static_cast<C>(fs[(size_t)q * qs + self0 - off]);
+      }
+    }
+  }
+  if (right_edge) {  // directions with e_x = -1 pull from x0 + VW
+    const uint32_t last = self0 + VW - 1;
+    const bool wall = x0 + VW == n;
+    gR = wall ? static_cast<C>(gs[(size_t)opp7(2) * qs + last])
+              : static_cast<C>(gs[(size_t)2 * qs + last + 1]);
+    if (FLOW && liquid) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        const int q = i == 0 ? 2 : 6 + 2 * i;  // 2, 8, 10, 12, 14
+        const int off = -1 + ey19(q) * n + ez19(q) * (int)nn;
+        fR[i] = wall ? static_cast<C>(fs[(size_t)opp19(q) * qs + last])
+                     : static_cast<C>(fs[(size_t)q * qs + last - off]);
+      }
+    }
+  }
+  // neighbour-lane values for the shift
+  C gl_in = __shfl_up(gv[1][VW - 1], 1, 64);
+  C gr_in = __shfl_down(gv[2][0], 1, 64);
+  if (left_edge) gl_in = gL;
+  if (right_edge) gr_in = gR;
+  C fl_in[5], fr_in[5];
+  if (FLOW && liquid) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const int qp = i == 0 ? 1 : 5 + 2 * i;
+      const int qm = i == 0 ? 2 : 6 + 2 * i;
+      fl_in[i] = __shfl_up(fv[qp][VW - 1], 1, 64);
+      fr_in[i] = __shfl_down(fv[qm][0], 1, 64);
+      if (left_edge) fl_in[i] = fL[i];
+      if (right_edge) fr_in[i] = fR[i];
+    }
+  }
+
+  // ---- collide each cell ----
+  C go[7][VW];
+  C fo[19][VW];
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) {
+    C g[7], f[19];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const int ex = ex7(q);
+      g[q] = ex == 0 ? gv[q][k]
+           : ex > 0 ? (k > 0 ? gv[q][k - 1] : gl_in)
+                    : (k < VW - 1 ? gv[q][k + 1] : gr_in);
+    }
+    if (FLOW && liquid) {
+#pragma unroll
+      for (int q = 0; q < 19; ++q) {
+        const int ex = ex19(q);
+        const int i = q <= 2 ? 0 : (q - 7) / 2 + 1;  // index among the x-moving pairs
+        f[q] = ex == 0 ? fv[q][k]
+             : ex > 0 ? (k > 0 ? fv[q][k - 1] : fl_in[i])
+                      : (k < VW - 1 ? fv[q][k + 1] : fr_in[i]);
+      }
+    }
+    bad = collide<FLOW>(f, g, liquid, r) || bad;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) go[q][k] = g[q];
+    if (FLOW && liquid) {
+#pragma unroll
+      for (int q = 0; q < 19; ++q) fo[q][k] = f[q];
+    }
+  }
+  if (bad) *flag = 1;
+
+  // ---- stores: one aligned vector per direction ----
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    V v;
+#pragma unroll
+    for (int k = 0; k < VW; ++k) v[k] = static_cast<Ts>(go[q][k]);
+    __builtin_nontemporal_store(v, reinterpret_cast<V*>(gd + (size_t)q * qs + self0));
+  }
+  if (FLOW && liquid) {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      V v;
+#pragma unroll
+      for (int k = 0; k < VW; ++k) v[k] = static_cast<Ts>(fo[q][k]);
+      __builtin_nontemporal_store(v, reinterpret_cast<V*>(fd + (size_t)q * qs + self0));
+    }
+  }
 }
 
 // --------------------------------------------------------------- front update
@@ -406,11 +625,11 @@ __device__ __forceinline__ double one_sided(int k, double xi0, double T0v, doubl
 }
 
 template <typename Ts, bool MZ>
-__device__ __forceinline__ double cell_T(const Ts* __restrict__ g, uint32_t nc, uint32_t cell,
+__device__ __forceinline__ double cell_T(const Ts* __restrict__ g, size_t qs, uint32_t cell,
                                          double t0) {
   double acc = 0.0;
 #pragma unroll
-  for (int q = 0; q < 7; ++q) acc += (double)load(g + (size_t)q * nc, cell);
+  for (int q = 0; q < 7; ++q) acc += (double)load(g + (size_t)q * qs, cell);
   return acc + t0;
 }
 
@@ -434,7 +653,6 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   const int o = blockIdx.y;
   if (x >= n) return;
   const int col = o * n + x;
-  const uint32_t nc = P.ncell;
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
   auto cell = [&](int a) -> uint32_t {
     return MZ ? (uint32_t)a * nn + (uint32_t)o * n + x : (uint32_t)o * nn + (uint32_t)a * n + x;
@@ -448,7 +666,7 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   for (int a = c0 - 1; a >= 0 && k < 2; --a) {
     const double d = sc - (a + 0.5);
     if (d >= 0.5) {
-      const double T = cell_T<Ts, MZ>(g, nc, cell(a), P.t0);
+      const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.t0);
       if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
       ++k;
     }
@@ -464,7 +682,7 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   for (int a = c0; a < n && k < 2; ++a) {
     const double d = (a + 0.5) - sc;
     if (d >= 0.5) {
-      const double T = cell_T<Ts, MZ>(g, nc, cell(a), P.t0);
+      const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.t0);
       if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
       ++k;
     }
@@ -493,7 +711,7 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
     for (int a = c0; a < c1; ++a) {
       const uint32_t i = cell(a);
 #pragma unroll
-      for (int q = 0; q < 19; ++q) store(f + (size_t)q * nc, i, 0.0f);
+      for (int q = 0; q < 19; ++q) store(f + (size_t)q * P.qstride, i, 0.0f);
     }
   }
   if (c1 > c0) melted[col] += c1 - c0;
@@ -535,15 +753,14 @@ __global__ void k_init(const int* __restrict__ cnt, const double* __restrict__ s
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
   if (x >= n) return;
-  const uint32_t nc = P.ncell;
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
   const int a = MZ ? z : y, o = MZ ? y : z;
   const bool liquid = a < cnt[o * n + x];
   const double Tt = (liquid ? seedT[a] : P.t_c) - P.t0;
   store(g, i, kW7Rest * Tt);
-  for (int q = 1; q < 7; ++q) store(g + (size_t)q * nc, i, kW7Axis * Tt);
+  for (int q = 1; q < 7; ++q) store(g + (size_t)q * P.qstride, i, kW7Axis * Tt);
   if (P.flow)
-    for (int q = 0; q < 19; ++q) store(f + (size_t)q * nc, i, 0.0);
+    for (int q = 0; q < 19; ++q) store(f + (size_t)q * P.qstride, i, 0.0);
 }
 
 template <typename Ts, bool MZ>
@@ -555,17 +772,16 @@ __global__ void k_fields(const Ts* __restrict__ f, const Ts* __restrict__ g,
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
   if (x >= n) return;
-  const uint32_t nc = P.ncell;
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
   const int a = MZ ? z : y, o = MZ ? y : z;
   const bool liquid = a < cnt[o * n + x];
   double Tt = 0.0;
-  for (int q = 0; q < 7; ++q) Tt += (double)load(g + (size_t)q * nc, i);
+  for (int q = 0; q < 7; ++q) Tt += (double)load(g + (size_t)q * P.qstride, i);
   double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
   if (P.flow && liquid) {
     double d = 0.0;
     for (int q = 0; q < 19; ++q) {
-      const double v = (double)load(f + (size_t)q * nc, i);
+      const double v = (double)load(f + (size_t)q * P.qstride, i);
       d += v;
       jx += ex19(q) * v;
       jy += ey19(q) * v;
@@ -595,8 +811,9 @@ __global__ void k_to_storage(const double* __restrict__ src, Ts* __restrict__ ds
   const uint64_t total = (uint64_t)qcount * P.ncell;
   if (i >= total) return;
   const int q = (int)(i / P.ncell);
+  const uint64_t cell = i - (uint64_t)q * P.ncell;
   const double shift = weight(qcount, q) * (qcount == 7 ? P.t0 : 1.0);
-  dst[i] = static_cast<Ts>(src[i] - shift);
+  dst[(uint64_t)q * P.qstride + cell] = static_cast<Ts>(src[i] - shift);
 }
 
 template <typename Ts>
@@ -606,8 +823,9 @@ __global__ void k_from_storage(const Ts* __restrict__ src, double* __restrict__ 
   const uint64_t total = (uint64_t)qcount * P.ncell;
   if (i >= total) return;
   const int q = (int)(i / P.ncell);
+  const uint64_t cell = i - (uint64_t)q * P.ncell;
   const double shift = weight(qcount, q) * (qcount == 7 ? P.t0 : 1.0);
-  dst[i] = (double)static_cast<typename Compute<Ts>::type>(src[i]) + shift;
+  dst[i] = (double)static_cast<typename Compute<Ts>::type>(src[(uint64_t)q * P.qstride + cell]) + shift;
 }
 
 // --------------------------------------------------------------- reductions
@@ -626,21 +844,13 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
-__global__ __launch_bounds__(kSumThreads) void k_sum4(const double* __restrict__ v0,
-                                                      const double* __restrict__ v1,
-                                                      const double* __restrict__ v2,
-                                                      const double* __restrict__ v3,
-                                                      int64_t count, double* __restrict__ out) {
+__global__ __launch_bounds__(kSumThreads) void k_sum(const double* __restrict__ v, int64_t count,
+                                                     double* __restrict__ out) {
   __shared__ double sh[kSumThreads / 64];
-  const double* vs[4] = {v0, v1, v2, v3};
-  for (int k = 0; k < 4; ++k) {
-    const double* v = vs[k];
-    double acc = 0.0;
-    if (v)
-      for (int64_t i = threadIdx.x; i < count; i += kSumThreads) acc += v[i];
-    const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) out[k] = t;
-  }
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += kSumThreads) acc += v[i];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = t;
 }
 
 __global__ __launch_bounds__(kSumThreads) void k_sum_int(const int* __restrict__ v, int64_t count,
@@ -653,16 +863,65 @@ __global__ __launch_bounds__(kSumThreads) void k_sum_int(const int* __restrict__
 }
 
 // --------------------------------------------------------------- dispatch
+// Cells per lane of the row-wave kernel for this precision and size (0: the
+// per-cell kernel).  A segment is 64*VW cells, so n must be a multiple of it.
+#ifndef LBM_ROW_VW_32
+#define LBM_ROW_VW_32 4
+#endif
+#ifndef LBM_ROW_VW_16
+#define LBM_ROW_VW_16 4
+#endif
+template <typename Ts>
+int row_width(int n) {
+  int vw = sizeof(Ts) == 8 ? 0 : (sizeof(Ts) == 4 ? LBM_ROW_VW_32 : LBM_ROW_VW_16);
+  while (vw > 1 && n % (64 * vw) != 0) vw /= 2;
+  return (vw >= 2 && n % (64 * vw) == 0) ? vw : 0;
+}
+
+template <typename Ts, int VW>
+hipError_t rows_dispatch(const KParams& P, const Ts* F, Ts* Fd, const Ts* G, Ts* Gd,
+                         const int* cnt, const int* cmin, const int* cmax, const double* s,
+                         const double* th, int* flag, hipStream_t st) {
+  dim3 block(64, 4, 1);
+  dim3 grid(P.n / (64 * VW), (P.n + 3) / 4, P.n);
+  if (P.flow) {
+    if (P.melt_z)
+      hipLaunchKernelGGL((k_stream_collide_rows<Ts, VW, true, true>), grid, block, 0, st, F, Fd, G,
+                         Gd, cnt, cmin, cmax, s, th, flag, P);
+    else
+      hipLaunchKernelGGL((k_stream_collide_rows<Ts, VW, true, false>), grid, block, 0, st, F, Fd, G,
+                         Gd, cnt, cmin, cmax, s, th, flag, P);
+  } else {
+    if (P.melt_z)
+      hipLaunchKernelGGL((k_stream_collide_rows<Ts, VW, false, true>), grid, block, 0, st, F, Fd, G,
+                         Gd, cnt, cmin, cmax, s, th, flag, P);
+    else
+      hipLaunchKernelGGL((k_stream_collide_rows<Ts, VW, false, false>), grid, block, 0, st, F, Fd,
+                         G, Gd, cnt, cmin, cmax, s, th, flag, P);
+  }
+  return hipGetLastError();
+}
+
 template <typename Ts>
 hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* gs, void* gd,
                        const int* cnt, const int* cmin, const int* cmax, const double* s,
                        const double* th, int* flag, hipStream_t st) {
-  dim3 block(64, 4, 1);
-  dim3 grid((P.n + 63) / 64, (P.n + 3) / 4, P.n);
   auto F = static_cast<const Ts*>(fs);
   auto Fd = static_cast<Ts*>(fd);
   auto G = static_cast<const Ts*>(gs);
   auto Gd = static_cast<Ts*>(gd);
+  if constexpr (sizeof(Ts) < 8) {
+    const int vw = row_width<Ts>(P.n);
+    if (vw == 8) return rows_dispatch<Ts, 8>(P, F, Fd, G, Gd, cnt, cmin, cmax, s, th, flag, st);
+    if (vw == 4) return rows_dispatch<Ts, 4>(P, F, Fd, G, Gd, cnt, cmin, cmax, s, th, flag, st);
+    if (vw == 2) return rows_dispatch<Ts, 2>(P, F, Fd, G, Gd, cnt, cmin, cmax, s, th, flag, st);
+  }
+  // whole x rows per workgroup (up to 512 cells): the +-1-shifted loads of a
+  // row then hit cache lines the same workgroup fetches
+  const int bx = P.n >= 512 ? 512 : ((P.n + 63) / 64) * 64;
+  const int by = bx >= 256 ? 1 : 256 / bx;
+  dim3 block(bx, by, 1);
+  dim3 grid((P.n + bx - 1) / bx, (P.n + by * kRows - 1) / (by * kRows), P.n);
   if (P.flow) {
     if (P.melt_z)
       hipLaunchKernelGGL((k_stream_collide<Ts, true, true>), grid, block, 0, st, F, Fd, G, Gd, cnt,
@@ -761,6 +1020,13 @@ hipError_t conv_dispatch(bool to_storage, const KParams& P, int qcount, const vo
     case kBF16S: return call<__bf16>;        \
     default: return hipErrorInvalidValue;    \
   }
+
+uint64_t population_stride(uint32_t ncell, int kind) {
+  // pad of kPadBytes per population, rounded to whole elements
+  constexpr uint64_t kPadBytes = LBM_POP_PAD_BYTES;
+  const uint64_t e = store_bytes(kind);
+  return (uint64_t)ncell + (e ? kPadBytes / e : 0);
+}
 
 size_t store_bytes(int kind) {
   switch (kind) {
@@ -868,13 +1134,14 @@ hipError_t launch_from_storage(int kind, const KParams& P, int q_count, const vo
 #undef CALL
 }
 
-hipError_t launch_sum(const double* v0, const double* v1, const double* v2, const double* v3,
-                      int64_t count, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum4, dim3(1), dim3(kSumThreads), 0, st, v0, v1, v2, v3, count, out);
+hipError_t launch_sum(const double* v, int64_t count, double* out, hipStream_t st) {
+  if (!v || !out || count < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kSumThreads), 0, st, v, count, out);
   return hipGetLastError();
 }
 
 hipError_t launch_sum_int(const int* v, int64_t count, double* out, hipStream_t st) {
+  if (!v || !out || count < 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sum_int, dim3(1), dim3(kSumThreads), 0, st, v, count, out);
   return hipGetLastError();
 }

@@ -140,9 +140,121 @@ def test_save_load_resume_is_bitwise():
 
 def test_mass_conservation_on_gpu():
     from paper_1604_03478_amd import Config, Sim
-    g = Sim(Config(n=32, ra=1e5, pr=1.0, ste=1.0, s0=4.2, precision="f64"))
+    g = Sim(Config(n=32, ra=1e5, pr=1.0, ste=1.0, s0=4.4, precision="f64"))
     m0 = g.diagnostics()["mass"]
-    g.step(200)
+    g.step(400)
     d = g.diagnostics()
     assert d["melted"] > 0
     assert abs(d["mass"] - (m0 + d["melted"])) < 1e-9
+    # each reduction covers exactly its own array (the front has n^2 values)
+    F = g.fields()
+    assert abs(d["front_sum"] - F["s"].sum()) < 1e-9
+    assert abs(d["mass"] - F["rho"].sum()) < 1e-9
+
+
+@pytest.mark.parametrize("prec,tol_T,tol_fl", [("f16s", 2e-3, 2e-4), ("bf16s", 2e-2, 2e-3)])
+def test_sixteen_bit_shifted_storage(prec, tol_T, tol_fl):
+    """16-bit storage of the shifted populations with FP32 collision.
+
+    Bound from the arithmetic: a stored deviation |g - w T0| <= w |T - T0| +
+    flux terms < 0.07 (T in [0, 1], T0 = 1/2) is rounded with unit roundoff
+    u = 2^-11 (FP16) or 2^-8 (BF16), so each step perturbs T = sum of 7
+    values by at most 7 * 0.07 * u (2.4e-4 FP16, 1.9e-3 BF16) and diffusion
+    damps older errors; over 200 steps the accumulated error stays within a
+    few steps' worth.  The front integrates T gradients, so the liquid
+    fraction error is bounded by alpha Ste |dG| t / n."""
+    orc, gpu = make_pair(200, n=40, ra=1e5, pr=1.0, ste=0.5, s0=11.2, precision=prec)
+    d = diffs(orc, gpu)
+    assert d["mask"] == 0, d
+    assert d["T"] <= tol_T and d["fl_rel"] <= tol_fl, d
+
+
+def _golden_conv64():
+    import os
+    from conftest import golden_path
+    path = golden_path("conv64_ra1e4_oracle.txt")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing")
+    fl, s, T, line = {}, {}, {}, {}
+    for ln in open(path):
+        if ln.startswith("#"):
+            continue
+        k, i, v = ln.split()
+        {"fl": fl, "s": s, "T": T, "Tline": line}[k][int(i)] = float(v)
+    return fl, s, T, line
+
+
+def test_convection_melting_64_full_run_fp32():
+    """The 64^3 convection-melting run (Ra = 1e4, Pr = 1, Ste = 0.1, 20000
+    steps, FP32 storage) against the FP64 oracle's stored trajectory:
+    max|dT| <= 1e-5 and relative liquid-fraction error <= 1e-6."""
+    from paper_1604_03478_amd import Config, Sim
+    fl, s, T, line = _golden_conv64()
+    g = Sim(Config(n=64, ra=1e4, pr=1.0, ste=0.1, s0=1.0, precision="f32"))
+    worst_fl = 0.0
+    done = 0
+    for st in sorted(fl):
+        g.step(st - done)
+        done = st
+        worst_fl = max(worst_fl, abs(g.liquid_fraction() - fl[st]) / fl[st])
+    F = g.fields()
+    Tg = F["T"].reshape(-1)
+    dT = max(abs(Tg[c] - v) for c, v in T.items())
+    dline = max(abs(F["T"][32, y, 32] - v) for y, v in line.items())
+    ds = max(abs(F["s"].reshape(-1)[c] - v) for c, v in s.items())
+    assert worst_fl <= 1e-6, worst_fl
+    assert dT <= 1e-5 and dline <= 1e-5, (dT, dline)
+    assert ds <= 1e-4, ds
+
+
+def _one_step_random(n, prec, seed, heating="y0", front=(0.0, None), flow=1):
+    """Hand the same seeded random state (rough front) to both sides, take
+    one step, compare post-collision populations cell by cell."""
+    from paper_1604_03478_amd import Config, Sim
+    from inputs import random_state
+    f, g, s = random_state(n, seed, flow=bool(flow), front=front)
+    orc = OracleSim(n, ra=1e5, pr=1.0, ste=2.0, s0=1.0, heating=HEAT[heating], flow=flow)
+    if flow:
+        orc.f[:] = f
+    orc.g[:] = g
+    orc.s[:] = s
+    gpu = Sim(Config(n=n, ra=1e5, pr=1.0, ste=2.0, s0=1.0, heating=heating, flow=flow,
+                     precision=prec))
+    gpu.set_populations(f, g, s)
+    del f, g
+    orc.step(1)
+    gpu.step(1)
+    fg, gg, sg = gpu.get_populations()
+    out = {"g": float(np.abs(gg - orc.g).max()), "s": float(np.abs(sg - orc.s).max())}
+    if flow:
+        a = np.arange(n) + 0.5
+        if heating == "y0":
+            liq = a[None, :, None] < orc.s[:, None, :]
+        else:
+            liq = a[:, None, None] < orc.s[None, :, :]
+        out["f"] = float(np.abs(fg - orc.f)[:, liq].max())
+        out["fscale"] = float(np.abs(orc.f[:, liq]).max())
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("heating", ["y0", "z0"])
+def test_one_step_random_state_128(prec, heating):
+    """128^3: the row-wave kernel (two cells per lane for 32- and 16-bit
+    storage) and its per-cell fallback near a rough front, one step from a
+    random state.  Bars: FP64 round-off; FP32 a few ulps of the O(0.1)
+    outputs; FP16 half an ulp of the stored deviations."""
+    d = _one_step_random(128, prec, seed=7, heating=heating, front=(20.0, 60.0))
+    tol = {"f64": 1e-14, "f32": 2e-6, "f16s": 2e-3}[prec]
+    assert d["g"] <= tol * 2 and d["f"] <= tol * 10, d
+    assert d["s"] <= {"f64": 1e-13, "f32": 1e-5, "f16s": 1e-3}[prec], d
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_one_step_random_state_256(prec):
+    """Full size, 256^3, in the launch configuration the benchmark times
+    (four cells per lane), one step from a random state, every cell."""
+    d = _one_step_random(256, prec, seed=11, front=(100.0, 160.0))
+    tol = {"f32": 2e-6, "f16s": 2e-3}[prec]
+    assert d["g"] <= tol * 2 and d["f"] <= tol * 10, d
+    assert d["s"] <= {"f32": 1e-5, "f16s": 1e-3}[prec], d
