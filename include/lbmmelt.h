@@ -54,10 +54,10 @@ typedef enum {
   LBM_ESTATE = -5     /* call not valid in the context's current state       */
 } lbm_status;
 
-/* Storage precision of the distributions.  LBM_F64 and LBM_F32 collide in
- * the storage type; the two 16-bit formats store the shifted populations
- * (f_q - w_q*rho0 and g_q - w_q*T0) and collide in FP32.  The front and all
- * reductions are FP64 in every mode. */
+/* Storage precision of the distributions.  Every format stores the shifted
+ * populations f_q - w_q*rho0 and g_q - w_q*(t_h + t_m)/2.  LBM_F64 and LBM_F32 collide
+ * in the storage type; the two 16-bit formats collide in FP32.  The front
+ * and all reductions are FP64 in every mode. */
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 } lbm_precision;
 
 typedef enum {

@@ -234,6 +234,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   k.melt_z = params->heating == LBM_HEAT_Z0;
   k.flow = params->flow;
   k.t0 = L.t0;
+  k.tref = 0.5 * (params->t_h + params->t_m);
   k.t_m = params->t_m;
   k.t_c = params->t_c;
   k.gbeta = L.gbeta;
@@ -325,8 +326,9 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (rc) return rc;
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
-  const lbmk::KParams& k = c->kp;
+  lbmk::KParams& k = c->kp;
   for (int64_t i = 0; i < nsteps; ++i) {
+    k.step = (uint32_t)c->step;
     const int nx = c->cur ^ 1, sx = c->scur ^ 1;
     if (c->timing) {
       if (c->ev_used + 2 > c->ev.size()) {

@@ -11,15 +11,17 @@ namespace lbmk {
 enum StoreKind { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
 
 // Everything a step kernel needs, in lattice units.  Distributions are
-// stored shifted: f_q - w_q * rho0 (rho0 = 1) and g_q - w_q * t0, so every
-// kernel works on deviations from the rest state.
+// stored shifted: f_q - w_q * rho0 (rho0 = 1) and g_q - w_q * tref with
+// tref = (t_h + t_m)/2, the middle of the liquid temperature range, so every
+// kernel works on small deviations from a rest state.
 struct KParams {
   int n;           // cells per edge
   uint32_t ncell;  // n^3
   uint64_t qstride;  // elements between consecutive population arrays (>= ncell)
   int melt_z;      // 0: melt axis y (hot wall y=0, cold wall y=n); 1: axis z
   int flow;        // 0: energy distribution only
-  double t0;       // reference temperature (storage shift and buoyancy)
+  double t0;       // buoyancy reference temperature
+  double tref;     // storage shift of g: (t_h + t_m)/2
   double t_m;      // melting temperature (front Dirichlet value)
   double t_c;      // cold-wall temperature (melt axis y only)
   double gbeta;    // buoyancy: F_z = gbeta * (T - t0)
@@ -29,6 +31,7 @@ struct KParams {
   double alpha;    // thermal diffusivity (front update)
   double ste;      // Stefan number (front update)
   double dT;       // nominal t_h - t_m (front update)
+  uint32_t step;   // step counter (seeds the per-cell random stream of rounding)
 };
 
 size_t store_bytes(int kind);

@@ -11,9 +11,9 @@
 //     x, so every population load and store of a wave is one contiguous
 //     256 B (FP32) segment.  Pull streaming: each stored value is read once
 //     and written once per step (208 B per FP32 cell update).
-//   * Populations are stored shifted (f - w*rho0, g - w*t0) and the whole
+//   * Populations are stored shifted (f - w*rho0, g - w*tref) and the whole
 //     collision works on deviations, which keeps FP32 and 16-bit storage
-//     accurate.
+//     accurate; tref = (t_h + t_m)/2 centres the liquid temperature range.
 //   * The 19x19 and 7x7 moment transforms use the integer structure of the
 //     orthogonal bases (pairwise sums and differences), about 250 flops per
 //     cell instead of 1444 for a dense product; no MFMA (the transform is a
@@ -39,14 +39,79 @@ namespace lbmk {
 namespace {
 
 // --------------------------------------------------------------- storage
-template <typename Ts> struct Compute { using type = float; };
-template <> struct Compute<double> { using type = double; };
+// Arithmetic types of the collision: `type` for the flow (f, D3Q19),
+// `gtype` for the energy distribution (g, D3Q7).  16-bit storage collides in
+// FP32.  FP32 storage collides the flow in FP32 and the energy distribution
+// in FP64 (rounded stochastically to FP32 at the store): temperature round
+// off accumulated over 1e4+ steps is what moves the front, and the D3Q7 part
+// is a small share of the arithmetic.
+#ifndef LBM_F32_FLOW_T
+#define LBM_F32_FLOW_T float
+#endif
+#ifndef LBM_F32_HEAT_T
+#define LBM_F32_HEAT_T double
+#endif
+template <typename Ts> struct Compute { using type = float; using gtype = float; };
+template <> struct Compute<double> { using type = double; using gtype = double; };
+template <> struct Compute<float> { using type = LBM_F32_FLOW_T; using gtype = LBM_F32_HEAT_T; };
 
-template <typename Ts>
-__device__ __forceinline__ typename Compute<Ts>::type load(const Ts* __restrict__ base, uint32_t i) {
+// Rounding of the collision result to the storage format.  With stochastic
+// rounding the value is rounded up or down with probabilities proportional
+// to its distance from the two neighbours (random bits added below the
+// storage precision, then truncation toward zero), so the rounding error has
+// zero mean even when the same value is stored step after step.
+// Measured at 64^3 over 20000 steps against the FP64 oracle: FP16 storage
+// with round-to-nearest drifts to a 1e-2 relative liquid-fraction error,
+// with stochastic rounding 4.5e-6; FP32 storage with an FP64 energy collision
+// and stochastic rounding stays at 1e-10.
+#ifndef LBM_STOCHASTIC_ROUNDING
+#define LBM_STOCHASTIC_ROUNDING 1
+#endif
+
+// One 32-bit random stream per cell and step (counter based: a mix of the
+// cell index and the step; each stored value advances it by one LCG step).
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ uint32_t next_rand(uint32_t& st) {
+  st = st * 1664525u + 1013904223u;
+  return st;
+}
+
+template <typename Ts, typename C>
+__device__ __forceinline__ Ts round_store(C v, uint32_t& rs) {
+#if LBM_STOCHASTIC_ROUNDING
+  if constexpr (sizeof(Ts) == 4 && sizeof(C) == 8) {
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    b += (uint64_t)(next_rand(rs) >> 3);  // 29 bits below FP32 precision
+    b &= ~((1ull << 29) - 1);
+    return static_cast<Ts>(__longlong_as_double((long long)b));
+  } else if constexpr (sizeof(Ts) == 2 && sizeof(C) == 4) {
+    uint32_t b = __float_as_uint(v);
+    constexpr int drop = __is_same(Ts, _Float16) ? 13 : 16;  // bits below the 16-bit format
+    b += next_rand(rs) >> (32 - drop);
+    b &= ~((1u << drop) - 1);
+    return static_cast<Ts>(__uint_as_float(b));
+  }
+#endif
+  (void)rs;
+  return static_cast<Ts>(v);
+}
+
+template <typename R, typename Ts>
+__device__ __forceinline__ R load_as(const Ts* __restrict__ base, uint32_t i) {
   const Ts* p = reinterpret_cast<const Ts*>(reinterpret_cast<const char*>(base) +
                                             (uint32_t)(i * (uint32_t)sizeof(Ts)));
-  return static_cast<typename Compute<Ts>::type>(*p);
+  return static_cast<R>(*p);
+}
+template <typename Ts>
+__device__ __forceinline__ typename Compute<Ts>::type load(const Ts* __restrict__ base, uint32_t i) {
+  return load_as<typename Compute<Ts>::type>(base, i);
 }
 
 template <typename Ts, typename C>
@@ -58,9 +123,9 @@ __device__ __forceinline__ void store(Ts* __restrict__ base, uint32_t i, C v) {
 // Stores of the step kernel: written once, read only in the next step, so
 // they bypass the caches (non-temporal).
 template <typename Ts, typename C>
-__device__ __forceinline__ void store_stream(Ts* __restrict__ base, uint32_t i, C v) {
+__device__ __forceinline__ void store_stream(Ts* __restrict__ base, uint32_t i, C v, uint32_t& rs) {
   Ts* p = reinterpret_cast<Ts*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(Ts)));
-  __builtin_nontemporal_store(static_cast<Ts>(v), p);
+  __builtin_nontemporal_store(round_store<Ts>(v, rs), p);
 }
 
 // --------------------------------------------------------------- lattices
@@ -95,20 +160,35 @@ constexpr double kW7Axis = 0.125;  // D3Q7 weight of the six moving directions
 constexpr double kW7Rest = 0.25;
 
 // --------------------------------------------------------------- collision
-template <typename C>
+template <typename C, typename G>
 struct Rates {
-  C sv, qj, qe, gb, t0;
+  C sv, gb;  // shear rate and buoyancy coefficient of the flow
+  G qj, qe;  // rates of the energy distribution
+  G tref;    // storage shift of g: the stored value is g_q - w_q * tref
+  G dbuoy;   // tref - t0, so that T - t0 = (T - tref) + dbuoy
 };
+
+template <typename C, typename G>
+__device__ __forceinline__ Rates<C, G> make_rates(const KParams& P) {
+  Rates<C, G> r;
+  r.sv = (C)P.s_nu;
+  r.gb = (C)P.gbeta;
+  r.qj = (G)P.q_j;
+  r.qe = (G)P.q_e;
+  r.tref = (G)P.tref;
+  r.dbuoy = (G)(P.tref - P.t0);
+  return r;
+}
 
 // MRT collision of f (Eq. (2) with the force of Eq. (1)) and of g (Eq. (4))
 // on shifted populations, in place (f is left untouched in solid cells).
 // Gravity is along z, so the force has one component F_z = gbeta (T - t0).
 // Returns true when a non-finite value appeared.
-template <bool FLOW, typename C>
-__device__ __forceinline__ bool collide(C (&f)[19], C (&g)[7], bool liquid, const Rates<C>& r) {
-  C Tt = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);  // T - t0
+template <bool FLOW, typename C, typename G>
+__device__ __forceinline__ bool collide(C (&f)[19], G (&g)[7], bool liquid, const Rates<C, G>& r) {
+  const G Tt = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);  // T - tref
   C ux = C(0), uy = C(0), uz = C(0);
-  bool bad = !(fabs(Tt) < C(1e30));
+  bool bad = !(fabs(Tt) < G(1e30));
 
   if (FLOW && liquid) {
     // ---- forward transform m = M f (orthogonal D3Q19 basis) ----
@@ -143,7 +223,7 @@ __device__ __forceinline__ bool collide(C (&f)[19], C (&g)[7], bool liquid, cons
     const C m16 = Xxy - Xxz, m17 = Yyz - Yxy, m18 = Zxz - Zyz;
 
     // ---- macroscopic, force, equilibria (incompressible, rho0 = 1) ----
-    const C Fz = r.gb * Tt;
+    const C Fz = r.gb * (C)(Tt + r.dbuoy);
     ux = jx;
     uy = jy;
     uz = jz + C(0.5) * Fz;
@@ -229,24 +309,24 @@ __device__ __forceinline__ bool collide(C (&f)[19], C (&g)[7], bool liquid, cons
 
   // ---- D3Q7 MRT collision of g (Eq. (4)), c_sT^2 = 1/4 ----
   {
-    const C T = Tt + r.t0;
-    const C px = g[1] + g[2], py = g[3] + g[4], pz = g[5] + g[6];
-    const C n1 = g[1] - g[2], n2 = g[3] - g[4], n3 = g[5] - g[6];
-    const C n4 = C(6) * g[0] - (px + py + pz);
-    const C n5 = C(2) * px - py - pz;
-    const C n6 = py - pz;
-    const C n1s = n1 - r.qj * (n1 - ux * T);
-    const C n2s = n2 - r.qj * (n2 - uy * T);
-    const C n3s = n3 - r.qj * (n3 - uz * T);
-    const C n4s = n4 - r.qe * (n4 - C(0.75) * Tt);
-    const C ke = C(1) - r.qe;
-    const C b0 = Tt * C(1.0 / 7.0);
-    const C b1 = C(0.5) * n1s, b2 = C(0.5) * n2s, b3 = C(0.5) * n3s;
-    const C b4 = n4s * C(1.0 / 42.0), b5 = ke * n5 * C(1.0 / 12.0), b6 = ke * n6 * C(0.25);
-    const C c1 = b0 - b4 + C(2) * b5;
-    const C c3 = b0 - b4 - b5 + b6;
-    const C c5 = b0 - b4 - b5 - b6;
-    g[0] = b0 + C(6) * b4;
+    const G T = Tt + r.tref;
+    const G px = g[1] + g[2], py = g[3] + g[4], pz = g[5] + g[6];
+    const G n1 = g[1] - g[2], n2 = g[3] - g[4], n3 = g[5] - g[6];
+    const G n4 = G(6) * g[0] - (px + py + pz);
+    const G n5 = G(2) * px - py - pz;
+    const G n6 = py - pz;
+    const G n1s = n1 - r.qj * (n1 - G(ux) * T);
+    const G n2s = n2 - r.qj * (n2 - G(uy) * T);
+    const G n3s = n3 - r.qj * (n3 - G(uz) * T);
+    const G n4s = n4 - r.qe * (n4 - G(0.75) * Tt);
+    const G ke = G(1) - r.qe;
+    const G b0 = Tt * G(1.0 / 7.0);
+    const G b1 = G(0.5) * n1s, b2 = G(0.5) * n2s, b3 = G(0.5) * n3s;
+    const G b4 = n4s * G(1.0 / 42.0), b5 = ke * n5 * G(1.0 / 12.0), b6 = ke * n6 * G(0.25);
+    const G c1 = b0 - b4 + G(2) * b5;
+    const G c3 = b0 - b4 - b5 + b6;
+    const G c5 = b0 - b4 - b5 - b6;
+    g[0] = b0 + G(6) * b4;
     g[1] = c1 + b1;
     g[2] = c1 - b1;
     g[3] = c3 + b2;
@@ -266,6 +346,7 @@ __device__ __forceinline__ void update_cell(
     const int* __restrict__ cmin, const int* __restrict__ cmax, const double* __restrict__ s,
     const double* __restrict__ th, int* __restrict__ flag, const KParams& P) {
   using C = typename Compute<Ts>::type;
+  using G = typename Compute<Ts>::gtype;
   const int n = P.n;
   if (x >= n || y >= n) return;
   const size_t qs = P.qstride;
@@ -281,14 +362,10 @@ __device__ __forceinline__ void update_cell(
   const bool all_sol = (a - 1) >= cmax[col];
   const bool fast = interior & (all_liq | all_sol);
 
-  Rates<C> r;
-  r.sv = (C)P.s_nu;
-  r.qj = (C)P.q_j;
-  r.qe = (C)P.q_e;
-  r.gb = (C)P.gbeta;
-  r.t0 = (C)P.t0;
+  const Rates<C, G> r = make_rates<C, G>(P);
 
-  C f[19], g[7];
+  C f[19];
+  G g[7];
 
   if (__all(fast)) {
     // ---------- fast path: one phase, only x walls possible ----------
@@ -298,13 +375,13 @@ __device__ __forceinline__ void update_cell(
       const int off = ex + ey7(q) * n + ez7(q) * (int)nn;
       const Ts* bq = gs + (size_t)q * qs;
       if (ex == 0) {
-        g[q] = static_cast<C>(LBM_LOAD(bq + (self - off)));
+        g[q] = static_cast<G>(LBM_LOAD(bq + (self - off)));
       } else {
         // adiabatic x wall: bounce-back, chosen by a per-lane address select
         // (no branch, so the loads of all directions stay in flight together)
         const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
         const Ts* p = wall ? gs + (size_t)opp7(q) * qs + self : bq + (self - off);
-        g[q] = static_cast<C>(LBM_LOAD(p));
+        g[q] = static_cast<G>(LBM_LOAD(p));
       }
     }
     if (FLOW && liquid) {
@@ -326,22 +403,22 @@ __device__ __forceinline__ void update_cell(
   } else {
     // ---------- general path: walls and the front, link by link ----------
     const double s_self = s[col];
-    const C wTm = C(kW7Axis) * (C)(P.t_m - P.t0);
+    const G wTm = G(kW7Axis) * (G)(P.t_m - P.tref);
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
       const int ex = ex7(q), ey = ey7(q), ez = ez7(q), p = opp7(q);
       const int sx = x - ex, sy = y - ey, sz = z - ez;
       const Ts* bq = gs + (size_t)q * qs;
       const Ts* bp = gs + (size_t)p * qs;
-      C v;
+      G v;
       if ((unsigned)sx >= (unsigned)n || (unsigned)sy >= (unsigned)n || (unsigned)sz >= (unsigned)n) {
         // thermal wall: Dirichlet (anti-bounce-back) or adiabatic (bounce-back)
         const int sa = MZ ? sz : sy;
-        const C gp = load(bp, self);
+        const G gp = load_as<G>(bp, self);
         if (sa < 0) {
-          v = -gp + C(2.0 * kW7Axis) * (C)(th[col] - P.t0);
+          v = -gp + G(2.0 * kW7Axis) * (G)(th[col] - P.tref);
         } else if (!MZ && sa >= n) {
-          v = -gp + C(2.0 * kW7Axis) * (C)(P.t_c - P.t0);
+          v = -gp + G(2.0 * kW7Axis) * (G)(P.t_c - P.tref);
         } else {
           v = gp;
         }
@@ -351,7 +428,7 @@ __device__ __forceinline__ void update_cell(
         const bool src_liq = sa < cnt[scol];
         const uint32_t src = self - (uint32_t)(ex + ey * n + ez * (int)nn);
         if (src_liq == liquid) {
-          v = load(bq, src);
+          v = load_as<G>(bq, src);
         } else {
           // interpolated anti-bounce-back at the front (wall value t_m)
           const bool along = MZ ? (ez != 0) : (ey != 0);
@@ -361,8 +438,8 @@ __device__ __forceinline__ void update_cell(
           } else {
             d = ((a + 0.5) - s_self) / (s[scol] - s_self);
           }
-          const C dl = (C)d;
-          const C gp = load(bp, self);
+          const G dl = (G)d;
+          const G gp = load_as<G>(bp, self);
           if (d < 0.5) {
             const int bx = x + ex, by = y + ey, bz = z + ez;
             bool behind = (unsigned)bx < (unsigned)n && (unsigned)by < (unsigned)n &&
@@ -373,13 +450,13 @@ __device__ __forceinline__ void update_cell(
             }
             if (behind) {
               const uint32_t bidx = self + (uint32_t)(ex + ey * n + ez * (int)nn);
-              v = -(C(2) * dl * gp + (C(1) - C(2) * dl) * load(bp, bidx)) + C(2) * wTm;
+              v = -(G(2) * dl * gp + (G(1) - G(2) * dl) * load_as<G>(bp, bidx)) + G(2) * wTm;
             } else {
-              v = -gp + C(2) * wTm;
+              v = -gp + G(2) * wTm;
             }
           } else {
-            const C inv2d = C(1) / (C(2) * dl);
-            v = -gp * inv2d + (C(2) * dl - C(1)) * inv2d * load(bq, self) + wTm / dl;
+            const G inv2d = G(1) / (G(2) * dl);
+            v = -gp * inv2d + (G(2) * dl - G(1)) * inv2d * load_as<G>(bq, self) + wTm / dl;
           }
         }
       }
@@ -404,12 +481,13 @@ __device__ __forceinline__ void update_cell(
     }
   }
   if (collide<FLOW>(f, g, liquid, r)) *flag = 1;
+  uint32_t rs = mix32(self * 0x9e3779b1u + P.step * 0x85ebca77u);
   if (FLOW && liquid) {
 #pragma unroll
-    for (int q = 0; q < 19; ++q) store_stream(fd + (size_t)q * qs, self, f[q]);
+    for (int q = 0; q < 19; ++q) store_stream(fd + (size_t)q * qs, self, f[q], rs);
   }
 #pragma unroll
-  for (int q = 0; q < 7; ++q) store_stream(gd + (size_t)q * qs, self, g[q]);
+  for (int q = 0; q < 7; ++q) store_stream(gd + (size_t)q * qs, self, g[q], rs);
 }
 
 // Rows of cells along y handled one after another by each thread.
@@ -449,6 +527,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
     const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
     int* __restrict__ flag, KParams P) {
   using C = typename Compute<Ts>::type;
+  using G = typename Compute<Ts>::gtype;
   using V = vec_t<Ts, VW>;
   using VI = vec_t<int, VW>;
   const int n = P.n;
@@ -483,21 +562,16 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   const bool liquid = all_liq;
   const bool left_edge = lane == 0, right_edge = lane == 63;
 
-  Rates<C> r;
-  r.sv = (C)P.s_nu;
-  r.qj = (C)P.q_j;
-  r.qe = (C)P.q_e;
-  r.gb = (C)P.gbeta;
-  r.t0 = (C)P.t0;
+  const Rates<C, G> r = make_rates<C, G>(P);
 
   // ---- loads: one aligned vector per direction, from its source row ----
-  C gv[7][VW];
+  G gv[7][VW];
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
     const int roff = ey7(q) * n + ez7(q) * (int)nn;
     const V v = *reinterpret_cast<const V*>(gs + (size_t)q * qs + (self0 - roff));
 #pragma unroll
-    for (int k = 0; k < VW; ++k) gv[q][k] = static_cast<C>(v[k]);
+    for (int k = 0; k < VW; ++k) gv[q][k] = static_cast<G>(v[k]);
   }
   C fv[19][VW];
   if (FLOW && liquid) {
@@ -511,12 +585,12 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   }
   // segment-edge values of the x-moving directions (bounce-back at x walls:
   // adiabatic for g, no-slip for f; otherwise the neighbouring segment)
-  C gL = C(0), gR = C(0);
+  G gL = G(0), gR = G(0);
   C fL[5] = {C(0), C(0), C(0), C(0), C(0)}, fR[5] = {C(0), C(0), C(0), C(0), C(0)};
   if (left_edge) {  // directions with e_x = +1 pull from x0 - 1
     const bool wall = xw == 0;
-    gL = wall ? static_cast<C>(gs[(size_t)opp7(1) * qs + self0])
-              : static_cast<C>(gs[(size_t)1 * qs + self0 - 1]);
+    gL = wall ? static_cast<G>(gs[(size_t)opp7(1) * qs + self0])
+              : static_cast<G>(gs[(size_t)1 * qs + self0 - 1]);
     if (FLOW && liquid) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
@@ -530,8 +604,8 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   if (right_edge) {  // directions with e_x = -1 pull from x0 + VW
     const uint32_t last = self0 + VW - 1;
     const bool wall = x0 + VW == n;
-    gR = wall ? static_cast<C>(gs[(size_t)opp7(2) * qs + last])
-              : static_cast<C>(gs[(size_t)2 * qs + last + 1]);
+    gR = wall ? static_cast<G>(gs[(size_t)opp7(2) * qs + last])
+              : static_cast<G>(gs[(size_t)2 * qs + last + 1]);
     if (FLOW && liquid) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
@@ -543,8 +617,8 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
     }
   }
   // neighbour-lane values for the shift
-  C gl_in = __shfl_up(gv[1][VW - 1], 1, 64);
-  C gr_in = __shfl_down(gv[2][0], 1, 64);
+  G gl_in = __shfl_up(gv[1][VW - 1], 1, 64);
+  G gr_in = __shfl_down(gv[2][0], 1, 64);
   if (left_edge) gl_in = gL;
   if (right_edge) gr_in = gR;
   C fl_in[5], fr_in[5];
@@ -561,12 +635,13 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   }
 
   // ---- collide each cell ----
-  C go[7][VW];
+  G go[7][VW];
   C fo[19][VW];
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < VW; ++k) {
-    C g[7], f[19];
+    G g[7];
+    C f[19];
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
       const int ex = ex7(q);
@@ -595,11 +670,12 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   if (bad) *flag = 1;
 
   // ---- stores: one aligned vector per direction ----
+  uint32_t rs = mix32(self0 * 0x9e3779b1u + P.step * 0x85ebca77u);
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
     V v;
 #pragma unroll
-    for (int k = 0; k < VW; ++k) v[k] = static_cast<Ts>(go[q][k]);
+    for (int k = 0; k < VW; ++k) v[k] = round_store<Ts>(go[q][k], rs);
     __builtin_nontemporal_store(v, reinterpret_cast<V*>(gd + (size_t)q * qs + self0));
   }
   if (FLOW && liquid) {
@@ -607,7 +683,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
     for (int q = 0; q < 19; ++q) {
       V v;
 #pragma unroll
-      for (int k = 0; k < VW; ++k) v[k] = static_cast<Ts>(fo[q][k]);
+      for (int k = 0; k < VW; ++k) v[k] = round_store<Ts>(fo[q][k], rs);
       __builtin_nontemporal_store(v, reinterpret_cast<V*>(fd + (size_t)q * qs + self0));
     }
   }
@@ -626,11 +702,11 @@ __device__ __forceinline__ double one_sided(int k, double xi0, double T0v, doubl
 
 template <typename Ts, bool MZ>
 __device__ __forceinline__ double cell_T(const Ts* __restrict__ g, size_t qs, uint32_t cell,
-                                         double t0) {
+                                         double tref) {
   double acc = 0.0;
 #pragma unroll
   for (int q = 0; q < 7; ++q) acc += (double)load(g + (size_t)q * qs, cell);
-  return acc + t0;
+  return acc + tref;
 }
 
 __device__ __forceinline__ int count_liquid(double sv, int n) {
@@ -666,7 +742,7 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   for (int a = c0 - 1; a >= 0 && k < 2; --a) {
     const double d = sc - (a + 0.5);
     if (d >= 0.5) {
-      const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.t0);
+      const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.tref);
       if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
       ++k;
     }
@@ -682,7 +758,7 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   for (int a = c0; a < n && k < 2; ++a) {
     const double d = (a + 0.5) - sc;
     if (d >= 0.5) {
-      const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.t0);
+      const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.tref);
       if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
       ++k;
     }
@@ -756,7 +832,7 @@ __global__ void k_init(const int* __restrict__ cnt, const double* __restrict__ s
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
   const int a = MZ ? z : y, o = MZ ? y : z;
   const bool liquid = a < cnt[o * n + x];
-  const double Tt = (liquid ? seedT[a] : P.t_c) - P.t0;
+  const double Tt = (liquid ? seedT[a] : P.t_c) - P.tref;
   store(g, i, kW7Rest * Tt);
   for (int q = 1; q < 7; ++q) store(g + (size_t)q * P.qstride, i, kW7Axis * Tt);
   if (P.flow)
@@ -788,9 +864,9 @@ __global__ void k_fields(const Ts* __restrict__ f, const Ts* __restrict__ g,
       jz += ez19(q) * v;
     }
     r = 1.0 + d;
-    jz -= 0.5 * P.gbeta * Tt;
+    jz -= 0.5 * P.gbeta * (Tt + P.tref - P.t0);
   }
-  if (T) T[i] = Tt + P.t0;
+  if (T) T[i] = Tt + P.tref;
   if (rho) rho[i] = r;
   if (ux) ux[i] = jx;
   if (uy) uy[i] = jy;
@@ -812,7 +888,7 @@ __global__ void k_to_storage(const double* __restrict__ src, Ts* __restrict__ ds
   if (i >= total) return;
   const int q = (int)(i / P.ncell);
   const uint64_t cell = i - (uint64_t)q * P.ncell;
-  const double shift = weight(qcount, q) * (qcount == 7 ? P.t0 : 1.0);
+  const double shift = weight(qcount, q) * (qcount == 7 ? P.tref : 1.0);
   dst[(uint64_t)q * P.qstride + cell] = static_cast<Ts>(src[i] - shift);
 }
 
@@ -824,7 +900,7 @@ __global__ void k_from_storage(const Ts* __restrict__ src, double* __restrict__ 
   if (i >= total) return;
   const int q = (int)(i / P.ncell);
   const uint64_t cell = i - (uint64_t)q * P.ncell;
-  const double shift = weight(qcount, q) * (qcount == 7 ? P.t0 : 1.0);
+  const double shift = weight(qcount, q) * (qcount == 7 ? P.tref : 1.0);
   dst[i] = (double)static_cast<typename Compute<Ts>::type>(src[(uint64_t)q * P.qstride + cell]) + shift;
 }
 
@@ -865,11 +941,14 @@ __global__ __launch_bounds__(kSumThreads) void k_sum_int(const int* __restrict__
 // --------------------------------------------------------------- dispatch
 // Cells per lane of the row-wave kernel for this precision and size (0: the
 // per-cell kernel).  A segment is 64*VW cells, so n must be a multiple of it.
+// Measured on MI355X at 256^3: for FP32 the per-cell kernel (8 waves/SIMD)
+// beats the row-wave kernel (VW = 2: 136 VGPRs, VW = 4: 198); for 16-bit
+// storage two cells per lane (4-byte accesses) beat 2-byte accesses.
 #ifndef LBM_ROW_VW_32
-#define LBM_ROW_VW_32 4
+#define LBM_ROW_VW_32 0
 #endif
 #ifndef LBM_ROW_VW_16
-#define LBM_ROW_VW_16 4
+#define LBM_ROW_VW_16 2
 #endif
 template <typename Ts>
 int row_width(int n) {
