@@ -23,6 +23,12 @@ Modes:
   (default)       the benchmark line
   --mode profile  a short run of the FP32 workload only (for rocprofv3)
   --mode copy     a plain device copy of known size (counter calibration)
+  --mode precision
+                  storage precision against an FP64 run of the same melting
+                  configuration (256^3, 1e5 steps by default): liquid fraction
+                  and temperature errors of FP32, FP16 and BF16 storage, each
+                  with its throughput, plus an FP64 run at half resolution and
+                  equal Fourier number for the discretization error
 """
 from __future__ import annotations
 
@@ -115,13 +121,62 @@ def cpu_baseline(n: int, steps: int):
                       f"({n ** 3 * steps / 1e6:.1f}M FP64 cell updates, {el:.1f} s)"}
 
 
+def precision_study(n: int, steps: int, stream):
+    """Same melting run (side-heated, Ra = 1e5, Pr = 1, Ste = 0.1, front seeded
+    at s0 = 1) in FP64, FP32, FP16 and BF16 storage; errors against FP64."""
+    import numpy as np
+    import torch
+    from paper_1604_03478_amd import Sim
+    every = max(1, steps // 20)
+    runs = {}
+    for prec in ("f64", "f32", "f16s", "bf16s"):
+        sim = Sim(workload_config(n, prec, False), stream=stream)
+        fl, t_gpu = [], 0.0
+        for k in range(steps // every):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(every)
+            torch.cuda.synchronize()
+            t_gpu += time.perf_counter() - t0
+            fl.append(sim.liquid_fraction())
+            print(f"precision: {prec} step {(k + 1) * every} fl {fl[-1]:.9f}", file=sys.stderr,
+                  flush=True)
+        T = sim.fields()["T"]
+        runs[prec] = {"fl": fl, "T": T, "mlups": n ** 3 * steps / t_gpu / 1e6}
+        sim.close()
+    # discretization band: FP64 at n/2, same Fourier number (t scales with n)
+    half = n // 2
+    sim = Sim(workload_config(half, "f64", False), stream=stream)
+    sim.step(steps // 2)
+    fl_half = sim.liquid_fraction()
+    sim.close()
+    ref = runs["f64"]
+    out = {"mode": "precision", "n": n, "steps": steps, "workload":
+           f"convection melting {n}^3, side-heated, Ra=1e5, Pr=1, Ste=0.1, s0=1",
+           "fl_f64": ref["fl"][-1], "fl_f64_half_resolution": fl_half,
+           "discretization_rel": abs(fl_half - ref["fl"][-1]) / ref["fl"][-1]}
+    for prec in ("f32", "f16s", "bf16s"):
+        r = runs[prec]
+        rel = [abs(a - b) / b for a, b in zip(r["fl"], ref["fl"])]
+        out[prec] = {"fl_rel_err_final": rel[-1], "fl_rel_err_max": max(rel),
+                     "max_abs_dT": float(np.abs(r["T"] - ref["T"]).max()),
+                     "mlups_melting_state": round(r["mlups"], 1)}
+    out["f64_mlups_melting_state"] = round(ref["mlups"], 1)
+    band = max(out["f32"]["fl_rel_err_max"], 0.1 * out["discretization_rel"])
+    out["equal_error_band"] = band
+    for prec in ("f16s", "bf16s"):
+        out[prec]["within_band"] = out[prec]["fl_rel_err_max"] <= band
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--mode", choices=["bench", "profile", "copy"], default="bench")
+    ap.add_argument("--mode", choices=["bench", "profile", "copy", "precision"], default="bench")
+    ap.add_argument("--precision-steps", type=int, default=100000)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -163,6 +218,10 @@ def main():
         ms = time_steps(sim, stream, args.steps)
         print(json.dumps({"mode": "profile", "n": args.n, "steps": args.steps,
                           "ms_per_step": ms}), flush=True)
+        return
+
+    if args.mode == "precision":
+        precision_study(args.n, args.precision_steps, stream)
         return
 
     n, K, W = args.n, args.steps, args.warmup

@@ -365,17 +365,19 @@ void orc_destroy(orc_sim *S) {
 
 /* ------------------------------------------------------------------------ */
 /* thermal boundary type of the wall crossed when leaving the box           */
-/* returns 0 adiabatic, 1 Dirichlet (value in *tw)                          */
-static int wall_type(const orc_sim *S, int x, int y, int z, int sx, int sy,
-                     int sz, double *tw) {
+/* returns 0 adiabatic, 1 Dirichlet (value in *tw; *hot = 1 for the heated  */
+/* wall, whose value is the per-column th)                                  */
+static int wall_type(const orc_sim *S, const double *th, int x, int y, int z,
+                     int sx, int sy, int sz, double *tw, int *hot) {
   int n = S->n;
   const orc_params *p = &S->p;
+  *hot = 0;
   if (p->heating == 0) {
-    if (sy < 0) { *tw = S->th[column_of(S, x, y, z)]; return 1; }
+    if (sy < 0) { *tw = th[column_of(S, x, y, z)]; *hot = 1; return 1; }
     if (sy >= n) { *tw = p->t_c; return 1; }
     return 0; /* reading R6: x and z walls adiabatic; top/bottom per section 1 */
   }
-  if (sz < 0) { *tw = S->th[column_of(S, x, y, z)]; return 1; }
+  if (sz < 0) { *tw = th[column_of(S, x, y, z)]; *hot = 1; return 1; }
   (void)sx;
   return 0;
 }
@@ -384,14 +386,125 @@ static int wall_type(const orc_sim *S, int x, int y, int z, int sx, int sy,
  * neighbour on the other side of the front */
 static double link_fraction(const orc_sim *S, const double *s, int x, int y,
                             int z, const int *e) {
-  int n = S->n;
   int c = column_of(S, x, y, z);
   double a = melt_coord(S, x, y, z) + 0.5;
   int along_melt = (S->p.heating == 0) ? (e[1] != 0) : (e[2] != 0);
   if (along_melt) return fabs(s[c] - a);
   int cn = column_of(S, x + e[0], y + e[1], z + e[2]);
-  (void)n;
   return (a - s[c]) / (s[cn] - s[c]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* one cell of the step: pull-streaming (left sides of Eq. (1) and Eq. (4)) */
+
+static void stream_cell(const orc_sim *S, const double *f, const double *g,
+                        const double *s, const double *th, int x, int y, int z,
+                        int liquid, double *fl, double *gl) {
+  const int n = S->n;
+  const long long nc = S->ncell;
+  const orc_params *p = &S->p;
+  long long i = cell_index(n, x, y, z);
+  for (int q = 0; q < Q7; ++q) {
+    int sx = x - E7[q][0], sy = y - E7[q][1], sz = z - E7[q][2];
+    int po = S->opp7[q];
+    if (p->periodic) {
+      gl[q] = g[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))];
+    } else if (!in_box(n, sx, sy, sz)) {
+      double tw = 0.0;
+      int hot;
+      if (wall_type(S, th, x, y, z, sx, sy, sz, &tw, &hot))
+        gl[q] = -g[po * nc + i] + 2.0 * S->w7[q] * tw; /* anti-bounce-back */
+      else
+        gl[q] = g[po * nc + i]; /* bounce-back: zero flux */
+    } else if (is_liquid(S, s, sx, sy, sz) == liquid) {
+      gl[q] = g[q * nc + cell_index(n, sx, sy, sz)];
+    } else {
+      /* reading R8: interpolated anti-bounce-back at the front, wall value
+       * T_m; the link direction p points from this cell toward the front */
+      const int *ep = E7[po];
+      double d = link_fraction(S, s, x, y, z, ep);
+      double w = S->w7[q];
+      int bx = x + E7[q][0], by = y + E7[q][1], bz = z + E7[q][2];
+      if (d < 0.5) {
+        if (in_box(n, bx, by, bz) && is_liquid(S, s, bx, by, bz) == liquid)
+          gl[q] = -(2.0 * d * g[po * nc + i] +
+                    (1.0 - 2.0 * d) * g[po * nc + cell_index(n, bx, by, bz)]) +
+                  2.0 * w * p->t_m;
+        else
+          gl[q] = -g[po * nc + i] + 2.0 * w * p->t_m;
+      } else {
+        gl[q] = -g[po * nc + i] / (2.0 * d) +
+                (2.0 * d - 1.0) / (2.0 * d) * g[q * nc + i] + w * p->t_m / d;
+      }
+    }
+  }
+  if (p->flow && liquid) {
+    /* halfway bounce-back from walls and solid cells */
+    for (int q = 0; q < Q19; ++q) {
+      int sx = x - E19[q][0], sy = y - E19[q][1], sz = z - E19[q][2];
+      if (p->periodic)
+        fl[q] = f[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))];
+      else if (in_box(n, sx, sy, sz) && is_liquid(S, s, sx, sy, sz))
+        fl[q] = f[q * nc + cell_index(n, sx, sy, sz)];
+      else
+        fl[q] = f[S->opp19[q] * nc + i];
+    }
+  }
+}
+
+/* Collision of one cell: MRT of f (Eq. (2)) with the Boussinesq force of
+ * Eq. (1) when the flow is on and the cell is liquid, and MRT of g (Eq. (4))
+ * in every cell (u = 0 in solid cells). */
+static void collide_cell(const orc_sim *S, int liquid, const double *fl,
+                         const double *gl, double *fo, double *go) {
+  const orc_params *p = &S->p;
+  double m[Q19], me[Q19], Fv[Q19], Fm[Q19], ms[Q19];
+  double nm[Q7], ne[Q7], ns[Q7];
+  double T = 0.0;
+  for (int q = 0; q < Q7; ++q) T += gl[q];
+  double ux = 0.0, uy = 0.0, uz = 0.0;
+  if (p->flow && liquid) {
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int q = 0; q < Q19; ++q) {
+      rho += fl[q];
+      jx += E19[q][0] * fl[q];
+      jy += E19[q][1] * fl[q];
+      jz += E19[q][2] * fl[q];
+    }
+    const double rho0 = 1.0;
+    double Fx = 0.0, Fy = 0.0, Fz = S->gbeta * (T - S->t0);
+    ux = (jx + 0.5 * Fx) / rho0;
+    uy = (jy + 0.5 * Fy) / rho0;
+    uz = (jz + 0.5 * Fz) / rho0;
+    for (int k = 0; k < Q19; ++k) {
+      m[k] = 0.0;
+      for (int q = 0; q < Q19; ++q) m[k] += S->M[k][q] * fl[q];
+    }
+    meq19(rho, rho0 * ux, rho0 * uy, rho0 * uz, me);
+    guo19(S->w19, ux, uy, uz, Fx, Fy, Fz, Fv);
+    for (int k = 0; k < Q19; ++k) {
+      Fm[k] = 0.0;
+      for (int q = 0; q < Q19; ++q) Fm[k] += S->M[k][q] * Fv[q];
+    }
+    for (int k = 0; k < Q19; ++k)
+      ms[k] = m[k] - S->S[k] * (m[k] - me[k]) + (1.0 - 0.5 * S->S[k]) * Fm[k];
+    for (int q = 0; q < Q19; ++q) {
+      double v = 0.0;
+      for (int k = 0; k < Q19; ++k) v += S->Minv[q][k] * ms[k];
+      fo[q] = v;
+    }
+  }
+  for (int k = 0; k < Q7; ++k) {
+    nm[k] = 0.0;
+    for (int q = 0; q < Q7; ++q) nm[k] += S->N[k][q] * gl[q];
+  }
+  neq7(T, ux, uy, uz, ne);
+  for (int k = 0; k < Q7; ++k) ns[k] = nm[k] - S->QR[k] * (nm[k] - ne[k]);
+  for (int q = 0; q < Q7; ++q) {
+    double v = 0.0;
+    for (int k = 0; k < Q7; ++k) v += S->Ninv[q][k] * ns[k];
+    go[q] = v;
+  }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -407,110 +520,20 @@ static void stream_collide(orc_sim *S) {
 
 #pragma omp parallel for schedule(static)
   for (int z = 0; z < n; ++z) {
-    double fl[Q19], gl[Q7], m[Q19], me[Q19], Fv[Q19], Fm[Q19], ms[Q19];
-    double nm[Q7], ne[Q7], ns[Q7];
+    double fl[Q19], gl[Q7], fo[Q19], go[Q7];
     for (int y = 0; y < n; ++y)
       for (int x = 0; x < n; ++x) {
         long long i = cell_index(n, x, y, z);
         int liquid = is_liquid(S, s, x, y, z);
-
-        /* ---- pull-stream g (Eq. (4) left side) ---- */
-        for (int q = 0; q < Q7; ++q) {
-          int sx = x - E7[q][0], sy = y - E7[q][1], sz = z - E7[q][2];
-          int po = S->opp7[q];
-          if (p->periodic) {
-            gl[q] = g[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))];
-          } else if (!in_box(n, sx, sy, sz)) {
-            double tw = 0.0;
-            if (wall_type(S, x, y, z, sx, sy, sz, &tw))
-              gl[q] = -g[po * nc + i] + 2.0 * S->w7[q] * tw; /* anti-bounce-back */
-            else
-              gl[q] = g[po * nc + i]; /* bounce-back: zero flux */
-          } else if (is_liquid(S, s, sx, sy, sz) == liquid) {
-            gl[q] = g[q * nc + cell_index(n, sx, sy, sz)];
-          } else {
-            /* reading R8: interpolated anti-bounce-back at the front, wall
-             * value T_m; p_dir points from this cell toward the front */
-            const int *ep = E7[po];
-            double d = link_fraction(S, s, x, y, z, ep);
-            double w = S->w7[q];
-            int bx = x + E7[q][0], by = y + E7[q][1], bz = z + E7[q][2];
-            if (d < 0.5) {
-              if (in_box(n, bx, by, bz) && is_liquid(S, s, bx, by, bz) == liquid)
-                gl[q] = -(2.0 * d * g[po * nc + i] +
-                          (1.0 - 2.0 * d) * g[po * nc + cell_index(n, bx, by, bz)]) +
-                        2.0 * w * p->t_m;
-              else
-                gl[q] = -g[po * nc + i] + 2.0 * w * p->t_m;
-            } else {
-              gl[q] = -g[po * nc + i] / (2.0 * d) +
-                      (2.0 * d - 1.0) / (2.0 * d) * g[q * nc + i] + w * p->t_m / d;
-            }
-          }
-        }
-        double T = 0.0;
-        for (int q = 0; q < Q7; ++q) T += gl[q];
-
-        double ux = 0.0, uy = 0.0, uz = 0.0;
+        stream_cell(S, f, g, s, S->th, x, y, z, liquid, fl, gl);
+        collide_cell(S, liquid, fl, gl, fo, go);
         if (p->flow && liquid) {
-          /* ---- pull-stream f (Eq. (1) left side), halfway bounce-back ---- */
-          for (int q = 0; q < Q19; ++q) {
-            int sx = x - E19[q][0], sy = y - E19[q][1], sz = z - E19[q][2];
-            if (p->periodic)
-              fl[q] = f[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))];
-            else if (in_box(n, sx, sy, sz) && is_liquid(S, s, sx, sy, sz))
-              fl[q] = f[q * nc + cell_index(n, sx, sy, sz)];
-            else
-              fl[q] = f[S->opp19[q] * nc + i];
-          }
-          /* ---- macroscopic quantities and Boussinesq force ---- */
-          double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-          for (int q = 0; q < Q19; ++q) {
-            rho += fl[q];
-            jx += E19[q][0] * fl[q];
-            jy += E19[q][1] * fl[q];
-            jz += E19[q][2] * fl[q];
-          }
-          const double rho0 = 1.0;
-          double Fx = 0.0, Fy = 0.0, Fz = S->gbeta * (T - S->t0);
-          ux = (jx + 0.5 * Fx) / rho0;
-          uy = (jy + 0.5 * Fy) / rho0;
-          uz = (jz + 0.5 * Fz) / rho0;
-          /* ---- MRT collision, Eq. (2), with the force term of Eq. (1) ---- */
-          for (int k = 0; k < Q19; ++k) {
-            m[k] = 0.0;
-            for (int q = 0; q < Q19; ++q) m[k] += S->M[k][q] * fl[q];
-          }
-          meq19(rho, rho0 * ux, rho0 * uy, rho0 * uz, me);
-          guo19(S->w19, ux, uy, uz, Fx, Fy, Fz, Fv);
-          for (int k = 0; k < Q19; ++k) {
-            Fm[k] = 0.0;
-            for (int q = 0; q < Q19; ++q) Fm[k] += S->M[k][q] * Fv[q];
-          }
-          for (int k = 0; k < Q19; ++k)
-            ms[k] = m[k] - S->S[k] * (m[k] - me[k]) + (1.0 - 0.5 * S->S[k]) * Fm[k];
-          for (int q = 0; q < Q19; ++q) {
-            double v = 0.0;
-            for (int k = 0; k < Q19; ++k) v += S->Minv[q][k] * ms[k];
-            fn[q * nc + i] = v;
-          }
+          for (int q = 0; q < Q19; ++q) fn[q * nc + i] = fo[q];
         } else if (p->flow) {
           /* solid cell: no density distribution; keep whatever is stored */
           for (int q = 0; q < Q19; ++q) fn[q * nc + i] = f[q * nc + i];
         }
-
-        /* ---- MRT collision of g, Eq. (4) ---- */
-        for (int k = 0; k < Q7; ++k) {
-          nm[k] = 0.0;
-          for (int q = 0; q < Q7; ++q) nm[k] += S->N[k][q] * gl[q];
-        }
-        neq7(T, ux, uy, uz, ne);
-        for (int k = 0; k < Q7; ++k) ns[k] = nm[k] - S->QR[k] * (nm[k] - ne[k]);
-        for (int q = 0; q < Q7; ++q) {
-          double v = 0.0;
-          for (int k = 0; k < Q7; ++k) v += S->Ninv[q][k] * ns[k];
-          gn[q * nc + i] = v;
-        }
+        for (int q = 0; q < Q7; ++q) gn[q * nc + i] = go[q];
       }
   }
   double *t;
@@ -518,10 +541,10 @@ static void stream_collide(orc_sim *S) {
   t = S->g; S->g = S->gn; S->gn = t;
 }
 
-/* temperature of a cell from the current (post-collision) energy populations */
-static double cell_T(const orc_sim *S, long long i) {
+/* temperature of a cell from post-collision energy populations */
+static double cell_T_of(const orc_sim *S, const double *g, long long i) {
   double T = 0.0;
-  for (int q = 0; q < Q7; ++q) T += S->g[q * S->ncell + i];
+  for (int q = 0; q < Q7; ++q) T += g[q * S->ncell + i];
   return T;
 }
 
@@ -534,79 +557,152 @@ static long long cell_of_column(const orc_sim *S, int c, int a) {
 }
 
 /* Gradient of a one-sided quadratic through (0, Tm), (xi1, T1), (xi2, T2),
- * taken at xi = 0 with respect to xi.  One node: the chord slope. */
+ * taken at xi = 0 with respect to xi.  One node: the chord slope.  With
+ * dT, dxi non-NULL also its partial derivatives. */
 static double one_sided_slope(int k, const double *xi, const double *Tv,
-                              double tm) {
-  if (k >= 2)
-    return ((Tv[0] - tm) * xi[1] * xi[1] - (Tv[1] - tm) * xi[0] * xi[0]) /
-           (xi[0] * xi[1] * (xi[1] - xi[0]));
-  if (k == 1 && xi[0] > 0.0) return (Tv[0] - tm) / xi[0];
+                              double tm, double *dT, double *dxi) {
+  if (dT) { dT[0] = dT[1] = 0.0; dxi[0] = dxi[1] = 0.0; }
+  if (k >= 2) {
+    double A = Tv[0] - tm, B = Tv[1] - tm;
+    double D = xi[0] * xi[1] * (xi[1] - xi[0]);
+    double num = A * xi[1] * xi[1] - B * xi[0] * xi[0];
+    if (dT) {
+      double dD0 = xi[1] * xi[1] - 2.0 * xi[0] * xi[1];
+      double dD1 = 2.0 * xi[0] * xi[1] - xi[0] * xi[0];
+      dT[0] = xi[1] * xi[1] / D;
+      dT[1] = -xi[0] * xi[0] / D;
+      dxi[0] = (-2.0 * B * xi[0] * D - num * dD0) / (D * D);
+      dxi[1] = (2.0 * A * xi[1] * D - num * dD1) / (D * D);
+    }
+    return num / D;
+  }
+  if (k == 1 && xi[0] > 0.0) {
+    if (dT) {
+      dT[0] = 1.0 / xi[0];
+      dxi[0] = -(Tv[0] - tm) / (xi[0] * xi[0]);
+    }
+    return (Tv[0] - tm) / xi[0];
+  }
   return 0.0;
 }
 
-/* reading R9: front velocity of every column from Eq. (6), evaluated with the
- * current temperatures and front heights (explicit, Jacobi in columns). */
-void orc_front_velocity(const orc_sim *S, double *V) {
+/* Derivatives of the front velocity of one column with respect to its inputs
+ * (node selection frozen). */
+typedef struct {
+  int nnode;
+  long long node_cell[4];
+  double dV_dT[4];
+  double dV_dth;
+  int scol[5];      /* self, x+1, x-1, o+1, o-1 (mirrored at the walls) */
+  double dV_ds[5];
+} vderiv;
+
+/* reading R9: front velocity of column c from Eq. (6), from the temperatures
+ * of post-collision populations g and the fronts s (explicit, Jacobi). */
+static double front_velocity_column(const orc_sim *S, const double *g,
+                                    const double *s, const double *th, int c,
+                                    vderiv *dv) {
   const int n = S->n;
   const orc_params *p = &S->p;
-  const double *s = S->s;
-  if (p->periodic) {
-    for (int c = 0; c < n * n; ++c) V[c] = 0.0;
-    return;
-  }
-  for (int c = 0; c < n * n; ++c) {
-    double sc = s[c];
-    int cnt = 0; /* liquid cells in this column */
-    for (int a = 0; a < n; ++a)
-      if (a + 0.5 < sc) cnt++;
+  double sc = s[c];
+  int cnt = 0; /* liquid cells in this column */
+  for (int a = 0; a < n; ++a)
+    if (a + 0.5 < sc) cnt++;
 
-    /* liquid side: xi measured from the front toward the heated wall */
-    double xi[2], Tv[2];
-    int k = 0;
-    for (int a = cnt - 1; a >= 0 && k < 2; --a) {
-      double d = sc - (a + 0.5);
-      if (d >= 0.5) {
-        xi[k] = d;
-        Tv[k] = cell_T(S, cell_of_column(S, c, a));
-        k++;
-      }
-    }
-    if (k < 2) {
-      xi[k] = sc;
-      Tv[k] = S->th[c];
+  /* liquid side: xi measured from the front toward the heated wall */
+  double xi[2], Tv[2], dT[2], dxi[2];
+  long long nodes[2];
+  int k = 0, wall_l = -1;
+  for (int a = cnt - 1; a >= 0 && k < 2; --a) {
+    double d = sc - (a + 0.5);
+    if (d >= 0.5) {
+      xi[k] = d;
+      nodes[k] = cell_of_column(S, c, a);
+      Tv[k] = cell_T_of(S, g, nodes[k]);
       k++;
     }
-    double dTl_dxi = one_sided_slope(k, xi, Tv, p->t_m);
-    double Gl = -dTl_dxi; /* dT/da, a increasing away from the heated wall */
+  }
+  if (k < 2) {
+    xi[k] = sc;
+    Tv[k] = th[c];
+    wall_l = k;
+    k++;
+  }
+  int kl = k;
+  long long nodes_l[2] = {nodes[0], nodes[1]};
+  double dTl[2], dxil[2];
+  double sl = one_sided_slope(kl, xi, Tv, p->t_m, dTl, dxil);
+  double Gl = -sl; /* dT/da, a increasing away from the heated wall */
 
-    /* solid side: xi measured from the front toward the far wall */
-    k = 0;
-    for (int a = cnt; a < n && k < 2; ++a) {
-      double d = (a + 0.5) - sc;
-      if (d >= 0.5) {
-        xi[k] = d;
-        Tv[k] = cell_T(S, cell_of_column(S, c, a));
-        k++;
-      }
-    }
-    if (k < 2 && p->heating == 0) {
-      xi[k] = n - sc;
-      Tv[k] = p->t_c;
+  /* solid side: xi measured from the front toward the far wall */
+  k = 0;
+  for (int a = cnt; a < n && k < 2; ++a) {
+    double d = (a + 0.5) - sc;
+    if (d >= 0.5) {
+      xi[k] = d;
+      nodes[k] = cell_of_column(S, c, a);
+      Tv[k] = cell_T_of(S, g, nodes[k]);
       k++;
     }
-    double Gs = one_sided_slope(k, xi, Tv, p->t_m);
-
-    /* slopes of the front by central differences, mirrored at the walls */
-    int x = c % n, o = c / n;
-    double sxp = s[(o)*n + (x + 1 < n ? x + 1 : x)];
-    double sxm = s[(o)*n + (x - 1 >= 0 ? x - 1 : x)];
-    double sop = s[(o + 1 < n ? o + 1 : o) * n + x];
-    double som = s[(o - 1 >= 0 ? o - 1 : o) * n + x];
-    double dsx = 0.5 * (sxp - sxm), dso = 0.5 * (sop - som);
-
-    V[c] = (1.0 + dsx * dsx + dso * dso) * S->alpha * p->ste * (Gs - Gl) /
-           (p->t_h - p->t_m);
   }
+  int wall_s = -1;
+  if (k < 2 && p->heating == 0) {
+    xi[k] = n - sc;
+    Tv[k] = p->t_c;
+    wall_s = k;
+    k++;
+  }
+  int ks = k;
+  double Gs = one_sided_slope(ks, xi, Tv, p->t_m, dT, dxi);
+
+  /* slopes of the front by central differences, mirrored at the walls */
+  int x = c % n, o = c / n;
+  int cxp = o * n + (x + 1 < n ? x + 1 : x), cxm = o * n + (x - 1 >= 0 ? x - 1 : x);
+  int cop = (o + 1 < n ? o + 1 : o) * n + x, com = (o - 1 >= 0 ? o - 1 : o) * n + x;
+  double dsx = 0.5 * (s[cxp] - s[cxm]), dso = 0.5 * (s[cop] - s[com]);
+  double P = 1.0 + dsx * dsx + dso * dso;
+  double K = S->alpha * p->ste / (p->t_h - p->t_m);
+  double V = P * K * (Gs - Gl);
+
+  if (dv) {
+    /* V = P K (sigma_s + sigma_l) with sigma_l = -Gl, sigma_s = Gs */
+    dv->nnode = 0;
+    dv->dV_dth = 0.0;
+    for (int j = 0; j < kl; ++j) {
+      if (j == wall_l) {
+        dv->dV_dth += P * K * dTl[j];
+      } else {
+        dv->node_cell[dv->nnode] = nodes_l[j];
+        dv->dV_dT[dv->nnode] = P * K * dTl[j];
+        dv->nnode++;
+      }
+    }
+    for (int j = 0; j < ks; ++j) {
+      if (j == wall_s) continue; /* cold wall value is a constant */
+      dv->node_cell[dv->nnode] = nodes[j];
+      dv->dV_dT[dv->nnode] = P * K * dT[j];
+      dv->nnode++;
+    }
+    /* own front through the distances xi (liquid side +1, solid side -1) */
+    double dself = 0.0;
+    for (int j = 0; j < kl; ++j) dself += dxil[j];
+    for (int j = 0; j < ks; ++j) dself -= dxi[j];
+    dv->scol[0] = c;
+    dv->dV_ds[0] = P * K * dself;
+    /* fronts of the neighbours through the slope factor */
+    double KG = K * (Gs - Gl);
+    dv->scol[1] = cxp; dv->dV_ds[1] = KG * dsx;
+    dv->scol[2] = cxm; dv->dV_ds[2] = -KG * dsx;
+    dv->scol[3] = cop; dv->dV_ds[3] = KG * dso;
+    dv->scol[4] = com; dv->dV_ds[4] = -KG * dso;
+  }
+  return V;
+}
+
+void orc_front_velocity(const orc_sim *S, double *V) {
+  const int n = S->n;
+  for (int c = 0; c < n * n; ++c)
+    V[c] = S->p.periodic ? 0.0 : front_velocity_column(S, S->g, S->s, S->th, c, NULL);
 }
 
 static void front_update(orc_sim *S) {
@@ -651,6 +747,297 @@ void orc_step(orc_sim *S, long long nsteps) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* reference adjoint (reverse mode of the step above, phase and node        */
+/* selection frozen at the forward values)                                  */
+
+/* vector-Jacobian product of the equilibrium moments meq19(rho, j) */
+static void meq19_vjp(double jx, double jy, double jz, const double *l,
+                      double *lrho, double *ljx, double *ljy, double *ljz) {
+  double a9 = l[9] - 0.5 * l[10];   /* weight of 3 jx^2 - j^2 */
+  double a11 = l[11] - 0.5 * l[12]; /* weight of jy^2 - jz^2 */
+  double aq = 19.0 * l[1] - 5.5 * l[2]; /* weight of j^2 */
+  *lrho = l[0] - 11.0 * l[1] + 3.0 * l[2];
+  *ljx = 2.0 * jx * aq + l[3] - 2.0 / 3.0 * l[4] + 4.0 * jx * a9 + jy * l[13] + jz * l[15];
+  *ljy = 2.0 * jy * aq + l[5] - 2.0 / 3.0 * l[6] - 2.0 * jy * a9 + 2.0 * jy * a11 +
+         jx * l[13] + jz * l[14];
+  *ljz = 2.0 * jz * aq + l[7] - 2.0 / 3.0 * l[8] - 2.0 * jz * a9 - 2.0 * jz * a11 +
+         jy * l[14] + jx * l[15];
+}
+
+/* reverse of collide_cell: (lfo, lgo) -> (lfl, lgl) at the same inputs */
+static void collide_cell_adjoint(const orc_sim *S, int liquid, const double *fl,
+                                 const double *gl, const double *lfo,
+                                 const double *lgo, double *lfl, double *lgl) {
+  const orc_params *p = &S->p;
+  double T = 0.0;
+  for (int q = 0; q < Q7; ++q) T += gl[q];
+  double ux = 0.0, uy = 0.0, uz = 0.0, Fz = 0.0, rho = 0.0;
+  int fluid = p->flow && liquid;
+  if (fluid) {
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int q = 0; q < Q19; ++q) {
+      rho += fl[q];
+      jx += E19[q][0] * fl[q];
+      jy += E19[q][1] * fl[q];
+      jz += E19[q][2] * fl[q];
+    }
+    Fz = S->gbeta * (T - S->t0);
+    ux = jx;
+    uy = jy;
+    uz = jz + 0.5 * Fz;
+  }
+  /* energy distribution: g' = Ninv[(I - Q) N gl + Q neq(T, u)] */
+  double lns[Q7], ln[Q7], lne[Q7];
+  for (int k = 0; k < Q7; ++k) {
+    lns[k] = 0.0;
+    for (int q = 0; q < Q7; ++q) lns[k] += S->Ninv[q][k] * lgo[q];
+    ln[k] = (1.0 - S->QR[k]) * lns[k];
+    lne[k] = S->QR[k] * lns[k];
+  }
+  double lT = lne[0] + ux * lne[1] + uy * lne[2] + uz * lne[3] + 0.75 * lne[4];
+  double lux = T * lne[1], luy = T * lne[2], luz = T * lne[3];
+  if (fluid) {
+    double lms[Q19], lm[Q19], lme[Q19], lFm[Q19], lFv[Q19];
+    for (int k = 0; k < Q19; ++k) {
+      lms[k] = 0.0;
+      for (int q = 0; q < Q19; ++q) lms[k] += S->Minv[q][k] * lfo[q];
+      lm[k] = (1.0 - S->S[k]) * lms[k];
+      lme[k] = S->S[k] * lms[k];
+      lFm[k] = (1.0 - 0.5 * S->S[k]) * lms[k];
+    }
+    for (int q = 0; q < Q19; ++q) {
+      lFv[q] = 0.0;
+      for (int k = 0; k < Q19; ++k) lFv[q] += S->M[k][q] * lFm[k];
+    }
+    double lrho, a, b, c;
+    meq19_vjp(ux, uy, uz, lme, &lrho, &a, &b, &c);
+    lux += a;
+    luy += b;
+    luz += c;
+    /* Guo forcing term, F = (0, 0, Fz) */
+    double lFz = 0.0;
+    for (int q = 0; q < Q19; ++q) {
+      double ex = E19[q][0], ey = E19[q][1], ez = E19[q][2];
+      double w = S->w19[q];
+      double eF = ez * Fz, eu = ex * ux + ey * uy + ez * uz;
+      lux += lFv[q] * w * (9.0 * ex * eF);
+      luy += lFv[q] * w * (9.0 * ey * eF);
+      luz += lFv[q] * w * (-3.0 * Fz + 9.0 * ez * eF);
+      lFz += lFv[q] * w * (3.0 * (ez - uz) + 9.0 * eu * ez);
+    }
+    /* u = j + F/2, F_z = gbeta (T - t0) */
+    lFz += 0.5 * luz;
+    lT += S->gbeta * lFz;
+    for (int q = 0; q < Q19; ++q) {
+      double v = lrho + E19[q][0] * lux + E19[q][1] * luy + E19[q][2] * luz;
+      for (int k = 0; k < Q19; ++k) v += S->M[k][q] * lm[k];
+      lfl[q] = v;
+    }
+  } else {
+    for (int q = 0; q < Q19; ++q) lfl[q] = 0.0;
+  }
+  for (int q = 0; q < Q7; ++q) {
+    double v = lT;
+    for (int k = 0; k < Q7; ++k) v += S->N[k][q] * ln[k];
+    lgl[q] = v;
+  }
+}
+
+/* reverse of stream_cell: scatter (lfl, lgl) of cell (x,y,z) into the
+ * adjoints of the previous state (lf, lg), of the fronts (ls) and of the
+ * hot-wall temperatures (lth) */
+static void stream_cell_adjoint(const orc_sim *S, const double *g, const double *s,
+                                int x, int y, int z, int liquid,
+                                const double *lfl, const double *lgl, double *lf,
+                                double *lg, double *ls, double *lth) {
+  const int n = S->n;
+  const long long nc = S->ncell;
+  const orc_params *p = &S->p;
+  long long i = cell_index(n, x, y, z);
+  for (int q = 0; q < Q7; ++q) {
+    double l = lgl[q];
+    int sx = x - E7[q][0], sy = y - E7[q][1], sz = z - E7[q][2];
+    int po = S->opp7[q];
+    if (p->periodic) {
+      lg[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))] += l;
+    } else if (!in_box(n, sx, sy, sz)) {
+      double tw = 0.0;
+      int hot;
+      if (wall_type(S, S->th, x, y, z, sx, sy, sz, &tw, &hot)) {
+        lg[po * nc + i] -= l;
+        if (hot) lth[column_of(S, x, y, z)] += 2.0 * S->w7[q] * l;
+      } else {
+        lg[po * nc + i] += l;
+      }
+    } else if (is_liquid(S, s, sx, sy, sz) == liquid) {
+      lg[q * nc + cell_index(n, sx, sy, sz)] += l;
+    } else {
+      const int *ep = E7[po];
+      double d = link_fraction(S, s, x, y, z, ep);
+      double w = S->w7[q];
+      int bx = x + E7[q][0], by = y + E7[q][1], bz = z + E7[q][2];
+      double ld = 0.0;
+      if (d < 0.5) {
+        if (in_box(n, bx, by, bz) && is_liquid(S, s, bx, by, bz) == liquid) {
+          long long b = cell_index(n, bx, by, bz);
+          lg[po * nc + i] -= 2.0 * d * l;
+          lg[po * nc + b] -= (1.0 - 2.0 * d) * l;
+          ld = (-2.0 * g[po * nc + i] + 2.0 * g[po * nc + b]) * l;
+        } else {
+          lg[po * nc + i] -= l;
+        }
+      } else {
+        lg[po * nc + i] -= l / (2.0 * d);
+        lg[q * nc + i] += (2.0 * d - 1.0) / (2.0 * d) * l;
+        ld = (g[po * nc + i] / (2.0 * d * d) + g[q * nc + i] / (2.0 * d * d) -
+              w * p->t_m / (d * d)) * l;
+      }
+      if (ld != 0.0) {
+        int c = column_of(S, x, y, z);
+        double a = melt_coord(S, x, y, z) + 0.5;
+        int along_melt = (p->heating == 0) ? (ep[1] != 0) : (ep[2] != 0);
+        if (along_melt) {
+          ls[c] += (s[c] > a ? 1.0 : -1.0) * ld;
+        } else {
+          int cn = column_of(S, x + ep[0], y + ep[1], z + ep[2]);
+          double den = s[cn] - s[c];
+          ls[c] += ld * (a - s[cn]) / (den * den);
+          ls[cn] += ld * (-(a - s[c]) / (den * den));
+        }
+      }
+    }
+  }
+  if (p->flow && liquid) {
+    for (int q = 0; q < Q19; ++q) {
+      int sx = x - E19[q][0], sy = y - E19[q][1], sz = z - E19[q][2];
+      if (p->periodic)
+        lf[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))] += lfl[q];
+      else if (in_box(n, sx, sy, sz) && is_liquid(S, s, sx, sy, sz))
+        lf[q * nc + cell_index(n, sx, sy, sz)] += lfl[q];
+      else
+        lf[S->opp19[q] * nc + i] += lfl[q];
+    }
+  }
+}
+
+/* Reverse of one whole step from the state (f, g, s) to (f1, g1, s1).  On
+ * entry (lf1, lg1, ls1) hold the adjoint of the later state (modified in
+ * place); on return (lf, lg, ls) hold the adjoint of the earlier state (they
+ * are overwritten) and lth has been incremented. */
+static void step_adjoint(const orc_sim *S, const double *f, const double *g,
+                         const double *s, const double *g1, const double *s1,
+                         double *lf1, double *lg1, const double *ls1, double *lf,
+                         double *lg, double *ls, double *lth) {
+  const int n = S->n;
+  const long long nc = S->ncell;
+  const orc_params *p = &S->p;
+  memset(lf, 0, sizeof(double) * Q19 * nc);
+  memset(lg, 0, sizeof(double) * Q7 * nc);
+  memset(ls, 0, sizeof(double) * n * n);
+  /* phase switch: refilled populations do not depend on the earlier state */
+  if (p->flow)
+    for (int c = 0; c < n * n; ++c)
+      for (int a = 0; a < n; ++a)
+        if ((a + 0.5) < s1[c] && !((a + 0.5) < s[c])) {
+          long long i = cell_of_column(S, c, a);
+          for (int q = 0; q < Q19; ++q) lf1[q * nc + i] = 0.0;
+        }
+  /* front update s1 = clamp(s + V(g1, s)) */
+  if (!p->periodic)
+    for (int c = 0; c < n * n; ++c) {
+      vderiv dv;
+      double V = front_velocity_column(S, g1, s, S->th, c, &dv);
+      double v = s[c] + V;
+      if (v < 0.0 || v > n) continue; /* clamped: no dependence */
+      double l = ls1[c];
+      ls[c] += l;
+      for (int j = 0; j < dv.nnode; ++j)
+        for (int q = 0; q < Q7; ++q) lg1[q * nc + dv.node_cell[j]] += l * dv.dV_dT[j];
+      for (int j = 0; j < 5; ++j) ls[dv.scol[j]] += l * dv.dV_ds[j];
+      lth[c] += l * dv.dV_dth;
+    }
+  /* collision and streaming, cell by cell (scatter; serial for determinism) */
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        double fl[Q19], gl[Q7], lfo[Q19], lgo[Q7], lfl[Q19], lgl[Q7];
+        long long i = cell_index(n, x, y, z);
+        int liquid = is_liquid(S, s, x, y, z);
+        stream_cell(S, f, g, s, S->th, x, y, z, liquid, fl, gl);
+        for (int q = 0; q < Q19; ++q) lfo[q] = p->flow ? lf1[q * nc + i] : 0.0;
+        for (int q = 0; q < Q7; ++q) lgo[q] = lg1[q * nc + i];
+        collide_cell_adjoint(S, liquid, fl, gl, lfo, lgo, lfl, lgl);
+        stream_cell_adjoint(S, g, s, x, y, z, liquid, lfl, lgl, lf, lg, ls, lth);
+        if (p->flow && !liquid) /* solid cells copy f through */
+          for (int q = 0; q < Q19; ++q) lf[q * nc + i] += lf1[q * nc + i];
+      }
+}
+
+/* ---- recording of a forward run and its reverse sweep ---- */
+typedef struct {
+  long long nsteps;
+  double *f, *g, *s; /* (nsteps + 1) states */
+} orc_record_t;
+
+static orc_record_t g_record = {0, NULL, NULL, NULL};
+
+static void record_free(void) {
+  free(g_record.f); free(g_record.g); free(g_record.s);
+  g_record.f = g_record.g = g_record.s = NULL;
+  g_record.nsteps = 0;
+}
+
+/* Step nsteps forward from the current state, keeping every state (test
+ * sizes only: (nsteps + 1) * 26 * n^3 doubles).  Returns 0 on success. */
+int orc_record(orc_sim *S, long long nsteps) {
+  record_free();
+  const long long nc = S->ncell, nn = (long long)S->n * S->n;
+  g_record.f = (double *)malloc(sizeof(double) * Q19 * nc * (nsteps + 1));
+  g_record.g = (double *)malloc(sizeof(double) * Q7 * nc * (nsteps + 1));
+  g_record.s = (double *)malloc(sizeof(double) * nn * (nsteps + 1));
+  if (!g_record.f || !g_record.g || !g_record.s) {
+    record_free();
+    return -1;
+  }
+  g_record.nsteps = nsteps;
+  for (long long t = 0; t <= nsteps; ++t) {
+    memcpy(g_record.f + t * Q19 * nc, S->f, sizeof(double) * Q19 * nc);
+    memcpy(g_record.g + t * Q7 * nc, S->g, sizeof(double) * Q7 * nc);
+    memcpy(g_record.s + t * nn, S->s, sizeof(double) * nn);
+    if (t < nsteps) orc_step(S, 1);
+  }
+  return 0;
+}
+
+/* Reverse sweep over the recorded run.  (lf, lg, ls): on entry the adjoint of
+ * the final state, on return that of the recorded initial state.  lth (n^2)
+ * receives the gradient with respect to the hot-wall temperatures.  For the
+ * liquid fraction J = dJ * f_l, pass lf = lg = 0 and ls = dJ / n^3. */
+int orc_adjoint(orc_sim *S, double *lf, double *lg, double *ls, double *lth) {
+  if (!g_record.f) return -1;
+  const long long nc = S->ncell, nn = (long long)S->n * S->n;
+  double *tf = (double *)malloc(sizeof(double) * Q19 * nc);
+  double *tg = (double *)malloc(sizeof(double) * Q7 * nc);
+  double *ts = (double *)malloc(sizeof(double) * nn);
+  if (!tf || !tg || !ts) {
+    free(tf); free(tg); free(ts);
+    return -1;
+  }
+  for (long long c = 0; c < nn; ++c) lth[c] = 0.0;
+  for (long long t = g_record.nsteps - 1; t >= 0; --t) {
+    const double *f = g_record.f + t * Q19 * nc, *g = g_record.g + t * Q7 * nc;
+    const double *s = g_record.s + t * nn;
+    const double *g1 = g_record.g + (t + 1) * Q7 * nc, *s1 = g_record.s + (t + 1) * nn;
+    step_adjoint(S, f, g, s, g1, s1, lf, lg, ls, tf, tg, ts, lth);
+    memcpy(lf, tf, sizeof(double) * Q19 * nc);
+    memcpy(lg, tg, sizeof(double) * Q7 * nc);
+    memcpy(ls, ts, sizeof(double) * nn);
+  }
+  free(tf); free(tg); free(ts);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* outputs                                                                  */
 
 /* reading R11: liquid fraction from the front heights */
@@ -671,7 +1058,7 @@ void orc_fields(const orc_sim *S, double *T, double *ux, double *uy, double *uz,
     for (int y = 0; y < n; ++y)
       for (int x = 0; x < n; ++x) {
         long long i = cell_index(n, x, y, z);
-        double t = cell_T(S, i);
+        double t = cell_T_of(S, S->g, i);
         if (T) T[i] = t;
         int liquid = is_liquid(S, S->s, x, y, z);
         double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;

@@ -91,6 +91,8 @@ def _load():
         lib.orc_set_rates.argtypes = [vp, dp, dp]
         lib.orc_equilibrium_moments.argtypes = [d, d, d, d, d, d, d, d, dp, dp]
         lib.orc_guo_force.argtypes = [vp, d, d, d, d, d, d, dp]
+        lib.orc_record.argtypes = [vp, ll]
+        lib.orc_adjoint.argtypes = [vp, dp, dp, dp, dp]
         assert lib.orc_sizeof_params() == ctypes.sizeof(_Params), "oracle params layout mismatch"
         _lib = lib
     return _lib
@@ -244,6 +246,26 @@ class OracleSim:
         self._lib.orc_guo_force(self._h, *[float(v) for v in u], *[float(v) for v in F],
                                 _dp(out))
         return out
+
+    # ---- reference adjoint ----
+    def record(self, nsteps: int) -> None:
+        """Step forward keeping every state (for the reverse sweep)."""
+        if self._lib.orc_record(self._h, int(nsteps)) != 0:
+            raise MemoryError("oracle record allocation failed")
+
+    def adjoint(self, lf=None, lg=None, ls=None):
+        """Reverse sweep over the recorded run.  (lf, lg, ls): adjoint of the
+        final state (default: that of the liquid fraction, ls = 1/n^3).
+        Returns (lf0, lg0, ls0, lth): adjoint of the recorded initial state
+        and the gradient with respect to the hot-wall temperatures."""
+        n = self.n
+        lf = np.zeros((19, n, n, n)) if lf is None else np.array(lf, dtype=np.float64)
+        lg = np.zeros((7, n, n, n)) if lg is None else np.array(lg, dtype=np.float64)
+        ls = np.full((n, n), 1.0 / n ** 3) if ls is None else np.array(ls, dtype=np.float64)
+        lth = np.zeros((n, n))
+        if self._lib.orc_adjoint(self._h, _dp(lf), _dp(lg), _dp(ls), _dp(lth)) != 0:
+            raise RuntimeError("no recorded run")
+        return lf, lg, ls, lth
 
     @staticmethod
     def equilibrium_moments(rho, j, T, u):
