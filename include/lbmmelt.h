@@ -169,6 +169,35 @@ int lbm_diagnostics(lbm_ctx *ctx, double out[5]);
 int lbm_save_state(lbm_ctx *ctx, void *host_buf, size_t *bytes);
 int lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
 
+/* Gradient of the liquid fraction with respect to the hot-wall temperatures
+ * (reverse mode; not part of the paper, which runs the forward method only).
+ * lbm_forward_ckpt runs nsteps >= 1 steps from the current state exactly as
+ * lbm_step does and keeps a device copy of the state every every_k >= 1
+ * steps (ceil(nsteps/every_k) states); *fl (may be NULL) receives the liquid
+ * fraction at the end.  lbm_adjoint then writes grad_th[c] = dJ/dT_h(c) for
+ * J = dJ_dfl * f_l at the end of that run: it recomputes each segment of
+ * every_k steps from its checkpoint (holding every_k + 1 states in device
+ * memory) and applies the transposed step in reverse order.  The phase
+ * masks and the node selection of Eq. (6) are those of the forward run (the
+ * gradient of the piecewise-smooth map along that schedule).  grad_th has
+ * n^2 values in the column layout of s and points to device memory if
+ * on_device != 0.  lbm_adjoint needs a preceding lbm_forward_ckpt with no
+ * step taken since (else LBM_ESTATE); it does not change the state.  Both
+ * synchronize.  Errors: LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EDEVICE. */
+int lbm_forward_ckpt(lbm_ctx *ctx, int64_t nsteps, int32_t every_k, double *fl);
+int lbm_adjoint(lbm_ctx *ctx, double dJ_dfl, double *grad_th, int on_device);
+
+/* The schedule of the run recorded by the last lbm_forward_ckpt: for every
+ * step and the state after the last one, 3*n^2 ints (liquid count of every
+ * column, index of its first liquid node and of its first solid node used
+ * by Eq. (6)); (nsteps + 1) * 3 * n^2 ints in all.  lbm_step_replay takes
+ * nsteps steps along such a schedule (phases and node selection fixed, every
+ * other quantity recomputed): the map whose derivative lbm_adjoint gives,
+ * for finite-difference checks.  The schedule is host memory; both
+ * synchronize. */
+int lbm_get_schedule(lbm_ctx *ctx, int32_t *out, size_t count);
+int lbm_step_replay(lbm_ctx *ctx, const int32_t *schedule, int64_t nsteps);
+
 /* Kernel timing for measurement.  While enabled (enable != 0), every step
  * brackets its fused stream-collide kernel with a pair of HIP events on the
  * context stream.  lbm_kernel_time synchronizes, returns the summed duration

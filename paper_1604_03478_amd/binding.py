@@ -59,6 +59,7 @@ class Lattice(ctypes.Structure):
 EXPORTS = ("lbm_init", "lbm_destroy", "lbm_step", "lbm_liquid_fraction", "lbm_fields",
            "lbm_get_lattice", "lbm_get_step", "lbm_set_hot_wall", "lbm_set_populations",
            "lbm_get_populations", "lbm_diagnostics", "lbm_save_state", "lbm_load_state",
+           "lbm_forward_ckpt", "lbm_adjoint", "lbm_get_schedule", "lbm_step_replay",
            "lbm_kernel_timing", "lbm_kernel_time", "lbm_last_error")
 
 _lib = None
@@ -87,6 +88,10 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_diagnostics.argtypes = [vp, dp]
     lib.lbm_save_state.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.lbm_load_state.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.lbm_forward_ckpt.argtypes = [vp, i64, ctypes.c_int32, dp]
+    lib.lbm_adjoint.argtypes = [vp, ctypes.c_double, vp, i32]
+    lib.lbm_get_schedule.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.lbm_step_replay.argtypes = [vp, vp, i64]
     lib.lbm_kernel_timing.argtypes = [vp, i32]
     lib.lbm_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lbm_last_error.restype = ctypes.c_char_p
@@ -201,6 +206,38 @@ class Sim:
         return {"mass": out[0], "energy": out[1], "front_sum": out[2], "melted": int(out[3]),
                 "frozen": int(out[4])}
 
+    # ---- reverse mode ----
+    def forward_ckpt(self, nsteps: int, every_k: int) -> float:
+        """Run nsteps keeping a checkpoint every every_k steps; returns f_l."""
+        fl = ctypes.c_double()
+        _check(self._lib.lbm_forward_ckpt(self._h, int(nsteps), int(every_k), ctypes.byref(fl)))
+        return fl.value
+
+    def adjoint(self, dJ_dfl: float = 1.0, device: bool = False):
+        """dJ/dT_h (n x n) for J = dJ_dfl * f_l of the last forward_ckpt run:
+        a numpy array, or an FP64 torch tensor on the current device."""
+        n = self.n
+        if device:
+            out = torch.empty((n, n), dtype=torch.float64,
+                              device=torch.device("cuda", torch.cuda.current_device()))
+            _check(self._lib.lbm_adjoint(self._h, float(dJ_dfl), ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        out = np.empty((n, n))
+        _check(self._lib.lbm_adjoint(self._h, float(dJ_dfl), _ptr(out), 0))
+        return out
+
+    def schedule(self, nsteps: int) -> np.ndarray:
+        """Schedule of the last forward_ckpt run of nsteps steps."""
+        out = np.empty((nsteps + 1) * 3 * self.n * self.n, dtype=np.int32)
+        _check(self._lib.lbm_get_schedule(self._h, _ptr(out), out.size))
+        return out
+
+    def step_replay(self, schedule: np.ndarray, nsteps: int) -> None:
+        a = np.ascontiguousarray(schedule, dtype=np.int32)
+        if a.size < (nsteps + 1) * 3 * self.n * self.n:
+            raise ValueError("schedule too short")
+        _check(self._lib.lbm_step_replay(self._h, _ptr(a), int(nsteps)))
+
     # ---- measurement ----
     def kernel_timing(self, enable: bool) -> None:
         _check(self._lib.lbm_kernel_timing(self._h, int(bool(enable))))
@@ -252,3 +289,27 @@ class Sim:
     def load_state(self, blob: bytes) -> None:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self._lib.lbm_load_state(self._h, buf, len(blob)))
+
+
+class LiquidFraction(torch.autograd.Function):
+    """f_l after ``nsteps`` steps as a function of the hot-wall temperature
+    field T_h (n x n tensor on the GPU, column layout of the front).
+
+    forward: a fresh context from ``cfg`` at its initial state, T_h set, run
+    with a checkpoint every ``every_k`` steps.  backward: the hand-written
+    adjoint (recompute between checkpoints, transposed step in reverse)."""
+
+    @staticmethod
+    def forward(ctx, th, cfg, nsteps, every_k):
+        sim = Sim(cfg)
+        sim.set_hot_wall(th)
+        fl = sim.forward_ckpt(int(nsteps), int(every_k))
+        ctx.sim = sim
+        ctx.th_dtype = th.dtype
+        return torch.tensor(fl, dtype=torch.float64, device=th.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = ctx.sim.adjoint(1.0, device=True)
+        ctx.sim.close()
+        return (grad_out * g).to(ctx.th_dtype), None, None, None

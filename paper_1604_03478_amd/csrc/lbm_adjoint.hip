@@ -1,0 +1,745 @@
+// Adjoint (reverse mode) of the double-MRT melting step on gfx950.
+//
+// For J = f_l after N steps (front-based liquid fraction), the reverse sweep
+// propagates the adjoint lambda = dJ/dX of the state X = (f*, g*, s) from
+// the last step to the first and accumulates dJ/dT_h for the hot-wall
+// temperature of every column.  The forward step it reverses is the one of
+// lbm_kernels.hip: pull-streaming (Eq. (1), Eq. (4)) with wall, solid and
+// interpolated front conditions, MRT collisions (Eq. (2), Eq. (4)), front
+// velocity from the interface energy balance (Eq. (6)), phase switch.  Phase
+// masks and the node selection of Eq. (6) are piecewise constant in the
+// state; the adjoint is that of the forward run's own schedule.
+//
+// Per step, in reverse order of the forward operations:
+//   k_adj_front        per column: phase switch (refilled f has no
+//                      dependence), s' = s + V(g*, s): adjoint into the node
+//                      temperatures, into s and its neighbours, into T_h
+//   k_adj_front_gather per column: sums the neighbour contributions to s
+//   k_adj_collide      per cell: recomputes the pulled populations and
+//                      applies the transposed collision Jacobian
+//   k_adj_stream       per cell: transposed streaming as a gather over every
+//                      reader of each stored population (no atomics)
+//   k_adj_interface    per column: dependence of the interpolated
+//                      anti-bounce-back on the front through the link
+//                      fractions, and of the hot-wall condition on T_h
+// Adjoint arithmetic is FP64 for every storage format.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbmk {
+namespace {
+
+constexpr double kD19[19] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36,
+                             72, 12,   24,  4,  4,  4,  8,  8,  8};
+constexpr double kD7[7] = {7, 2, 2, 2, 42, 12, 4};
+
+// m = M v for the orthogonal D3Q19 basis (integer structure, pairwise sums)
+__device__ __forceinline__ void m19(const double (&f)[19], double (&m)[19]) {
+  const double axp = f[1] + f[2], axm = f[1] - f[2];
+  const double ayp = f[3] + f[4], aym = f[3] - f[4];
+  const double azp = f[5] + f[6], azm = f[5] - f[6];
+  const double a78 = f[7] + f[8], b78 = f[7] - f[8], a910 = f[9] + f[10], b910 = f[9] - f[10];
+  const double Sxy = a78 + a910, Xxy = b78 + b910, Yxy = a78 - a910, Pxy = b78 - b910;
+  const double a1112 = f[11] + f[12], b1112 = f[11] - f[12];
+  const double a1314 = f[13] + f[14], b1314 = f[13] - f[14];
+  const double Sxz = a1112 + a1314, Xxz = b1112 + b1314, Zxz = a1112 - a1314, Pxz = b1112 - b1314;
+  const double a1516 = f[15] + f[16], b1516 = f[15] - f[16];
+  const double a1718 = f[17] + f[18], b1718 = f[17] - f[18];
+  const double Syz = a1516 + a1718, Yyz = b1516 + b1718, Zyz = a1516 - a1718, Pyz = b1516 - b1718;
+  const double A = axp + ayp + azp, E = Sxy + Sxz + Syz;
+  const double Ed = Sxy + Sxz - 2.0 * Syz;
+  m[0] = f[0] + A + E;
+  m[1] = -30.0 * f[0] - 11.0 * A + 8.0 * E;
+  m[2] = 12.0 * f[0] - 4.0 * A + E;
+  m[3] = axm + Xxy + Xxz;
+  m[4] = -4.0 * axm + Xxy + Xxz;
+  m[5] = aym + Yxy + Yyz;
+  m[6] = -4.0 * aym + Yxy + Yyz;
+  m[7] = azm + Zxz + Zyz;
+  m[8] = -4.0 * azm + Zxz + Zyz;
+  m[9] = 2.0 * axp - ayp - azp + Ed;
+  m[10] = -4.0 * axp + 2.0 * ayp + 2.0 * azp + Ed;
+  m[11] = ayp - azp + Sxy - Sxz;
+  m[12] = -2.0 * ayp + 2.0 * azp + Sxy - Sxz;
+  m[13] = Pxy;
+  m[14] = Pyz;
+  m[15] = Pxz;
+  m[16] = Xxy - Xxz;
+  m[17] = Yyz - Yxy;
+  m[18] = Zxz - Zyz;
+}
+
+// f = M^T a
+__device__ __forceinline__ void m19t(const double (&a)[19], double (&f)[19]) {
+  const double Aax = a[0] - 11.0 * a[1] - 4.0 * a[2];
+  const double Aed = a[0] + 8.0 * a[1] + a[2];
+  f[0] = a[0] - 30.0 * a[1] + 12.0 * a[2];
+  {
+    const double c = Aax + 2.0 * a[9] - 4.0 * a[10], d = a[3] - 4.0 * a[4];
+    f[1] = c + d;
+    f[2] = c - d;
+  }
+  {
+    const double c = Aax - a[9] + 2.0 * a[10] + a[11] - 2.0 * a[12], d = a[5] - 4.0 * a[6];
+    f[3] = c + d;
+    f[4] = c - d;
+  }
+  {
+    const double c = Aax - a[9] + 2.0 * a[10] - a[11] + 2.0 * a[12], d = a[7] - 4.0 * a[8];
+    f[5] = c + d;
+    f[6] = c - d;
+  }
+  {
+    const double b = Aed + a[9] + a[10] + a[11] + a[12], X = a[3] + a[4] + a[16],
+                 Y = a[5] + a[6] - a[17];
+    f[7] = b + X + Y + a[13];
+    f[8] = b - X + Y - a[13];
+    f[9] = b + X - Y - a[13];
+    f[10] = b - X - Y + a[13];
+  }
+  {
+    const double b = Aed + a[9] + a[10] - a[11] - a[12], X = a[3] + a[4] - a[16],
+                 Z = a[7] + a[8] + a[18];
+    f[11] = b + X + Z + a[15];
+    f[12] = b - X + Z - a[15];
+    f[13] = b + X - Z - a[15];
+    f[14] = b - X - Z + a[15];
+  }
+  {
+    const double b = Aed - 2.0 * a[9] - 2.0 * a[10], Y = a[5] + a[6] + a[17],
+                 Z = a[7] + a[8] - a[18];
+    f[15] = b + Y + Z + a[14];
+    f[16] = b - Y + Z - a[14];
+    f[17] = b + Y - Z - a[14];
+    f[18] = b - Y - Z + a[14];
+  }
+}
+
+// n = N g (D3Q7) and g = N^T b
+__device__ __forceinline__ void m7(const double (&g)[7], double (&nm)[7]) {
+  const double px = g[1] + g[2], py = g[3] + g[4], pz = g[5] + g[6];
+  nm[0] = g[0] + px + py + pz;
+  nm[1] = g[1] - g[2];
+  nm[2] = g[3] - g[4];
+  nm[3] = g[5] - g[6];
+  nm[4] = 6.0 * g[0] - (px + py + pz);
+  nm[5] = 2.0 * px - py - pz;
+  nm[6] = py - pz;
+}
+__device__ __forceinline__ void m7t(const double (&b)[7], double (&g)[7]) {
+  const double c1 = b[0] - b[4] + 2.0 * b[5];
+  const double c3 = b[0] - b[4] - b[5] + b[6];
+  const double c5 = b[0] - b[4] - b[5] - b[6];
+  g[0] = b[0] + 6.0 * b[4];
+  g[1] = c1 + b[1];
+  g[2] = c1 - b[1];
+  g[3] = c3 + b[2];
+  g[4] = c3 - b[2];
+  g[5] = c5 + b[3];
+  g[6] = c5 - b[3];
+}
+
+// ---- geometry helpers ----
+struct Geo {
+  int n;
+  uint32_t nn;
+  __device__ uint32_t cell(int x, int y, int z) const {
+    return (uint32_t)z * nn + (uint32_t)y * (uint32_t)n + (uint32_t)x;
+  }
+  __device__ bool in(int x, int y, int z) const {
+    return (unsigned)x < (unsigned)n && (unsigned)y < (unsigned)n && (unsigned)z < (unsigned)n;
+  }
+};
+
+template <bool MZ>
+__device__ __forceinline__ int melt_of(int y, int z) { return MZ ? z : y; }
+template <bool MZ>
+__device__ __forceinline__ int col_of(int x, int y, int z, int n) { return (MZ ? y : z) * n + x; }
+template <bool MZ>
+__device__ __forceinline__ bool liquid_at(const int* cnt, int x, int y, int z, int n) {
+  return melt_of<MZ>(y, z) < cnt[col_of<MZ>(x, y, z, n)];
+}
+template <bool MZ>
+__device__ __forceinline__ uint32_t cell_in_column(int c, int a, int n) {
+  const int x = c % n, o = c / n;
+  return MZ ? ((uint32_t)a * n + o) * n + x : ((uint32_t)o * n + a) * n + x;
+}
+
+// link fraction from cell (x,y,z) along direction (ex,ey,ez) to the front
+template <bool MZ>
+__device__ __forceinline__ double link_delta(const double* s, int x, int y, int z, int ex, int ey,
+                                             int ez, int n) {
+  const int c = col_of<MZ>(x, y, z, n);
+  const double a = melt_of<MZ>(y, z) + 0.5;
+  const bool along = MZ ? (ez != 0) : (ey != 0);
+  if (along) return fabs(s[c] - a);
+  const int cn = col_of<MZ>(x + ex, y + ey, z + ez, n);
+  return (a - s[c]) / (s[cn] - s[c]);
+}
+
+template <typename Ts>
+__device__ __forceinline__ double sv(const Ts* a, size_t qs, int q, uint32_t i) {
+  return (double)static_cast<typename Compute<Ts>::type>(a[(size_t)q * qs + i]);
+}
+
+// pulled (pre-collision) shifted populations of one cell, in FP64
+template <typename Ts, bool FLOW, bool MZ>
+__device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const double* th,
+                          const int* cnt, int x, int y, int z, bool liquid, const KParams& P,
+                          double (&fl)[19], double (&gl)[7]) {
+  const Geo G{P.n, (uint32_t)P.n * (uint32_t)P.n};
+  const int n = P.n;
+  const size_t qs = P.qstride;
+  const uint32_t i = G.cell(x, y, z);
+  const double w = 0.125, wTm = w * (P.t_m - P.tref);
+  for (int q = 0; q < 7; ++q) {
+    const int ex = ex7(q), ey = ey7(q), ez = ez7(q), p = opp7(q);
+    const int sx = x - ex, sy = y - ey, sz = z - ez;
+    double v;
+    if (!G.in(sx, sy, sz)) {
+      const int sa = melt_of<MZ>(sy, sz);
+      const double gp = sv(g, qs, p, i);
+      if (sa < 0)
+        v = -gp + 2.0 * w * (th[col_of<MZ>(x, y, z, n)] - P.tref);
+      else if (!MZ && sa >= n)
+        v = -gp + 2.0 * w * (P.t_c - P.tref);
+      else
+        v = gp;
+    } else if (liquid_at<MZ>(cnt, sx, sy, sz, n) == liquid) {
+      v = sv(g, qs, q, G.cell(sx, sy, sz));
+    } else {
+      const double d = link_delta<MZ>(s, x, y, z, -ex, -ey, -ez, n);
+      const double gp = sv(g, qs, p, i);
+      if (d < 0.5) {
+        const int bx = x + ex, by = y + ey, bz = z + ez;
+        const bool behind = G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == liquid;
+        v = behind ? -(2.0 * d * gp + (1.0 - 2.0 * d) * sv(g, qs, p, G.cell(bx, by, bz))) + 2.0 * wTm
+                   : -gp + 2.0 * wTm;
+      } else {
+        v = -gp / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * sv(g, qs, q, i) + wTm / d;
+      }
+    }
+    gl[q] = v;
+  }
+  if (FLOW && liquid) {
+    for (int q = 0; q < 19; ++q) {
+      const int sx = x - ex19(q), sy = y - ey19(q), sz = z - ez19(q);
+      const bool ok = G.in(sx, sy, sz) && liquid_at<MZ>(cnt, sx, sy, sz, n);
+      fl[q] = ok ? sv(f, qs, q, G.cell(sx, sy, sz)) : sv(f, qs, opp19(q), i);
+    }
+  }
+}
+
+// Transposed collision Jacobian of one cell: (lfo, lgo) -> (lfl, lgl)
+template <bool FLOW>
+__device__ void collide_adjoint(const double (&fl)[19], const double (&gl)[7], bool liquid,
+                                const KParams& P, const double (&lfo)[19],
+                                const double (&lgo)[7], double (&lfl)[19], double (&lgl)[7]) {
+  const bool fluid = FLOW && liquid;
+  double Tt = 0.0;  // T - tref
+  for (int q = 0; q < 7; ++q) Tt += gl[q];
+  const double T = Tt + P.tref;
+  double ux = 0.0, uy = 0.0, uz = 0.0, Fz = 0.0, m[19];
+  if (fluid) {
+    m19(fl, m);
+    Fz = P.gbeta * (Tt + P.tref - P.t0);
+    ux = m[3];
+    uy = m[5];
+    uz = m[7] + 0.5 * Fz;
+  }
+  // ---- energy distribution: g' = N^T D^-1 [(I - Q) N gl + Q n_eq(T, u)] ----
+  const double Q[7] = {0.0, P.q_j, P.q_j, P.q_j, P.q_e, P.q_e, P.q_e};
+  double lns[7], ln[7], lne[7];
+  m7(lgo, lns);
+  for (int k = 0; k < 7; ++k) {
+    lns[k] /= kD7[k];
+    ln[k] = (1.0 - Q[k]) * lns[k];
+    lne[k] = Q[k] * lns[k];
+  }
+  double lT = ux * lne[1] + uy * lne[2] + uz * lne[3] + 0.75 * lne[4];
+  double lux = T * lne[1], luy = T * lne[2], luz = T * lne[3];
+  if (fluid) {
+    // ---- flow: f' = M^T D^-1 [m - S (m - m_eq) + (I - S/2) F_m] ----
+    const double sv_ = P.s_nu;
+    const double S[19] = {0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, sv_,
+                          1.4, sv_,  1.4, sv_, sv_, sv_, 1.98, 1.98, 1.98};
+    double lms[19], lm[19], le[19], lF[19];
+    m19(lfo, lms);
+    for (int k = 0; k < 19; ++k) {
+      lms[k] /= kD19[k];
+      lm[k] = (1.0 - S[k]) * lms[k];
+      le[k] = S[k] * lms[k];
+      lF[k] = (1.0 - 0.5 * S[k]) * lms[k];
+    }
+    // equilibria (deviation form, rho0 = 1): dependence on drho and u
+    const double aq = 19.0 * le[1] - 5.5 * le[2];
+    const double a9 = le[9] - 0.5 * le[10], a11 = le[11] - 0.5 * le[12];
+    const double ldrho = -11.0 * le[1] + 3.0 * le[2];
+    lux += 2.0 * ux * aq - 2.0 / 3.0 * le[4] + 4.0 * ux * a9 + uy * le[13] + uz * le[15];
+    luy += 2.0 * uy * aq - 2.0 / 3.0 * le[6] - 2.0 * uy * a9 + 2.0 * uy * a11 + ux * le[13] +
+           uz * le[14];
+    luz += 2.0 * uz * aq - 2.0 / 3.0 * le[8] - 2.0 * uz * a9 - 2.0 * uz * a11 + uy * le[14] +
+           ux * le[15];
+    // forcing moments with F = (0, 0, Fz)
+    const double cF = 38.0 * lF[1] - 11.0 * lF[2] - 2.0 * lF[9] + lF[10] - 2.0 * lF[11] + lF[12];
+    luz += Fz * cF;
+    luy += Fz * lF[14];
+    lux += Fz * lF[15];
+    double lFz = uz * cF + lF[7] - 2.0 / 3.0 * lF[8] + uy * lF[14] + ux * lF[15];
+    // u = j + F/2, F_z = gbeta (T - t0)
+    lFz += 0.5 * luz;
+    lT += P.gbeta * lFz;
+    lm[0] += ldrho;
+    lm[3] += lux;
+    lm[5] += luy;
+    lm[7] += luz;
+    m19t(lm, lfl);
+  } else {
+    for (int q = 0; q < 19; ++q) lfl[q] = 0.0;
+  }
+  m7t(ln, lgl);
+  for (int q = 0; q < 7; ++q) lgl[q] += lT;
+}
+
+// ---- front velocity and its derivatives (node selection frozen) ----
+struct VDer {
+  double V;
+  int nnode;
+  uint32_t node[4];
+  double dT[4];
+  double dth;
+  int col[5];
+  double ds[5];
+};
+
+__device__ __forceinline__ double slope_der(int k, const double* xi, const double* Tv, double tm,
+                                            double* dT, double* dxi) {
+  dT[0] = dT[1] = dxi[0] = dxi[1] = 0.0;
+  if (k >= 2) {
+    const double A = Tv[0] - tm, B = Tv[1] - tm;
+    const double D = xi[0] * xi[1] * (xi[1] - xi[0]);
+    const double num = A * xi[1] * xi[1] - B * xi[0] * xi[0];
+    const double dD0 = xi[1] * xi[1] - 2.0 * xi[0] * xi[1];
+    const double dD1 = 2.0 * xi[0] * xi[1] - xi[0] * xi[0];
+    dT[0] = xi[1] * xi[1] / D;
+    dT[1] = -xi[0] * xi[0] / D;
+    dxi[0] = (-2.0 * B * xi[0] * D - num * dD0) / (D * D);
+    dxi[1] = (2.0 * A * xi[1] * D - num * dD1) / (D * D);
+    return num / D;
+  }
+  if (k == 1 && xi[0] > 0.0) {
+    dT[0] = 1.0 / xi[0];
+    dxi[0] = -(Tv[0] - tm) / (xi[0] * xi[0]);
+    return (Tv[0] - tm) / xi[0];
+  }
+  return 0.0;
+}
+
+template <typename Ts, bool MZ>
+__device__ void front_der(const Ts* g1, const double* s, const double* th, int c,
+                          const KParams& P, VDer& d) {
+  const int n = P.n;
+  const size_t qs = P.qstride;
+  const double sc = s[c];
+  const int cnt = count_liquid(sc, n);
+  auto Tcell = [&](uint32_t i) {
+    double acc = 0.0;
+    for (int q = 0; q < 7; ++q) acc += sv(g1, qs, q, i);
+    return acc + P.tref;
+  };
+  double xi[2], Tv[2], dT[2], dxi[2];
+  uint32_t nd[2] = {0, 0};
+  int k = 0, wall = -1;
+  for (int a = cnt - 1; a >= 0 && k < 2; --a) {
+    const double dd = sc - (a + 0.5);
+    if (dd >= 0.5) {
+      xi[k] = dd;
+      nd[k] = cell_in_column<MZ>(c, a, n);
+      Tv[k] = Tcell(nd[k]);
+      ++k;
+    }
+  }
+  if (k < 2) {
+    xi[k] = sc;
+    Tv[k] = th[c];
+    wall = k;
+    ++k;
+  }
+  const int kl = k;
+  double dTl[2], dxil[2];
+  const double sl = slope_der(kl, xi, Tv, P.t_m, dTl, dxil);
+  const uint32_t ndl[2] = {nd[0], nd[1]};
+  const int wall_l = wall;
+  k = 0;
+  wall = -1;
+  for (int a = cnt; a < n && k < 2; ++a) {
+    const double dd = (a + 0.5) - sc;
+    if (dd >= 0.5) {
+      xi[k] = dd;
+      nd[k] = cell_in_column<MZ>(c, a, n);
+      Tv[k] = Tcell(nd[k]);
+      ++k;
+    }
+  }
+  if (k < 2 && !MZ) {
+    xi[k] = n - sc;
+    Tv[k] = P.t_c;
+    wall = k;
+    ++k;
+  }
+  const int ks = k;
+  const double ss = slope_der(ks, xi, Tv, P.t_m, dT, dxi);
+  const int x = c % n, o = c / n;
+  const int cxp = o * n + (x + 1 < n ? x + 1 : x), cxm = o * n + (x > 0 ? x - 1 : x);
+  const int cop = (o + 1 < n ? o + 1 : o) * n + x, com = (o > 0 ? o - 1 : o) * n + x;
+  const double dsx = 0.5 * (s[cxp] - s[cxm]), dso = 0.5 * (s[cop] - s[com]);
+  const double Pf = 1.0 + dsx * dsx + dso * dso;
+  const double K = P.alpha * P.ste / P.dT;
+  d.V = Pf * K * (ss + sl);
+  d.nnode = 0;
+  d.dth = 0.0;
+  for (int j = 0; j < kl; ++j) {
+    if (j == wall_l) {
+      d.dth += Pf * K * dTl[j];
+    } else {
+      d.node[d.nnode] = ndl[j];
+      d.dT[d.nnode++] = Pf * K * dTl[j];
+    }
+  }
+  for (int j = 0; j < ks; ++j) {
+    if (j == wall) continue;
+    d.node[d.nnode] = nd[j];
+    d.dT[d.nnode++] = Pf * K * dT[j];
+  }
+  double dself = 0.0;
+  for (int j = 0; j < kl; ++j) dself += dxil[j];
+  for (int j = 0; j < ks; ++j) dself -= dxi[j];
+  const double KG = K * (ss + sl);
+  d.col[0] = c;
+  d.ds[0] = Pf * K * dself;
+  d.col[1] = cxp;
+  d.ds[1] = KG * dsx;
+  d.col[2] = cxm;
+  d.ds[2] = -KG * dsx;
+  d.col[3] = cop;
+  d.ds[3] = KG * dso;
+  d.col[4] = com;
+  d.ds[4] = -KG * dso;
+}
+
+// ---------------------------------------------------------------- kernels
+// Adjoint buffers are dense FP64 arrays [q][n^3] (populations) and [n^2].
+
+template <typename Ts, bool FLOW, bool MZ>
+__global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict__ g1,
+                            const double* __restrict__ s1, const double* __restrict__ th,
+                            const double* __restrict__ ls1, double* __restrict__ lg1,
+                            double* __restrict__ lf1, double* __restrict__ out5,
+                            double* __restrict__ own, double* __restrict__ lth, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
+  if (x >= n) return;
+  const int c = o * n + x;
+  const size_t nc = P.ncell, nn = (size_t)n * n;
+  if (FLOW) {  // refilled populations of newly liquid cells do not depend on anything
+    const int c0 = count_liquid(s0[c], n), c1 = count_liquid(s1[c], n);
+    for (int a = c0; a < c1; ++a) {
+      const uint32_t i = cell_in_column<MZ>(c, a, n);
+      for (int q = 0; q < 19; ++q) lf1[(size_t)q * nc + i] = 0.0;
+    }
+  }
+  VDer d;
+  front_der<Ts, MZ>(g1, s0, th, c, P, d);
+  const double v = s0[c] + d.V;
+  const double l = ls1[c];
+  if (v < 0.0 || v > (double)n) {  // clamped: no dependence
+    own[c] = 0.0;
+    for (int j = 0; j < 5; ++j) out5[j * nn + c] = 0.0;
+    return;
+  }
+  own[c] = l;
+  for (int k = 0; k < d.nnode; ++k)
+    for (int q = 0; q < 7; ++q) lg1[(size_t)q * nc + d.node[k]] += l * d.dT[k];
+  for (int j = 0; j < 5; ++j) out5[j * nn + c] = l * d.ds[j];
+  lth[c] += l * d.dth;
+}
+
+// s contributions: own slot 0; slot 1 of the x-1 neighbour (its x+1 is this
+// column), slot 2 of x+1, slot 3 of o-1, slot 4 of o+1; at the walls the
+// mirrored slots of the column itself
+__global__ void k_adj_front_gather(const double* __restrict__ own, const double* __restrict__ out5,
+                                   double* __restrict__ ls0, int n) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
+  if (x >= n) return;
+  const size_t nn = (size_t)n * n;
+  const int c = o * n + x;
+  double acc = own[c] + out5[0 * nn + c];
+  if (x > 0) acc += out5[1 * nn + c - 1]; else acc += out5[2 * nn + c];
+  if (x < n - 1) acc += out5[2 * nn + c + 1]; else acc += out5[1 * nn + c];
+  if (o > 0) acc += out5[3 * nn + c - n]; else acc += out5[4 * nn + c];
+  if (o < n - 1) acc += out5[4 * nn + c + n]; else acc += out5[3 * nn + c];
+  ls0[c] = acc;
+}
+
+template <typename Ts, bool FLOW, bool MZ>
+__global__ __launch_bounds__(256) void k_adj_collide(
+    const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
+    const double* __restrict__ th, const int* __restrict__ cnt, const double* __restrict__ lf1,
+    const double* __restrict__ lg1, double* __restrict__ lfh, double* __restrict__ lgh,
+    KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= n) return;
+  const size_t nc = P.ncell;
+  const uint32_t i = ((uint32_t)z * n + y) * n + x;
+  const bool liquid = liquid_at<MZ>(cnt, x, y, z, n);
+  double fl[19], gl[7], lfo[19], lgo[7], lfl[19], lgl[7];
+  pull_cell<Ts, FLOW, MZ>(f0, g0, s0, th, cnt, x, y, z, liquid, P, fl, gl);
+  for (int q = 0; q < 19; ++q) lfo[q] = (FLOW && liquid) ? lf1[(size_t)q * nc + i] : 0.0;
+  for (int q = 0; q < 7; ++q) lgo[q] = lg1[(size_t)q * nc + i];
+  collide_adjoint<FLOW>(fl, gl, liquid, P, lfo, lgo, lfl, lgl);
+  if (FLOW)
+    for (int q = 0; q < 19; ++q) lfh[(size_t)q * nc + i] = lfl[q];
+  for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = lgl[q];
+}
+
+template <typename Ts, bool FLOW, bool MZ>
+__global__ __launch_bounds__(256) void k_adj_stream(
+    const double* __restrict__ s0, const int* __restrict__ cnt, const double* __restrict__ lfh,
+    const double* __restrict__ lgh, const double* __restrict__ lf1, double* __restrict__ lf0,
+    double* __restrict__ lg0, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= n) return;
+  const Geo G{n, (uint32_t)n * (uint32_t)n};
+  const size_t nc = P.ncell;
+  const uint32_t i = G.cell(x, y, z);
+  const bool L = liquid_at<MZ>(cnt, x, y, z, n);
+  auto LG = [&](int q, uint32_t j) { return lgh[(size_t)q * nc + j]; };
+
+  for (int p = 0; p < 7; ++p) {
+    const int ex = ex7(p), ey = ey7(p), ez = ez7(p), q = opp7(p);
+    double acc = 0.0;
+    // (a) regular pull of direction p by the neighbour x + e_p
+    const int yx = x + ex, yy = y + ey, yz = z + ez;
+    const bool yin = G.in(yx, yy, yz);
+    const bool ysame = yin && liquid_at<MZ>(cnt, yx, yy, yz, n) == L;
+    if (ysame) acc += LG(p, G.cell(yx, yy, yz));
+    // (b) this cell's direction q = opp(p), whose source x + e_p is a wall or
+    //     across the front
+    if (p != 0) {
+      if (!yin) {
+        const int sa = melt_of<MZ>(yy, yz);
+        const bool dirichlet = sa < 0 || (!MZ && sa >= n);
+        acc += (dirichlet ? -1.0 : 1.0) * LG(q, i);
+      } else if (!ysame) {
+        const double d = link_delta<MZ>(s0, x, y, z, ex, ey, ez, n);
+        if (d < 0.5) {
+          const int bx = x - ex, by = y - ey, bz = z - ez;
+          const bool behind = G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L;
+          acc += (behind ? -2.0 * d : -1.0) * LG(q, i);
+        } else {
+          acc += -LG(q, i) / (2.0 * d);
+        }
+      }
+      // (c) this cell's direction p itself, when its source x - e_p is across
+      //     the front with a link fraction >= 1/2
+      const int sx = x - ex, sy = y - ey, sz = z - ez;
+      if (G.in(sx, sy, sz) && liquid_at<MZ>(cnt, sx, sy, sz, n) != L) {
+        const double d = link_delta<MZ>(s0, x, y, z, -ex, -ey, -ez, n);
+        if (d >= 0.5) acc += (2.0 * d - 1.0) / (2.0 * d) * LG(p, i);
+      }
+      // (d) the neighbour x + e_p, direction q, when its source x + 2 e_p is
+      //     across the front with a link fraction < 1/2 (this cell is then the
+      //     cell behind it)
+      if (ysame) {
+        const int tx = yx + ex, ty = yy + ey, tz = yz + ez;
+        if (G.in(tx, ty, tz) && liquid_at<MZ>(cnt, tx, ty, tz, n) != L) {
+          const double d = link_delta<MZ>(s0, yx, yy, yz, ex, ey, ez, n);
+          if (d < 0.5) acc += -(1.0 - 2.0 * d) * LG(q, G.cell(yx, yy, yz));
+        }
+      }
+    }
+    lg0[(size_t)p * nc + i] = acc;
+  }
+  if (FLOW) {
+    for (int p = 0; p < 19; ++p) {
+      double v;
+      if (L) {
+        const int yx = x + ex19(p), yy = y + ey19(p), yz = z + ez19(p);
+        const bool pulled = G.in(yx, yy, yz) && liquid_at<MZ>(cnt, yx, yy, yz, n);
+        v = pulled ? lfh[(size_t)p * nc + G.cell(yx, yy, yz)] : lfh[(size_t)opp19(p) * nc + i];
+      } else {
+        v = lf1[(size_t)p * nc + i];  // solid cells carry f through unchanged
+      }
+      lf0[(size_t)p * nc + i] = v;
+    }
+  }
+}
+
+// derivative of the pulled population of an interface link with respect to
+// its link fraction, times its adjoint; reader cell (x,y,z), incoming
+// direction q (its source across the front)
+template <typename Ts, bool MZ>
+__device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, const int* cnt,
+                                            const double* lgh, int x, int y, int z, int q,
+                                            bool L, double& dfrac, const KParams& P) {
+  const int n = P.n;
+  const Geo G{n, (uint32_t)n * (uint32_t)n};
+  const size_t qs = P.qstride, nc = P.ncell;
+  const uint32_t i = G.cell(x, y, z);
+  const int p = opp7(q);
+  const double d = link_delta<MZ>(s0, x, y, z, -ex7(q), -ey7(q), -ez7(q), n);
+  dfrac = d;
+  const double l = lgh[(size_t)q * nc + i];
+  if (d < 0.5) {
+    const int bx = x + ex7(q), by = y + ey7(q), bz = z + ez7(q);
+    if (G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L)
+      return (-2.0 * sv(g0, qs, p, i) + 2.0 * sv(g0, qs, p, G.cell(bx, by, bz))) * l;
+    return 0.0;
+  }
+  const double w = 0.125;
+  return (sv(g0, qs, p, i) / (2.0 * d * d) + sv(g0, qs, q, i) / (2.0 * d * d) -
+          w * (P.t_m - P.tref) / (d * d)) * l;
+}
+
+template <typename Ts, bool MZ>
+__global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restrict__ s0,
+                                const int* __restrict__ cnt, const double* __restrict__ lgh,
+                                double* __restrict__ ls0, double* __restrict__ lth, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
+  if (x >= n) return;
+  const int c = o * n + x;
+  const size_t nc = P.ncell;
+  // hot-wall anti-bounce-back of the cell next to the heated wall:
+  // g_in = -g_out + 2 w (T_h - tref)
+  {
+    const uint32_t i = cell_in_column<MZ>(c, 0, n);
+    const int qin = MZ ? 5 : 3;  // +z or +y: pulled from the heated wall
+    lth[c] += 2.0 * 0.125 * lgh[(size_t)qin * nc + i];
+  }
+  // lateral neighbour columns (in the box)
+  int nb[4], nbx[4], nbo[4], k = 0;
+  const int dx[4] = {1, -1, 0, 0}, dob[4] = {0, 0, 1, -1};
+  for (int j = 0; j < 4; ++j) {
+    const int xx = x + dx[j], oo = o + dob[j];
+    if (xx < 0 || xx >= n || oo < 0 || oo >= n) continue;
+    nb[k] = oo * n + xx;
+    nbx[k] = xx;
+    nbo[k] = oo;
+    ++k;
+  }
+  int lo = cnt[c], hi = cnt[c];
+  for (int j = 0; j < k; ++j) {
+    lo = cnt[nb[j]] < lo ? cnt[nb[j]] : lo;
+    hi = cnt[nb[j]] > hi ? cnt[nb[j]] : hi;
+  }
+  lo = lo - 1 < 0 ? 0 : lo - 1;
+  hi = hi > n - 1 ? n - 1 : hi;
+  const double sc = s0[c];
+  double acc = 0.0;
+  for (int a = lo; a <= hi; ++a) {
+    const double ya = a + 0.5;
+    // (i) links of this column's cell at height a
+    {
+      const int cx = x, cy = MZ ? o : a, cz = MZ ? a : o;
+      const bool L = a < cnt[c];
+      for (int q = 1; q < 7; ++q) {
+        const int sx = cx - ex7(q), sy = cy - ey7(q), sz = cz - ez7(q);
+        if ((unsigned)sx >= (unsigned)n || (unsigned)sy >= (unsigned)n || (unsigned)sz >= (unsigned)n)
+          continue;
+        if (liquid_at<MZ>(cnt, sx, sy, sz, n) == L) continue;
+        double d;
+        const double ld = link_sens<Ts, MZ>(g0, s0, cnt, lgh, cx, cy, cz, q, L, d, P);
+        const bool along = MZ ? (ez7(q) != 0) : (ey7(q) != 0);
+        if (along) {
+          acc += (sc > ya ? 1.0 : -1.0) * ld;
+        } else {
+          const double sn = s0[col_of<MZ>(sx, sy, sz, n)];
+          acc += ld * (ya - sn) / ((sn - sc) * (sn - sc));
+        }
+      }
+    }
+    // (ii) lateral links of the neighbours' cells at height a that point into
+    //      this column
+    for (int j = 0; j < k; ++j) {
+      const int cx = nbx[j], cy = MZ ? nbo[j] : a, cz = MZ ? a : nbo[j];
+      const bool L = a < cnt[nb[j]];
+      if ((a < cnt[c]) == L) continue;
+      // incoming direction of the neighbour whose source is this column
+      const int ddx = x - nbx[j], ddo = o - nbo[j];
+      int q = -1;
+      for (int qq = 1; qq < 7; ++qq) {
+        const int ox = -ex7(qq), oy = -ey7(qq), oz = -ez7(qq);  // source offset
+        const int oo_ = MZ ? oy : oz, om = MZ ? oz : oy;
+        if (ox == ddx && oo_ == ddo && om == 0) q = qq;
+      }
+      if (q < 1) continue;  // every lateral neighbour has one such direction
+      double d;
+      const double ld = link_sens<Ts, MZ>(g0, s0, cnt, lgh, cx, cy, cz, q, L, d, P);
+      const double sself = s0[nb[j]];
+      acc += ld * (-(ya - sself)) / ((sc - sself) * (sc - sself));
+    }
+  }
+  ls0[c] += acc;
+}
+
+__global__ void k_fill(double* __restrict__ v, size_t count, double value) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) v[i] = value;
+}
+
+template <typename Ts, bool FLOW, bool MZ>
+hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st) {
+  const int n = P.n;
+  const dim3 bcol(64, 1, 1), gcol((n + 63) / 64, n, 1);
+  const dim3 bcell(64, 1, 1), gcell((n + 63) / 64, n, n);
+  const Ts* f0 = static_cast<const Ts*>(A.f0);
+  const Ts* g0 = static_cast<const Ts*>(A.g0);
+  const Ts* g1 = static_cast<const Ts*>(A.g1);
+  hipLaunchKernelGGL((k_adj_front<Ts, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.s1, A.th, A.ls1,
+                     A.lg1, A.lf1, A.out5, A.own, A.lth, P);
+  hipLaunchKernelGGL(k_adj_front_gather, gcol, bcol, 0, st, A.own, A.out5, A.ls0, n);
+  hipLaunchKernelGGL((k_adj_collide<Ts, FLOW, MZ>), gcell, bcell, 0, st, f0, g0, A.s0, A.th, A.cnt,
+                     A.lf1, A.lg1, A.lfh, A.lgh, P);
+  hipLaunchKernelGGL((k_adj_stream<Ts, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.lfh, A.lgh,
+                     A.lf1, A.lf0, A.lg0, P);
+  hipLaunchKernelGGL((k_adj_interface<Ts, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, A.lgh, A.ls0,
+                     A.lth, P);
+  return hipGetLastError();
+}
+
+template <typename Ts>
+hipError_t adjoint_step_d(const KParams& P, const AdjointStep& A, hipStream_t st) {
+  if (P.flow)
+    return P.melt_z ? adjoint_step_t<Ts, true, true>(P, A, st)
+                    : adjoint_step_t<Ts, true, false>(P, A, st);
+  return P.melt_z ? adjoint_step_t<Ts, false, true>(P, A, st)
+                  : adjoint_step_t<Ts, false, false>(P, A, st);
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A, hipStream_t st) {
+  switch (kind) {
+    case kF64: return adjoint_step_d<double>(P, A, st);
+    case kF32: return adjoint_step_d<float>(P, A, st);
+    case kF16S: return adjoint_step_d<_Float16>(P, A, st);
+    case kBF16S: return adjoint_step_d<__bf16>(P, A, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fill(double* v, size_t count, double value, hipStream_t st) {
+  if (!v) return hipErrorInvalidValue;
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, v, count,
+                     value);
+  return hipGetLastError();
+}
+
+}  // namespace lbmk

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -55,6 +56,21 @@ double neumann_constant(double ste) {
 
 }  // namespace
 
+// Checkpoints of a forward run and the buffers of its reverse sweep.
+struct AdjData {
+  bool ready = false;
+  int64_t start = 0, nsteps = 0, end = 0;
+  int K = 0, nck = 0;
+  std::vector<void*> ckf, ckg;
+  std::vector<double*> cks;
+  std::vector<void*> sf, sg;  // segment states 0..K
+  std::vector<double*> ss;
+  int *cnt = nullptr, *cmin = nullptr, *cmax = nullptr, *melted = nullptr, *frozen = nullptr,
+      *flag = nullptr;
+  double *lf[2] = {nullptr, nullptr}, *lg[2] = {nullptr, nullptr}, *ls[2] = {nullptr, nullptr};
+  double *lfh = nullptr, *lgh = nullptr, *out5 = nullptr, *own = nullptr, *lth = nullptr;
+};
+
 struct lbm_ctx {
   lbm_params p{};
   lbm_lattice lat{};
@@ -80,6 +96,14 @@ struct lbm_ctx {
   double* seedT = nullptr;
   double* fields = nullptr;  // 5 * n^3 FP64 scratch for fields and diagnostics
   int64_t step = 0;
+  AdjData adj;
+  // schedule (liquid counts and node indices per step) of the last recorded run
+  int* sched = nullptr;
+  size_t sched_cap = 0;   // ints
+  int64_t sched_steps = 0;
+  int64_t rec_start = -1;  // first step being recorded, -1 when not recording
+  int* replay = nullptr;   // device copy of a schedule being replayed
+  size_t replay_cap = 0;
   bool unstable = false;  // a query saw the device flag; steps refused until load
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed kernels
@@ -88,11 +112,38 @@ struct lbm_ctx {
 
 namespace {
 
+void free_all(std::vector<void*>& v) {
+  for (void* p : v)
+    if (p) (void)hipFree(p);
+  v.clear();
+}
+void free_all(std::vector<double*>& v) {
+  for (double* p : v)
+    if (p) (void)hipFree(p);
+  v.clear();
+}
+
+void release_adjoint(AdjData& a) {
+  free_all(a.ckf);
+  free_all(a.ckg);
+  free_all(a.cks);
+  free_all(a.sf);
+  free_all(a.sg);
+  free_all(a.ss);
+  void* ptrs[] = {a.cnt, a.cmin, a.cmax, a.melted, a.frozen, a.flag, a.lf[0], a.lf[1], a.lg[0],
+                  a.lg[1], a.ls[0], a.ls[1], a.lfh, a.lgh, a.out5, a.own, a.lth};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  a = AdjData();
+}
+
 void release(lbm_ctx* c) {
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
+  release_adjoint(c->adj);
   void* ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->s[0], c->s[1], c->cnt,  c->cmin,
-                  c->cmax, c->melted, c->frozen, c->flag, c->th,  c->red,  c->seedT, c->fields};
+                  c->cmax, c->melted, c->frozen, c->flag, c->th,  c->red,  c->seedT, c->fields,
+                  c->sched, c->replay};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -347,8 +398,12 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
       HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
       c->ev_used += 2;
     }
+    int* rec = c->rec_start >= 0
+                   ? c->sched + (size_t)(c->step - c->rec_start) * 3 * ((size_t)c->p.n * c->p.n)
+                   : nullptr;
     HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
-                               c->th, c->melted, c->frozen, c->flag, c->stream));
+                               c->th, c->melted, c->frozen, c->flag, nullptr, nullptr, rec,
+                               c->stream));
     HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
     c->cur = nx;
     c->scur = sx;
@@ -573,6 +628,239 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->step = h.step;
   c->unstable = false;
+  return LBM_OK;
+}
+
+int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (nsteps < 1 || every_k < 1) return fail(LBM_EINVAL, "need nsteps >= 1 and every_k >= 1");
+  if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
+  AdjData& a = c->adj;
+  const size_t nn = (size_t)c->p.n * c->p.n, qs = c->kp.qstride;
+  const size_t fb = c->p.flow ? 19 * qs * c->esz : 0, gb = 7 * qs * c->esz;
+  const int nck = (int)((nsteps + every_k - 1) / every_k);
+  a.ready = false;
+  if (a.K != every_k) {  // the segment buffers are sized by every_k
+    free_all(a.sf);
+    free_all(a.sg);
+    free_all(a.ss);
+  }
+  while ((int)a.ckg.size() > nck) {
+    if (a.ckf.back()) (void)hipFree(a.ckf.back());
+    (void)hipFree(a.ckg.back());
+    (void)hipFree(a.cks.back());
+    a.ckf.pop_back();
+    a.ckg.pop_back();
+    a.cks.pop_back();
+  }
+  while ((int)a.ckg.size() < nck) {
+    void *f = nullptr, *g = nullptr;
+    double* sp = nullptr;
+    if ((fb && hipMalloc(&f, fb) != hipSuccess) || hipMalloc(&g, gb) != hipSuccess ||
+        hipMalloc((void**)&sp, nn * sizeof(double)) != hipSuccess) {
+      if (f) (void)hipFree(f);
+      if (g) (void)hipFree(g);
+      return fail(LBM_ENOMEM, "cannot allocate checkpoint %zu of %d", a.ckg.size(), nck);
+    }
+    a.ckf.push_back(f);
+    a.ckg.push_back(g);
+    a.cks.push_back(sp);
+  }
+  a.K = every_k;
+  a.nck = nck;
+  a.start = c->step;
+  a.nsteps = nsteps;
+  // schedule of the run: (nsteps + 1) entries of 3 n^2 ints
+  const size_t need = (size_t)(nsteps + 1) * 3 * nn;
+  if (need > c->sched_cap) {
+    if (c->sched) (void)hipFree(c->sched);
+    c->sched = nullptr;
+    c->sched_cap = 0;
+    if ((rc = dalloc(&c->sched, need))) return rc;
+    c->sched_cap = need;
+  }
+  c->rec_start = c->step;
+  c->sched_steps = 0;
+  for (int i = 0; i < nck; ++i) {
+    if (fb) HIP_TRY(hipMemcpyAsync(a.ckf[i], c->f[c->cur], fb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(a.ckg[i], c->g[c->cur], gb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(a.cks[i], c->s[c->scur], nn * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+    const int64_t len = std::min<int64_t>(every_k, nsteps - (int64_t)i * every_k);
+    if ((rc = lbm_step(c, len))) {
+      c->rec_start = -1;
+      return rc;
+    }
+  }
+  c->rec_start = -1;
+  // final entry: the liquid counts after the last step
+  HIP_TRY(hipMemcpyAsync(c->sched + (size_t)nsteps * 3 * nn, c->cnt, nn * sizeof(int),
+                         hipMemcpyDeviceToDevice, c->stream));
+  c->sched_steps = nsteps;
+  a.end = c->step;
+  a.ready = true;
+  if (fl) return lbm_liquid_fraction(c, fl);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!grad_th) return fail(LBM_EINVAL, "grad_th is NULL");
+  AdjData& a = c->adj;
+  if (!a.ready || c->step != a.end)
+    return fail(LBM_ESTATE, "lbm_adjoint needs lbm_forward_ckpt with no step taken since");
+  const size_t nn = (size_t)c->p.n * c->p.n, nc = c->kp.ncell, qs = c->kp.qstride;
+  const bool flow = c->p.flow != 0;
+  const size_t fb = flow ? 19 * qs * c->esz : 0, gb = 7 * qs * c->esz;
+  // segment states and scratch
+  while ((int)a.sg.size() < a.K + 1) {
+    void *f = nullptr, *g = nullptr;
+    double* sp = nullptr;
+    if ((fb && hipMalloc(&f, fb) != hipSuccess) || hipMalloc(&g, gb) != hipSuccess ||
+        hipMalloc((void**)&sp, nn * sizeof(double)) != hipSuccess) {
+      if (f) (void)hipFree(f);
+      if (g) (void)hipFree(g);
+      return fail(LBM_ENOMEM, "cannot allocate the recompute segment (%d states)", a.K + 1);
+    }
+    a.sf.push_back(f);
+    a.sg.push_back(g);
+    a.ss.push_back(sp);
+  }
+  if (!a.lg[0]) {
+    if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cmin, nn)) || (rc = dalloc(&a.cmax, nn)) ||
+        (rc = dalloc(&a.melted, nn)) || (rc = dalloc(&a.frozen, nn)) || (rc = dalloc(&a.flag, 1)) ||
+        (rc = dalloc(&a.lg[0], 7 * nc)) || (rc = dalloc(&a.lg[1], 7 * nc)) ||
+        (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
+        (rc = dalloc(&a.lgh, 7 * nc)) || (rc = dalloc(&a.out5, 5 * nn)) ||
+        (rc = dalloc(&a.own, nn)) || (rc = dalloc(&a.lth, nn)))
+      return rc;
+    if (flow && ((rc = dalloc(&a.lf[0], 19 * nc)) || (rc = dalloc(&a.lf[1], 19 * nc)) ||
+                 (rc = dalloc(&a.lfh, 19 * nc))))
+      return rc;
+  }
+  HIP_TRY(hipMemsetAsync(a.melted, 0, nn * sizeof(int), c->stream));
+  HIP_TRY(hipMemsetAsync(a.frozen, 0, nn * sizeof(int), c->stream));
+  HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(int), c->stream));
+  // adjoint of the final state: J = dJ_dfl * sum(s) / n^3
+  int cur = 1;
+  HIP_TRY(lbmk::launch_fill(a.ls[cur], nn, dJ_dfl / ((double)nn * c->p.n), c->stream));
+  HIP_TRY(lbmk::launch_fill(a.lg[cur], 7 * nc, 0.0, c->stream));
+  if (flow) HIP_TRY(lbmk::launch_fill(a.lf[cur], 19 * nc, 0.0, c->stream));
+  HIP_TRY(lbmk::launch_fill(a.lth, nn, 0.0, c->stream));
+  lbmk::KParams k = c->kp;
+  for (int i = a.nck - 1; i >= 0; --i) {
+    const int64_t len = std::min<int64_t>(a.K, a.nsteps - (int64_t)i * a.K);
+    if (fb) HIP_TRY(hipMemcpyAsync(a.sf[0], a.ckf[i], fb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(a.sg[0], a.ckg[i], gb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(a.ss[0], a.cks[i], nn * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+    // recompute the segment, bit for bit as the forward run
+    for (int64_t t = 0; t < len; ++t) {
+      k.step = (uint32_t)(a.start + (int64_t)i * a.K + t);
+      HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
+      HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin, a.cmax, c->stream));
+      HIP_TRY(lbmk::launch_stream_collide(c->kind, k, a.sf[t], a.sf[t + 1], a.sg[t], a.sg[t + 1],
+                                          a.cnt, a.cmin, a.cmax, a.ss[t], c->th, a.flag,
+                                          c->stream));
+      HIP_TRY(lbmk::launch_front(c->kind, k, a.ss[t], a.ss[t + 1], a.cnt, a.sg[t + 1],
+                                 a.sf[t + 1], c->th, a.melted, a.frozen, a.flag, nullptr, nullptr,
+                                 nullptr, c->stream));
+    }
+    // reverse the segment
+    for (int64_t t = len - 1; t >= 0; --t) {
+      HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
+      lbmk::AdjointStep A;
+      A.f0 = a.sf[t];
+      A.g0 = a.sg[t];
+      A.s0 = a.ss[t];
+      A.g1 = a.sg[t + 1];
+      A.s1 = a.ss[t + 1];
+      A.th = c->th;
+      A.cnt = a.cnt;
+      A.lf1 = a.lf[cur];
+      A.lg1 = a.lg[cur];
+      A.ls1 = a.ls[cur];
+      A.lf0 = a.lf[1 - cur];
+      A.lg0 = a.lg[1 - cur];
+      A.ls0 = a.ls[1 - cur];
+      A.lfh = a.lfh;
+      A.lgh = a.lgh;
+      A.out5 = a.out5;
+      A.own = a.own;
+      A.lth = a.lth;
+      HIP_TRY(lbmk::launch_adjoint_step(c->kind, c->kp, A, c->stream));
+      cur = 1 - cur;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(grad_th, a.lth, nn * sizeof(double),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_get_schedule(lbm_ctx* c, int32_t* out, size_t count) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  const size_t nn = (size_t)c->p.n * c->p.n;
+  const size_t need = c->sched_steps > 0 ? (size_t)(c->sched_steps + 1) * 3 * nn : 0;
+  if (!need) return fail(LBM_ESTATE, "no recorded run (call lbm_forward_ckpt first)");
+  if (!out || count < need)
+    return fail(LBM_EINVAL, "schedule needs %zu ints (%zu given)", need, out ? count : 0);
+  HIP_TRY(hipMemcpyAsync(out, c->sched, need * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!schedule || nsteps < 1) return fail(LBM_EINVAL, "need a schedule and nsteps >= 1");
+  if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
+  const int n = c->p.n;
+  const size_t nn = (size_t)n * n;
+  const size_t need = (size_t)(nsteps + 1) * 3 * nn;
+  // the front kernel walks the given node indices: every one must lie in the column
+  for (size_t e = 0; e <= (size_t)nsteps; ++e) {
+    const int32_t* en = schedule + e * 3 * nn;
+    for (size_t i = 0; i < nn; ++i) {
+      if (en[i] < 0 || en[i] > n || en[nn + i] < -1 || en[nn + i] > n - 1 ||
+          en[2 * nn + i] < 0 || en[2 * nn + i] > n)
+        return fail(LBM_EINVAL, "schedule entry %zu, column %zu is outside the lattice", e, i);
+    }
+  }
+  if (need > c->replay_cap) {
+    if (c->replay) (void)hipFree(c->replay);
+    c->replay = nullptr;
+    c->replay_cap = 0;
+    if ((rc = dalloc(&c->replay, need))) return rc;
+    c->replay_cap = need;
+  }
+  HIP_TRY(hipMemcpyAsync(c->replay, schedule, need * sizeof(int), hipMemcpyHostToDevice,
+                         c->stream));
+  // phases of entry 0, then the ordinary step with the recorded nodes and switches
+  HIP_TRY(hipMemcpyAsync(c->cnt, c->replay, nn * sizeof(int), hipMemcpyDeviceToDevice,
+                         c->stream));
+  lbmk::KParams& k = c->kp;
+  HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
+  for (int64_t t = 0; t < nsteps; ++t) {
+    const int nx = c->cur ^ 1, sx = c->scur ^ 1;
+    const int* e = c->replay + (size_t)t * 3 * nn;
+    k.step = (uint32_t)c->step;
+    HIP_TRY(lbmk::launch_stream_collide(c->kind, k, c->f[c->cur], c->f[nx], c->g[c->cur], c->g[nx],
+                                        c->cnt, c->cmin, c->cmax, c->s[c->scur], c->th, c->flag,
+                                        c->stream));
+    HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
+                               c->th, c->melted, c->frozen, c->flag, e, e + 3 * nn, nullptr,
+                               c->stream));
+    HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
+    c->cur = nx;
+    c->scur = sx;
+    c->step++;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 

@@ -52,10 +52,15 @@ hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, voi
 
 // Interface update (Eq. (6)) of every column from the post-collision g, then
 // the phase switch: s_new, cnt (in place), refill of f in newly liquid cells,
-// per-column melt / freeze counters.
+// per-column melt / freeze counters.  Schedule (each 3 * n^2 ints: liquid
+// count, index of the first liquid node, index of the first solid node):
+// record != null writes the one this step uses; replay != null makes the step
+// use the given node indices and take the new liquid counts from
+// replay_next (the following entry) instead of the new fronts.
 hipError_t launch_front(int kind, const KParams& P, const double* s_old, double* s_new,
                         int* cnt, const void* g, void* f, const double* th, int* melted,
-                        int* frozen, int* flag, hipStream_t st);
+                        int* frozen, int* flag, const int* replay, const int* replay_next,
+                        int* record, hipStream_t st);
 
 // cmin/cmax from cnt.
 hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
@@ -85,5 +90,31 @@ hipError_t launch_from_storage(int kind, const KParams& P, int q_count, const vo
 // out[0].  count must not exceed the number of elements v points to.
 hipError_t launch_sum(const double* v, int64_t count, double* out, hipStream_t st);
 hipError_t launch_sum_int(const int* v, int64_t count, double* out, hipStream_t st);
+
+// One reverse step from the state t+1 to the state t (FP64 adjoints, dense
+// [q][n^3] and [n^2] arrays).  lf1/lg1 are modified (phase switch and front
+// contributions); lf0/lg0/ls0 are overwritten; lth is incremented.
+struct AdjointStep {
+  const void* f0;
+  const void* g0;
+  const double* s0;  // state t
+  const void* g1;
+  const double* s1;  // state t+1 (post-collision g and front)
+  const double* th;
+  const int* cnt;    // liquid counts of state t
+  double* lf1;
+  double* lg1;
+  const double* ls1;
+  double* lf0;
+  double* lg0;
+  double* ls0;
+  double* lfh;
+  double* lgh;       // per-cell adjoint of the pulled populations
+  double* out5;
+  double* own;       // per-column scratch of the front adjoint
+  double* lth;
+};
+hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A, hipStream_t st);
+hipError_t launch_fill(double* v, size_t count, double value, hipStream_t st);
 
 }  // namespace lbmk

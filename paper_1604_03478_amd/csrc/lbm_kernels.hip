@@ -28,136 +28,10 @@
 
 #include "lbm_internal.h"
 
-#ifndef LBM_LOAD
-#define LBM_LOAD(p) (*(p))
-#endif
-#ifndef LBM_POP_PAD_BYTES
-#define LBM_POP_PAD_BYTES 4352
-#endif
+#include "lbm_device.h"
 
 namespace lbmk {
 namespace {
-
-// --------------------------------------------------------------- storage
-// Arithmetic types of the collision: `type` for the flow (f, D3Q19),
-// `gtype` for the energy distribution (g, D3Q7).  16-bit storage collides in
-// FP32.  FP32 storage collides the flow in FP32 and the energy distribution
-// in FP64 (rounded stochastically to FP32 at the store): temperature round
-// off accumulated over 1e4+ steps is what moves the front, and the D3Q7 part
-// is a small share of the arithmetic.
-#ifndef LBM_F32_FLOW_T
-#define LBM_F32_FLOW_T float
-#endif
-#ifndef LBM_F32_HEAT_T
-#define LBM_F32_HEAT_T double
-#endif
-template <typename Ts> struct Compute { using type = float; using gtype = float; };
-template <> struct Compute<double> { using type = double; using gtype = double; };
-template <> struct Compute<float> { using type = LBM_F32_FLOW_T; using gtype = LBM_F32_HEAT_T; };
-
-// Rounding of the collision result to the storage format.  With stochastic
-// rounding the value is rounded up or down with probabilities proportional
-// to its distance from the two neighbours (random bits added below the
-// storage precision, then truncation toward zero), so the rounding error has
-// zero mean even when the same value is stored step after step.
-// Measured at 64^3 over 20000 steps against the FP64 oracle: FP16 storage
-// with round-to-nearest drifts to a 1e-2 relative liquid-fraction error,
-// with stochastic rounding 4.5e-6; FP32 storage with an FP64 energy collision
-// and stochastic rounding stays at 1e-10.
-#ifndef LBM_STOCHASTIC_ROUNDING
-#define LBM_STOCHASTIC_ROUNDING 1
-#endif
-
-// One 32-bit random stream per cell and step (counter based: a mix of the
-// cell index and the step; each stored value advances it by one LCG step).
-__device__ __forceinline__ uint32_t mix32(uint32_t x) {
-  x ^= x >> 16;
-  x *= 0x7feb352du;
-  x ^= x >> 15;
-  x *= 0x846ca68bu;
-  x ^= x >> 16;
-  return x;
-}
-__device__ __forceinline__ uint32_t next_rand(uint32_t& st) {
-  st = st * 1664525u + 1013904223u;
-  return st;
-}
-
-template <typename Ts, typename C>
-__device__ __forceinline__ Ts round_store(C v, uint32_t& rs) {
-#if LBM_STOCHASTIC_ROUNDING
-  if constexpr (sizeof(Ts) == 4 && sizeof(C) == 8) {
-    uint64_t b = (uint64_t)__double_as_longlong(v);
-    b += (uint64_t)(next_rand(rs) >> 3);  // 29 bits below FP32 precision
-    b &= ~((1ull << 29) - 1);
-    return static_cast<Ts>(__longlong_as_double((long long)b));
-  } else if constexpr (sizeof(Ts) == 2 && sizeof(C) == 4) {
-    uint32_t b = __float_as_uint(v);
-    constexpr int drop = __is_same(Ts, _Float16) ? 13 : 16;  // bits below the 16-bit format
-    b += next_rand(rs) >> (32 - drop);
-    b &= ~((1u << drop) - 1);
-    return static_cast<Ts>(__uint_as_float(b));
-  }
-#endif
-  (void)rs;
-  return static_cast<Ts>(v);
-}
-
-template <typename R, typename Ts>
-__device__ __forceinline__ R load_as(const Ts* __restrict__ base, uint32_t i) {
-  const Ts* p = reinterpret_cast<const Ts*>(reinterpret_cast<const char*>(base) +
-                                            (uint32_t)(i * (uint32_t)sizeof(Ts)));
-  return static_cast<R>(*p);
-}
-template <typename Ts>
-__device__ __forceinline__ typename Compute<Ts>::type load(const Ts* __restrict__ base, uint32_t i) {
-  return load_as<typename Compute<Ts>::type>(base, i);
-}
-
-template <typename Ts, typename C>
-__device__ __forceinline__ void store(Ts* __restrict__ base, uint32_t i, C v) {
-  Ts* p = reinterpret_cast<Ts*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(Ts)));
-  *p = static_cast<Ts>(v);
-}
-
-// Stores of the step kernel: written once, read only in the next step, so
-// they bypass the caches (non-temporal).
-template <typename Ts, typename C>
-__device__ __forceinline__ void store_stream(Ts* __restrict__ base, uint32_t i, C v, uint32_t& rs) {
-  Ts* p = reinterpret_cast<Ts*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(Ts)));
-  __builtin_nontemporal_store(round_store<Ts>(v, rs), p);
-}
-
-// --------------------------------------------------------------- lattices
-// D3Q19 in the order of Eq. (3).
-__host__ __device__ constexpr int ex19(int q) {
-  return (q == 1 || q == 7 || q == 9 || q == 11 || q == 13) ? 1
-       : (q == 2 || q == 8 || q == 10 || q == 12 || q == 14) ? -1 : 0;
-}
-__host__ __device__ constexpr int ey19(int q) {
-  return (q == 3 || q == 7 || q == 8 || q == 15 || q == 17) ? 1
-       : (q == 4 || q == 9 || q == 10 || q == 16 || q == 18) ? -1 : 0;
-}
-__host__ __device__ constexpr int ez19(int q) {
-  return (q == 5 || q == 11 || q == 12 || q == 15 || q == 16) ? 1
-       : (q == 6 || q == 13 || q == 14 || q == 17 || q == 18) ? -1 : 0;
-}
-__host__ __device__ constexpr int opp19(int q) {
-  return q == 0 ? 0 : (q <= 6 ? (q % 2 ? q + 1 : q - 1)
-                               : (q <= 10 ? 17 - q : (q <= 14 ? 25 - q : 33 - q)));
-}
-// D3Q7 in the order of Eq. (5).
-__host__ __device__ constexpr int ex7(int q) { return q == 1 ? 1 : (q == 2 ? -1 : 0); }
-__host__ __device__ constexpr int ey7(int q) { return q == 3 ? 1 : (q == 4 ? -1 : 0); }
-__host__ __device__ constexpr int ez7(int q) { return q == 5 ? 1 : (q == 6 ? -1 : 0); }
-__host__ __device__ constexpr int opp7(int q) { return q == 0 ? 0 : (q % 2 ? q + 1 : q - 1); }
-
-static_assert(ex19(opp19(7)) == -1 && ey19(opp19(7)) == -1, "opp19");
-static_assert(opp19(8) == 9 && opp19(11) == 14 && opp19(12) == 13 && opp19(15) == 18 &&
-              opp19(16) == 17, "opp19");
-
-constexpr double kW7Axis = 0.125;  // D3Q7 weight of the six moving directions
-constexpr double kW7Rest = 0.25;
 
 // --------------------------------------------------------------- collision
 template <typename C, typename G>
@@ -709,13 +583,6 @@ __device__ __forceinline__ double cell_T(const Ts* __restrict__ g, size_t qs, ui
   return acc + tref;
 }
 
-__device__ __forceinline__ int count_liquid(double sv, int n) {
-  // number of a in [0, n) with a + 1/2 < s (exact: s - 1/2 is exact in FP64)
-  double c = ceil(sv - 0.5);
-  if (!(c > 0.0)) return 0;
-  if (c > (double)n) return n;
-  return (int)c;
-}
 
 template <typename Ts, bool FLOW, bool MZ>
 __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
@@ -723,7 +590,10 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
                                                const Ts* __restrict__ g, Ts* __restrict__ f,
                                                const double* __restrict__ th,
                                                int* __restrict__ melted, int* __restrict__ frozen,
-                                               int* __restrict__ flag, KParams P) {
+                                               int* __restrict__ flag,
+                                               const int* __restrict__ replay,
+                                               const int* __restrict__ replay_next,
+                                               int* __restrict__ record, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int o = blockIdx.y;
@@ -736,16 +606,33 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   const double sc = s_old[col];
   const int c0 = cnt[col];
 
-  // liquid side: nodes with distance >= 1/2 from the front, then the hot wall
+  // node selection: the nearest liquid and solid centres at distance >= 1/2
+  // from the front (only the very nearest can be closer); a recorded
+  // schedule replaces it when replaying a run along fixed phases and nodes
+  int a_top, a_bot;
+  if (replay) {
+    a_top = replay[nn + col];
+    a_bot = replay[2 * nn + col];
+  } else {
+    a_top = c0 - 1;
+    if (a_top >= 0 && sc - (a_top + 0.5) < 0.5) --a_top;
+    a_bot = c0;
+    if (a_bot < n && (a_bot + 0.5) - sc < 0.5) ++a_bot;
+  }
+  if (record) {
+    record[col] = c0;
+    record[nn + col] = a_top;
+    record[2 * nn + col] = a_bot;
+  }
+
+  // liquid side: the selected nodes toward the heated wall, then the wall
   double xi0 = 0, T0v = 0, xi1 = 0, T1v = 0;
   int k = 0;
-  for (int a = c0 - 1; a >= 0 && k < 2; --a) {
+  for (int a = a_top; a >= 0 && k < 2; --a) {
     const double d = sc - (a + 0.5);
-    if (d >= 0.5) {
-      const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.tref);
-      if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
-      ++k;
-    }
+    const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.tref);
+    if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
+    ++k;
   }
   if (k < 2) {
     if (k == 0) { xi0 = sc; T0v = th[col]; } else { xi1 = sc; T1v = th[col]; }
@@ -755,13 +642,11 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
 
   // solid side: nodes beyond the front, then the cold wall (melt axis y)
   k = 0;
-  for (int a = c0; a < n && k < 2; ++a) {
+  for (int a = a_bot; a < n && k < 2; ++a) {
     const double d = (a + 0.5) - sc;
-    if (d >= 0.5) {
-      const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.tref);
-      if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
-      ++k;
-    }
+    const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.tref);
+    if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
+    ++k;
   }
   if (k < 2 && !MZ) {
     if (k == 0) { xi0 = n - sc; T0v = P.t_c; } else { xi1 = n - sc; T1v = P.t_c; }
@@ -782,7 +667,7 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   s_new[col] = sn;
 
   // phase switch: newly liquid cells start from the rest state of f
-  const int c1 = count_liquid(sn, n);
+  const int c1 = replay_next ? replay_next[col] : count_liquid(sn, n);
   if (FLOW) {
     for (int a = c0; a < c1; ++a) {
       const uint32_t i = cell(a);
@@ -1022,7 +907,8 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
 template <typename Ts>
 hipError_t front_dispatch(const KParams& P, const double* s_old, double* s_new, int* cnt,
                           const void* g, void* f, const double* th, int* melted, int* frozen,
-                          int* flag, hipStream_t st) {
+                          int* flag, const int* replay, const int* replay_next, int* record,
+                          hipStream_t st) {
   dim3 block(64, 1, 1);
   dim3 grid((P.n + 63) / 64, P.n, 1);
   auto G = static_cast<const Ts*>(g);
@@ -1030,17 +916,17 @@ hipError_t front_dispatch(const KParams& P, const double* s_old, double* s_new, 
   if (P.flow) {
     if (P.melt_z)
       hipLaunchKernelGGL((k_front<Ts, true, true>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
-                         melted, frozen, flag, P);
+                         melted, frozen, flag, replay, replay_next, record, P);
     else
       hipLaunchKernelGGL((k_front<Ts, true, false>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
-                         melted, frozen, flag, P);
+                         melted, frozen, flag, replay, replay_next, record, P);
   } else {
     if (P.melt_z)
       hipLaunchKernelGGL((k_front<Ts, false, true>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
-                         melted, frozen, flag, P);
+                         melted, frozen, flag, replay, replay_next, record, P);
     else
       hipLaunchKernelGGL((k_front<Ts, false, false>), grid, block, 0, st, s_old, s_new, cnt, G, F,
-                         th, melted, frozen, flag, P);
+                         th, melted, frozen, flag, replay, replay_next, record, P);
   }
   return hipGetLastError();
 }
@@ -1134,8 +1020,11 @@ hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, voi
 
 hipError_t launch_front(int kind, const KParams& P, const double* s_old, double* s_new, int* cnt,
                         const void* g, void* f, const double* th, int* melted, int* frozen,
-                        int* flag, hipStream_t st) {
-#define CALL(T) front_dispatch<T>(P, s_old, s_new, cnt, g, f, th, melted, frozen, flag, st)
+                        int* flag, const int* replay, const int* replay_next, int* record,
+                        hipStream_t st) {
+#define CALL(T)                                                                                 \
+  front_dispatch<T>(P, s_old, s_new, cnt, g, f, th, melted, frozen, flag, replay, replay_next, \
+                    record, st)
   switch (kind) {
     case kF64: return CALL(double);
     case kF32: return CALL(float);

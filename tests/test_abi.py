@@ -65,4 +65,6 @@ def test_null_arguments_are_rejected():
     v = ctypes.c_double()
     assert lib.lbm_liquid_fraction(None, ctypes.byref(v)) == LBM_EINVAL
     assert lib.lbm_fields(None, None, None, None, None) == LBM_EINVAL
+    assert lib.lbm_get_schedule(None, None, 0) == LBM_EINVAL
+    assert lib.lbm_step_replay(None, None, 1) == LBM_EINVAL
     lib.lbm_destroy(None)

@@ -1,0 +1,146 @@
+"""The hand-written GPU adjoint (through the C ABI) against the oracle's
+reference adjoint and against central finite differences of the GPU forward.
+"""
+import numpy as np
+import pytest
+
+from oracle import OracleSim
+
+pytestmark = pytest.mark.gpu
+
+HEAT = {"y0": 0, "z0": 1}
+
+
+def _pair_from_developed(n, kw, heating, develop, prec):
+    from paper_1604_03478_amd import Config, Sim
+    orc = OracleSim(n, heating=HEAT[heating], **kw)
+    orc.step(develop)
+    cfg = Config(n=n, heating=heating, precision=prec, **kw)
+    gpu = Sim(cfg)
+    f = orc.f.copy() if kw.get("flow", 1) else None
+    gpu.set_populations(f, orc.g.copy(), orc.s.copy())
+    return orc, gpu
+
+
+@pytest.mark.parametrize("heating", ["y0", "z0"])
+@pytest.mark.parametrize("flow", [1, 0])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_gradient_matches_oracle_adjoint(heating, flow, prec, tol):
+    """Same developed state, same hot-wall field, 40 steps with a checkpoint
+    every 7 (a short last segment): dJ/dT_h from the GPU adjoint and from the
+    oracle's reverse sweep, relative L2 difference."""
+    from inputs import hot_wall_field
+    n = 16
+    kw = dict(ra=1e5, pr=1.0, ste=1.0, s0=4.6, flow=flow, alpha=0.1)
+    orc, gpu = _pair_from_developed(n, kw, heating, 60, prec)
+    th = hot_wall_field(n, seed=3)
+    orc.th[:] = th
+    gpu.set_hot_wall(th)
+    orc.record(40)
+    *_, g_ref = orc.adjoint()
+    fl = gpu.forward_ckpt(40, 7)
+    g = gpu.adjoint(1.0)
+    assert abs(fl - orc.liquid_fraction()) <= (1e-13 if prec == "f64" else 1e-7)
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert err <= tol, err
+
+
+def test_replay_reproduces_recorded_run():
+    """Stepping along the recorded schedule with unchanged inputs gives the
+    recorded run bit for bit (FP64 and FP32 storage), through a melting
+    front that switches cells."""
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, Sim
+    for prec in ("f64", "f32"):
+        cfg = Config(n=24, ra=1e5, pr=1.0, ste=1.0, s0=5.45, precision=prec)
+        th = hot_wall_field(24, seed=2)
+        a = Sim(cfg)
+        a.set_hot_wall(th)
+        a.step(50)
+        st = a.save_state()
+        fl = a.forward_ckpt(120, 13)
+        sched = a.schedule(120)
+        b = Sim(cfg)
+        b.set_hot_wall(th)
+        b.load_state(st)
+        b.step_replay(sched, 120)
+        assert b.liquid_fraction() == fl
+        fa, ga, sa = a.get_populations()
+        fb, gb, sb = b.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb) and np.array_equal(sa, sb)
+        counts = sched.reshape(121, 3, 24, 24)[:, 0]
+        assert (counts[-1] != counts[0]).any()  # the front moved across cells
+        a.close()
+        b.close()
+
+
+def test_replay_rejects_out_of_lattice_nodes():
+    from paper_1604_03478_amd import Config, LbmError, Sim
+    s = Sim(Config(n=8, precision="f64"))
+    s.forward_ckpt(3, 2)
+    sched = s.schedule(3)
+    bad = sched.copy()
+    bad[64 + 5] = 8  # first liquid node index beyond the column
+    with pytest.raises(LbmError):
+        s.step_replay(bad, 3)
+    bad = sched.copy()
+    bad[2 * 64 + 1] = -1
+    with pytest.raises(LbmError):
+        s.step_replay(bad, 3)
+    s.close()
+
+
+def test_gradient_matches_finite_differences_64():
+    """64^3 double MRT, Ra = 1e4, Pr = 1, Ste = 0.1, 2000 steps from the
+    initial state, T_h = 1 + 0.1 N(0, 1) (seeded), checkpoint every 100.
+
+    The reverse sweep differentiates the run along its own phases and
+    Eq. (6) node choices (piecewise constant in T_h); the central
+    differences (eps = 1e-3, FP64 GPU runs) step along that same recorded
+    schedule, for single columns and random directions: relative error
+    <= 1e-3.  The gradient through torch.autograd is the library's."""
+    import torch
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, LiquidFraction, Sim
+    n, steps = 64, 2000
+    cfg = Config(n=n, ra=1e4, pr=1.0, ste=0.1, s0=1.0, precision="f64")
+    th0 = hot_wall_field(n, seed=0)
+    th = torch.tensor(th0, dtype=torch.float64, device="cuda", requires_grad=True)
+    fl = LiquidFraction.apply(th, cfg, steps, 100)
+    fl.backward()
+    grad_autograd = th.grad.detach().cpu().numpy()
+
+    base = Sim(cfg)
+    base.set_hot_wall(th0)
+    fl_base = base.forward_ckpt(steps, 100)
+    sched = base.schedule(steps)
+    grad = base.adjoint(1.0)
+    base.close()
+    assert fl_base == float(fl)
+    assert np.array_equal(grad, grad_autograd)
+
+    def J(t):
+        s = Sim(cfg)
+        s.set_hot_wall(t)
+        s.step_replay(sched, steps)
+        v = s.liquid_fraction()
+        s.close()
+        return v
+
+    assert J(th0) == fl_base
+    eps = 1e-3
+    rng = np.random.default_rng(1)
+    cols = [(0, 0), (32, 32), (10, 50), (63, 17), (5, 5), (40, 1), (22, 60), (63, 63)]
+    errs = []
+    for c in cols:
+        e = np.zeros((n, n))
+        e[c] = 1.0
+        fd = (J(th0 + eps * e) - J(th0 - eps * e)) / (2 * eps)
+        errs.append(abs(fd - grad[c]) / abs(grad[c]))
+    for _ in range(4):
+        d = rng.standard_normal((n, n))
+        d /= np.linalg.norm(d)
+        fd = (J(th0 + eps * d) - J(th0 - eps * d)) / (2 * eps)
+        errs.append(abs(fd - (grad * d).sum()) / abs((grad * d).sum()))
+    print("relative errors", errs)
+    assert max(errs) <= 1e-3, errs
