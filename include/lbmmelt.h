@@ -190,7 +190,8 @@ int lbm_adjoint(lbm_ctx *ctx, double dJ_dfl, double *grad_th, int on_device);
 /* The schedule of the run recorded by the last lbm_forward_ckpt: for every
  * step and the state after the last one, 3*n^2 ints (liquid count of every
  * column, index of its first liquid node and of its first solid node used
- * by Eq. (6)); (nsteps + 1) * 3 * n^2 ints in all.  lbm_step_replay takes
+ * by Eq. (6)); (nsteps + 1) * 3 * n^2 ints in all (the node slots of the
+ * final entry are unused: zeros).  lbm_step_replay takes
  * nsteps steps along such a schedule (phases and node selection fixed, every
  * other quantity recomputed): the map whose derivative lbm_adjoint gives,
  * for finite-difference checks.  The schedule is host memory; both

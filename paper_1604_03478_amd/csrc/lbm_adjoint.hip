@@ -180,9 +180,13 @@ __device__ __forceinline__ double link_delta(const double* s, int x, int y, int 
   return (a - s[c]) / (s[cn] - s[c]);
 }
 
-template <typename Ts>
-__device__ __forceinline__ double sv(const Ts* a, size_t qs, int q, uint32_t i) {
-  return (double)static_cast<typename Compute<Ts>::type>(a[(size_t)q * qs + i]);
+// stored population q of linear cell i = (z n + y) n + x, in FP64 (the
+// row-interleaved layout of a distribution with Q directions)
+template <int Q, typename Ts>
+__device__ __forceinline__ double sv(const Ts* a, const KParams& P, int q, uint32_t i) {
+  const uint32_t n = (uint32_t)P.n, x = i % n, row = i / n;
+  return (double)static_cast<typename Compute<Ts>::type>(
+      a[((uint64_t)row * Q + q) * P.pitch + x]);
 }
 
 // pulled (pre-collision) shifted populations of one cell, in FP64
@@ -192,7 +196,6 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
                           double (&fl)[19], double (&gl)[7]) {
   const Geo G{P.n, (uint32_t)P.n * (uint32_t)P.n};
   const int n = P.n;
-  const size_t qs = P.qstride;
   const uint32_t i = G.cell(x, y, z);
   const double w = 0.125, wTm = w * (P.t_m - P.tref);
   for (int q = 0; q < 7; ++q) {
@@ -201,7 +204,7 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
     double v;
     if (!G.in(sx, sy, sz)) {
       const int sa = melt_of<MZ>(sy, sz);
-      const double gp = sv(g, qs, p, i);
+      const double gp = sv<7>(g, P, p, i);
       if (sa < 0)
         v = -gp + 2.0 * w * (th[col_of<MZ>(x, y, z, n)] - P.tref);
       else if (!MZ && sa >= n)
@@ -209,17 +212,17 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
       else
         v = gp;
     } else if (liquid_at<MZ>(cnt, sx, sy, sz, n) == liquid) {
-      v = sv(g, qs, q, G.cell(sx, sy, sz));
+      v = sv<7>(g, P, q, G.cell(sx, sy, sz));
     } else {
       const double d = link_delta<MZ>(s, x, y, z, -ex, -ey, -ez, n);
-      const double gp = sv(g, qs, p, i);
+      const double gp = sv<7>(g, P, p, i);
       if (d < 0.5) {
         const int bx = x + ex, by = y + ey, bz = z + ez;
         const bool behind = G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == liquid;
-        v = behind ? -(2.0 * d * gp + (1.0 - 2.0 * d) * sv(g, qs, p, G.cell(bx, by, bz))) + 2.0 * wTm
+        v = behind ? -(2.0 * d * gp + (1.0 - 2.0 * d) * sv<7>(g, P, p, G.cell(bx, by, bz))) + 2.0 * wTm
                    : -gp + 2.0 * wTm;
       } else {
-        v = -gp / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * sv(g, qs, q, i) + wTm / d;
+        v = -gp / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * sv<7>(g, P, q, i) + wTm / d;
       }
     }
     gl[q] = v;
@@ -228,7 +231,7 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
     for (int q = 0; q < 19; ++q) {
       const int sx = x - ex19(q), sy = y - ey19(q), sz = z - ez19(q);
       const bool ok = G.in(sx, sy, sz) && liquid_at<MZ>(cnt, sx, sy, sz, n);
-      fl[q] = ok ? sv(f, qs, q, G.cell(sx, sy, sz)) : sv(f, qs, opp19(q), i);
+      fl[q] = ok ? sv<19>(f, P, q, G.cell(sx, sy, sz)) : sv<19>(f, P, opp19(q), i);
     }
   }
 }
@@ -342,12 +345,11 @@ template <typename Ts, bool MZ>
 __device__ void front_der(const Ts* g1, const double* s, const double* th, int c,
                           const KParams& P, VDer& d) {
   const int n = P.n;
-  const size_t qs = P.qstride;
   const double sc = s[c];
   const int cnt = count_liquid(sc, n);
   auto Tcell = [&](uint32_t i) {
     double acc = 0.0;
-    for (int q = 0; q < 7; ++q) acc += sv(g1, qs, q, i);
+    for (int q = 0; q < 7; ++q) acc += sv<7>(g1, P, q, i);
     return acc + P.tref;
   };
   double xi[2], Tv[2], dT[2], dxi[2];
@@ -589,7 +591,7 @@ __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, cons
                                             bool L, double& dfrac, const KParams& P) {
   const int n = P.n;
   const Geo G{n, (uint32_t)n * (uint32_t)n};
-  const size_t qs = P.qstride, nc = P.ncell;
+  const size_t nc = P.ncell;
   const uint32_t i = G.cell(x, y, z);
   const int p = opp7(q);
   const double d = link_delta<MZ>(s0, x, y, z, -ex7(q), -ey7(q), -ez7(q), n);
@@ -598,11 +600,11 @@ __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, cons
   if (d < 0.5) {
     const int bx = x + ex7(q), by = y + ey7(q), bz = z + ez7(q);
     if (G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L)
-      return (-2.0 * sv(g0, qs, p, i) + 2.0 * sv(g0, qs, p, G.cell(bx, by, bz))) * l;
+      return (-2.0 * sv<7>(g0, P, p, i) + 2.0 * sv<7>(g0, P, p, G.cell(bx, by, bz))) * l;
     return 0.0;
   }
   const double w = 0.125;
-  return (sv(g0, qs, p, i) / (2.0 * d * d) + sv(g0, qs, q, i) / (2.0 * d * d) -
+  return (sv<7>(g0, P, p, i) / (2.0 * d * d) + sv<7>(g0, P, q, i) / (2.0 * d * d) -
           w * (P.t_m - P.tref) / (d * d)) * l;
 }
 

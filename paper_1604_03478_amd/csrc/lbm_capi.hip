@@ -112,6 +112,11 @@ struct lbm_ctx {
 
 namespace {
 
+// bytes of one distribution with Q directions in the row-interleaved layout
+size_t dist_bytes(const lbm_ctx* c, int Q) {
+  return (size_t)Q * c->kp.pitch * ((size_t)c->p.n * c->p.n) * c->esz;
+}
+
 void free_all(std::vector<void*>& v) {
   for (void* p : v)
     if (p) (void)hipFree(p);
@@ -154,10 +159,14 @@ int validate(const lbm_params* p) {
   if (p->n < 4 || p->n > 1024) return fail(LBM_EINVAL, "n = %d outside [4, 1024]", p->n);
   if (p->precision < LBM_F64 || p->precision > LBM_BF16S)
     return fail(LBM_EINVAL, "precision = %d is not an lbm_precision", p->precision);
-  const double bytes = std::pow((double)p->n, 3) * (double)lbmk::store_bytes(p->precision);
-  if (bytes > 4294967295.0)
-    return fail(LBM_EINVAL, "n = %d too large for this storage precision (one population "
-                "array must stay below 4 GiB)", p->n);
+  // two buffers of each distribution must leave room for the rest on one
+  // 288 GB device
+  const double bytes = 2.0 * ((p->flow ? 19 : 0) + 7) *
+                       (double)lbmk::row_pitch(p->n, p->precision) * (double)p->n * p->n *
+                       (double)lbmk::store_bytes(p->precision);
+  if (bytes > 256.0 * 1073741824.0)
+    return fail(LBM_EINVAL, "n = %d too large for this storage precision (%.0f GiB of "
+                "distributions)", p->n, bytes / 1073741824.0);
   if (p->heating != LBM_HEAT_Y0 && p->heating != LBM_HEAT_Z0)
     return fail(LBM_EINVAL, "heating = %d is not an lbm_heating", p->heating);
   if (p->flow != 0 && p->flow != 1) return fail(LBM_EINVAL, "flow must be 0 or 1");
@@ -281,7 +290,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   lbmk::KParams& k = c->kp;
   k.n = n;
   k.ncell = (uint32_t)nc;
-  k.qstride = lbmk::population_stride((uint32_t)nc, c->kind);
+  k.pitch = lbmk::row_pitch(n, c->kind);
   k.melt_z = params->heating == LBM_HEAT_Z0;
   k.flow = params->flow;
   k.t0 = L.t0;
@@ -310,18 +319,18 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
       return bail(fail(LBM_EDEVICE, "hipStreamCreate failed"));
     c->own_stream = true;
   }
-  const size_t qs = k.qstride;
+  const size_t fbytes = dist_bytes(c, 19), gbytes = dist_bytes(c, 7);
   if (params->flow) {
     for (int b = 0; b < 2; ++b)
-      if (hipMalloc(&c->f[b], 19 * qs * c->esz) != hipSuccess) {
+      if (hipMalloc(&c->f[b], fbytes) != hipSuccess) {
         c->f[b] = nullptr;
-        return bail(fail(LBM_ENOMEM, "cannot allocate f (%zu bytes)", 19 * qs * c->esz));
+        return bail(fail(LBM_ENOMEM, "cannot allocate f (%zu bytes)", fbytes));
       }
   }
   for (int b = 0; b < 2; ++b)
-    if (hipMalloc(&c->g[b], 7 * qs * c->esz) != hipSuccess) {
+    if (hipMalloc(&c->g[b], gbytes) != hipSuccess) {
       c->g[b] = nullptr;
-      return bail(fail(LBM_ENOMEM, "cannot allocate g (%zu bytes)", 7 * qs * c->esz));
+      return bail(fail(LBM_ENOMEM, "cannot allocate g (%zu bytes)", gbytes));
     }
   if ((rc = dalloc(&c->s[0], nn)) || (rc = dalloc(&c->s[1], nn)) || (rc = dalloc(&c->cnt, nn)) ||
       (rc = dalloc(&c->cmin, nn)) || (rc = dalloc(&c->cmax, nn)) ||
@@ -557,7 +566,7 @@ int lbm_save_state(lbm_ctx* c, void* host_buf, size_t* bytes) {
   if (rc) return rc;
   if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
   const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
-  const size_t fb = c->p.flow ? 19 * nc * c->esz : 0, gb = 7 * nc * c->esz;
+  const size_t fb = c->p.flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
   const size_t need = sizeof(StateHeader) + fb + gb + nn * (sizeof(double) + 2 * sizeof(int));
   if (!host_buf) {
     *bytes = need;
@@ -565,7 +574,7 @@ int lbm_save_state(lbm_ctx* c, void* host_buf, size_t* bytes) {
   }
   if (*bytes < need) return fail(LBM_EINVAL, "buffer holds %zu bytes, %zu needed", *bytes, need);
   StateHeader h{};
-  memcpy(h.magic, "LBMMELT1", 8);
+  memcpy(h.magic, "LBMMELT2", 8);
   h.n = c->p.n;
   h.precision = c->p.precision;
   h.flow = c->p.flow;
@@ -575,14 +584,10 @@ int lbm_save_state(lbm_ctx* c, void* host_buf, size_t* bytes) {
   char* b = static_cast<char*>(host_buf);
   memcpy(b, &h, sizeof(h));
   b += sizeof(h);
-  const size_t pb = nc * c->esz, sb = c->kp.qstride * c->esz;  // bytes per population
-  for (size_t q = 0; fb && q < 19; ++q)
-    HIP_TRY(hipMemcpyAsync(b + q * pb, static_cast<char*>(c->f[c->cur]) + q * sb, pb,
-                           hipMemcpyDeviceToHost, c->stream));
+  // distributions as stored (row-interleaved layout, storage precision)
+  if (fb) HIP_TRY(hipMemcpyAsync(b, c->f[c->cur], fb, hipMemcpyDeviceToHost, c->stream));
   b += fb;
-  for (size_t q = 0; q < 7; ++q)
-    HIP_TRY(hipMemcpyAsync(b + q * pb, static_cast<char*>(c->g[c->cur]) + q * sb, pb,
-                           hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(b, c->g[c->cur], gb, hipMemcpyDeviceToHost, c->stream));
   b += gb;
   HIP_TRY(hipMemcpyAsync(b, c->s[c->scur], nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   b += nn * sizeof(double);
@@ -599,24 +604,19 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes) {
   if (rc) return rc;
   if (!host_buf) return fail(LBM_EINVAL, "host_buf is NULL");
   const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
-  const size_t fb = c->p.flow ? 19 * nc * c->esz : 0, gb = 7 * nc * c->esz;
+  const size_t fb = c->p.flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
   const size_t need = sizeof(StateHeader) + fb + gb + nn * (sizeof(double) + 2 * sizeof(int));
   if (bytes < need) return fail(LBM_EINVAL, "state blob has %zu bytes, %zu needed", bytes, need);
   StateHeader h;
   memcpy(&h, host_buf, sizeof(h));
-  if (memcmp(h.magic, "LBMMELT1", 8) != 0) return fail(LBM_EINVAL, "not a state blob");
+  if (memcmp(h.magic, "LBMMELT2", 8) != 0) return fail(LBM_EINVAL, "not a state blob");
   if (h.n != c->p.n || h.precision != c->p.precision || h.flow != c->p.flow ||
       h.heating != c->p.heating || h.ncell != nc)
     return fail(LBM_EINVAL, "state blob was made by an incompatible context");
   const char* b = static_cast<const char*>(host_buf) + sizeof(h);
-  const size_t pb = nc * c->esz, sb = c->kp.qstride * c->esz;  // bytes per population
-  for (size_t q = 0; fb && q < 19; ++q)
-    HIP_TRY(hipMemcpyAsync(static_cast<char*>(c->f[c->cur]) + q * sb, b + q * pb, pb,
-                           hipMemcpyHostToDevice, c->stream));
+  if (fb) HIP_TRY(hipMemcpyAsync(c->f[c->cur], b, fb, hipMemcpyHostToDevice, c->stream));
   b += fb;
-  for (size_t q = 0; q < 7; ++q)
-    HIP_TRY(hipMemcpyAsync(static_cast<char*>(c->g[c->cur]) + q * sb, b + q * pb, pb,
-                           hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->g[c->cur], b, gb, hipMemcpyHostToDevice, c->stream));
   b += gb;
   HIP_TRY(hipMemcpyAsync(c->s[c->scur], b, nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
   b += nn * sizeof(double);
@@ -637,8 +637,8 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
   if (nsteps < 1 || every_k < 1) return fail(LBM_EINVAL, "need nsteps >= 1 and every_k >= 1");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   AdjData& a = c->adj;
-  const size_t nn = (size_t)c->p.n * c->p.n, qs = c->kp.qstride;
-  const size_t fb = c->p.flow ? 19 * qs * c->esz : 0, gb = 7 * qs * c->esz;
+  const size_t nn = (size_t)c->p.n * c->p.n;
+  const size_t fb = c->p.flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
   const int nck = (int)((nsteps + every_k - 1) / every_k);
   a.ready = false;
   if (a.K != every_k) {  // the segment buffers are sized by every_k
@@ -694,9 +694,12 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
     }
   }
   c->rec_start = -1;
-  // final entry: the liquid counts after the last step
+  // final entry: the liquid counts after the last step (its node slots are
+  // not used and hold zeros)
   HIP_TRY(hipMemcpyAsync(c->sched + (size_t)nsteps * 3 * nn, c->cnt, nn * sizeof(int),
                          hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(c->sched + (size_t)nsteps * 3 * nn + nn, 0, 2 * nn * sizeof(int),
+                         c->stream));
   c->sched_steps = nsteps;
   a.end = c->step;
   a.ready = true;
@@ -712,9 +715,9 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   AdjData& a = c->adj;
   if (!a.ready || c->step != a.end)
     return fail(LBM_ESTATE, "lbm_adjoint needs lbm_forward_ckpt with no step taken since");
-  const size_t nn = (size_t)c->p.n * c->p.n, nc = c->kp.ncell, qs = c->kp.qstride;
+  const size_t nn = (size_t)c->p.n * c->p.n, nc = c->kp.ncell;
   const bool flow = c->p.flow != 0;
-  const size_t fb = flow ? 19 * qs * c->esz : 0, gb = 7 * qs * c->esz;
+  const size_t fb = flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
   // segment states and scratch
   while ((int)a.sg.size() < a.K + 1) {
     void *f = nullptr, *g = nullptr;
@@ -823,11 +826,14 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
   const size_t nn = (size_t)n * n;
   const size_t need = (size_t)(nsteps + 1) * 3 * nn;
   // the front kernel walks the given node indices: every one must lie in the column
+  // (the node slots of the final entry are not used)
   for (size_t e = 0; e <= (size_t)nsteps; ++e) {
     const int32_t* en = schedule + e * 3 * nn;
+    const bool nodes = e < (size_t)nsteps;
     for (size_t i = 0; i < nn; ++i) {
-      if (en[i] < 0 || en[i] > n || en[nn + i] < -1 || en[nn + i] > n - 1 ||
-          en[2 * nn + i] < 0 || en[2 * nn + i] > n)
+      if (en[i] < 0 || en[i] > n ||
+          (nodes && (en[nn + i] < -1 || en[nn + i] > n - 1 || en[2 * nn + i] < 0 ||
+                     en[2 * nn + i] > n)))
         return fail(LBM_EINVAL, "schedule entry %zu, column %zu is outside the lattice", e, i);
     }
   }

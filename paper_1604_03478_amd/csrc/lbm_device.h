@@ -8,12 +8,6 @@
 
 #include "lbm_internal.h"
 
-#ifndef LBM_LOAD
-#define LBM_LOAD(p) (*(p))
-#endif
-#ifndef LBM_POP_PAD_BYTES
-#define LBM_POP_PAD_BYTES 4352
-#endif
 
 
 namespace lbmk {
@@ -106,6 +100,19 @@ template <typename Ts, typename C>
 __device__ __forceinline__ void store_stream(Ts* __restrict__ base, uint32_t i, C v, uint32_t& rs) {
   Ts* p = reinterpret_cast<Ts*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(Ts)));
   __builtin_nontemporal_store(round_store<Ts>(v, rs), p);
+}
+
+// --------------------------------------------------------------- layout
+// Row-interleaved distributions (see row_pitch): the Q direction rows of one
+// lattice row (y, z) are contiguous, so the update of a row reads and writes a
+// few contiguous blocks rather than Q arrays that lie far apart in HBM.
+template <int Q, typename Ts>
+__device__ __forceinline__ Ts* row_ptr(Ts* base, const KParams& P, int y, int z) {
+  return base + ((uint64_t)z * (uint64_t)P.n + (uint64_t)y) * (uint64_t)Q * P.pitch;
+}
+__device__ __forceinline__ uint64_t pop_index(const KParams& P, int Q, int q, int x, int y,
+                                              int z) {
+  return (((uint64_t)z * P.n + y) * (uint64_t)Q + q) * P.pitch + x;
 }
 
 // --------------------------------------------------------------- lattices

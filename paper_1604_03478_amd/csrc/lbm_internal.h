@@ -17,7 +17,7 @@ enum StoreKind { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
 struct KParams {
   int n;           // cells per edge
   uint32_t ncell;  // n^3
-  uint64_t qstride;  // elements between consecutive population arrays (>= ncell)
+  uint32_t pitch;  // elements of one direction row (>= n; rows start 128-byte aligned)
   int melt_z;      // 0: melt axis y (hot wall y=0, cold wall y=n); 1: axis z
   int flow;        // 0: energy distribution only
   double t0;       // buoyancy reference temperature
@@ -36,10 +36,12 @@ struct KParams {
 
 size_t store_bytes(int kind);
 
-// Population-array stride for n^3 cells: n^3 plus a pad that keeps the arrays
-// of different directions from starting at the same offset modulo large
-// powers of two.
-uint64_t population_stride(uint32_t ncell, int kind);
+// Layout of a distribution with Q directions in HBM: row-interleaved.  For
+// every lattice row (y, z), its Q direction rows of `pitch` elements (x
+// fastest) lie next to each other; rows follow in (z, y) order.  Population
+// q of cell (x, y, z) is element ((z n + y) Q + q) pitch + x.  A distribution
+// takes Q * pitch * n^2 elements.
+uint32_t row_pitch(int n, int kind);
 
 // One fused stream + collide pass over all cells: reads (fs, gs), writes
 // (fd, gd).  cnt/cmin/cmax: liquid-cell count per column and its min / max

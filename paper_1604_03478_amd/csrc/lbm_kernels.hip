@@ -212,7 +212,9 @@ __device__ __forceinline__ bool collide(C (&f)[19], G (&g)[7], bool liquid, cons
 }
 
 // --------------------------------------------------------------- step kernel
-// One cell of the fused step: pull-stream f and g, collide, store.
+// One cell of the fused step: pull-stream f and g, collide, store.  Addresses
+// are a row pointer (64-bit, the same for a whole lattice row) plus a small
+// per-lane offset q * pitch + x.
 template <typename Ts, bool FLOW, bool MZ>
 __device__ __forceinline__ void update_cell(
     int x, int y, int z, const Ts* __restrict__ fs, Ts* __restrict__ fd,
@@ -223,7 +225,7 @@ __device__ __forceinline__ void update_cell(
   using G = typename Compute<Ts>::gtype;
   const int n = P.n;
   if (x >= n || y >= n) return;
-  const size_t qs = P.qstride;
+  const uint32_t pitch = P.pitch;
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
   const uint32_t self = (uint32_t)z * nn + (uint32_t)y * (uint32_t)n + (uint32_t)x;
   const int a = MZ ? z : y;  // coordinate along the melt axis
@@ -237,6 +239,11 @@ __device__ __forceinline__ void update_cell(
   const bool fast = interior & (all_liq | all_sol);
 
   const Rates<C, G> r = make_rates<C, G>(P);
+  // this row and the rows the directions pull from (valid rows only)
+  const Ts* g_self = row_ptr<7>(gs, P, y, z);
+  const Ts* f_self = row_ptr<19>(fs, P, y, z);
+  auto g_src = [&](int q) { return row_ptr<7>(gs, P, y - ey7(q), z - ez7(q)); };
+  auto f_src = [&](int q) { return row_ptr<19>(fs, P, y - ey19(q), z - ez19(q)); };
 
   C f[19];
   G g[7];
@@ -246,31 +253,27 @@ __device__ __forceinline__ void update_cell(
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
       const int ex = ex7(q);
-      const int off = ex + ey7(q) * n + ez7(q) * (int)nn;
-      const Ts* bq = gs + (size_t)q * qs;
       if (ex == 0) {
-        g[q] = static_cast<G>(LBM_LOAD(bq + (self - off)));
+        g[q] = load_as<G>(g_src(q), q * pitch + x);
       } else {
         // adiabatic x wall: bounce-back, chosen by a per-lane address select
         // (no branch, so the loads of all directions stay in flight together)
         const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
-        const Ts* p = wall ? gs + (size_t)opp7(q) * qs + self : bq + (self - off);
-        g[q] = static_cast<G>(LBM_LOAD(p));
+        const uint32_t i = wall ? opp7(q) * pitch + x : q * pitch + (x - ex);
+        g[q] = load_as<G>(wall ? g_self : g_src(q), i);
       }
     }
     if (FLOW && liquid) {
 #pragma unroll
       for (int q = 0; q < 19; ++q) {
         const int ex = ex19(q);
-        const int off = ex + ey19(q) * n + ez19(q) * (int)nn;
-        const Ts* bq = fs + (size_t)q * qs;
         if (ex == 0) {
-          f[q] = static_cast<C>(LBM_LOAD(bq + (self - off)));
+          f[q] = load_as<C>(f_src(q), q * pitch + x);
         } else {
           // no-slip x wall: halfway bounce-back by a per-lane address select
           const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
-          const Ts* p = wall ? fs + (size_t)opp19(q) * qs + self : bq + (self - off);
-          f[q] = static_cast<C>(LBM_LOAD(p));
+          const uint32_t i = wall ? opp19(q) * pitch + x : q * pitch + (x - ex);
+          f[q] = load_as<C>(wall ? f_self : f_src(q), i);
         }
       }
     }
@@ -282,13 +285,11 @@ __device__ __forceinline__ void update_cell(
     for (int q = 0; q < 7; ++q) {
       const int ex = ex7(q), ey = ey7(q), ez = ez7(q), p = opp7(q);
       const int sx = x - ex, sy = y - ey, sz = z - ez;
-      const Ts* bq = gs + (size_t)q * qs;
-      const Ts* bp = gs + (size_t)p * qs;
       G v;
       if ((unsigned)sx >= (unsigned)n || (unsigned)sy >= (unsigned)n || (unsigned)sz >= (unsigned)n) {
         // thermal wall: Dirichlet (anti-bounce-back) or adiabatic (bounce-back)
         const int sa = MZ ? sz : sy;
-        const G gp = load_as<G>(bp, self);
+        const G gp = load_as<G>(g_self, p * pitch + x);
         if (sa < 0) {
           v = -gp + G(2.0 * kW7Axis) * (G)(th[col] - P.tref);
         } else if (!MZ && sa >= n) {
@@ -300,9 +301,8 @@ __device__ __forceinline__ void update_cell(
         const int sa = MZ ? sz : sy, so = MZ ? sy : sz;
         const int scol = so * n + sx;
         const bool src_liq = sa < cnt[scol];
-        const uint32_t src = self - (uint32_t)(ex + ey * n + ez * (int)nn);
         if (src_liq == liquid) {
-          v = load_as<G>(bq, src);
+          v = load_as<G>(g_src(q), q * pitch + sx);
         } else {
           // interpolated anti-bounce-back at the front (wall value t_m)
           const bool along = MZ ? (ez != 0) : (ey != 0);
@@ -313,7 +313,7 @@ __device__ __forceinline__ void update_cell(
             d = ((a + 0.5) - s_self) / (s[scol] - s_self);
           }
           const G dl = (G)d;
-          const G gp = load_as<G>(bp, self);
+          const G gp = load_as<G>(g_self, p * pitch + x);
           if (d < 0.5) {
             const int bx = x + ex, by = y + ey, bz = z + ez;
             bool behind = (unsigned)bx < (unsigned)n && (unsigned)by < (unsigned)n &&
@@ -323,14 +323,15 @@ __device__ __forceinline__ void update_cell(
               behind = (ba < cnt[bo * n + bx]) == liquid;
             }
             if (behind) {
-              const uint32_t bidx = self + (uint32_t)(ex + ey * n + ez * (int)nn);
-              v = -(G(2) * dl * gp + (G(1) - G(2) * dl) * load_as<G>(bp, bidx)) + G(2) * wTm;
+              const G gb = load_as<G>(row_ptr<7>(gs, P, by, bz), p * pitch + bx);
+              v = -(G(2) * dl * gp + (G(1) - G(2) * dl) * gb) + G(2) * wTm;
             } else {
               v = -gp + G(2) * wTm;
             }
           } else {
             const G inv2d = G(1) / (G(2) * dl);
-            v = -gp * inv2d + (G(2) * dl - G(1)) * inv2d * load_as<G>(bq, self) + wTm / dl;
+            v = -gp * inv2d + (G(2) * dl - G(1)) * inv2d * load_as<G>(g_self, q * pitch + x) +
+                wTm / dl;
           }
         }
       }
@@ -347,29 +348,27 @@ __device__ __forceinline__ void update_cell(
           const int sa = MZ ? sz : sy, so = MZ ? sy : sz;
           ok = sa < cnt[so * n + sx];
         }
-        // halfway bounce-back from walls and solid cells (address select)
-        const uint32_t src = self - (uint32_t)(ex + ey * n + ez * (int)nn);
-        const Ts* p = ok ? fs + (size_t)q * qs + src : fs + (size_t)opp19(q) * qs + self;
-        f[q] = static_cast<C>(*p);
+        // halfway bounce-back from walls and solid cells (address select: the
+        // source row of an out-of-box link is never dereferenced)
+        const Ts* src = ok ? f_src(q) + ((int)(q * pitch) + sx) : f_self + (opp19(q) * pitch + x);
+        f[q] = static_cast<C>(*src);
       }
     }
   }
   if (collide<FLOW>(f, g, liquid, r)) *flag = 1;
   uint32_t rs = mix32(self * 0x9e3779b1u + P.step * 0x85ebca77u);
   if (FLOW && liquid) {
+    Ts* fr = row_ptr<19>(fd, P, y, z);
 #pragma unroll
-    for (int q = 0; q < 19; ++q) store_stream(fd + (size_t)q * qs, self, f[q], rs);
+    for (int q = 0; q < 19; ++q) store_stream(fr, q * pitch + x, f[q], rs);
   }
+  Ts* gr = row_ptr<7>(gd, P, y, z);
 #pragma unroll
-  for (int q = 0; q < 7; ++q) store_stream(gd + (size_t)q * qs, self, g[q], rs);
+  for (int q = 0; q < 7; ++q) store_stream(gr, q * pitch + x, g[q], rs);
 }
 
-// Rows of cells along y handled one after another by each thread.
-#ifndef LBM_ROWS_PER_THREAD
-#define LBM_ROWS_PER_THREAD 1
-#endif
-constexpr int kRows = LBM_ROWS_PER_THREAD;
-
+// One lattice row per workgroup (blockIdx.y = y, blockIdx.z = z): the row
+// pointers are uniform over the workgroup.
 template <typename Ts, bool FLOW, bool MZ>
 __global__ __launch_bounds__(512) void k_stream_collide(
     const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
@@ -377,10 +376,8 @@ __global__ __launch_bounds__(512) void k_stream_collide(
     const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
     int* __restrict__ flag, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y0 = (blockIdx.y * blockDim.y + threadIdx.y) * kRows;
-  const int z = blockIdx.z;
-  for (int k = 0; k < kRows; ++k)
-    update_cell<Ts, FLOW, MZ>(x, y0 + k, z, fs, fd, gs, gd, cnt, cmin, cmax, s, th, flag, P);
+  update_cell<Ts, FLOW, MZ>(x, blockIdx.y, blockIdx.z, fs, fd, gs, gd, cnt, cmin, cmax, s, th,
+                            flag, P);
 }
 
 // --------------------------------------------------------------- row-wave step kernel
@@ -411,7 +408,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   const int z = blockIdx.z;
   if (y >= n) return;  // whole wave
   const int x0 = xw + lane * VW;
-  const size_t qs = P.qstride;
+  const uint32_t pitch = P.pitch;
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
   const uint32_t self0 = (uint32_t)z * nn + (uint32_t)y * (uint32_t)n + (uint32_t)x0;
   const int a = MZ ? z : y;
@@ -435,6 +432,10 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   }
   const bool liquid = all_liq;
   const bool left_edge = lane == 0, right_edge = lane == 63;
+  const Ts* g_self = row_ptr<7>(gs, P, y, z);
+  const Ts* f_self = row_ptr<19>(fs, P, y, z);
+  auto g_src = [&](int q) { return row_ptr<7>(gs, P, y - ey7(q), z - ez7(q)); };
+  auto f_src = [&](int q) { return row_ptr<19>(fs, P, y - ey19(q), z - ez19(q)); };
 
   const Rates<C, G> r = make_rates<C, G>(P);
 
@@ -442,8 +443,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   G gv[7][VW];
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
-    const int roff = ey7(q) * n + ez7(q) * (int)nn;
-    const V v = *reinterpret_cast<const V*>(gs + (size_t)q * qs + (self0 - roff));
+    const V v = *reinterpret_cast<const V*>(g_src(q) + (q * pitch + x0));
 #pragma unroll
     for (int k = 0; k < VW; ++k) gv[q][k] = static_cast<G>(v[k]);
   }
@@ -451,8 +451,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   if (FLOW && liquid) {
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
-      const int roff = ey19(q) * n + ez19(q) * (int)nn;
-      const V v = *reinterpret_cast<const V*>(fs + (size_t)q * qs + (self0 - roff));
+      const V v = *reinterpret_cast<const V*>(f_src(q) + (q * pitch + x0));
 #pragma unroll
       for (int k = 0; k < VW; ++k) fv[q][k] = static_cast<C>(v[k]);
     }
@@ -463,30 +462,28 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
   C fL[5] = {C(0), C(0), C(0), C(0), C(0)}, fR[5] = {C(0), C(0), C(0), C(0), C(0)};
   if (left_edge) {  // directions with e_x = +1 pull from x0 - 1
     const bool wall = xw == 0;
-    gL = wall ? static_cast<G>(gs[(size_t)opp7(1) * qs + self0])
-              : static_cast<G>(gs[(size_t)1 * qs + self0 - 1]);
+    gL = wall ? static_cast<G>(g_self[opp7(1) * pitch + x0])
+              : static_cast<G>(g_self[1 * pitch + x0 - 1]);
     if (FLOW && liquid) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
         const int q = i == 0 ? 1 : 5 + 2 * i;  // 1, 7, 9, 11, 13
-        const int off = 1 + ey19(q) * n + ez19(q) * (int)nn;
-        fL[i] = wall ? static_cast<C>(fs[(size_t)opp19(q) * qs + self0])
-                     : static_cast<C>(fs[(size_t)q * qs + self0 - off]);
+        fL[i] = wall ? static_cast<C>(f_self[opp19(q) * pitch + x0])
+                     : static_cast<C>(f_src(q)[q * pitch + x0 - 1]);
       }
     }
   }
   if (right_edge) {  // directions with e_x = -1 pull from x0 + VW
-    const uint32_t last = self0 + VW - 1;
+    const uint32_t last = x0 + VW - 1;
     const bool wall = x0 + VW == n;
-    gR = wall ? static_cast<G>(gs[(size_t)opp7(2) * qs + last])
-              : static_cast<G>(gs[(size_t)2 * qs + last + 1]);
+    gR = wall ? static_cast<G>(g_self[opp7(2) * pitch + last])
+              : static_cast<G>(g_self[2 * pitch + last + 1]);
     if (FLOW && liquid) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) {
         const int q = i == 0 ? 2 : 6 + 2 * i;  // 2, 8, 10, 12, 14
-        const int off = -1 + ey19(q) * n + ez19(q) * (int)nn;
-        fR[i] = wall ? static_cast<C>(fs[(size_t)opp19(q) * qs + last])
-                     : static_cast<C>(fs[(size_t)q * qs + last - off]);
+        fR[i] = wall ? static_cast<C>(f_self[opp19(q) * pitch + last])
+                     : static_cast<C>(f_src(q)[q * pitch + last + 1]);
       }
     }
   }
@@ -550,7 +547,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
     V v;
 #pragma unroll
     for (int k = 0; k < VW; ++k) v[k] = round_store<Ts>(go[q][k], rs);
-    __builtin_nontemporal_store(v, reinterpret_cast<V*>(gd + (size_t)q * qs + self0));
+    __builtin_nontemporal_store(v, reinterpret_cast<V*>(row_ptr<7>(gd, P, y, z) + (q * pitch + x0)));
   }
   if (FLOW && liquid) {
 #pragma unroll
@@ -558,7 +555,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_rows(
       V v;
 #pragma unroll
       for (int k = 0; k < VW; ++k) v[k] = round_store<Ts>(fo[q][k], rs);
-      __builtin_nontemporal_store(v, reinterpret_cast<V*>(fd + (size_t)q * qs + self0));
+      __builtin_nontemporal_store(v, reinterpret_cast<V*>(row_ptr<19>(fd, P, y, z) + (q * pitch + x0)));
     }
   }
 }
@@ -574,13 +571,14 @@ __device__ __forceinline__ double one_sided(int k, double xi0, double T0v, doubl
   return 0.0;
 }
 
-template <typename Ts, bool MZ>
-__device__ __forceinline__ double cell_T(const Ts* __restrict__ g, size_t qs, uint32_t cell,
-                                         double tref) {
+template <typename Ts>
+__device__ __forceinline__ double cell_T(const Ts* __restrict__ g, const KParams& P, int x, int y,
+                                         int z) {
+  const Ts* row = row_ptr<7>(g, P, y, z);
   double acc = 0.0;
 #pragma unroll
-  for (int q = 0; q < 7; ++q) acc += (double)load(g + (size_t)q * qs, cell);
-  return acc + tref;
+  for (int q = 0; q < 7; ++q) acc += (double)load(row, q * P.pitch + x);
+  return acc + P.tref;
 }
 
 
@@ -600,9 +598,8 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   if (x >= n) return;
   const int col = o * n + x;
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
-  auto cell = [&](int a) -> uint32_t {
-    return MZ ? (uint32_t)a * nn + (uint32_t)o * n + x : (uint32_t)o * nn + (uint32_t)a * n + x;
-  };
+  // temperature of the cell at height a of this column
+  auto T_at = [&](int a) { return MZ ? cell_T(g, P, x, o, a) : cell_T(g, P, x, a, o); };
   const double sc = s_old[col];
   const int c0 = cnt[col];
 
@@ -630,7 +627,7 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   int k = 0;
   for (int a = a_top; a >= 0 && k < 2; --a) {
     const double d = sc - (a + 0.5);
-    const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.tref);
+    const double T = T_at(a);
     if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
     ++k;
   }
@@ -644,7 +641,7 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   k = 0;
   for (int a = a_bot; a < n && k < 2; ++a) {
     const double d = (a + 0.5) - sc;
-    const double T = cell_T<Ts, MZ>(g, P.qstride, cell(a), P.tref);
+    const double T = T_at(a);
     if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
     ++k;
   }
@@ -670,9 +667,9 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   const int c1 = replay_next ? replay_next[col] : count_liquid(sn, n);
   if (FLOW) {
     for (int a = c0; a < c1; ++a) {
-      const uint32_t i = cell(a);
+      Ts* row = MZ ? row_ptr<19>(f, P, o, a) : row_ptr<19>(f, P, a, o);
 #pragma unroll
-      for (int q = 0; q < 19; ++q) store(f + (size_t)q * P.qstride, i, 0.0f);
+      for (int q = 0; q < 19; ++q) store(row, q * P.pitch + x, 0.0f);
     }
   }
   if (c1 > c0) melted[col] += c1 - c0;
@@ -714,14 +711,16 @@ __global__ void k_init(const int* __restrict__ cnt, const double* __restrict__ s
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
   if (x >= n) return;
-  const uint32_t i = ((uint32_t)z * n + y) * n + x;
   const int a = MZ ? z : y, o = MZ ? y : z;
   const bool liquid = a < cnt[o * n + x];
   const double Tt = (liquid ? seedT[a] : P.t_c) - P.tref;
-  store(g, i, kW7Rest * Tt);
-  for (int q = 1; q < 7; ++q) store(g + (size_t)q * P.qstride, i, kW7Axis * Tt);
-  if (P.flow)
-    for (int q = 0; q < 19; ++q) store(f + (size_t)q * P.qstride, i, 0.0);
+  Ts* gr = row_ptr<7>(g, P, y, z);
+  store(gr, x, kW7Rest * Tt);
+  for (int q = 1; q < 7; ++q) store(gr, q * P.pitch + x, kW7Axis * Tt);
+  if (P.flow) {
+    Ts* fr = row_ptr<19>(f, P, y, z);
+    for (int q = 0; q < 19; ++q) store(fr, q * P.pitch + x, 0.0);
+  }
 }
 
 template <typename Ts, bool MZ>
@@ -737,12 +736,14 @@ __global__ void k_fields(const Ts* __restrict__ f, const Ts* __restrict__ g,
   const int a = MZ ? z : y, o = MZ ? y : z;
   const bool liquid = a < cnt[o * n + x];
   double Tt = 0.0;
-  for (int q = 0; q < 7; ++q) Tt += (double)load(g + (size_t)q * P.qstride, i);
+  const Ts* gr = row_ptr<7>(g, P, y, z);
+  for (int q = 0; q < 7; ++q) Tt += (double)load(gr, q * P.pitch + x);
   double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
   if (P.flow && liquid) {
+    const Ts* fr = row_ptr<19>(f, P, y, z);
     double d = 0.0;
     for (int q = 0; q < 19; ++q) {
-      const double v = (double)load(f + (size_t)q * P.qstride, i);
+      const double v = (double)load(fr, q * P.pitch + x);
       d += v;
       jx += ex19(q) * v;
       jy += ey19(q) * v;
@@ -772,9 +773,10 @@ __global__ void k_to_storage(const double* __restrict__ src, Ts* __restrict__ ds
   const uint64_t total = (uint64_t)qcount * P.ncell;
   if (i >= total) return;
   const int q = (int)(i / P.ncell);
-  const uint64_t cell = i - (uint64_t)q * P.ncell;
+  const uint32_t cell = (uint32_t)(i - (uint64_t)q * P.ncell);
+  const uint32_t n = (uint32_t)P.n, x = cell % n, y = (cell / n) % n, z = cell / (n * n);
   const double shift = weight(qcount, q) * (qcount == 7 ? P.tref : 1.0);
-  dst[(uint64_t)q * P.qstride + cell] = static_cast<Ts>(src[i] - shift);
+  dst[pop_index(P, qcount, q, x, y, z)] = static_cast<Ts>(src[i] - shift);
 }
 
 template <typename Ts>
@@ -784,9 +786,11 @@ __global__ void k_from_storage(const Ts* __restrict__ src, double* __restrict__ 
   const uint64_t total = (uint64_t)qcount * P.ncell;
   if (i >= total) return;
   const int q = (int)(i / P.ncell);
-  const uint64_t cell = i - (uint64_t)q * P.ncell;
+  const uint32_t cell = (uint32_t)(i - (uint64_t)q * P.ncell);
+  const uint32_t n = (uint32_t)P.n, x = cell % n, y = (cell / n) % n, z = cell / (n * n);
   const double shift = weight(qcount, q) * (qcount == 7 ? P.tref : 1.0);
-  dst[i] = (double)static_cast<typename Compute<Ts>::type>(src[(uint64_t)q * P.qstride + cell]) + shift;
+  dst[i] = (double)static_cast<typename Compute<Ts>::type>(src[pop_index(P, qcount, q, x, y, z)]) +
+           shift;
 }
 
 // --------------------------------------------------------------- reductions
@@ -880,12 +884,12 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
     if (vw == 4) return rows_dispatch<Ts, 4>(P, F, Fd, G, Gd, cnt, cmin, cmax, s, th, flag, st);
     if (vw == 2) return rows_dispatch<Ts, 2>(P, F, Fd, G, Gd, cnt, cmin, cmax, s, th, flag, st);
   }
-  // whole x rows per workgroup (up to 512 cells): the +-1-shifted loads of a
-  // row then hit cache lines the same workgroup fetches
+  // one whole x row per workgroup (up to 512 cells): the +-1-shifted loads of
+  // a row hit cache lines the same workgroup fetches, and the row pointers are
+  // uniform
   const int bx = P.n >= 512 ? 512 : ((P.n + 63) / 64) * 64;
-  const int by = bx >= 256 ? 1 : 256 / bx;
-  dim3 block(bx, by, 1);
-  dim3 grid((P.n + bx - 1) / bx, (P.n + by * kRows - 1) / (by * kRows), P.n);
+  dim3 block(bx, 1, 1);
+  dim3 grid((P.n + bx - 1) / bx, P.n, P.n);
   if (P.flow) {
     if (P.melt_z)
       hipLaunchKernelGGL((k_stream_collide<Ts, true, true>), grid, block, 0, st, F, Fd, G, Gd, cnt,
@@ -986,11 +990,12 @@ hipError_t conv_dispatch(bool to_storage, const KParams& P, int qcount, const vo
     default: return hipErrorInvalidValue;    \
   }
 
-uint64_t population_stride(uint32_t ncell, int kind) {
-  // pad of kPadBytes per population, rounded to whole elements
-  constexpr uint64_t kPadBytes = LBM_POP_PAD_BYTES;
-  const uint64_t e = store_bytes(kind);
-  return (uint64_t)ncell + (e ? kPadBytes / e : 0);
+uint32_t row_pitch(int n, int kind) {
+  // rows start on 128-byte boundaries
+  const uint32_t e = (uint32_t)store_bytes(kind);
+  if (!e) return 0;
+  const uint32_t bytes = ((uint32_t)n * e + 127u) / 128u * 128u;
+  return bytes / e;
 }
 
 size_t store_bytes(int kind) {
