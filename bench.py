@@ -45,7 +45,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_CELL = {"f32": 208, "f16s": 104, "bf16s": 104, "f64": 416}
-KERNEL_SRC = os.path.join(ROOT, "paper_1604_03478_amd", "csrc", "lbm_kernels.hip")
+# sources the stream-collide kernel is compiled from
+KERNEL_SRC = [os.path.join(ROOT, "paper_1604_03478_amd", "csrc", f)
+              for f in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h")]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stream_collide_f32_256_counters.md")
 
 
@@ -87,13 +89,21 @@ def measure(n, precision, all_liquid, steps, warmup, stream):
     return ms, kms, fl
 
 
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def traffic_from_profile(n: int):
     """HBM bytes per stream-collide launch from the committed counter summary,
     if it was taken on the current kernel source."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     text = open(TRAFFIC_SUMMARY).read()
-    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    src_hash = kernel_source_sha()
     m = re.search(r"kernel-source-sha256:\s*([0-9a-f]{64})", text)
     t = re.search(r"hbm-bytes-per-launch:\s*([0-9.eE+]+)", text)
     nn = re.search(r"lattice:\s*(\d+)", text)

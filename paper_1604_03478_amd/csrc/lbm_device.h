@@ -94,6 +94,24 @@ __device__ __forceinline__ void store(Ts* __restrict__ base, uint32_t i, C v) {
   *p = static_cast<Ts>(v);
 }
 
+// Population loads of the step kernel: every stored value is read once per
+// step (the +-1 x shift of a row is caught by the workgroup's own loads), so
+// they may bypass the caches as well.  Measured on MI355X at 256^3 (FP32,
+// all liquid): 5.47 TB/s with non-temporal loads, 5.55 without; off.
+#ifndef LBM_NT_LOADS
+#define LBM_NT_LOADS 0
+#endif
+template <typename R, typename Ts>
+__device__ __forceinline__ R load_stream(const Ts* __restrict__ base, uint32_t i) {
+  const Ts* p = reinterpret_cast<const Ts*>(reinterpret_cast<const char*>(base) +
+                                            (uint32_t)(i * (uint32_t)sizeof(Ts)));
+#if LBM_NT_LOADS
+  return static_cast<R>(__builtin_nontemporal_load(p));
+#else
+  return static_cast<R>(*p);
+#endif
+}
+
 // Stores of the step kernel: written once, read only in the next step, so
 // they bypass the caches (non-temporal).
 template <typename Ts, typename C>

@@ -254,13 +254,13 @@ __device__ __forceinline__ void update_cell(
     for (int q = 0; q < 7; ++q) {
       const int ex = ex7(q);
       if (ex == 0) {
-        g[q] = load_as<G>(g_src(q), q * pitch + x);
+        g[q] = load_stream<G>(g_src(q), q * pitch + x);
       } else {
         // adiabatic x wall: bounce-back, chosen by a per-lane address select
         // (no branch, so the loads of all directions stay in flight together)
         const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
         const uint32_t i = wall ? opp7(q) * pitch + x : q * pitch + (x - ex);
-        g[q] = load_as<G>(wall ? g_self : g_src(q), i);
+        g[q] = load_stream<G>(wall ? g_self : g_src(q), i);
       }
     }
     if (FLOW && liquid) {
@@ -268,12 +268,12 @@ __device__ __forceinline__ void update_cell(
       for (int q = 0; q < 19; ++q) {
         const int ex = ex19(q);
         if (ex == 0) {
-          f[q] = load_as<C>(f_src(q), q * pitch + x);
+          f[q] = load_stream<C>(f_src(q), q * pitch + x);
         } else {
           // no-slip x wall: halfway bounce-back by a per-lane address select
           const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
           const uint32_t i = wall ? opp19(q) * pitch + x : q * pitch + (x - ex);
-          f[q] = load_as<C>(wall ? f_self : f_src(q), i);
+          f[q] = load_stream<C>(wall ? f_self : f_src(q), i);
         }
       }
     }
@@ -289,7 +289,7 @@ __device__ __forceinline__ void update_cell(
       if ((unsigned)sx >= (unsigned)n || (unsigned)sy >= (unsigned)n || (unsigned)sz >= (unsigned)n) {
         // thermal wall: Dirichlet (anti-bounce-back) or adiabatic (bounce-back)
         const int sa = MZ ? sz : sy;
-        const G gp = load_as<G>(g_self, p * pitch + x);
+        const G gp = load_stream<G>(g_self, p * pitch + x);
         if (sa < 0) {
           v = -gp + G(2.0 * kW7Axis) * (G)(th[col] - P.tref);
         } else if (!MZ && sa >= n) {
@@ -302,7 +302,7 @@ __device__ __forceinline__ void update_cell(
         const int scol = so * n + sx;
         const bool src_liq = sa < cnt[scol];
         if (src_liq == liquid) {
-          v = load_as<G>(g_src(q), q * pitch + sx);
+          v = load_stream<G>(g_src(q), q * pitch + sx);
         } else {
           // interpolated anti-bounce-back at the front (wall value t_m)
           const bool along = MZ ? (ez != 0) : (ey != 0);
@@ -313,7 +313,7 @@ __device__ __forceinline__ void update_cell(
             d = ((a + 0.5) - s_self) / (s[scol] - s_self);
           }
           const G dl = (G)d;
-          const G gp = load_as<G>(g_self, p * pitch + x);
+          const G gp = load_stream<G>(g_self, p * pitch + x);
           if (d < 0.5) {
             const int bx = x + ex, by = y + ey, bz = z + ez;
             bool behind = (unsigned)bx < (unsigned)n && (unsigned)by < (unsigned)n &&
@@ -323,14 +323,14 @@ __device__ __forceinline__ void update_cell(
               behind = (ba < cnt[bo * n + bx]) == liquid;
             }
             if (behind) {
-              const G gb = load_as<G>(row_ptr<7>(gs, P, by, bz), p * pitch + bx);
+              const G gb = load_stream<G>(row_ptr<7>(gs, P, by, bz), p * pitch + bx);
               v = -(G(2) * dl * gp + (G(1) - G(2) * dl) * gb) + G(2) * wTm;
             } else {
               v = -gp + G(2) * wTm;
             }
           } else {
             const G inv2d = G(1) / (G(2) * dl);
-            v = -gp * inv2d + (G(2) * dl - G(1)) * inv2d * load_as<G>(g_self, q * pitch + x) +
+            v = -gp * inv2d + (G(2) * dl - G(1)) * inv2d * load_stream<G>(g_self, q * pitch + x) +
                 wTm / dl;
           }
         }
@@ -351,7 +351,7 @@ __device__ __forceinline__ void update_cell(
         // halfway bounce-back from walls and solid cells (address select: the
         // source row of an out-of-box link is never dereferenced)
         const Ts* src = ok ? f_src(q) + ((int)(q * pitch) + sx) : f_self + (opp19(q) * pitch + x);
-        f[q] = static_cast<C>(*src);
+        f[q] = load_stream<C>(src, 0);
       }
     }
   }
@@ -378,186 +378,6 @@ __global__ __launch_bounds__(512) void k_stream_collide(
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   update_cell<Ts, FLOW, MZ>(x, blockIdx.y, blockIdx.z, fs, fd, gs, gd, cnt, cmin, cmax, s, th,
                             flag, P);
-}
-
-// --------------------------------------------------------------- row-wave step kernel
-// One wave per 64*VW consecutive cells of an x row; each lane owns VW
-// consecutive cells.  Every population is read as one aligned VW-wide vector
-// per lane from its source row; the +-1 shift in x of the x-moving
-// directions comes from the neighbouring lane (wave shuffle), and only the
-// two segment-edge lanes read one extra value from memory (bounce-back at
-// an x wall, or the first cell of the next segment).  Waves that are not in
-// the bulk of one phase fall back to the per-cell path, 64 cells at a time.
-template <typename T, int W>
-using vec_t = T __attribute__((ext_vector_type(W)));
-
-template <typename Ts, int VW, bool FLOW, bool MZ>
-__global__ __launch_bounds__(256) void k_stream_collide_rows(
-    const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
-    Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
-    const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
-    int* __restrict__ flag, KParams P) {
-  using C = typename Compute<Ts>::type;
-  using G = typename Compute<Ts>::gtype;
-  using V = vec_t<Ts, VW>;
-  using VI = vec_t<int, VW>;
-  const int n = P.n;
-  const int lane = threadIdx.x;          // blockDim.x == 64: one wave per segment
-  const int xw = blockIdx.x * (64 * VW);  // first cell of the segment
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (y >= n) return;  // whole wave
-  const int x0 = xw + lane * VW;
-  const uint32_t pitch = P.pitch;
-  const uint32_t nn = (uint32_t)n * (uint32_t)n;
-  const uint32_t self0 = (uint32_t)z * nn + (uint32_t)y * (uint32_t)n + (uint32_t)x0;
-  const int a = MZ ? z : y;
-  const int o = MZ ? y : z;
-  const int col0 = o * n + x0;
-
-  const VI mn = *reinterpret_cast<const VI*>(cmin + col0);
-  const VI mx = *reinterpret_cast<const VI*>(cmax + col0);
-  bool all_liq = true, all_sol = true;
-#pragma unroll
-  for (int k = 0; k < VW; ++k) {
-    all_liq = all_liq && (a + 1) < mn[k];
-    all_sol = all_sol && (a - 1) >= mx[k];
-  }
-  const bool interior = (y > 0) & (y < n - 1) & (z > 0) & (z < n - 1);
-  if (!__all(interior & (all_liq | all_sol))) {
-    for (int k = 0; k < VW; ++k)
-      update_cell<Ts, FLOW, MZ>(xw + 64 * k + lane, y, z, fs, fd, gs, gd, cnt, cmin, cmax, s, th,
-                                flag, P);
-    return;
-  }
-  const bool liquid = all_liq;
-  const bool left_edge = lane == 0, right_edge = lane == 63;
-  const Ts* g_self = row_ptr<7>(gs, P, y, z);
-  const Ts* f_self = row_ptr<19>(fs, P, y, z);
-  auto g_src = [&](int q) { return row_ptr<7>(gs, P, y - ey7(q), z - ez7(q)); };
-  auto f_src = [&](int q) { return row_ptr<19>(fs, P, y - ey19(q), z - ez19(q)); };
-
-  const Rates<C, G> r = make_rates<C, G>(P);
-
-  // ---- loads: one aligned vector per direction, from its source row ----
-  G gv[7][VW];
-#pragma unroll
-  for (int q = 0; q < 7; ++q) {
-    const V v = *reinterpret_cast<const V*>(g_src(q) + (q * pitch + x0));
-#pragma unroll
-    for (int k = 0; k < VW; ++k) gv[q][k] = static_cast<G>(v[k]);
-  }
-  C fv[19][VW];
-  if (FLOW && liquid) {
-#pragma unroll
-    for (int q = 0; q < 19; ++q) {
-      const V v = *reinterpret_cast<const V*>(f_src(q) + (q * pitch + x0));
-#pragma unroll
-      for (int k = 0; k < VW; ++k) fv[q][k] = static_cast<C>(v[k]);
-    }
-  }
-  // segment-edge values of the x-moving directions (bounce-back at x walls:
-  // adiabatic for g, no-slip for f; otherwise the neighbouring segment)
-  G gL = G(0), gR = G(0);
-  C fL[5] = {C(0), C(0), C(0), C(0), C(0)}, fR[5] = {C(0), C(0), C(0), C(0), C(0)};
-  if (left_edge) {  // directions with e_x = +1 pull from x0 - 1
-    const bool wall = xw == 0;
-    gL = wall ? static_cast<G>(g_self[opp7(1) * pitch + x0])
-              : static_cast<G>(g_self[1 * pitch + x0 - 1]);
-    if (FLOW && liquid) {
-#pragma unroll
-      for (int i = 0; i < 5; ++i) {
-        const int q = i == 0 ? 1 : 5 + 2 * i;  // 1, 7, 9, 11, 13
-        fL[i] = wall ? static_cast<C>(f_self[opp19(q) * pitch + x0])
-                     : static_cast<C>(f_src(q)[q * pitch + x0 - 1]);
-      }
-    }
-  }
-  if (right_edge) {  // directions with e_x = -1 pull from x0 + VW
-    const uint32_t last = x0 + VW - 1;
-    const bool wall = x0 + VW == n;
-    gR = wall ? static_cast<G>(g_self[opp7(2) * pitch + last])
-              : static_cast<G>(g_self[2 * pitch + last + 1]);
-    if (FLOW && liquid) {
-#pragma unroll
-      for (int i = 0; i < 5; ++i) {
-        const int q = i == 0 ? 2 : 6 + 2 * i;  // 2, 8, 10, 12, 14
-        fR[i] = wall ? static_cast<C>(f_self[opp19(q) * pitch + last])
-                     : static_cast<C>(f_src(q)[q * pitch + last + 1]);
-      }
-    }
-  }
-  // neighbour-lane values for the shift
-  G gl_in = __shfl_up(gv[1][VW - 1], 1, 64);
-  G gr_in = __shfl_down(gv[2][0], 1, 64);
-  if (left_edge) gl_in = gL;
-  if (right_edge) gr_in = gR;
-  C fl_in[5], fr_in[5];
-  if (FLOW && liquid) {
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      const int qp = i == 0 ? 1 : 5 + 2 * i;
-      const int qm = i == 0 ? 2 : 6 + 2 * i;
-      fl_in[i] = __shfl_up(fv[qp][VW - 1], 1, 64);
-      fr_in[i] = __shfl_down(fv[qm][0], 1, 64);
-      if (left_edge) fl_in[i] = fL[i];
-      if (right_edge) fr_in[i] = fR[i];
-    }
-  }
-
-  // ---- collide each cell ----
-  G go[7][VW];
-  C fo[19][VW];
-  bool bad = false;
-#pragma unroll
-  for (int k = 0; k < VW; ++k) {
-    G g[7];
-    C f[19];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      const int ex = ex7(q);
-      g[q] = ex == 0 ? gv[q][k]
-           : ex > 0 ? (k > 0 ? gv[q][k - 1] : gl_in)
-                    : (k < VW - 1 ? gv[q][k + 1] : gr_in);
-    }
-    if (FLOW && liquid) {
-#pragma unroll
-      for (int q = 0; q < 19; ++q) {
-        const int ex = ex19(q);
-        const int i = q <= 2 ? 0 : (q - 7) / 2 + 1;  // index among the x-moving pairs
-        f[q] = ex == 0 ? fv[q][k]
-             : ex > 0 ? (k > 0 ? fv[q][k - 1] : fl_in[i])
-                      : (k < VW - 1 ? fv[q][k + 1] : fr_in[i]);
-      }
-    }
-    bad = collide<FLOW>(f, g, liquid, r) || bad;
-#pragma unroll
-    for (int q = 0; q < 7; ++q) go[q][k] = g[q];
-    if (FLOW && liquid) {
-#pragma unroll
-      for (int q = 0; q < 19; ++q) fo[q][k] = f[q];
-    }
-  }
-  if (bad) *flag = 1;
-
-  // ---- stores: one aligned vector per direction ----
-  uint32_t rs = mix32(self0 * 0x9e3779b1u + P.step * 0x85ebca77u);
-#pragma unroll
-  for (int q = 0; q < 7; ++q) {
-    V v;
-#pragma unroll
-    for (int k = 0; k < VW; ++k) v[k] = round_store<Ts>(go[q][k], rs);
-    __builtin_nontemporal_store(v, reinterpret_cast<V*>(row_ptr<7>(gd, P, y, z) + (q * pitch + x0)));
-  }
-  if (FLOW && liquid) {
-#pragma unroll
-    for (int q = 0; q < 19; ++q) {
-      V v;
-#pragma unroll
-      for (int k = 0; k < VW; ++k) v[k] = round_store<Ts>(fo[q][k], rs);
-      __builtin_nontemporal_store(v, reinterpret_cast<V*>(row_ptr<19>(fd, P, y, z) + (q * pitch + x0)));
-    }
-  }
 }
 
 // --------------------------------------------------------------- front update
@@ -828,48 +648,6 @@ __global__ __launch_bounds__(kSumThreads) void k_sum_int(const int* __restrict__
 }
 
 // --------------------------------------------------------------- dispatch
-// Cells per lane of the row-wave kernel for this precision and size (0: the
-// per-cell kernel).  A segment is 64*VW cells, so n must be a multiple of it.
-// Measured on MI355X at 256^3: for FP32 the per-cell kernel (8 waves/SIMD)
-// beats the row-wave kernel (VW = 2: 136 VGPRs, VW = 4: 198); for 16-bit
-// storage two cells per lane (4-byte accesses) beat 2-byte accesses.
-#ifndef LBM_ROW_VW_32
-#define LBM_ROW_VW_32 0
-#endif
-#ifndef LBM_ROW_VW_16
-#define LBM_ROW_VW_16 2
-#endif
-template <typename Ts>
-int row_width(int n) {
-  int vw = sizeof(Ts) == 8 ? 0 : (sizeof(Ts) == 4 ? LBM_ROW_VW_32 : LBM_ROW_VW_16);
-  while (vw > 1 && n % (64 * vw) != 0) vw /= 2;
-  return (vw >= 2 && n % (64 * vw) == 0) ? vw : 0;
-}
-
-template <typename Ts, int VW>
-hipError_t rows_dispatch(const KParams& P, const Ts* F, Ts* Fd, const Ts* G, Ts* Gd,
-                         const int* cnt, const int* cmin, const int* cmax, const double* s,
-                         const double* th, int* flag, hipStream_t st) {
-  dim3 block(64, 4, 1);
-  dim3 grid(P.n / (64 * VW), (P.n + 3) / 4, P.n);
-  if (P.flow) {
-    if (P.melt_z)
-      hipLaunchKernelGGL((k_stream_collide_rows<Ts, VW, true, true>), grid, block, 0, st, F, Fd, G,
-                         Gd, cnt, cmin, cmax, s, th, flag, P);
-    else
-      hipLaunchKernelGGL((k_stream_collide_rows<Ts, VW, true, false>), grid, block, 0, st, F, Fd, G,
-                         Gd, cnt, cmin, cmax, s, th, flag, P);
-  } else {
-    if (P.melt_z)
-      hipLaunchKernelGGL((k_stream_collide_rows<Ts, VW, false, true>), grid, block, 0, st, F, Fd, G,
-                         Gd, cnt, cmin, cmax, s, th, flag, P);
-    else
-      hipLaunchKernelGGL((k_stream_collide_rows<Ts, VW, false, false>), grid, block, 0, st, F, Fd,
-                         G, Gd, cnt, cmin, cmax, s, th, flag, P);
-  }
-  return hipGetLastError();
-}
-
 template <typename Ts>
 hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* gs, void* gd,
                        const int* cnt, const int* cmin, const int* cmax, const double* s,
@@ -878,12 +656,6 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
   auto Fd = static_cast<Ts*>(fd);
   auto G = static_cast<const Ts*>(gs);
   auto Gd = static_cast<Ts*>(gd);
-  if constexpr (sizeof(Ts) < 8) {
-    const int vw = row_width<Ts>(P.n);
-    if (vw == 8) return rows_dispatch<Ts, 8>(P, F, Fd, G, Gd, cnt, cmin, cmax, s, th, flag, st);
-    if (vw == 4) return rows_dispatch<Ts, 4>(P, F, Fd, G, Gd, cnt, cmin, cmax, s, th, flag, st);
-    if (vw == 2) return rows_dispatch<Ts, 2>(P, F, Fd, G, Gd, cnt, cmin, cmax, s, th, flag, st);
-  }
   // one whole x row per workgroup (up to 512 cells): the +-1-shifted loads of
   // a row hit cache lines the same workgroup fetches, and the row pointers are
   // uniform
