@@ -13,6 +13,10 @@ state (front at the far wall), so that every cell runs the full double MRT
 and moves 208 B (FP32).  The melting state of the same configuration
 (front near the heated wall) is timed as well and reported separately.
 
+Also reported: the 512^3 bottom-heated configuration in FP16 shifted storage
+(`bottom512`), the adjoint timings (`adjoint`), and the measured ceiling of a
+two-stream elementwise kernel (`roofline.copy_ceiling_GBps`).
+
 Output: one JSON line (see the contract in the repository notes).  The
 roofline object uses the stream-collide kernel's average duration measured
 live with HIP events on the stream it runs on; `traffic` comes from the
@@ -23,6 +27,9 @@ Modes:
   (default)       the benchmark line
   --mode profile  a short run of the FP32 workload only (for rocprofv3)
   --mode copy     a plain device copy of known size (counter calibration)
+  --mode adjoint  the checkpointed forward run and the reverse sweep alone
+                  (64^3 x 2000 steps with a checkpoint every 100, and
+                  256^3 x 100 steps every 10), for rocprofv3
   --mode precision
                   storage precision against an FP64 run of the same melting
                   configuration (256^3, 1e5 steps by default): liquid fraction
@@ -45,6 +52,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_CELL = {"f32": 208, "f16s": 104, "bf16s": 104, "f64": 416}
+# one reverse step, FP32 storage, FP64 adjoint: transposed collision (state
+# 104 B + adjoint 208 B read, 208 B written) and transposed streaming (208 B
+# read, 208 B written)
+ADJ_BYTES_PER_CELL = 520 + 416
 # sources the stream-collide kernel is compiled from
 KERNEL_SRC = [os.path.join(ROOT, "paper_1604_03478_amd", "csrc", f)
               for f in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h")]
@@ -87,6 +98,86 @@ def measure(n, precision, all_liquid, steps, warmup, stream):
     fl = sim.liquid_fraction()
     sim.close()
     return ms, kms, fl
+
+
+def copy_ceiling(stream, nbytes: int = 2 << 30):
+    """GB/s of torch's elementwise kernel reading and writing nbytes each
+    (dst = src * 1): a measured ceiling for a two-stream kernel on this machine."""
+    import torch
+    with torch.cuda.stream(stream):
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            torch.mul(src, 1.0, out=dst)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        del src, dst
+    return 2 * nbytes / (e0.elapsed_time(e1) / 10) / 1e6
+
+
+def bottom_heated_512(stream, steps: int, warmup: int):
+    """The large configuration: 512^3, hot wall z = 0 (every other wall
+    adiabatic), Ra = 1e6, Pr = 1, Ste = 0.1, FP16 shifted storage with FP32
+    collision and FP64 front and reductions.  Throughput of the all-liquid
+    state (every cell moves 104 B) and of the initial melting state."""
+    from paper_1604_03478_amd import Config, Sim
+    n = 512
+    out = {"workload": "convection melting 512^3, bottom-heated (hot z=0), Ra=1e6, Pr=1, "
+                       "Ste=0.1, fp16 shifted storage, fp32 collide, fp64 front"}
+    for key, s0 in (("all_liquid", float(n)), ("melting_state", 1.0)):
+        cfg = Config(n=n, ra=1e6, pr=1.0, ste=0.1, s0=s0, heating="z0", precision="f16s")
+        sim = Sim(cfg, stream=stream)
+        sim.step(warmup)
+        ms = time_steps(sim, stream, steps)
+        kms = kernel_ms(sim, steps)
+        fl = sim.liquid_fraction()
+        sim.close()
+        d = {"MLUPS": round(n ** 3 / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+             "kernel_ms": round(kms, 4), "liquid_fraction": round(fl, 6)}
+        if key == "all_liquid":
+            d["achieved_GBps"] = round(BYTES_PER_CELL["f16s"] * n ** 3 / (kms * 1e-3) / 1e9, 1)
+        out[key] = d
+    return out
+
+
+def adjoint_timing(stream, n: int, steps: int, every: int):
+    """Gradient of f_l after `steps` steps with respect to T_h(x, z), FP32
+    storage, checkpoint every `every` steps: time of the checkpointed forward
+    run, of the reverse sweep (recompute included) and of plain steps."""
+    import numpy as np
+    import torch
+    from paper_1604_03478_amd import Config, Sim
+    cfg = Config(n=n, ra=1e4 if n <= 64 else 1e5, pr=1.0, ste=0.1, s0=1.0, precision="f32")
+    th = 1.0 + 0.1 * np.random.default_rng(0).standard_normal((n, n))
+    sim = Sim(cfg, stream=stream)
+    sim.set_hot_wall(th)
+    blob = sim.save_state()
+    plain = time_steps(sim, stream, steps)
+    sim.load_state(blob)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.forward_ckpt(steps, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    grad = sim.adjoint(1.0, device=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    sim.close()
+    fwd, adj = (t1 - t0) * 1e3, (t2 - t1) * 1e3
+    rev = max(adj - plain * steps, 0.0) / steps
+    return {"n": n, "steps": steps, "every_k": every,
+            "plain_ms_per_step": round(plain, 4), "forward_ckpt_ms": round(fwd, 2),
+            "adjoint_ms": round(adj, 2), "adjoint_over_forward": round(adj / (plain * steps), 2),
+            "reverse_ms_per_step_est": round(rev, 4),
+            "reverse_GBps_est": round(ADJ_BYTES_PER_CELL * n ** 3 / (rev * 1e-3) / 1e9, 1)
+            if rev > 0 else None,
+            "grad_norm": float(torch.linalg.norm(grad).item())}
 
 
 def kernel_source_sha() -> str:
@@ -185,10 +276,13 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--mode", choices=["bench", "profile", "copy", "precision"], default="bench")
+    ap.add_argument("--mode", choices=["bench", "profile", "copy", "precision", "adjoint"],
+                    default="bench")
     ap.add_argument("--precision-steps", type=int, default=100000)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 512^3 and adjoint legs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -232,6 +326,12 @@ def main():
 
     if args.mode == "precision":
         precision_study(args.n, args.precision_steps, stream)
+        return
+
+    if args.mode == "adjoint":
+        print(json.dumps({"mode": "adjoint",
+                          "runs": [adjoint_timing(stream, 64, 2000, 100),
+                                   adjoint_timing(stream, 256, 100, 10)]}), flush=True)
         return
 
     n, K, W = args.n, args.steps, args.warmup
@@ -288,6 +388,14 @@ def main():
             "note": "front near the heated wall: solid cells move only g (56 B)",
         },
     }
+    print("bench: copy ceiling, 512^3 bottom-heated fp16, adjoint", file=sys.stderr, flush=True)
+    ceiling = copy_ceiling(stream)
+    line["roofline"]["copy_ceiling_GBps"] = round(ceiling, 1)
+    line["roofline"]["frac_of_copy"] = round(achieved / ceiling, 4)
+    if not args.no_extras:
+        line["bottom512"] = bottom_heated_512(stream, 100, 20)
+        line["adjoint"] = [adjoint_timing(stream, 64, 2000, 100),
+                           adjoint_timing(stream, 256, 100, 10)]
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)

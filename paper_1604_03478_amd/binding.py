@@ -191,14 +191,16 @@ class Sim:
         _check(self._lib.lbm_liquid_fraction(self._h, ctypes.byref(v)))
         return v.value
 
-    def fields(self) -> dict:
+    def fields(self, which=("T", "u", "rho", "s")) -> dict:
+        """Macroscopic fields in FP64 (host); `which` selects the outputs."""
         n = self.n
-        T = np.empty((n, n, n))
-        u = np.empty((3, n, n, n))
-        rho = np.empty((n, n, n))
-        s = np.empty((n, n))
+        T = np.empty((n, n, n)) if "T" in which else None
+        u = np.empty((3, n, n, n)) if "u" in which else None
+        rho = np.empty((n, n, n)) if "rho" in which else None
+        s = np.empty((n, n)) if "s" in which else None
         _check(self._lib.lbm_fields(self._h, _ptr(T), _ptr(u), _ptr(rho), _ptr(s)))
-        return {"T": T, "u": u, "rho": rho, "s": s}
+        out = {"T": T, "u": u, "rho": rho, "s": s}
+        return {k: v for k, v in out.items() if v is not None}
 
     def diagnostics(self) -> dict:
         out = np.zeros(5)

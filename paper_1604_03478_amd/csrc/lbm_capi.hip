@@ -437,16 +437,20 @@ int lbm_liquid_fraction(lbm_ctx* c, double* fl) {
 int lbm_fields(lbm_ctx* c, double* T, double* u, double* rho, double* s) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if ((rc = ensure_fields(c))) return rc;
   const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
-  double* d = c->fields;
-  HIP_TRY(lbmk::launch_fields(c->kind, c->kp, c->f[c->cur], c->g[c->cur], c->cnt, d, d + nc,
-                              d + 2 * nc, d + 3 * nc, d + 4 * nc, c->stream));
-  if (T) HIP_TRY(hipMemcpyAsync(T, d, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  if (u)
-    HIP_TRY(hipMemcpyAsync(u, d + nc, 3 * nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  if (rho)
-    HIP_TRY(hipMemcpyAsync(rho, d + 4 * nc, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (T || u || rho) {  // the cell fields are computed only when asked for
+    if ((rc = ensure_fields(c))) return rc;
+    double* d = c->fields;
+    HIP_TRY(lbmk::launch_fields(c->kind, c->kp, c->f[c->cur], c->g[c->cur], c->cnt, d, d + nc,
+                                d + 2 * nc, d + 3 * nc, d + 4 * nc, c->stream));
+    if (T) HIP_TRY(hipMemcpyAsync(T, d, nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (u)
+      HIP_TRY(hipMemcpyAsync(u, d + nc, 3 * nc * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    if (rho)
+      HIP_TRY(hipMemcpyAsync(rho, d + 4 * nc, nc * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+  }
   if (s)
     HIP_TRY(hipMemcpyAsync(s, c->s[c->scur], nn * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
