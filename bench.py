@@ -25,7 +25,8 @@ kernel source (else null).
 
 Modes:
   (default)       the benchmark line
-  --mode profile  a short run of the FP32 workload only (for rocprofv3)
+  --mode profile  a short run of the all-liquid workload only (for rocprofv3;
+                  FP32 unless --precision says otherwise)
   --mode copy     a plain device copy of known size (counter calibration)
   --mode adjoint  the checkpointed forward run and the reverse sweep alone
                   (64^3 x 2000 steps with a checkpoint every 100, and
@@ -279,6 +280,8 @@ def main():
     ap.add_argument("--mode", choices=["bench", "profile", "copy", "precision", "adjoint"],
                     default="bench")
     ap.add_argument("--precision-steps", type=int, default=100000)
+    ap.add_argument("--precision", choices=["f32", "f16s", "bf16s", "f64"], default="f32",
+                    help="storage precision of --mode profile")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -317,11 +320,11 @@ def main():
 
     if args.mode == "profile":
         from paper_1604_03478_amd import Sim
-        sim = Sim(workload_config(args.n, "f32", True), stream=stream)
+        sim = Sim(workload_config(args.n, args.precision, True), stream=stream)
         sim.step(args.warmup)
         ms = time_steps(sim, stream, args.steps)
-        print(json.dumps({"mode": "profile", "n": args.n, "steps": args.steps,
-                          "ms_per_step": ms}), flush=True)
+        print(json.dumps({"mode": "profile", "n": args.n, "precision": args.precision,
+                          "steps": args.steps, "ms_per_step": ms}), flush=True)
         return
 
     if args.mode == "precision":

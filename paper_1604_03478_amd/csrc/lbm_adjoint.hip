@@ -11,9 +11,12 @@
 // state; the adjoint is that of the forward run's own schedule.
 //
 // Per step, in reverse order of the forward operations:
-//   k_adj_front        per column: phase switch (refilled f has no
-//                      dependence), s' = s + V(g*, s): adjoint into the node
+//   k_adj_front        per column: s' = s + V(g*, s): adjoint into the node
 //                      temperatures, into s and its neighbours, into T_h
+//                      (the phase switch needs nothing: f of a solid cell
+//                      is dead data and a melting cell is refilled, so the
+//                      adjoint of f is kept only where the cell is liquid
+//                      on both sides of a step)
 //   k_adj_front_gather per column: sums the neighbour contributions to s
 //   k_adj_collide      per cell: recomputes the pulled populations and
 //                      applies the transposed collision Jacobian
@@ -439,20 +442,13 @@ template <typename Ts, bool FLOW, bool MZ>
 __global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict__ g1,
                             const double* __restrict__ s1, const double* __restrict__ th,
                             const double* __restrict__ ls1, double* __restrict__ lg1,
-                            double* __restrict__ lf1, double* __restrict__ out5,
-                            double* __restrict__ own, double* __restrict__ lth, KParams P) {
+                            double* __restrict__ out5, double* __restrict__ own,
+                            double* __restrict__ lth, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
   if (x >= n) return;
   const int c = o * n + x;
   const size_t nc = P.ncell, nn = (size_t)n * n;
-  if (FLOW) {  // refilled populations of newly liquid cells do not depend on anything
-    const int c0 = count_liquid(s0[c], n), c1 = count_liquid(s1[c], n);
-    for (int a = c0; a < c1; ++a) {
-      const uint32_t i = cell_in_column<MZ>(c, a, n);
-      for (int q = 0; q < 19; ++q) lf1[(size_t)q * nc + i] = 0.0;
-    }
-  }
   VDer d;
   front_der<Ts, MZ>(g1, s0, th, c, P, d);
   const double v = s0[c] + d.V;
@@ -489,7 +485,8 @@ __global__ void k_adj_front_gather(const double* __restrict__ own, const double*
 template <typename Ts, bool FLOW, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_collide(
     const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
-    const double* __restrict__ th, const int* __restrict__ cnt, const double* __restrict__ lf1,
+    const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
+    const double* __restrict__ lf1,
     const double* __restrict__ lg1, double* __restrict__ lfh, double* __restrict__ lgh,
     KParams P) {
   const int n = P.n;
@@ -498,12 +495,15 @@ __global__ __launch_bounds__(256) void k_adj_collide(
   const size_t nc = P.ncell;
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
   const bool liquid = liquid_at<MZ>(cnt, x, y, z, n);
+  // f of a cell that is solid after the step is dead data (never read; a
+  // melting cell is refilled), so its adjoint is zero and is not stored
+  const bool live1 = liquid && melt_of<MZ>(y, z) < count_liquid(s1[col_of<MZ>(x, y, z, n)], n);
   double fl[19], gl[7], lfo[19], lgo[7], lfl[19], lgl[7];
   pull_cell<Ts, FLOW, MZ>(f0, g0, s0, th, cnt, x, y, z, liquid, P, fl, gl);
-  for (int q = 0; q < 19; ++q) lfo[q] = (FLOW && liquid) ? lf1[(size_t)q * nc + i] : 0.0;
+  for (int q = 0; q < 19; ++q) lfo[q] = (FLOW && live1) ? lf1[(size_t)q * nc + i] : 0.0;
   for (int q = 0; q < 7; ++q) lgo[q] = lg1[(size_t)q * nc + i];
   collide_adjoint<FLOW>(fl, gl, liquid, P, lfo, lgo, lfl, lgl);
-  if (FLOW)
+  if (FLOW && liquid)  // read only at liquid cells
     for (int q = 0; q < 19; ++q) lfh[(size_t)q * nc + i] = lfl[q];
   for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = lgl[q];
 }
@@ -511,8 +511,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(
 template <typename Ts, bool FLOW, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_stream(
     const double* __restrict__ s0, const int* __restrict__ cnt, const double* __restrict__ lfh,
-    const double* __restrict__ lgh, const double* __restrict__ lf1, double* __restrict__ lf0,
-    double* __restrict__ lg0, KParams P) {
+    const double* __restrict__ lgh, double* __restrict__ lf0, double* __restrict__ lg0,
+    KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= n) return;
@@ -567,17 +567,14 @@ __global__ __launch_bounds__(256) void k_adj_stream(
     }
     lg0[(size_t)p * nc + i] = acc;
   }
-  if (FLOW) {
+  // adjoint of f before the step: only liquid cells read their f (solid
+  // cells hold dead data, whose adjoint is zero and is not stored)
+  if (FLOW && L) {
     for (int p = 0; p < 19; ++p) {
-      double v;
-      if (L) {
-        const int yx = x + ex19(p), yy = y + ey19(p), yz = z + ez19(p);
-        const bool pulled = G.in(yx, yy, yz) && liquid_at<MZ>(cnt, yx, yy, yz, n);
-        v = pulled ? lfh[(size_t)p * nc + G.cell(yx, yy, yz)] : lfh[(size_t)opp19(p) * nc + i];
-      } else {
-        v = lf1[(size_t)p * nc + i];  // solid cells carry f through unchanged
-      }
-      lf0[(size_t)p * nc + i] = v;
+      const int yx = x + ex19(p), yy = y + ey19(p), yz = z + ez19(p);
+      const bool pulled = G.in(yx, yy, yz) && liquid_at<MZ>(cnt, yx, yy, yz, n);
+      lf0[(size_t)p * nc + i] =
+          pulled ? lfh[(size_t)p * nc + G.cell(yx, yy, yz)] : lfh[(size_t)opp19(p) * nc + i];
     }
   }
 }
@@ -704,12 +701,12 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   const Ts* g0 = static_cast<const Ts*>(A.g0);
   const Ts* g1 = static_cast<const Ts*>(A.g1);
   hipLaunchKernelGGL((k_adj_front<Ts, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.s1, A.th, A.ls1,
-                     A.lg1, A.lf1, A.out5, A.own, A.lth, P);
+                     A.lg1, A.out5, A.own, A.lth, P);
   hipLaunchKernelGGL(k_adj_front_gather, gcol, bcol, 0, st, A.own, A.out5, A.ls0, n);
-  hipLaunchKernelGGL((k_adj_collide<Ts, FLOW, MZ>), gcell, bcell, 0, st, f0, g0, A.s0, A.th, A.cnt,
-                     A.lf1, A.lg1, A.lfh, A.lgh, P);
+  hipLaunchKernelGGL((k_adj_collide<Ts, FLOW, MZ>), gcell, bcell, 0, st, f0, g0, A.s0, A.s1, A.th,
+                     A.cnt, A.lf1, A.lg1, A.lfh, A.lgh, P);
   hipLaunchKernelGGL((k_adj_stream<Ts, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.lfh, A.lgh,
-                     A.lf1, A.lf0, A.lg0, P);
+                     A.lf0, A.lg0, P);
   hipLaunchKernelGGL((k_adj_interface<Ts, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, A.lgh, A.ls0,
                      A.lth, P);
   return hipGetLastError();

@@ -42,8 +42,12 @@ template <> struct Compute<float> { using type = LBM_F32_FLOW_T; using gtype = L
 #define LBM_STOCHASTIC_ROUNDING 1
 #endif
 
-// One 32-bit random stream per cell and step (counter based: a mix of the
-// cell index and the step; each stored value advances it by one LCG step).
+// Random bits of the rounding: one 32-bit hash per cell and step (a mix of
+// the cell index and the step), then a Weyl sequence over the values the cell
+// stores (each adds the 32-bit golden-ratio constant).  Every value's offset
+// is uniform over the hash, so its rounding error has zero mean; within a
+// cell the offsets are spread evenly (low discrepancy), and advancing the
+// stream costs one integer add instead of a 32-bit multiply.
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -53,7 +57,7 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   return x;
 }
 __device__ __forceinline__ uint32_t next_rand(uint32_t& st) {
-  st = st * 1664525u + 1013904223u;
+  st += 0x9e3779b9u;
   return st;
 }
 

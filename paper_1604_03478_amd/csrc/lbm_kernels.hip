@@ -239,46 +239,52 @@ __device__ __forceinline__ void update_cell(
   const bool fast = interior & (all_liq | all_sol);
 
   const Rates<C, G> r = make_rates<C, G>(P);
-  // this row and the rows the directions pull from (valid rows only)
-  const Ts* g_self = row_ptr<7>(gs, P, y, z);
-  const Ts* f_self = row_ptr<19>(fs, P, y, z);
-  auto g_src = [&](int q) { return row_ptr<7>(gs, P, y - ey7(q), z - ez7(q)); };
-  auto f_src = [&](int q) { return row_ptr<19>(fs, P, y - ey19(q), z - ez19(q)); };
 
   C f[19];
   G g[7];
 
   if (__all(fast)) {
     // ---------- fast path: one phase, only x walls possible ----------
+    // Every source row lies in the 3x3 block of rows around (y, z).  Offsets
+    // are counted from the block's first row (y - 1, z - 1), so all loads of
+    // a distribution share one uniform base and differ by a 32-bit lane
+    // offset; an x-wall bounce-back selects another offset, not another
+    // pointer, and the loads of all directions stay in flight together.
+    const Ts* gb = row_ptr<7>(gs, P, y - 1, z - 1);
+    const Ts* fb = row_ptr<19>(fs, P, y - 1, z - 1);
+    const uint32_t un = (uint32_t)n;
+    auto row_ofs = [&](uint32_t Q, int dy, int dz) {  // row (y + dy, z + dz)
+      return ((uint32_t)(1 + dz) * un + (uint32_t)(1 + dy)) * (Q * pitch);
+    };
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
       const int ex = ex7(q);
-      if (ex == 0) {
-        g[q] = load_stream<G>(g_src(q), q * pitch + x);
-      } else {
-        // adiabatic x wall: bounce-back, chosen by a per-lane address select
-        // (no branch, so the loads of all directions stay in flight together)
+      uint32_t i = row_ofs(7, -ey7(q), -ez7(q)) + q * pitch + (uint32_t)(x - ex);
+      if (ex != 0) {  // adiabatic x wall: bounce-back
         const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
-        const uint32_t i = wall ? opp7(q) * pitch + x : q * pitch + (x - ex);
-        g[q] = load_stream<G>(wall ? g_self : g_src(q), i);
+        i = wall ? row_ofs(7, 0, 0) + opp7(q) * pitch + x : i;
       }
+      g[q] = load_stream<G>(gb, i);
     }
     if (FLOW && liquid) {
 #pragma unroll
       for (int q = 0; q < 19; ++q) {
         const int ex = ex19(q);
-        if (ex == 0) {
-          f[q] = load_stream<C>(f_src(q), q * pitch + x);
-        } else {
-          // no-slip x wall: halfway bounce-back by a per-lane address select
+        uint32_t i = row_ofs(19, -ey19(q), -ez19(q)) + q * pitch + (uint32_t)(x - ex);
+        if (ex != 0) {  // no-slip x wall: halfway bounce-back
           const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
-          const uint32_t i = wall ? opp19(q) * pitch + x : q * pitch + (x - ex);
-          f[q] = load_stream<C>(wall ? f_self : f_src(q), i);
+          i = wall ? row_ofs(19, 0, 0) + opp19(q) * pitch + x : i;
         }
+        f[q] = load_stream<C>(fb, i);
       }
     }
   } else {
     // ---------- general path: walls and the front, link by link ----------
+    // this row and the rows the directions pull from (valid rows only)
+    const Ts* g_self = row_ptr<7>(gs, P, y, z);
+    const Ts* f_self = row_ptr<19>(fs, P, y, z);
+    auto g_src = [&](int q) { return row_ptr<7>(gs, P, y - ey7(q), z - ez7(q)); };
+    auto f_src = [&](int q) { return row_ptr<19>(fs, P, y - ey19(q), z - ez19(q)); };
     const double s_self = s[col];
     const G wTm = G(kW7Axis) * (G)(P.t_m - P.tref);
 #pragma unroll
