@@ -55,8 +55,10 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_CELL = {"f32": 208, "f16s": 104, "bf16s": 104, "f64": 416}
 # one reverse step, FP32 storage, FP64 adjoint: transposed collision (state
 # 104 B + adjoint 208 B read, 208 B written) and transposed streaming (208 B
-# read, 208 B written)
-ADJ_BYTES_PER_CELL = 520 + 416
+# read, 208 B written) in a liquid cell; a solid cell moves only g and its
+# adjoint (28 + 56 B read, 56 B written; 56 B read, 56 B written)
+ADJ_BYTES_LIQUID = 520 + 416
+ADJ_BYTES_SOLID = 140 + 112
 # sources the stream-collide kernel is compiled from
 KERNEL_SRC = [os.path.join(ROOT, "paper_1604_03478_amd", "csrc", f)
               for f in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h")]
@@ -169,15 +171,17 @@ def adjoint_timing(stream, n: int, steps: int, every: int):
     grad = sim.adjoint(1.0, device=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    fl = sim.liquid_fraction()
     sim.close()
     fwd, adj = (t1 - t0) * 1e3, (t2 - t1) * 1e3
     rev = max(adj - plain * steps, 0.0) / steps
-    return {"n": n, "steps": steps, "every_k": every,
+    # algorithmic bytes of a reverse step at the final liquid fraction
+    rev_bytes = n ** 3 * (fl * ADJ_BYTES_LIQUID + (1.0 - fl) * ADJ_BYTES_SOLID)
+    return {"n": n, "steps": steps, "every_k": every, "liquid_fraction": round(fl, 6),
             "plain_ms_per_step": round(plain, 4), "forward_ckpt_ms": round(fwd, 2),
             "adjoint_ms": round(adj, 2), "adjoint_over_forward": round(adj / (plain * steps), 2),
             "reverse_ms_per_step_est": round(rev, 4),
-            "reverse_GBps_est": round(ADJ_BYTES_PER_CELL * n ** 3 / (rev * 1e-3) / 1e9, 1)
-            if rev > 0 else None,
+            "reverse_GBps_est": round(rev_bytes / (rev * 1e-3) / 1e9, 1) if rev > 0 else None,
             "grad_norm": float(torch.linalg.norm(grad).item())}
 
 
@@ -206,21 +210,28 @@ def traffic_from_profile(n: int):
 
 def cpu_baseline(n: int, steps: int):
     """The FP64 oracle, as it stands, on this host's cores: a bounded sample
-    of the same workload (a few steps of the all-liquid 256^3 state)."""
+    of the same workload (a few steps of the all-liquid 256^3 state) with all
+    the threads OpenMP gives it, then one step on one thread."""
     from oracle import OracleSim
-    from oracle.oracle import build_oracle
-    build_oracle()
+    from oracle import oracle as orc_mod
+    orc_mod.build_oracle()
     orc = OracleSim(n, ra=1e5, pr=1.0, ste=0.1, t_h=1.0, t_c=0.0, t_m=0.0, ma=0.1,
                     s0=float(n), heating=0, flow=1)
+    cores = orc_mod.threads()
     orc.step(1)  # first touch of the buffers
     t0 = time.perf_counter()
     orc.step(steps)
     el = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    orc_mod.set_threads(1)
+    t1 = time.perf_counter()
+    orc.step(1)
+    el1 = time.perf_counter() - t1
+    orc_mod.set_threads(cores)
     return {"value": n ** 3 * steps / el / 1e6, "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{steps} steps of the {n}^3 all-liquid double-MRT state "
-                      f"({n ** 3 * steps / 1e6:.1f}M FP64 cell updates, {el:.1f} s)"}
+            "kind": "oracle", "value_1thread": n ** 3 / el1 / 1e6,
+            "sample": f"{steps} steps of the {n}^3 all-liquid double-MRT state on {cores} "
+                      f"threads ({n ** 3 * steps / 1e6:.1f}M FP64 cell updates, {el:.1f} s), "
+                      f"then 1 step on 1 thread ({el1:.1f} s)"}
 
 
 def precision_study(n: int, steps: int, stream):

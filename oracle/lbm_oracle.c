@@ -31,6 +31,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q19 19
 #define Q7 7
@@ -1173,4 +1176,21 @@ void orc_equilibrium_moments(double rho, double jx, double jy, double jz,
 void orc_guo_force(const orc_sim *S, double ux, double uy, double uz, double Fx,
                    double Fy, double Fz, double *F) {
   guo19(S->w19, ux, uy, uz, Fx, Fy, Fz, F);
+}
+
+/* Threads of the cell loop (OpenMP); for timing the oracle itself. */
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_set_threads(int k) {
+#ifdef _OPENMP
+  if (k > 0) omp_set_num_threads(k);
+#else
+  (void)k;
+#endif
 }

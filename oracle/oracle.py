@@ -93,9 +93,20 @@ def _load():
         lib.orc_guo_force.argtypes = [vp, d, d, d, d, d, d, dp]
         lib.orc_record.argtypes = [vp, ll]
         lib.orc_adjoint.argtypes = [vp, dp, dp, dp, dp]
+        lib.orc_threads.restype = i
+        lib.orc_set_threads.argtypes = [i]
         assert lib.orc_sizeof_params() == ctypes.sizeof(_Params), "oracle params layout mismatch"
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's cell loop uses."""
+    return int(_load().orc_threads())
+
+
+def set_threads(k: int) -> None:
+    _load().orc_set_threads(int(k))
 
 
 def _dp(a: np.ndarray):

@@ -38,6 +38,13 @@ namespace {
 constexpr double kD19[19] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36,
                              72, 12,   24,  4,  4,  4,  8,  8,  8};
 constexpr double kD7[7] = {7, 2, 2, 2, 42, 12, 4};
+// their reciprocals (a multiply instead of an FP64 divide per moment)
+constexpr double kInvD19[19] = {1.0 / 19, 1.0 / 2394, 1.0 / 252, 1.0 / 10, 1.0 / 40, 1.0 / 10,
+                                1.0 / 40, 1.0 / 10,   1.0 / 40,  1.0 / 36, 1.0 / 72, 1.0 / 12,
+                                1.0 / 24, 1.0 / 4,    1.0 / 4,   1.0 / 4,  1.0 / 8,  1.0 / 8,
+                                1.0 / 8};
+constexpr double kInvD7[7] = {1.0 / 7, 1.0 / 2, 1.0 / 2, 1.0 / 2, 1.0 / 42, 1.0 / 12, 1.0 / 4};
+static_assert(kInvD19[1] * kD19[1] > 0.999 && kInvD7[4] * kD7[4] > 0.999, "norms");
 
 // m = M v for the orthogonal D3Q19 basis (integer structure, pairwise sums)
 __device__ __forceinline__ void m19(const double (&f)[19], double (&m)[19]) {
@@ -192,6 +199,46 @@ __device__ __forceinline__ double sv(const Ts* a, const KParams& P, int q, uint3
       a[((uint64_t)row * Q + q) * P.pitch + x]);
 }
 
+// stored population q of cell (x, y, z), in FP64
+template <int Q, typename Ts>
+__device__ __forceinline__ double sv_at(const Ts* a, const KParams& P, int q, int x, int y, int z) {
+  return (double)static_cast<typename Compute<Ts>::type>(a[pop_index(P, Q, q, x, y, z)]);
+}
+
+// Fast-path test of the reverse kernels: away from the y and z walls, and
+// every cell within two columns and two heights in one phase (the transposed
+// streaming reaches the source of a neighbour's link, two cells away).
+template <bool MZ>
+__device__ __forceinline__ bool adj_fast(const int* cmin2, const int* cmax2, int x, int y, int z,
+                                         int n) {
+  const int a = melt_of<MZ>(y, z), c = col_of<MZ>(x, y, z, n);
+  const bool interior = (y > 0) & (y < n - 1) & (z > 0) & (z < n - 1);
+  return interior & (((a + 2) < cmin2[c]) | ((a - 2) >= cmax2[c]));
+}
+
+// pulled populations of a cell on the fast path: regular pulls, bounce-back
+// at the adiabatic / no-slip x walls only
+template <typename Ts, bool FLOW>
+__device__ __forceinline__ void pull_fast(const Ts* f, const Ts* g, int x, int y, int z,
+                                          bool liquid, const KParams& P, double (&fl)[19],
+                                          double (&gl)[7]) {
+  const int n = P.n;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const int sx = x - ex7(q);
+    gl[q] = ((unsigned)sx < (unsigned)n) ? sv_at<7>(g, P, q, sx, y - ey7(q), z - ez7(q))
+                                         : sv_at<7>(g, P, opp7(q), x, y, z);
+  }
+  if (FLOW && liquid) {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      const int sx = x - ex19(q);
+      fl[q] = ((unsigned)sx < (unsigned)n) ? sv_at<19>(f, P, q, sx, y - ey19(q), z - ez19(q))
+                                           : sv_at<19>(f, P, opp19(q), x, y, z);
+    }
+  }
+}
+
 // pulled (pre-collision) shifted populations of one cell, in FP64
 template <typename Ts, bool FLOW, bool MZ>
 __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const double* th,
@@ -261,7 +308,7 @@ __device__ void collide_adjoint(const double (&fl)[19], const double (&gl)[7], b
   double lns[7], ln[7], lne[7];
   m7(lgo, lns);
   for (int k = 0; k < 7; ++k) {
-    lns[k] /= kD7[k];
+    lns[k] *= kInvD7[k];
     ln[k] = (1.0 - Q[k]) * lns[k];
     lne[k] = Q[k] * lns[k];
   }
@@ -275,7 +322,7 @@ __device__ void collide_adjoint(const double (&fl)[19], const double (&gl)[7], b
     double lms[19], lm[19], le[19], lF[19];
     m19(lfo, lms);
     for (int k = 0; k < 19; ++k) {
-      lms[k] /= kD19[k];
+      lms[k] *= kInvD19[k];
       lm[k] = (1.0 - S[k]) * lms[k];
       le[k] = S[k] * lms[k];
       lF[k] = (1.0 - 0.5 * S[k]) * lms[k];
@@ -486,7 +533,7 @@ template <typename Ts, bool FLOW, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_collide(
     const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
     const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
-    const double* __restrict__ lf1,
+    const int* __restrict__ cmin2, const int* __restrict__ cmax2, const double* __restrict__ lf1,
     const double* __restrict__ lg1, double* __restrict__ lfh, double* __restrict__ lgh,
     KParams P) {
   const int n = P.n;
@@ -499,7 +546,10 @@ __global__ __launch_bounds__(256) void k_adj_collide(
   // melting cell is refilled), so its adjoint is zero and is not stored
   const bool live1 = liquid && melt_of<MZ>(y, z) < count_liquid(s1[col_of<MZ>(x, y, z, n)], n);
   double fl[19], gl[7], lfo[19], lgo[7], lfl[19], lgl[7];
-  pull_cell<Ts, FLOW, MZ>(f0, g0, s0, th, cnt, x, y, z, liquid, P, fl, gl);
+  if (__all(adj_fast<MZ>(cmin2, cmax2, x, y, z, n)))
+    pull_fast<Ts, FLOW>(f0, g0, x, y, z, liquid, P, fl, gl);
+  else
+    pull_cell<Ts, FLOW, MZ>(f0, g0, s0, th, cnt, x, y, z, liquid, P, fl, gl);
   for (int q = 0; q < 19; ++q) lfo[q] = (FLOW && live1) ? lf1[(size_t)q * nc + i] : 0.0;
   for (int q = 0; q < 7; ++q) lgo[q] = lg1[(size_t)q * nc + i];
   collide_adjoint<FLOW>(fl, gl, liquid, P, lfo, lgo, lfl, lgl);
@@ -510,7 +560,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(
 
 template <typename Ts, bool FLOW, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_stream(
-    const double* __restrict__ s0, const int* __restrict__ cnt, const double* __restrict__ lfh,
+    const double* __restrict__ s0, const int* __restrict__ cnt, const int* __restrict__ cmin2,
+    const int* __restrict__ cmax2, const double* __restrict__ lfh,
     const double* __restrict__ lgh, double* __restrict__ lf0, double* __restrict__ lg0,
     KParams P) {
   const int n = P.n;
@@ -521,6 +572,28 @@ __global__ __launch_bounds__(256) void k_adj_stream(
   const uint32_t i = G.cell(x, y, z);
   const bool L = liquid_at<MZ>(cnt, x, y, z, n);
   auto LG = [&](int q, uint32_t j) { return lgh[(size_t)q * nc + j]; };
+
+  if (__all(adj_fast<MZ>(cmin2, cmax2, x, y, z, n))) {
+    // one phase all around: each stored population was read by the regular
+    // pull of the neighbour x + e_p, or by this cell's bounce-back at an x wall
+#pragma unroll
+    for (int p = 0; p < 7; ++p) {
+      const int ex = ex7(p);
+      const bool in = (unsigned)(x + ex) < (unsigned)n;
+      lg0[(size_t)p * nc + i] =
+          in ? LG(p, G.cell(x + ex, y + ey7(p), z + ez7(p))) : LG(opp7(p), i);
+    }
+    if (FLOW && L) {
+#pragma unroll
+      for (int p = 0; p < 19; ++p) {
+        const int ex = ex19(p);
+        const bool in = (unsigned)(x + ex) < (unsigned)n;
+        lf0[(size_t)p * nc + i] = in ? lfh[(size_t)p * nc + G.cell(x + ex, y + ey19(p), z + ez19(p))]
+                                     : lfh[(size_t)opp19(p) * nc + i];
+      }
+    }
+    return;
+  }
 
   for (int p = 0; p < 7; ++p) {
     const int ex = ex7(p), ey = ey7(p), ez = ez7(p), q = opp7(p);
@@ -696,7 +769,9 @@ template <typename Ts, bool FLOW, bool MZ>
 hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st) {
   const int n = P.n;
   const dim3 bcol(64, 1, 1), gcol((n + 63) / 64, n, 1);
-  const dim3 bcell(64, 1, 1), gcell((n + 63) / 64, n, n);
+  // one lattice row per workgroup (up to 256 lanes)
+  const int bx = n >= 256 ? 256 : ((n + 63) / 64) * 64;
+  const dim3 bcell(bx, 1, 1), gcell((n + bx - 1) / bx, n, n);
   const Ts* f0 = static_cast<const Ts*>(A.f0);
   const Ts* g0 = static_cast<const Ts*>(A.g0);
   const Ts* g1 = static_cast<const Ts*>(A.g1);
@@ -704,8 +779,9 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
                      A.lg1, A.out5, A.own, A.lth, P);
   hipLaunchKernelGGL(k_adj_front_gather, gcol, bcol, 0, st, A.own, A.out5, A.ls0, n);
   hipLaunchKernelGGL((k_adj_collide<Ts, FLOW, MZ>), gcell, bcell, 0, st, f0, g0, A.s0, A.s1, A.th,
-                     A.cnt, A.lf1, A.lg1, A.lfh, A.lgh, P);
-  hipLaunchKernelGGL((k_adj_stream<Ts, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.lfh, A.lgh,
+                     A.cnt, A.cmin2, A.cmax2, A.lf1, A.lg1, A.lfh, A.lgh, P);
+  hipLaunchKernelGGL((k_adj_stream<Ts, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
+                     A.cmax2, A.lfh, A.lgh,
                      A.lf0, A.lg0, P);
   hipLaunchKernelGGL((k_adj_interface<Ts, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, A.lgh, A.ls0,
                      A.lth, P);

@@ -66,7 +66,7 @@ struct AdjData {
   std::vector<void*> sf, sg;  // segment states 0..K
   std::vector<double*> ss;
   int *cnt = nullptr, *cmin = nullptr, *cmax = nullptr, *melted = nullptr, *frozen = nullptr,
-      *flag = nullptr;
+      *flag = nullptr, *cmin2 = nullptr, *cmax2 = nullptr;
   double *lf[2] = {nullptr, nullptr}, *lg[2] = {nullptr, nullptr}, *ls[2] = {nullptr, nullptr};
   double *lfh = nullptr, *lgh = nullptr, *out5 = nullptr, *own = nullptr, *lth = nullptr;
 };
@@ -135,7 +135,8 @@ void release_adjoint(AdjData& a) {
   free_all(a.sf);
   free_all(a.sg);
   free_all(a.ss);
-  void* ptrs[] = {a.cnt, a.cmin, a.cmax, a.melted, a.frozen, a.flag, a.lf[0], a.lf[1], a.lg[0],
+  void* ptrs[] = {a.cnt,   a.cmin,  a.cmax,  a.cmin2, a.cmax2, a.melted, a.frozen, a.flag,
+                  a.lf[0], a.lf[1], a.lg[0],
                   a.lg[1], a.ls[0], a.ls[1], a.lfh, a.lgh, a.out5, a.own, a.lth};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -738,6 +739,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   }
   if (!a.lg[0]) {
     if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cmin, nn)) || (rc = dalloc(&a.cmax, nn)) ||
+        (rc = dalloc(&a.cmin2, nn)) || (rc = dalloc(&a.cmax2, nn)) ||
         (rc = dalloc(&a.melted, nn)) || (rc = dalloc(&a.frozen, nn)) || (rc = dalloc(&a.flag, 1)) ||
         (rc = dalloc(&a.lg[0], 7 * nc)) || (rc = dalloc(&a.lg[1], 7 * nc)) ||
         (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
@@ -779,6 +781,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
     // reverse the segment
     for (int64_t t = len - 1; t >= 0; --t) {
       HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
+      HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin2, a.cmax2, c->stream, 2));
       lbmk::AdjointStep A;
       A.f0 = a.sf[t];
       A.g0 = a.sg[t];
@@ -787,6 +790,8 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
       A.s1 = a.ss[t + 1];
       A.th = c->th;
       A.cnt = a.cnt;
+      A.cmin2 = a.cmin2;
+      A.cmax2 = a.cmax2;
       A.lf1 = a.lf[cur];
       A.lg1 = a.lg[cur];
       A.ls1 = a.ls[cur];

@@ -64,9 +64,10 @@ hipError_t launch_front(int kind, const KParams& P, const double* s_old, double*
                         int* frozen, int* flag, const int* replay, const int* replay_next,
                         int* record, hipStream_t st);
 
-// cmin/cmax from cnt.
+// cmin/cmax: min and max of cnt over the (2 radius + 1)^2 columns around each
+// column (radius 1 for the step kernel, 2 for the adjoint's fast path).
 hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
-                                hipStream_t st);
+                                hipStream_t st, int radius = 1);
 
 // cnt from s.
 hipError_t launch_counts(const KParams& P, const double* s, int* cnt, hipStream_t st);
@@ -104,6 +105,8 @@ struct AdjointStep {
   const double* s1;  // state t+1 (post-collision g and front)
   const double* th;
   const int* cnt;    // liquid counts of state t
+  const int* cmin2;  // their min / max over the 5x5 columns around each column
+  const int* cmax2;
   double* lf1;
   double* lg1;
   const double* ls1;
