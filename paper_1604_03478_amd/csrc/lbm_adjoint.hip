@@ -30,6 +30,7 @@
 #include <stdint.h>
 
 #include "lbm_device.h"
+#include "lbm_adjoint.h"
 #include "lbm_internal.h"
 
 namespace lbmk {

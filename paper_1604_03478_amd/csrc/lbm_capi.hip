@@ -1,6 +1,6 @@
 // Host side of liblbmmelt: the C ABI declared in include/lbmmelt.h.
 //
-// Owns the device memory of one simulation (double-buffered SoA
+// Owns the device memory of one simulation (double-buffered row-interleaved
 // distributions in HBM, the front, per-column counters), maps the physical
 // parameters of the problem statement (section 1 of Li, Yang & Zhang,
 // arXiv:1604.03478) to lattice units, and enqueues the gfx950 kernels on one
@@ -16,6 +16,7 @@
 #include <new>
 #include <vector>
 
+#include "lbm_adjoint.h"
 #include "lbm_internal.h"
 #include "lbmmelt.h"
 

@@ -7,10 +7,13 @@
 //   front: Eq. (6), one height per column along the melt axis.
 //
 // Design (MI355X):
-//   * SoA storage, x fastest; one thread per cell, 64 lanes of a wave along
-//     x, so every population load and store of a wave is one contiguous
-//     256 B (FP32) segment.  Pull streaming: each stored value is read once
-//     and written once per step (208 B per FP32 cell update).
+//   * Row-interleaved storage (lbm_device.h): the 19 (f) or 7 (g) direction
+//     rows of one lattice row (y, z) are contiguous, x fastest.  One
+//     workgroup per lattice row, one thread per cell, so every population
+//     load and store of a wave is one contiguous 256 B (FP32) segment and a
+//     row update reads 9 neighbouring row blocks and writes its own.  Pull
+//     streaming: each stored value is read once and written once per step
+//     (208 B per FP32 cell update).
 //   * Populations are stored shifted (f - w*rho0, g - w*tref) and the whole
 //     collision works on deviations, which keeps FP32 and 16-bit storage
 //     accurate; tref = (t_h + t_m)/2 centres the liquid temperature range.

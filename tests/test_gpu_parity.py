@@ -249,9 +249,8 @@ def _one_step_random(n, prec, seed, heating="y0", front=(0.0, None), flow=1):
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("heating", ["y0", "z0"])
 def test_one_step_random_state_128(prec, heating):
-    """128^3: the row-wave kernel (two cells per lane for 32- and 16-bit
-    storage) and its per-cell fallback near the front, one step from a
-    random state.  FP64 gets a rough front (heights independent per column,
+    """128^3: several workgroups of rows, the fast path and the general path
+    near the front, one step from a random state.  FP64 gets a rough front (heights independent per column,
     many lateral interface links) and round-off bars.  The reduced
     precisions get a smooth front: on a rough one the slope factor
     1 + s_x^2 + s_z^2 of Eq. (6) reaches ~800 and amplifies any rounding of T
