@@ -157,8 +157,9 @@ def test_sixteen_bit_shifted_storage(prec, unit_roundoff):
     """16-bit storage of the shifted populations with FP32 collision, 40^3,
     20 steps.
 
-    Bound from the arithmetic: the stored deviations g_q - w_q T_m are at
-    most 1/4 in magnitude (rest population, T <= 1), so one store perturbs
+    Bound from the arithmetic: the stored deviations g_q - w_q T_ref
+    (T_ref = (t_h + t_m)/2) are below 1/4 in magnitude (the rest population
+    w_0 (T - T_ref) is at most 1/8 for T in [0, 1]), so one store perturbs
     T = sum of 7 values by at most 7 * 1/4 * u; ignoring any damping by
     diffusion the error after t steps is at most t times that.  Rounding of
     the same near-steady values repeats step after step, so the error does
