@@ -21,6 +21,14 @@
  * oracle implements the readings documented with the repository's design
  * notes; each such reading is marked "reading:" below.
  *
+ * Parity unpinned (no value in the paper or closed form fixes them; the
+ * GPU-oracle comparison is their only quantitative check): the convection
+ * results themselves (the paper's figures are not available), the values of
+ * the non-hydrodynamic rates of Eq. (2) and the rate q_e of Eq. (4).  Every
+ * other function is pinned by tests against the paper's tables, closed forms
+ * (Neumann, Guo forcing moments, BGK limit, diffusion decay rates),
+ * invariants and finite differences (the reverse sweep).
+ *
  * Style: plain loops in IEEE double, dense 19x19 / 7x7 matrices, the inverse
  * transforms obtained by Gauss-Jordan elimination, no fusion or reordering of
  * the step beyond the order the method defines.  Loop order is fixed
