@@ -217,34 +217,48 @@ __device__ __forceinline__ bool adj_fast(const int* cmin2, const int* cmax2, int
   return interior & (((a + 2) < cmin2[c]) | ((a - 2) >= cmax2[c]));
 }
 
+// What the transposed collision needs of the pulled populations: the
+// collision is affine in them except through the equilibria and the force,
+// which depend on T and u only, so its Jacobian is fixed by T - tref = sum g
+// and j = sum e f (of the shifted populations; the shifts add nothing).
+struct Macro {
+  double Tt = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  __device__ void add_g(double v) { Tt += v; }
+  __device__ void add_f(int q, double v) {
+    jx += ex19(q) * v;
+    jy += ey19(q) * v;
+    jz += ez19(q) * v;
+  }
+};
+
 // pulled populations of a cell on the fast path: regular pulls, bounce-back
 // at the adiabatic / no-slip x walls only
 template <typename Ts, bool FLOW>
 __device__ __forceinline__ void pull_fast(const Ts* f, const Ts* g, int x, int y, int z,
-                                          bool liquid, const KParams& P, double (&fl)[19],
-                                          double (&gl)[7]) {
+                                          bool liquid, const KParams& P, Macro& M) {
   const int n = P.n;
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
     const int sx = x - ex7(q);
-    gl[q] = ((unsigned)sx < (unsigned)n) ? sv_at<7>(g, P, q, sx, y - ey7(q), z - ez7(q))
-                                         : sv_at<7>(g, P, opp7(q), x, y, z);
+    M.add_g(((unsigned)sx < (unsigned)n) ? sv_at<7>(g, P, q, sx, y - ey7(q), z - ez7(q))
+                                         : sv_at<7>(g, P, opp7(q), x, y, z));
   }
   if (FLOW && liquid) {
 #pragma unroll
-    for (int q = 0; q < 19; ++q) {
+    for (int q = 1; q < 19; ++q) {  // the rest population carries no momentum
       const int sx = x - ex19(q);
-      fl[q] = ((unsigned)sx < (unsigned)n) ? sv_at<19>(f, P, q, sx, y - ey19(q), z - ez19(q))
-                                           : sv_at<19>(f, P, opp19(q), x, y, z);
+      M.add_f(q, ((unsigned)sx < (unsigned)n) ? sv_at<19>(f, P, q, sx, y - ey19(q), z - ez19(q))
+                                              : sv_at<19>(f, P, opp19(q), x, y, z));
     }
   }
 }
 
-// pulled (pre-collision) shifted populations of one cell, in FP64
+// pulled (pre-collision) shifted populations of one cell (general path), in
+// FP64, reduced to T and j
 template <typename Ts, bool FLOW, bool MZ>
 __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const double* th,
                           const int* cnt, int x, int y, int z, bool liquid, const KParams& P,
-                          double (&fl)[19], double (&gl)[7]) {
+                          Macro& M) {
   const Geo G{P.n, (uint32_t)P.n * (uint32_t)P.n};
   const int n = P.n;
   const uint32_t i = G.cell(x, y, z);
@@ -276,33 +290,32 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
         v = -gp / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * sv<7>(g, P, q, i) + wTm / d;
       }
     }
-    gl[q] = v;
+    M.add_g(v);
   }
   if (FLOW && liquid) {
-    for (int q = 0; q < 19; ++q) {
+    for (int q = 1; q < 19; ++q) {
       const int sx = x - ex19(q), sy = y - ey19(q), sz = z - ez19(q);
       const bool ok = G.in(sx, sy, sz) && liquid_at<MZ>(cnt, sx, sy, sz, n);
-      fl[q] = ok ? sv<19>(f, P, q, G.cell(sx, sy, sz)) : sv<19>(f, P, opp19(q), i);
+      M.add_f(q, ok ? sv<19>(f, P, q, G.cell(sx, sy, sz)) : sv<19>(f, P, opp19(q), i));
     }
   }
 }
 
-// Transposed collision Jacobian of one cell: (lfo, lgo) -> (lfl, lgl)
+// Transposed collision Jacobian of one cell at the state (T, u) of its
+// pulled populations: (lfo, lgo) -> (lfl, lgl)
 template <bool FLOW>
-__device__ void collide_adjoint(const double (&fl)[19], const double (&gl)[7], bool liquid,
-                                const KParams& P, const double (&lfo)[19],
-                                const double (&lgo)[7], double (&lfl)[19], double (&lgl)[7]) {
+__device__ void collide_adjoint(const Macro& M, bool liquid, const KParams& P,
+                                const double (&lfo)[19], const double (&lgo)[7],
+                                double (&lfl)[19], double (&lgl)[7]) {
   const bool fluid = FLOW && liquid;
-  double Tt = 0.0;  // T - tref
-  for (int q = 0; q < 7; ++q) Tt += gl[q];
+  const double Tt = M.Tt;  // T - tref
   const double T = Tt + P.tref;
-  double ux = 0.0, uy = 0.0, uz = 0.0, Fz = 0.0, m[19];
+  double ux = 0.0, uy = 0.0, uz = 0.0, Fz = 0.0;
   if (fluid) {
-    m19(fl, m);
     Fz = P.gbeta * (Tt + P.tref - P.t0);
-    ux = m[3];
-    uy = m[5];
-    uz = m[7] + 0.5 * Fz;
+    ux = M.jx;
+    uy = M.jy;
+    uz = M.jz + 0.5 * Fz;
   }
   // ---- energy distribution: g' = N^T D^-1 [(I - Q) N gl + Q n_eq(T, u)] ----
   const double Q[7] = {0.0, P.q_j, P.q_j, P.q_j, P.q_e, P.q_e, P.q_e};
@@ -546,14 +559,15 @@ __global__ __launch_bounds__(256) void k_adj_collide(
   // f of a cell that is solid after the step is dead data (never read; a
   // melting cell is refilled), so its adjoint is zero and is not stored
   const bool live1 = liquid && melt_of<MZ>(y, z) < count_liquid(s1[col_of<MZ>(x, y, z, n)], n);
-  double fl[19], gl[7], lfo[19], lgo[7], lfl[19], lgl[7];
+  Macro M;
   if (__all(adj_fast<MZ>(cmin2, cmax2, x, y, z, n)))
-    pull_fast<Ts, FLOW>(f0, g0, x, y, z, liquid, P, fl, gl);
+    pull_fast<Ts, FLOW>(f0, g0, x, y, z, liquid, P, M);
   else
-    pull_cell<Ts, FLOW, MZ>(f0, g0, s0, th, cnt, x, y, z, liquid, P, fl, gl);
+    pull_cell<Ts, FLOW, MZ>(f0, g0, s0, th, cnt, x, y, z, liquid, P, M);
+  double lfo[19], lgo[7], lfl[19], lgl[7];
   for (int q = 0; q < 19; ++q) lfo[q] = (FLOW && live1) ? lf1[(size_t)q * nc + i] : 0.0;
   for (int q = 0; q < 7; ++q) lgo[q] = lg1[(size_t)q * nc + i];
-  collide_adjoint<FLOW>(fl, gl, liquid, P, lfo, lgo, lfl, lgl);
+  collide_adjoint<FLOW>(M, liquid, P, lfo, lgo, lfl, lgl);
   if (FLOW && liquid)  // read only at liquid cells
     for (int q = 0; q < 19; ++q) lfh[(size_t)q * nc + i] = lfl[q];
   for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = lgl[q];
