@@ -1186,6 +1186,52 @@ void orc_guo_force(const orc_sim *S, double ux, double uy, double uz, double Fx,
   guo19(S->w19, ux, uy, uz, Fx, Fy, Fz, F);
 }
 
+/* ------------------------------------------------------------------------ */
+/* heated-wall Nusselt number (section 3.2, Fig. 4(b) and Fig. 5(b))         */
+
+/* Derivative at xq of the polynomial interpolating (x[k], v[k]), k < m, in
+ * Lagrange form: sum_k v[k] L_k'(xq). */
+static double lagrange_derivative(int m, const double *x, const double *v, double xq) {
+  double d = 0.0;
+  for (int k = 0; k < m; ++k) {
+    double lk = 0.0; /* L_k'(xq) = sum_j [1/(x_k - x_j)] prod_{i != k, j} (xq - x_i)/(x_k - x_i) */
+    for (int j = 0; j < m; ++j) {
+      if (j == k) continue;
+      double term = 1.0 / (x[k] - x[j]);
+      for (int i = 0; i < m; ++i)
+        if (i != k && i != j) term *= (xq - x[i]) / (x[k] - x[i]);
+      lk += term;
+    }
+    d += v[k] * lk;
+  }
+  return d;
+}
+
+/* Local Nusselt number of every column on the heated wall.  The paper plots
+ * it without defining it; reading R16: Nu = -H (dT/da)(a = 0) / (T_h - T_m)
+ * with H = n and a the melt-axis coordinate.  dT/da is the derivative of the
+ * quadratic through the wall point (0, T_w) and the first two cell centres
+ * (1/2 and 3/2) when both are liquid (s > 3/2); for a thinner liquid layer
+ * (0 < s <= 3/2) the chord to the front point (s, T_m); 0 without liquid. */
+void orc_wall_nusselt(const orc_sim *S, double *nu) {
+  int n = S->n;
+  double dT = S->p.t_h - S->p.t_m;
+  for (int c = 0; c < n * n; ++c) {
+    double s = S->s[c], Tw = S->th[c], slope = 0.0;
+    if (s > 1.5) {
+      double x[3] = {0.0, 0.5, 1.5};
+      double v[3] = {Tw, cell_T_of(S, S->g, cell_of_column(S, c, 0)),
+                     cell_T_of(S, S->g, cell_of_column(S, c, 1))};
+      slope = lagrange_derivative(3, x, v, 0.0);
+    } else if (s > 0.0) {
+      double x[2] = {0.0, s};
+      double v[2] = {Tw, S->p.t_m};
+      slope = lagrange_derivative(2, x, v, 0.0);
+    }
+    nu[c] = -(double)n * slope / dT;
+  }
+}
+
 /* Threads of the cell loop (OpenMP); for timing the oracle itself. */
 int orc_threads(void) {
 #ifdef _OPENMP

@@ -93,6 +93,7 @@ def _load():
         lib.orc_guo_force.argtypes = [vp, d, d, d, d, d, d, dp]
         lib.orc_record.argtypes = [vp, ll]
         lib.orc_adjoint.argtypes = [vp, dp, dp, dp, dp]
+        lib.orc_wall_nusselt.argtypes = [vp, dp]
         lib.orc_threads.restype = i
         lib.orc_set_threads.argtypes = [i]
         assert lib.orc_sizeof_params() == ctypes.sizeof(_Params), "oracle params layout mismatch"
@@ -216,6 +217,12 @@ class OracleSim:
         V = np.zeros((self.n, self.n))
         self._lib.orc_front_velocity(self._h, _dp(V))
         return V
+
+    def wall_nusselt(self) -> np.ndarray:
+        """Local Nusselt number on the heated wall, per column (n x n)."""
+        out = np.zeros((self.n, self.n))
+        self._lib.orc_wall_nusselt(self._h, _dp(out))
+        return out
 
     def derived(self) -> Derived:
         out = np.zeros(9)
