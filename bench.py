@@ -31,6 +31,8 @@ Modes:
   --mode adjoint  the checkpointed forward run and the reverse sweep alone
                   (64^3 x 2000 steps with a checkpoint every 100, and
                   256^3 x 100 steps every 10), for rocprofv3
+  --mode paper    the paper's two convection cases (Pr = 0.02, Ra = 25000 to
+                  Fo = 1.00 and Ra = 10000 to Fo = 1.57) at --n (default 256)
   --mode precision
                   storage precision against an FP64 run of the same melting
                   configuration (256^3, 1e5 steps by default): liquid fraction
@@ -185,6 +187,49 @@ def adjoint_timing(stream, n: int, steps: int, every: int):
             "grad_norm": float(torch.linalg.norm(grad).item())}
 
 
+def paper_cases(n: int, stream):
+    """The paper's convection cases (section 3.2): Pr = 0.02, Ste = 0.1,
+    side-heated cube, case 1 Ra = 25000 to Fo = 1.00, case 2 Ra = 10000 to
+    Fo = 1.57 (the same lattice time), FP32 storage: throughput of the whole
+    run and the quantities the paper discusses (liquid fraction against Fo,
+    heated-wall Nusselt numbers, temperature stratification)."""
+    import numpy as np
+    import torch
+    from paper_1604_03478_amd import Config, Sim
+    out = {"mode": "paper", "n": n, "workload": f"convection melting {n}^3, side-heated, "
+           "Pr=0.02, Ste=0.1, fp32 storage, front seeded at s0=1"}
+    for case, ra, fo_end in ((1, 25000.0, 1.00), (2, 10000.0, 1.57)):
+        sim = Sim(Config(n=n, ra=ra, pr=0.02, ste=0.1, s0=1.0, precision="f32"), stream=stream)
+        alpha = sim.lattice()["alpha"]
+        fos = [f for f in (0.25, 0.5, 0.75, 1.0, 1.25, 1.57) if f <= fo_end + 1e-9]
+        done, fl, t_gpu = 0, {}, 0.0
+        for fo in fos:
+            t = int(round(fo * n * n / alpha))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(t - done)
+            torch.cuda.synchronize()
+            t_gpu += time.perf_counter() - t0
+            done = t
+            fl[str(fo)] = round(sim.liquid_fraction(), 6)
+            print(f"paper: case {case} Fo {fo} step {t} f_l {fl[str(fo)]}", file=sys.stderr,
+                  flush=True)
+        nu = sim.wall_nusselt()
+        F = sim.fields(which=("T", "s"))
+        T, s = F["T"], F["s"]
+        depth = max(int(0.5 * s.min()), 1)
+        Tm = T[:, depth, :]
+        out[f"case{case}"] = {
+            "ra": ra, "fo": fo_end, "steps": done, "MLUPS": round(n ** 3 * done / t_gpu / 1e6, 1),
+            "liquid_fraction": fl, "nu_mean": round(float(nu.mean()), 4),
+            "nu_mid_x": round(float(nu[:, n // 2].mean()), 4),
+            "nu_side_x": round(float(0.5 * (nu[:, 0].mean() + nu[:, n - 1].mean())), 4),
+            "T_liquid_top_quarter": round(float(Tm[3 * n // 4:].mean()), 4),
+            "T_liquid_bottom_quarter": round(float(Tm[: n // 4].mean()), 4)}
+        sim.close()
+    print(json.dumps(out), flush=True)
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     for path in KERNEL_SRC:
@@ -288,8 +333,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--mode", choices=["bench", "profile", "copy", "precision", "adjoint"],
-                    default="bench")
+    ap.add_argument("--mode", choices=["bench", "profile", "copy", "precision", "adjoint",
+                                       "paper"], default="bench")
     ap.add_argument("--precision-steps", type=int, default=100000)
     ap.add_argument("--precision", choices=["f32", "f16s", "bf16s", "f64"], default="f32",
                     help="storage precision of --mode profile")
@@ -340,6 +385,10 @@ def main():
 
     if args.mode == "precision":
         precision_study(args.n, args.precision_steps, stream)
+        return
+
+    if args.mode == "paper":
+        paper_cases(args.n, stream)
         return
 
     if args.mode == "adjoint":

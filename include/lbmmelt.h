@@ -130,6 +130,16 @@ int lbm_liquid_fraction(lbm_ctx *ctx, double *fl);
  * force).  Synchronizes; LBM_EUNSTABLE as for lbm_liquid_fraction. */
 int lbm_fields(lbm_ctx *ctx, double *T, double *u, double *rho, double *s);
 
+/* Local Nusselt number on the heated wall, per column (n^2 FP64 values to
+ * host memory, column layout of s): the distribution the paper shows for its
+ * convection cases (section 3.2, Fig. 4(b) and Fig. 5(b)), which it does not
+ * define.  Here Nu = -n (dT/da)(a = 0) / (t_h - t_m), a the melt-axis
+ * coordinate, dT/da from the quadratic through the wall point (0, T_w) and
+ * the first two cell centres (1/2, 3/2) when both are liquid, else from the
+ * chord to the front point (s, t_m); 0 in a column with no liquid.
+ * Synchronizes; LBM_EUNSTABLE as for lbm_liquid_fraction. */
+int lbm_wall_nusselt(lbm_ctx *ctx, double *nu);
+
 /* Derived lattice parameters of the context. */
 int lbm_get_lattice(const lbm_ctx *ctx, lbm_lattice *out);
 

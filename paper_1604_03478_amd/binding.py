@@ -60,6 +60,7 @@ EXPORTS = ("lbm_init", "lbm_destroy", "lbm_step", "lbm_liquid_fraction", "lbm_fi
            "lbm_get_lattice", "lbm_get_step", "lbm_set_hot_wall", "lbm_set_populations",
            "lbm_get_populations", "lbm_diagnostics", "lbm_save_state", "lbm_load_state",
            "lbm_forward_ckpt", "lbm_adjoint", "lbm_get_schedule", "lbm_step_replay",
+           "lbm_wall_nusselt",
            "lbm_kernel_timing", "lbm_kernel_time", "lbm_last_error")
 
 _lib = None
@@ -91,6 +92,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_forward_ckpt.argtypes = [vp, i64, ctypes.c_int32, dp]
     lib.lbm_adjoint.argtypes = [vp, ctypes.c_double, vp, i32]
     lib.lbm_get_schedule.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.lbm_wall_nusselt.argtypes = [vp, dp]
     lib.lbm_step_replay.argtypes = [vp, vp, i64]
     lib.lbm_kernel_timing.argtypes = [vp, i32]
     lib.lbm_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
@@ -201,6 +203,12 @@ class Sim:
         _check(self._lib.lbm_fields(self._h, _ptr(T), _ptr(u), _ptr(rho), _ptr(s)))
         out = {"T": T, "u": u, "rho": rho, "s": s}
         return {k: v for k, v in out.items() if v is not None}
+
+    def wall_nusselt(self) -> np.ndarray:
+        """Local Nusselt number on the heated wall, per column (n x n)."""
+        out = np.empty((self.n, self.n))
+        _check(self._lib.lbm_wall_nusselt(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
 
     def diagnostics(self) -> dict:
         out = np.zeros(5)

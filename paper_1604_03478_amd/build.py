@@ -9,8 +9,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbmmelt.so")
-SOURCES = [os.path.join(CSRC, "lbm_kernels.hip"), os.path.join(CSRC, "lbm_adjoint.hip"),
-           os.path.join(CSRC, "lbm_capi.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ("lbm_kernels.hip", "lbm_adjoint.hip", "lbm_diag.hip", "lbm_capi.hip")]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.  Code
 # object v5 keeps the library loadable by the HIP runtime that ships with the

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "lbm_adjoint.h"
+#include "lbm_diag.h"
 #include "lbm_internal.h"
 #include "lbmmelt.h"
 
@@ -96,6 +97,7 @@ struct lbm_ctx {
   double* red = nullptr;
   double* seedT = nullptr;
   double* fields = nullptr;  // 5 * n^3 FP64 scratch for fields and diagnostics
+  double* wall = nullptr;    // n^2 FP64 scratch of per-column wall diagnostics
   int64_t step = 0;
   AdjData adj;
   // schedule (liquid counts and node indices per step) of the last recorded run
@@ -150,7 +152,7 @@ void release(lbm_ctx* c) {
   release_adjoint(c->adj);
   void* ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->s[0], c->s[1], c->cnt,  c->cmin,
                   c->cmax, c->melted, c->frozen, c->flag, c->th,  c->red,  c->seedT, c->fields,
-                  c->sched, c->replay};
+                  c->sched, c->replay, c->wall};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -456,6 +458,18 @@ int lbm_fields(lbm_ctx* c, double* T, double* u, double* rho, double* s) {
   if (s)
     HIP_TRY(hipMemcpyAsync(s, c->s[c->scur], nn * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
+  return check_unstable(c);
+}
+
+int lbm_wall_nusselt(lbm_ctx* c, double* nu) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!nu) return fail(LBM_EINVAL, "nu is NULL");
+  const size_t nn = (size_t)c->p.n * c->p.n;
+  if (!c->wall && (rc = dalloc(&c->wall, nn))) return rc;
+  HIP_TRY(lbmk::launch_wall_nusselt(c->kind, c->kp, c->g[c->cur], c->s[c->scur], c->th, c->wall,
+                                    c->stream));
+  HIP_TRY(hipMemcpyAsync(nu, c->wall, nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   return check_unstable(c);
 }
 

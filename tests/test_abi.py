@@ -67,4 +67,5 @@ def test_null_arguments_are_rejected():
     assert lib.lbm_fields(None, None, None, None, None) == LBM_EINVAL
     assert lib.lbm_get_schedule(None, None, 0) == LBM_EINVAL
     assert lib.lbm_step_replay(None, None, 1) == LBM_EINVAL
+    assert lib.lbm_wall_nusselt(None, None) == LBM_EINVAL
     lib.lbm_destroy(None)
