@@ -312,8 +312,18 @@ static double neumann_seed_T(const orc_sim *S, double y) {
          (p->t_h - p->t_m) * erf(y / (2.0 * sqrt(S->alpha * t_init))) / erf(lam);
 }
 
+/* The subcooled solid of the two-phase Neumann solution (seed profile 2) at
+ * the time its front is at s0: T_c + (T_m - T_c) erfc(eta) / erfc(lam). */
+static double neumann_solid_T(const orc_sim *S, double y) {
+  const orc_params *p = &S->p;
+  double lam = p->seed_lambda;
+  double t_init = (p->s0 / (2.0 * lam)) * (p->s0 / (2.0 * lam)) / S->alpha;
+  return p->t_c + (p->t_m - p->t_c) * erfc(y / (2.0 * sqrt(S->alpha * t_init))) / erfc(lam);
+}
+
 /* reading R10: initial state.  f at rest equilibrium, g at equilibrium of the
- * seed temperature profile, solid at the initial temperature T_c. */
+ * seed temperature profile, solid at the initial temperature T_c (seed
+ * profile 2: the subcooled solid of the two-phase Neumann solution). */
 static void initial_state(orc_sim *S) {
   int n = S->n;
   const orc_params *p = &S->p;
@@ -330,10 +340,12 @@ static void initial_state(orc_sim *S) {
           T = S->t0;
         } else if (is_liquid(S, S->s, x, y, z)) {
           double a = melt_coord(S, x, y, z) + 0.5;
-          if (p->seed_profile == 1)
+          if (p->seed_profile >= 1)
             T = neumann_seed_T(S, a);
           else
             T = p->t_h + (p->t_m - p->t_h) * a / p->s0;
+        } else if (p->seed_profile == 2) {
+          T = neumann_solid_T(S, melt_coord(S, x, y, z) + 0.5);
         } else {
           T = p->t_c;
         }

@@ -61,3 +61,46 @@ def seed_time(s0: float, alpha: float, ste: float) -> float:
     """Time at which the exact front has reached s0."""
     lam = stefan_lambda(ste)
     return (s0 / (2.0 * lam)) ** 2 / alpha
+
+
+# ---------------------------------------------------------------- two phases
+# Melting of a semi-infinite solid initially subcooled to T_c < T_m, with
+# equal properties in both phases (reading R9).  Front s = 2 lam sqrt(alpha t);
+# liquid T = T_h - (T_h - T_m) erf(eta) / erf(lam); solid
+# T = T_c + (T_m - T_c) erfc(eta) / erfc(lam), eta = y / (2 sqrt(alpha t)).
+# The Stefan condition rho L ds/dt = k dT_s/dy - k dT_l/dy at y = s gives
+#     lam sqrt(pi) = Ste_l exp(-lam^2) / erf(lam) - Ste_s exp(-lam^2) / erfc(lam)
+# with Ste_l = c (T_h - T_m) / L and Ste_s = c (T_m - T_c) / L.
+
+def two_phase_lambda(ste_l: float, ste_s: float, tol: float = 1e-15) -> float:
+    """Root of lam sqrt(pi) - Ste_l e^{-lam^2}/erf(lam) + Ste_s e^{-lam^2}/erfc(lam)."""
+    if ste_l <= 0 or ste_s < 0:
+        raise ValueError("need Ste_l > 0 and Ste_s >= 0")
+
+    def h(lam):
+        e = math.exp(-lam * lam)
+        return lam * math.sqrt(math.pi) - ste_l * e / math.erf(lam) + ste_s * e / math.erfc(lam)
+
+    lo, hi = 1e-12, 1.0
+    while h(hi) < 0:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if h(mid) < 0:
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo < tol:
+            break
+    return 0.5 * (lo + hi)
+
+
+def two_phase_temperature(y, t, alpha, lam, t_h, t_m, t_c):
+    y = np.asarray(y, dtype=np.float64)
+    eta = y / (2.0 * math.sqrt(alpha * t))
+    erf = np.vectorize(math.erf)
+    erfc = np.vectorize(math.erfc)
+    s = 2.0 * lam * math.sqrt(alpha * t)
+    liquid = t_h - (t_h - t_m) * erf(eta) / math.erf(lam)
+    solid = t_c + (t_m - t_c) * erfc(eta) / math.erfc(lam)
+    return np.where(y < s, liquid, solid)

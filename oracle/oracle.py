@@ -147,7 +147,11 @@ class OracleSim:
                  ma=0.1, alpha=0.1, s0=1.0, heating=0, flow=1, seed_profile=0,
                  periodic=False):
         lib = _load()
-        lam = neumann.stefan_lambda(ste) if (seed_profile == 1 and ste > 0) else 0.0
+        lam = 0.0
+        if seed_profile == 1 and ste > 0:
+            lam = neumann.stefan_lambda(ste)
+        elif seed_profile == 2 and ste > 0:  # subcooled solid (two phases)
+            lam = neumann.two_phase_lambda(ste, ste * (t_m - t_c) / (t_h - t_m))
         self.params = _Params(int(n), float(ra), float(pr), float(ste), float(t_h),
                               float(t_c), float(t_m), float(ma), float(alpha), float(s0),
                               int(heating), int(flow), int(seed_profile), float(lam),
