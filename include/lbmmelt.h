@@ -79,9 +79,12 @@ typedef struct {
   int32_t heating;  /* lbm_heating                                            */
   int32_t flow;     /* 0: flow frozen (energy distribution only), 1: full    */
   int32_t precision;/* lbm_precision                                          */
-  int32_t seed_profile; /* initial liquid temperature: 0 linear from t_h to t_m
-                           across the seed layer, 1 the Neumann profile whose
-                           front is at s0                                    */
+  int32_t seed_profile; /* initial temperature: 0 linear from t_h to t_m
+                           across the seed layer, solid at t_c; 1 the
+                           Neumann profile whose front is at s0, solid at
+                           t_c; 2 the two-phase Neumann solution of a solid
+                           subcooled to t_c (equal properties) whose front
+                           is at s0, in both phases (ste > 0 for 1 and 2)  */
 } lbm_params;
 
 /* Lattice units derived from the parameters (Eq. (7) time scale: the

@@ -56,6 +56,24 @@ double neumann_constant(double ste) {
   return 0.5 * (lo + hi);
 }
 
+// Root of lam sqrt(pi) = Ste_l exp(-lam^2)/erf(lam) - Ste_s exp(-lam^2)/erfc(lam):
+// the similarity constant of melting into a solid subcooled to T_c (two
+// phases with equal properties; Ste_s = Ste (t_m - t_c)/(t_h - t_m)), by
+// bisection.  Ste_s = 0 gives neumann_constant.
+double two_phase_constant(double ste_l, double ste_s) {
+  auto h = [&](double l) {
+    const double e = std::exp(-l * l);
+    return l * std::sqrt(M_PI) - ste_l * e / std::erf(l) + ste_s * e / std::erfc(l);
+  };
+  double lo = 1e-12, hi = 1.0;
+  while (h(hi) < 0.0) hi *= 2.0;
+  for (int it = 0; it < 200 && hi - lo > 1e-16; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (h(mid) < 0.0 ? lo : hi) = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 }  // namespace
 
 // Checkpoints of a forward run and the buffers of its reverse sweep.
@@ -174,12 +192,12 @@ int validate(const lbm_params* p) {
   if (p->heating != LBM_HEAT_Y0 && p->heating != LBM_HEAT_Z0)
     return fail(LBM_EINVAL, "heating = %d is not an lbm_heating", p->heating);
   if (p->flow != 0 && p->flow != 1) return fail(LBM_EINVAL, "flow must be 0 or 1");
-  if (p->seed_profile != 0 && p->seed_profile != 1)
-    return fail(LBM_EINVAL, "seed_profile must be 0 or 1");
+  if (p->seed_profile < 0 || p->seed_profile > 2)
+    return fail(LBM_EINVAL, "seed_profile must be 0, 1 or 2");
   if (!(p->t_c <= p->t_m && p->t_m < p->t_h))
     return fail(LBM_EINVAL, "temperatures must satisfy t_c <= t_m < t_h");
   if (!(p->ste >= 0.0) || !std::isfinite(p->ste)) return fail(LBM_EINVAL, "ste must be >= 0");
-  if (p->seed_profile == 1 && !(p->ste > 0.0))
+  if (p->seed_profile >= 1 && !(p->ste > 0.0))
     return fail(LBM_EINVAL, "the Neumann seed profile needs ste > 0");
   if (!(p->ma > 0.0 && p->ma < 0.3)) return fail(LBM_EINVAL, "ma must lie in (0, 0.3)");
   if (!(p->s0 >= 0.0 && p->s0 <= p->n)) return fail(LBM_EINVAL, "s0 must lie in [0, n]");
@@ -346,17 +364,23 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   // initial front, hot wall, seed temperature profile along the melt axis
   std::vector<double> hs(nn, params->s0), ht(nn, params->t_h), seed(n, params->t_c);
   double lam = 0.0, t_init = 0.0;
-  if (params->seed_profile == 1) {
-    lam = neumann_constant(params->ste);
+  if (params->seed_profile >= 1) {
+    lam = params->seed_profile == 1
+              ? neumann_constant(params->ste)
+              : two_phase_constant(params->ste, params->ste * (params->t_m - params->t_c) /
+                                                    (params->t_h - params->t_m));
     t_init = (params->s0 / (2.0 * lam)) * (params->s0 / (2.0 * lam)) / L.alpha;
   }
   for (int a = 0; a < n; ++a) {
     const double y = a + 0.5;
-    if (!(y < params->s0)) continue;
-    if (params->seed_profile == 1)
-      seed[a] = params->t_h - (params->t_h - params->t_m) *
-                                  std::erf(y / (2.0 * std::sqrt(L.alpha * t_init))) /
-                                  std::erf(lam);
+    const double eta = params->seed_profile >= 1 ? y / (2.0 * std::sqrt(L.alpha * t_init)) : 0.0;
+    if (!(y < params->s0)) {  // solid: t_c, or the subcooled two-phase profile
+      if (params->seed_profile == 2)
+        seed[a] = params->t_c + (params->t_m - params->t_c) * std::erfc(eta) / std::erfc(lam);
+      continue;
+    }
+    if (params->seed_profile >= 1)
+      seed[a] = params->t_h - (params->t_h - params->t_m) * std::erf(eta) / std::erf(lam);
     else
       seed[a] = params->t_h + (params->t_m - params->t_h) * y / params->s0;
   }

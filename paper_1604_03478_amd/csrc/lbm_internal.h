@@ -72,8 +72,8 @@ hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int
 // cnt from s.
 hipError_t launch_counts(const KParams& P, const double* s, int* cnt, hipStream_t st);
 
-// Initial state: f at rest, g at equilibrium of seedT[a] in liquid cells and
-// of t_c in solid cells.
+// Initial state: f at rest, g at equilibrium of seedT[a] (a the melt-axis
+// coordinate; the host fills solid heights with t_c or the subcooled profile).
 hipError_t launch_init(int kind, const KParams& P, const int* cnt, const double* seedT, void* f,
                        void* g, hipStream_t st);
 

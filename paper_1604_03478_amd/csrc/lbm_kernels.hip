@@ -540,9 +540,8 @@ __global__ void k_init(const int* __restrict__ cnt, const double* __restrict__ s
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
   if (x >= n) return;
-  const int a = MZ ? z : y, o = MZ ? y : z;
-  const bool liquid = a < cnt[o * n + x];
-  const double Tt = (liquid ? seedT[a] : P.t_c) - P.tref;
+  const int a = MZ ? z : y;
+  const double Tt = seedT[a] - P.tref;  // per height, solid heights included
   Ts* gr = row_ptr<7>(g, P, y, z);
   store(gr, x, kW7Rest * Tt);
   for (int q = 1; q < 7; ++q) store(gr, q * P.pitch + x, kW7Axis * Tt);

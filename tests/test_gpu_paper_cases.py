@@ -132,3 +132,44 @@ def test_case_1_is_conduction_first_then_convection(cases64):
     nu = c["nu"]                     # [z][x]
     assert nu[:, n // 2].mean() > max(nu[:, 0].mean(), nu[:, n - 1].mean())
     assert s[:, n // 2].mean() > max(s[:, 0].mean(), s[:, n - 1].mean())
+
+
+# ---------------------------------------------------------------- subcooled solid
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_subcooled_conduction_matches_oracle(prec, tol):
+    """Solid subcooled to T_c = -0.5 < T_m = 0 (Eq. (6)'s solid-side gradient
+    is non-zero), two-phase seed, 24^3, D3Q7 only, 1500 steps."""
+    orc, gpu = make_pair(1500, n=24, flow=0, ste=0.1, s0=2.0, alpha=0.1, seed_profile=2,
+                         t_c=-0.5, precision=prec)
+    d = diffs(orc, gpu)
+    assert d["T"] <= tol and d["s"] <= tol and d["mask"] == 0, d
+
+
+def test_subcooled_conduction_follows_the_two_phase_solution():
+    """48^3 (the closed form is semi-infinite), FP32: the front against
+    2 lam sqrt(alpha t) (the oracle's own distance: 7.7e-4 -> 7.6e-6)."""
+    from paper_1604_03478_amd import Config, Sim
+    n, ste, t_c = 48, 0.1, -0.5
+    sim = Sim(Config(n=n, flow=0, ste=ste, s0=2.0, alpha=0.1, seed_profile=2, t_c=t_c,
+                     precision="f32"))
+    lam = neumann.two_phase_lambda(ste, ste * 0.5)
+    t0 = (2.0 / (2 * lam)) ** 2 / 0.1
+    for k in range(4):
+        sim.step(500)
+        s = sim.fields(which=("s",))["s"]
+        exact = 2 * lam * np.sqrt(0.1 * (t0 + 500 * (k + 1)))
+        assert np.ptp(s) <= 1e-6 and abs(s.mean() / exact - 1.0) <= 2e-3, (k, s.mean(), exact)
+    sim.close()
+
+
+@pytest.mark.parametrize("heating", ["y0", "z0"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_subcooled_convection_matches_oracle(heating, prec):
+    """Full double MRT with a subcooled solid (T_c = -0.3), 40^3, 300 steps."""
+    orc, gpu = make_pair(300, n=40, ra=1e5, pr=1.0, ste=0.5, s0=9.4, t_c=-0.3,
+                         heating=heating, precision=prec)
+    d = diffs(orc, gpu)
+    if prec == "f64":
+        assert d["T"] <= 1e-11 and d["s"] <= 1e-11 and d["mask"] == 0, d
+    else:
+        assert d["T"] <= 1e-5 and d["s"] <= 1e-5 and d["mask"] == 0 and d["fl_rel"] <= 1e-6, d
