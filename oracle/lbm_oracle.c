@@ -68,6 +68,8 @@ typedef struct {
   int seed_profile; /* 0 linear seed profile, 1 Neumann profile          */
   double seed_lambda; /* Neumann constant, used when seed_profile == 1  */
   int periodic;     /* test mode: periodic box, no walls, no front       */
+  double ks_kl;     /* solid / liquid conductivity (and diffusivity: equal
+                       rho c) ratio of Eq. (6); 0 or 1: equal properties   */
 } orc_params;
 
 typedef struct {
@@ -76,7 +78,8 @@ typedef struct {
   long long ncell;
   /* lattice parameters (reading R5) */
   double u0, nu, alpha, s_nu, q_j, q_e, gbeta, t0, latent;
-  double S[Q19], QR[Q7];
+  double kappa, alpha_s; /* conductivity ratio, solid diffusivity (reading R18) */
+  double S[Q19], QR[Q7], QRs[Q7]; /* QRs: energy rates in solid cells */
   double w19[Q19], w7[Q7];
   int opp19[Q19], opp7[Q7];
   double M[Q19][Q19], Minv[Q19][Q19];
@@ -280,6 +283,13 @@ static void derive_parameters(orc_sim *S) {
   S->QR[0] = 0.0;
   S->QR[1] = S->QR[2] = S->QR[3] = S->q_j;
   S->QR[4] = S->QR[5] = S->QR[6] = S->q_e;
+  /* reading R18: the solid conducts kappa times as well as the liquid and
+   * has the same rho c, so its diffusivity is kappa alpha */
+  S->kappa = p->ks_kl > 0.0 ? p->ks_kl : 1.0;
+  S->alpha_s = S->kappa * S->alpha;
+  S->QRs[0] = 0.0;
+  S->QRs[1] = S->QRs[2] = S->QRs[3] = 1.0 / (4.0 * S->alpha_s + 0.5);
+  S->QRs[4] = S->QRs[5] = S->QRs[6] = 1.0 / (0.5 + 1.0 / (16.0 * S->alpha_s));
 }
 
 static void init_tables(orc_sim *S) {
@@ -313,12 +323,14 @@ static double neumann_seed_T(const orc_sim *S, double y) {
 }
 
 /* The subcooled solid of the two-phase Neumann solution (seed profile 2) at
- * the time its front is at s0: T_c + (T_m - T_c) erfc(eta) / erfc(lam). */
+ * the time t its front is at s0 = 2 lam sqrt(alpha t):
+ * T_c + (T_m - T_c) erfc(y / (2 sqrt(alpha_s t))) / erfc(lam sqrt(alpha / alpha_s)). */
 static double neumann_solid_T(const orc_sim *S, double y) {
   const orc_params *p = &S->p;
   double lam = p->seed_lambda;
   double t_init = (p->s0 / (2.0 * lam)) * (p->s0 / (2.0 * lam)) / S->alpha;
-  return p->t_c + (p->t_m - p->t_c) * erfc(y / (2.0 * sqrt(S->alpha * t_init))) / erfc(lam);
+  return p->t_c + (p->t_m - p->t_c) * erfc(y / (2.0 * sqrt(S->alpha_s * t_init))) /
+                      erfc(lam * sqrt(S->alpha / S->alpha_s));
 }
 
 /* reading R10: initial state.  f at rest equilibrium, g at equilibrium of the
@@ -522,7 +534,8 @@ static void collide_cell(const orc_sim *S, int liquid, const double *fl,
     for (int q = 0; q < Q7; ++q) nm[k] += S->N[k][q] * gl[q];
   }
   neq7(T, ux, uy, uz, ne);
-  for (int k = 0; k < Q7; ++k) ns[k] = nm[k] - S->QR[k] * (nm[k] - ne[k]);
+  const double *QR = liquid ? S->QR : S->QRs;
+  for (int k = 0; k < Q7; ++k) ns[k] = nm[k] - QR[k] * (nm[k] - ne[k]);
   for (int q = 0; q < Q7; ++q) {
     double v = 0.0;
     for (int k = 0; k < Q7; ++k) v += S->Ninv[q][k] * ns[k];
@@ -685,10 +698,11 @@ static double front_velocity_column(const orc_sim *S, const double *g,
   double dsx = 0.5 * (s[cxp] - s[cxm]), dso = 0.5 * (s[cop] - s[com]);
   double P = 1.0 + dsx * dsx + dso * dso;
   double K = S->alpha * p->ste / (p->t_h - p->t_m);
-  double V = P * K * (Gs - Gl);
+  double kap = S->kappa; /* Eq. (6): k_s dT_s - k_l dT_l, in units of k_l */
+  double V = P * K * (kap * Gs - Gl);
 
   if (dv) {
-    /* V = P K (sigma_s + sigma_l) with sigma_l = -Gl, sigma_s = Gs */
+    /* V = P K (kappa sigma_s + sigma_l) with sigma_l = -Gl, sigma_s = Gs */
     dv->nnode = 0;
     dv->dV_dth = 0.0;
     for (int j = 0; j < kl; ++j) {
@@ -703,17 +717,17 @@ static double front_velocity_column(const orc_sim *S, const double *g,
     for (int j = 0; j < ks; ++j) {
       if (j == wall_s) continue; /* cold wall value is a constant */
       dv->node_cell[dv->nnode] = nodes[j];
-      dv->dV_dT[dv->nnode] = P * K * dT[j];
+      dv->dV_dT[dv->nnode] = P * K * kap * dT[j];
       dv->nnode++;
     }
     /* own front through the distances xi (liquid side +1, solid side -1) */
     double dself = 0.0;
     for (int j = 0; j < kl; ++j) dself += dxil[j];
-    for (int j = 0; j < ks; ++j) dself -= dxi[j];
+    for (int j = 0; j < ks; ++j) dself -= kap * dxi[j];
     dv->scol[0] = c;
     dv->dV_ds[0] = P * K * dself;
     /* fronts of the neighbours through the slope factor */
-    double KG = K * (Gs - Gl);
+    double KG = K * (kap * Gs - Gl);
     dv->scol[1] = cxp; dv->dV_ds[1] = KG * dsx;
     dv->scol[2] = cxm; dv->dV_ds[2] = -KG * dsx;
     dv->scol[3] = cop; dv->dV_ds[3] = KG * dso;
@@ -809,13 +823,15 @@ static void collide_cell_adjoint(const orc_sim *S, int liquid, const double *fl,
     uy = jy;
     uz = jz + 0.5 * Fz;
   }
-  /* energy distribution: g' = Ninv[(I - Q) N gl + Q neq(T, u)] */
+  /* energy distribution: g' = Ninv[(I - Q) N gl + Q neq(T, u)], with the
+   * rates of the cell's phase */
+  const double *QR = liquid ? S->QR : S->QRs;
   double lns[Q7], ln[Q7], lne[Q7];
   for (int k = 0; k < Q7; ++k) {
     lns[k] = 0.0;
     for (int q = 0; q < Q7; ++q) lns[k] += S->Ninv[q][k] * lgo[q];
-    ln[k] = (1.0 - S->QR[k]) * lns[k];
-    lne[k] = S->QR[k] * lns[k];
+    ln[k] = (1.0 - QR[k]) * lns[k];
+    lne[k] = QR[k] * lns[k];
   }
   double lT = lne[0] + ux * lne[1] + uy * lne[2] + uz * lne[3] + 0.75 * lne[4];
   double lux = T * lne[1], luy = T * lne[2], luz = T * lne[3];

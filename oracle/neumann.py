@@ -64,22 +64,28 @@ def seed_time(s0: float, alpha: float, ste: float) -> float:
 
 
 # ---------------------------------------------------------------- two phases
-# Melting of a semi-infinite solid initially subcooled to T_c < T_m, with
-# equal properties in both phases (reading R9).  Front s = 2 lam sqrt(alpha t);
-# liquid T = T_h - (T_h - T_m) erf(eta) / erf(lam); solid
-# T = T_c + (T_m - T_c) erfc(eta) / erfc(lam), eta = y / (2 sqrt(alpha t)).
-# The Stefan condition rho L ds/dt = k dT_s/dy - k dT_l/dy at y = s gives
-#     lam sqrt(pi) = Ste_l exp(-lam^2) / erf(lam) - Ste_s exp(-lam^2) / erfc(lam)
+# Melting of a semi-infinite solid initially subcooled to T_c < T_m.  The
+# solid conducts kappa times as well as the liquid with the same rho c
+# (diffusivities alpha and alpha_s = kappa alpha; kappa = 1: equal
+# properties, reading R9).  Front s = 2 lam sqrt(alpha t); liquid
+# T = T_h - (T_h - T_m) erf(eta) / erf(lam) with eta = y / (2 sqrt(alpha t));
+# solid T = T_c + (T_m - T_c) erfc(eta_s) / erfc(nu lam) with
+# eta_s = y / (2 sqrt(alpha_s t)), nu = sqrt(alpha / alpha_s).  The Stefan
+# condition rho L ds/dt = k_s dT_s/dy - k_l dT_l/dy at y = s gives
+#   lam sqrt(pi) = Ste_l exp(-lam^2) / erf(lam)
+#                  - sqrt(kappa) Ste_s exp(-nu^2 lam^2) / erfc(nu lam)
 # with Ste_l = c (T_h - T_m) / L and Ste_s = c (T_m - T_c) / L.
 
-def two_phase_lambda(ste_l: float, ste_s: float, tol: float = 1e-15) -> float:
-    """Root of lam sqrt(pi) - Ste_l e^{-lam^2}/erf(lam) + Ste_s e^{-lam^2}/erfc(lam)."""
-    if ste_l <= 0 or ste_s < 0:
-        raise ValueError("need Ste_l > 0 and Ste_s >= 0")
+def two_phase_lambda(ste_l: float, ste_s: float, kappa: float = 1.0,
+                     tol: float = 1e-15) -> float:
+    """Root of the two-phase Stefan condition above."""
+    if ste_l <= 0 or ste_s < 0 or kappa <= 0:
+        raise ValueError("need Ste_l > 0, Ste_s >= 0 and kappa > 0")
+    nu = 1.0 / math.sqrt(kappa)
 
     def h(lam):
-        e = math.exp(-lam * lam)
-        return lam * math.sqrt(math.pi) - ste_l * e / math.erf(lam) + ste_s * e / math.erfc(lam)
+        return (lam * math.sqrt(math.pi) - ste_l * math.exp(-lam * lam) / math.erf(lam)
+                + math.sqrt(kappa) * ste_s * math.exp(-nu * nu * lam * lam) / math.erfc(nu * lam))
 
     lo, hi = 1e-12, 1.0
     while h(hi) < 0:
@@ -95,12 +101,13 @@ def two_phase_lambda(ste_l: float, ste_s: float, tol: float = 1e-15) -> float:
     return 0.5 * (lo + hi)
 
 
-def two_phase_temperature(y, t, alpha, lam, t_h, t_m, t_c):
+def two_phase_temperature(y, t, alpha, lam, t_h, t_m, t_c, kappa: float = 1.0):
     y = np.asarray(y, dtype=np.float64)
-    eta = y / (2.0 * math.sqrt(alpha * t))
+    alpha_s = kappa * alpha
     erf = np.vectorize(math.erf)
     erfc = np.vectorize(math.erfc)
     s = 2.0 * lam * math.sqrt(alpha * t)
-    liquid = t_h - (t_h - t_m) * erf(eta) / math.erf(lam)
-    solid = t_c + (t_m - t_c) * erfc(eta) / math.erfc(lam)
+    liquid = t_h - (t_h - t_m) * erf(y / (2.0 * math.sqrt(alpha * t))) / math.erf(lam)
+    solid = t_c + (t_m - t_c) * erfc(y / (2.0 * math.sqrt(alpha_s * t))) / \
+        math.erfc(lam * math.sqrt(alpha / alpha_s))
     return np.where(y < s, liquid, solid)

@@ -54,6 +54,7 @@ class _Params(ctypes.Structure):
         ("seed_profile", ctypes.c_int),
         ("seed_lambda", ctypes.c_double),
         ("periodic", ctypes.c_int),
+        ("ks_kl", ctypes.c_double),
     ]
 
 
@@ -145,17 +146,17 @@ class OracleSim:
 
     def __init__(self, n, ra=1e4, pr=1.0, ste=0.1, t_h=1.0, t_c=0.0, t_m=0.0,
                  ma=0.1, alpha=0.1, s0=1.0, heating=0, flow=1, seed_profile=0,
-                 periodic=False):
+                 periodic=False, ks_kl=1.0):
         lib = _load()
         lam = 0.0
         if seed_profile == 1 and ste > 0:
             lam = neumann.stefan_lambda(ste)
         elif seed_profile == 2 and ste > 0:  # subcooled solid (two phases)
-            lam = neumann.two_phase_lambda(ste, ste * (t_m - t_c) / (t_h - t_m))
+            lam = neumann.two_phase_lambda(ste, ste * (t_m - t_c) / (t_h - t_m), ks_kl)
         self.params = _Params(int(n), float(ra), float(pr), float(ste), float(t_h),
                               float(t_c), float(t_m), float(ma), float(alpha), float(s0),
                               int(heating), int(flow), int(seed_profile), float(lam),
-                              int(bool(periodic)))
+                              int(bool(periodic)), float(ks_kl))
         h = lib.orc_create(ctypes.byref(self.params))
         if not h:
             raise MemoryError("oracle allocation failed")
