@@ -85,6 +85,9 @@ typedef struct {
                            t_c; 2 the two-phase Neumann solution of a solid
                            subcooled to t_c (equal properties) whose front
                            is at s0, in both phases (ste > 0 for 1 and 2)  */
+  double ks_kl;     /* solid / liquid thermal conductivity ratio of Eq. (6),
+                       >= 0; 0 or 1: equal properties.  rho c is the same in
+                       both phases, so the solid diffusivity is ks_kl * alpha */
 } lbm_params;
 
 /* Lattice units derived from the parameters (Eq. (7) time scale: the

@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("flow", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("seed_profile", ctypes.c_int32),
+        ("ks_kl", ctypes.c_double),
     ]
 
 
@@ -129,12 +130,13 @@ class Config:
     flow: int = 1
     precision: str = "f32"
     seed_profile: int = 0
+    ks_kl: float = 1.0
 
     def to_c(self) -> Params:
         return Params(int(self.n), float(self.ra), float(self.pr), float(self.ste),
                       float(self.t_h), float(self.t_c), float(self.t_m), float(self.ma),
                       float(self.alpha), float(self.s0), HEATING[self.heating], int(self.flow),
-                      PRECISIONS[self.precision], int(self.seed_profile))
+                      PRECISIONS[self.precision], int(self.seed_profile), float(self.ks_kl))
 
 
 class Sim:

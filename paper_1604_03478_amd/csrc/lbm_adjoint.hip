@@ -318,7 +318,8 @@ __device__ void collide_adjoint(const Macro& M, bool liquid, const KParams& P,
     uz = M.jz + 0.5 * Fz;
   }
   // ---- energy distribution: g' = N^T D^-1 [(I - Q) N gl + Q n_eq(T, u)] ----
-  const double Q[7] = {0.0, P.q_j, P.q_j, P.q_j, P.q_e, P.q_e, P.q_e};
+  const double qj = liquid ? P.q_j : P.q_js, qe = liquid ? P.q_e : P.q_es;
+  const double Q[7] = {0.0, qj, qj, qj, qe, qe, qe};
   double lns[7], ln[7], lne[7];
   m7(lgo, lns);
   for (int k = 0; k < 7; ++k) {
@@ -463,8 +464,8 @@ __device__ void front_der(const Ts* g1, const double* s, const double* th, int c
   const int cop = (o + 1 < n ? o + 1 : o) * n + x, com = (o > 0 ? o - 1 : o) * n + x;
   const double dsx = 0.5 * (s[cxp] - s[cxm]), dso = 0.5 * (s[cop] - s[com]);
   const double Pf = 1.0 + dsx * dsx + dso * dso;
-  const double K = P.alpha * P.ste / P.dT;
-  d.V = Pf * K * (ss + sl);
+  const double K = P.alpha * P.ste / P.dT, kap = P.kappa;  // Eq. (6): kappa on the solid side
+  d.V = Pf * K * (kap * ss + sl);
   d.nnode = 0;
   d.dth = 0.0;
   for (int j = 0; j < kl; ++j) {
@@ -478,12 +479,12 @@ __device__ void front_der(const Ts* g1, const double* s, const double* th, int c
   for (int j = 0; j < ks; ++j) {
     if (j == wall) continue;
     d.node[d.nnode] = nd[j];
-    d.dT[d.nnode++] = Pf * K * dT[j];
+    d.dT[d.nnode++] = Pf * K * kap * dT[j];
   }
   double dself = 0.0;
   for (int j = 0; j < kl; ++j) dself += dxil[j];
-  for (int j = 0; j < ks; ++j) dself -= dxi[j];
-  const double KG = K * (ss + sl);
+  for (int j = 0; j < ks; ++j) dself -= kap * dxi[j];
+  const double KG = K * (kap * ss + sl);
   d.col[0] = c;
   d.ds[0] = Pf * K * dself;
   d.col[1] = cxp;

@@ -56,14 +56,18 @@ double neumann_constant(double ste) {
   return 0.5 * (lo + hi);
 }
 
-// Root of lam sqrt(pi) = Ste_l exp(-lam^2)/erf(lam) - Ste_s exp(-lam^2)/erfc(lam):
-// the similarity constant of melting into a solid subcooled to T_c (two
-// phases with equal properties; Ste_s = Ste (t_m - t_c)/(t_h - t_m)), by
-// bisection.  Ste_s = 0 gives neumann_constant.
-double two_phase_constant(double ste_l, double ste_s) {
+// Similarity constant of melting into a solid subcooled to T_c whose
+// conductivity is kappa times the liquid's (same rho c, so its diffusivity
+// is kappa alpha): the root of
+//   lam sqrt(pi) = Ste_l exp(-lam^2)/erf(lam)
+//                  - sqrt(kappa) Ste_s exp(-lam^2/kappa)/erfc(lam/sqrt(kappa))
+// with Ste_s = Ste (t_m - t_c)/(t_h - t_m), by bisection.  Ste_s = 0 gives
+// neumann_constant.
+double two_phase_constant(double ste_l, double ste_s, double kappa) {
+  const double rk = std::sqrt(kappa);
   auto h = [&](double l) {
-    const double e = std::exp(-l * l);
-    return l * std::sqrt(M_PI) - ste_l * e / std::erf(l) + ste_s * e / std::erfc(l);
+    return l * std::sqrt(M_PI) - ste_l * std::exp(-l * l) / std::erf(l) +
+           rk * ste_s * std::exp(-l * l / kappa) / std::erfc(l / rk);
   };
   double lo = 1e-12, hi = 1.0;
   while (h(hi) < 0.0) hi *= 2.0;
@@ -201,6 +205,8 @@ int validate(const lbm_params* p) {
     return fail(LBM_EINVAL, "the Neumann seed profile needs ste > 0");
   if (!(p->ma > 0.0 && p->ma < 0.3)) return fail(LBM_EINVAL, "ma must lie in (0, 0.3)");
   if (!(p->s0 >= 0.0 && p->s0 <= p->n)) return fail(LBM_EINVAL, "s0 must lie in [0, n]");
+  if (!(p->ks_kl >= 0.0) || !std::isfinite(p->ks_kl))
+    return fail(LBM_EINVAL, "ks_kl must be >= 0 (0 or 1: equal phase properties)");
   if (p->flow) {
     if (!(p->ra > 0.0) || !(p->pr > 0.0) || !std::isfinite(p->ra) || !std::isfinite(p->pr))
       return fail(LBM_EINVAL, "ra and pr must be positive");
@@ -323,6 +329,13 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   k.s_nu = L.s_nu;
   k.q_j = L.q_j;
   k.q_e = L.q_e;
+  // solid: conductivity kappa k_l with the same rho c, diffusivity kappa alpha
+  k.kappa = params->ks_kl > 0.0 ? params->ks_kl : 1.0;
+  {
+    const double alpha_s = k.kappa * L.alpha;
+    k.q_js = 1.0 / (4.0 * alpha_s + 0.5);
+    k.q_es = 1.0 / (0.5 + 1.0 / (16.0 * alpha_s));
+  }
   k.alpha = L.alpha;
   k.ste = params->ste;
   k.dT = params->t_h - params->t_m;
@@ -367,16 +380,20 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   if (params->seed_profile >= 1) {
     lam = params->seed_profile == 1
               ? neumann_constant(params->ste)
-              : two_phase_constant(params->ste, params->ste * (params->t_m - params->t_c) /
-                                                    (params->t_h - params->t_m));
+              : two_phase_constant(params->ste,
+                                   params->ste * (params->t_m - params->t_c) /
+                                       (params->t_h - params->t_m),
+                                   k.kappa);
     t_init = (params->s0 / (2.0 * lam)) * (params->s0 / (2.0 * lam)) / L.alpha;
   }
   for (int a = 0; a < n; ++a) {
     const double y = a + 0.5;
     const double eta = params->seed_profile >= 1 ? y / (2.0 * std::sqrt(L.alpha * t_init)) : 0.0;
     if (!(y < params->s0)) {  // solid: t_c, or the subcooled two-phase profile
-      if (params->seed_profile == 2)
-        seed[a] = params->t_c + (params->t_m - params->t_c) * std::erfc(eta) / std::erfc(lam);
+      if (params->seed_profile == 2)  // solid diffusivity kappa alpha
+        seed[a] = params->t_c + (params->t_m - params->t_c) *
+                                    std::erfc(eta / std::sqrt(k.kappa)) /
+                                    std::erfc(lam / std::sqrt(k.kappa));
       continue;
     }
     if (params->seed_profile >= 1)

@@ -28,6 +28,9 @@ struct KParams {
   double s_nu;     // shear rate of the D3Q19 MRT
   double q_j;      // heat-flux rate of the D3Q7 MRT
   double q_e;      // rate of the remaining D3Q7 moments
+  double q_js;     // the same two rates in solid cells (solid diffusivity kappa * alpha)
+  double q_es;
+  double kappa;    // solid / liquid conductivity ratio of Eq. (6)
   double alpha;    // thermal diffusivity (front update)
   double ste;      // Stefan number (front update)
   double dT;       // nominal t_h - t_m (front update)

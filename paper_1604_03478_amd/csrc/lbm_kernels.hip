@@ -40,7 +40,8 @@ namespace {
 template <typename C, typename G>
 struct Rates {
   C sv, gb;  // shear rate and buoyancy coefficient of the flow
-  G qj, qe;  // rates of the energy distribution
+  G qj, qe;  // rates of the energy distribution (liquid cells)
+  G qjs, qes;  // the same in solid cells
   G tref;    // storage shift of g: the stored value is g_q - w_q * tref
   G dbuoy;   // tref - t0, so that T - t0 = (T - tref) + dbuoy
 };
@@ -52,6 +53,8 @@ __device__ __forceinline__ Rates<C, G> make_rates(const KParams& P) {
   r.gb = (C)P.gbeta;
   r.qj = (G)P.q_j;
   r.qe = (G)P.q_e;
+  r.qjs = (G)P.q_js;
+  r.qes = (G)P.q_es;
   r.tref = (G)P.tref;
   r.dbuoy = (G)(P.tref - P.t0);
   return r;
@@ -192,11 +195,12 @@ __device__ __forceinline__ bool collide(C (&f)[19], G (&g)[7], bool liquid, cons
     const G n4 = G(6) * g[0] - (px + py + pz);
     const G n5 = G(2) * px - py - pz;
     const G n6 = py - pz;
-    const G n1s = n1 - r.qj * (n1 - G(ux) * T);
-    const G n2s = n2 - r.qj * (n2 - G(uy) * T);
-    const G n3s = n3 - r.qj * (n3 - G(uz) * T);
-    const G n4s = n4 - r.qe * (n4 - G(0.75) * Tt);
-    const G ke = G(1) - r.qe;
+    const G qj = liquid ? r.qj : r.qjs, qe = liquid ? r.qe : r.qes;
+    const G n1s = n1 - qj * (n1 - G(ux) * T);
+    const G n2s = n2 - qj * (n2 - G(uy) * T);
+    const G n3s = n3 - qj * (n3 - G(uz) * T);
+    const G n4s = n4 - qe * (n4 - G(0.75) * Tt);
+    const G ke = G(1) - qe;
     const G b0 = Tt * G(1.0 / 7.0);
     const G b1 = G(0.5) * n1s, b2 = G(0.5) * n2s, b3 = G(0.5) * n3s;
     const G b4 = n4s * G(1.0 / 42.0), b5 = ke * n5 * G(1.0 / 12.0), b6 = ke * n6 * G(0.25);
@@ -486,7 +490,9 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   const double sop = s_old[(o + 1 < n ? o + 1 : o) * n + x];
   const double som = s_old[(o > 0 ? o - 1 : o) * n + x];
   const double dsx = 0.5 * (sxp - sxm), dso = 0.5 * (sop - som);
-  const double V = (1.0 + dsx * dsx + dso * dso) * P.alpha * P.ste * (Gs - Gl) / P.dT;
+  // Eq. (6): k_s dT_s - k_l dT_l in units of k_l (kappa = k_s / k_l)
+  const double V =
+      (1.0 + dsx * dsx + dso * dso) * P.alpha * P.ste * (P.kappa * Gs - Gl) / P.dT;
   double sn = sc + V;
   if (!(sn == sn)) *flag = 1;
   sn = sn < 0.0 ? 0.0 : (sn > (double)n ? (double)n : sn);

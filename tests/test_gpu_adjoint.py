@@ -45,6 +45,29 @@ def test_gradient_matches_oracle_adjoint(heating, flow, prec, tol):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_gradient_matches_oracle_adjoint_subcooled_unequal_conductivities(prec, tol):
+    """Solid subcooled to T_c = -0.3 and twice as conductive (kappa = 2): the
+    solid side of Eq. (6) and the solid rates enter the reverse sweep."""
+    from inputs import hot_wall_field
+    n = 16
+    kw = dict(ra=1e5, pr=1.0, ste=1.0, s0=4.6, flow=1, alpha=0.1, t_c=-0.3)
+    orc = OracleSim(n, heating=0, ks_kl=2.0, **kw)
+    orc.step(60)
+    from paper_1604_03478_amd import Config, Sim
+    gpu = Sim(Config(n=n, heating="y0", precision=prec, ks_kl=2.0, **kw))
+    gpu.set_populations(orc.f.copy(), orc.g.copy(), orc.s.copy())
+    th = hot_wall_field(n, seed=4)
+    orc.th[:] = th
+    gpu.set_hot_wall(th)
+    orc.record(40)
+    *_, g_ref = orc.adjoint()
+    gpu.forward_ckpt(40, 7)
+    g = gpu.adjoint(1.0)
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert err <= tol, err
+
+
 def test_replay_reproduces_recorded_run():
     """Stepping along the recorded schedule with unchanged inputs gives the
     recorded run bit for bit (FP64 and FP32 storage), through a melting

@@ -173,3 +173,46 @@ def test_subcooled_convection_matches_oracle(heating, prec):
         assert d["T"] <= 1e-11 and d["s"] <= 1e-11 and d["mask"] == 0, d
     else:
         assert d["T"] <= 1e-5 and d["s"] <= 1e-5 and d["mask"] == 0 and d["fl_rel"] <= 1e-6, d
+
+
+# ---------------------------------------------------------------- unequal properties
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+@pytest.mark.parametrize("kappa", [0.5, 2.0])
+def test_unequal_conductivities_conduction_matches_oracle(kappa, prec, tol):
+    """k_s = kappa k_l (solid diffusivity kappa alpha), subcooled two-phase
+    seed, 24^3, D3Q7 only, 1500 steps."""
+    orc, gpu = make_pair(1500, n=24, flow=0, ste=0.1, s0=2.0, alpha=0.1, seed_profile=2,
+                         t_c=-0.5, ks_kl=kappa, precision=prec)
+    d = diffs(orc, gpu)
+    assert d["T"] <= tol and d["s"] <= tol and d["mask"] == 0, d
+
+
+@pytest.mark.parametrize("kappa,n", [(0.5, 48), (2.0, 64)])
+def test_unequal_conductivities_follow_the_two_phase_solution(kappa, n):
+    """FP32 front against 2 lam(kappa) sqrt(alpha t) (the oracle's own
+    distance: <= 7.7e-4, <= 1e-4 after 2000 steps)."""
+    from paper_1604_03478_amd import Config, Sim
+    ste, t_c = 0.1, -0.5
+    sim = Sim(Config(n=n, flow=0, ste=ste, s0=2.0, alpha=0.1, seed_profile=2, t_c=t_c,
+                     ks_kl=kappa, precision="f32"))
+    lam = neumann.two_phase_lambda(ste, ste * 0.5, kappa)
+    t0 = (2.0 / (2 * lam)) ** 2 / 0.1
+    for k in range(4):
+        sim.step(500)
+        s = sim.fields(which=("s",))["s"]
+        exact = 2 * lam * np.sqrt(0.1 * (t0 + 500 * (k + 1)))
+        assert np.ptp(s) <= 1e-6 and abs(s.mean() / exact - 1.0) <= 2e-3, (k, s.mean(), exact)
+    sim.close()
+
+
+@pytest.mark.parametrize("heating", ["y0", "z0"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_unequal_conductivities_convection_matches_oracle(heating, prec):
+    """Full double MRT, k_s = 2 k_l, subcooled solid (T_c = -0.3), 40^3, 300 steps."""
+    orc, gpu = make_pair(300, n=40, ra=1e5, pr=1.0, ste=0.5, s0=9.4, t_c=-0.3, ks_kl=2.0,
+                         heating=heating, precision=prec)
+    d = diffs(orc, gpu)
+    if prec == "f64":
+        assert d["T"] <= 1e-11 and d["s"] <= 1e-11 and d["mask"] == 0, d
+    else:
+        assert d["T"] <= 1e-5 and d["s"] <= 1e-5 and d["mask"] == 0 and d["fl_rel"] <= 1e-6, d
