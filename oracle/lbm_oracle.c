@@ -70,6 +70,8 @@ typedef struct {
   int periodic;     /* test mode: periodic box, no walls, no front       */
   double ks_kl;     /* solid / liquid conductivity (and diffusivity: equal
                        rho c) ratio of Eq. (6); 0 or 1: equal properties   */
+  int front_scheme; /* 0: Eq. (6) from temperature gradients; 1: the heat the
+                       lattice carries across the interface (reading R19)  */
 } orc_params;
 
 typedef struct {
@@ -90,6 +92,7 @@ typedef struct {
   double *th;     /* hot-wall temperature per column */
   long long step;
   long long melted, frozen;
+  double wall_heat; /* heat let in through the walls (front scheme 1 only) */
 } orc_sim;
 
 /* ------------------------------------------------------------------------ */
@@ -742,11 +745,53 @@ void orc_front_velocity(const orc_sim *S, double *V) {
     V[c] = S->p.periodic ? 0.0 : front_velocity_column(S, S->g, S->s, S->th, c, NULL);
 }
 
+/* reading R19: the energy the lattice carries into the interface during the
+ * streaming that produced the current state, per column.  The streaming
+ * moves every population of a cell to a neighbour except across a boundary
+ * link, where the population the cell sends toward the wall or the front is
+ * lost and the one it receives back is set by the boundary rule.  For an
+ * interface link, (sent - received) is heat given to the front: links along
+ * the melt axis count for their own column, a lateral link for the column of
+ * its solid cell (whose front has to move).  Wall links add (received -
+ * sent) to the heat let in through the walls.  gold, fold, s: the state
+ * before that streaming. */
+static void front_heat(orc_sim *S, const double *fold, const double *gold, const double *s,
+                       double *Q) {
+  const int n = S->n;
+  const long long nc = S->ncell;
+  for (int c = 0; c < n * n; ++c) Q[c] = 0.0;
+  double fl[Q19], gl[Q7];
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        long long i = cell_index(n, x, y, z);
+        int liquid = is_liquid(S, s, x, y, z);
+        stream_cell(S, fold, gold, s, S->th, x, y, z, liquid, fl, gl);
+        for (int q = 1; q < Q7; ++q) {
+          int sx = x - E7[q][0], sy = y - E7[q][1], sz = z - E7[q][2];
+          double sent = gold[S->opp7[q] * nc + i], received = gl[q];
+          if (!in_box(n, sx, sy, sz)) {
+            S->wall_heat += received - sent;
+          } else if (is_liquid(S, s, sx, sy, sz) != liquid) {
+            int along_melt = (S->p.heating == 0) ? (E7[q][1] != 0) : (E7[q][2] != 0);
+            int col = (along_melt || !liquid) ? column_of(S, x, y, z) : column_of(S, sx, sy, sz);
+            Q[col] += sent - received;
+          }
+        }
+      }
+}
+
 static void front_update(orc_sim *S) {
   const int n = S->n;
   if (S->p.periodic) return;
   double *V = (double *)malloc(sizeof(double) * n * n);
-  orc_front_velocity(S, V);
+  if (S->p.front_scheme == 1) {
+    /* the state before this step's streaming is in the scratch buffers */
+    front_heat(S, S->fn, S->gn, S->s, V);
+    for (int c = 0; c < n * n; ++c) V[c] /= S->latent;
+  } else {
+    orc_front_velocity(S, V);
+  }
   for (int c = 0; c < n * n; ++c) {
     double v = S->s[c] + V[c];
     if (v < 0.0) v = 0.0;
@@ -1030,6 +1075,7 @@ static void record_free(void) {
  * sizes only: (nsteps + 1) * 26 * n^3 doubles).  Returns 0 on success. */
 int orc_record(orc_sim *S, long long nsteps) {
   record_free();
+  if (S->p.front_scheme != 0) return -2; /* the reverse sweep follows Eq. (6) */
   const long long nc = S->ncell, nn = (long long)S->n * S->n;
   g_record.f = (double *)malloc(sizeof(double) * Q19 * nc * (nsteps + 1));
   g_record.g = (double *)malloc(sizeof(double) * Q7 * nc * (nsteps + 1));
@@ -1080,6 +1126,18 @@ int orc_adjoint(orc_sim *S, double *lf, double *lg, double *ls, double *lth) {
 /* outputs                                                                  */
 
 /* reading R11: liquid fraction from the front heights */
+/* thermal energy of the cavity: sum of T over the cells (rho c = 1 per cell)
+ * plus the latent heat of the melted layers, L sum of s over the columns */
+double orc_energy(const orc_sim *S) {
+  double e = 0.0;
+  for (long long i = 0; i < S->ncell; ++i) e += cell_T_of(S, S->g, i);
+  double fs = 0.0;
+  for (int c = 0; c < S->n * S->n; ++c) fs += S->s[c];
+  return e + S->latent * fs;
+}
+
+double orc_wall_heat(const orc_sim *S) { return S->wall_heat; }
+
 double orc_liquid_fraction(const orc_sim *S) {
   double acc = 0.0;
   for (int c = 0; c < S->n * S->n; ++c) acc += S->s[c];

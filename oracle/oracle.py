@@ -55,6 +55,7 @@ class _Params(ctypes.Structure):
         ("seed_lambda", ctypes.c_double),
         ("periodic", ctypes.c_int),
         ("ks_kl", ctypes.c_double),
+        ("front_scheme", ctypes.c_int),
     ]
 
 
@@ -95,6 +96,10 @@ def _load():
         lib.orc_record.argtypes = [vp, ll]
         lib.orc_adjoint.argtypes = [vp, dp, dp, dp, dp]
         lib.orc_wall_nusselt.argtypes = [vp, dp]
+        lib.orc_energy.argtypes = [vp]
+        lib.orc_energy.restype = d
+        lib.orc_wall_heat.argtypes = [vp]
+        lib.orc_wall_heat.restype = d
         lib.orc_threads.restype = i
         lib.orc_set_threads.argtypes = [i]
         assert lib.orc_sizeof_params() == ctypes.sizeof(_Params), "oracle params layout mismatch"
@@ -146,7 +151,7 @@ class OracleSim:
 
     def __init__(self, n, ra=1e4, pr=1.0, ste=0.1, t_h=1.0, t_c=0.0, t_m=0.0,
                  ma=0.1, alpha=0.1, s0=1.0, heating=0, flow=1, seed_profile=0,
-                 periodic=False, ks_kl=1.0):
+                 periodic=False, ks_kl=1.0, front_scheme=0):
         lib = _load()
         lam = 0.0
         if seed_profile == 1 and ste > 0:
@@ -156,7 +161,7 @@ class OracleSim:
         self.params = _Params(int(n), float(ra), float(pr), float(ste), float(t_h),
                               float(t_c), float(t_m), float(ma), float(alpha), float(s0),
                               int(heating), int(flow), int(seed_profile), float(lam),
-                              int(bool(periodic)), float(ks_kl))
+                              int(bool(periodic)), float(ks_kl), int(front_scheme))
         h = lib.orc_create(ctypes.byref(self.params))
         if not h:
             raise MemoryError("oracle allocation failed")
@@ -223,6 +228,14 @@ class OracleSim:
         self._lib.orc_front_velocity(self._h, _dp(V))
         return V
 
+    def energy(self) -> float:
+        """Sum of T over the cells plus L times the sum of the fronts."""
+        return float(self._lib.orc_energy(self._h))
+
+    def wall_heat(self) -> float:
+        """Heat let in through the walls so far (front scheme 1 only)."""
+        return float(self._lib.orc_wall_heat(self._h))
+
     def wall_nusselt(self) -> np.ndarray:
         """Local Nusselt number on the heated wall, per column (n x n)."""
         out = np.zeros((self.n, self.n))
@@ -273,7 +286,10 @@ class OracleSim:
     # ---- reference adjoint ----
     def record(self, nsteps: int) -> None:
         """Step forward keeping every state (for the reverse sweep)."""
-        if self._lib.orc_record(self._h, int(nsteps)) != 0:
+        rc = self._lib.orc_record(self._h, int(nsteps))
+        if rc == -2:
+            raise ValueError("the reference adjoint follows the Eq. (6) front update only")
+        if rc != 0:
             raise MemoryError("oracle record allocation failed")
 
     def adjoint(self, lf=None, lg=None, ls=None):
