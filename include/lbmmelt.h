@@ -88,6 +88,12 @@ typedef struct {
   double ks_kl;     /* solid / liquid thermal conductivity ratio of Eq. (6),
                        >= 0; 0 or 1: equal properties.  rho c is the same in
                        both phases, so the solid diffusivity is ks_kl * alpha */
+  int32_t front_scheme; /* interface update: 0 Eq. (6) with one-sided
+                           temperature gradients; 1 the same energy balance
+                           taken from the heat the lattice carries across
+                           the interface links in each step (conserves
+                           sum(T) + L sum(s) up to the wall heat; no
+                           adjoint or replay)                              */
 } lbm_params;
 
 /* Lattice units derived from the parameters (Eq. (7) time scale: the

@@ -18,6 +18,7 @@
 
 #include "lbm_adjoint.h"
 #include "lbm_diag.h"
+#include "lbm_front_heat.h"
 #include "lbm_internal.h"
 #include "lbmmelt.h"
 
@@ -120,6 +121,7 @@ struct lbm_ctx {
   double* seedT = nullptr;
   double* fields = nullptr;  // 5 * n^3 FP64 scratch for fields and diagnostics
   double* wall = nullptr;    // n^2 FP64 scratch of per-column wall diagnostics
+  double* heat = nullptr;    // n^2 FP64 front heat of a step (front_scheme 1)
   int64_t step = 0;
   AdjData adj;
   // schedule (liquid counts and node indices per step) of the last recorded run
@@ -174,7 +176,7 @@ void release(lbm_ctx* c) {
   release_adjoint(c->adj);
   void* ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->s[0], c->s[1], c->cnt,  c->cmin,
                   c->cmax, c->melted, c->frozen, c->flag, c->th,  c->red,  c->seedT, c->fields,
-                  c->sched, c->replay, c->wall};
+                  c->sched, c->replay, c->wall, c->heat};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -207,6 +209,8 @@ int validate(const lbm_params* p) {
   if (!(p->s0 >= 0.0 && p->s0 <= p->n)) return fail(LBM_EINVAL, "s0 must lie in [0, n]");
   if (!(p->ks_kl >= 0.0) || !std::isfinite(p->ks_kl))
     return fail(LBM_EINVAL, "ks_kl must be >= 0 (0 or 1: equal phase properties)");
+  if (p->front_scheme != 0 && p->front_scheme != 1)
+    return fail(LBM_EINVAL, "front_scheme must be 0 (Eq. (6) gradients) or 1 (interface heat)");
   if (p->flow) {
     if (!(p->ra > 0.0) || !(p->pr > 0.0) || !std::isfinite(p->ra) || !std::isfinite(p->pr))
       return fail(LBM_EINVAL, "ra and pr must be positive");
@@ -371,7 +375,8 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
       (rc = dalloc(&c->cmin, nn)) || (rc = dalloc(&c->cmax, nn)) ||
       (rc = dalloc(&c->melted, nn)) || (rc = dalloc(&c->frozen, nn)) ||
       (rc = dalloc(&c->flag, 1)) || (rc = dalloc(&c->th, nn)) || (rc = dalloc(&c->red, 8)) ||
-      (rc = dalloc(&c->seedT, (size_t)n)))
+      (rc = dalloc(&c->seedT, (size_t)n)) ||
+      (params->front_scheme == 1 && (rc = dalloc(&c->heat, nn))))
     return bail(rc);
 
   // initial front, hot wall, seed temperature profile along the melt axis
@@ -455,9 +460,12 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     int* rec = c->rec_start >= 0
                    ? c->sched + (size_t)(c->step - c->rec_start) * 3 * ((size_t)c->p.n * c->p.n)
                    : nullptr;
+    if (c->heat)  // conservative front: heat of the streaming from the state g[cur]
+      HIP_TRY(lbmk::launch_front_heat(c->kind, k, c->g[c->cur], c->s[c->scur], c->cnt, c->heat,
+                                      c->stream));
     HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
                                c->th, c->melted, c->frozen, c->flag, nullptr, nullptr, rec,
-                               c->stream));
+                               c->heat, c->stream));
     HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
     c->cur = nx;
     c->scur = sx;
@@ -696,6 +704,8 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (nsteps < 1 || every_k < 1) return fail(LBM_EINVAL, "need nsteps >= 1 and every_k >= 1");
+  if (c->p.front_scheme != 0)
+    return fail(LBM_EINVAL, "the adjoint follows the Eq. (6) front update (front_scheme 0)");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   AdjData& a = c->adj;
   const size_t nn = (size_t)c->p.n * c->p.n;
@@ -832,7 +842,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
                                           c->stream));
       HIP_TRY(lbmk::launch_front(c->kind, k, a.ss[t], a.ss[t + 1], a.cnt, a.sg[t + 1],
                                  a.sf[t + 1], c->th, a.melted, a.frozen, a.flag, nullptr, nullptr,
-                                 nullptr, c->stream));
+                                 nullptr, nullptr, c->stream));
     }
     // reverse the segment
     for (int64_t t = len - 1; t >= 0; --t) {
@@ -886,6 +896,8 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (!schedule || nsteps < 1) return fail(LBM_EINVAL, "need a schedule and nsteps >= 1");
+  if (c->p.front_scheme != 0)
+    return fail(LBM_EINVAL, "replay follows the Eq. (6) front update (front_scheme 0)");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   const int n = c->p.n;
   const size_t nn = (size_t)n * n;
@@ -925,7 +937,7 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
                                         c->stream));
     HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
                                c->th, c->melted, c->frozen, c->flag, e, e + 3 * nn, nullptr,
-                               c->stream));
+                               nullptr, c->stream));
     HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
     c->cur = nx;
     c->scur = sx;

@@ -61,11 +61,13 @@ hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, voi
 // count, index of the first liquid node, index of the first solid node):
 // record != null writes the one this step uses; replay != null makes the step
 // use the given node indices and take the new liquid counts from
-// replay_next (the following entry) instead of the new fronts.
+// replay_next (the following entry) instead of the new fronts.  heat != null
+// (n^2 values from launch_front_heat) moves every front by heat * Ste /
+// (t_h - t_m), the conservative form of the same balance, instead of Eq. (6).
 hipError_t launch_front(int kind, const KParams& P, const double* s_old, double* s_new,
                         int* cnt, const void* g, void* f, const double* th, int* melted,
                         int* frozen, int* flag, const int* replay, const int* replay_next,
-                        int* record, hipStream_t st);
+                        int* record, const double* heat, hipStream_t st);
 
 // cmin/cmax: min and max of cnt over the (2 radius + 1)^2 columns around each
 // column (radius 1 for the step kernel, 2 for the adjoint's fast path).

@@ -424,7 +424,8 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
                                                int* __restrict__ flag,
                                                const int* __restrict__ replay,
                                                const int* __restrict__ replay_next,
-                                               int* __restrict__ record, KParams P) {
+                                               int* __restrict__ record,
+                                               const double* __restrict__ heat, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int o = blockIdx.y;
@@ -455,44 +456,48 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
     record[2 * nn + col] = a_bot;
   }
 
-  // liquid side: the selected nodes toward the heated wall, then the wall
-  double xi0 = 0, T0v = 0, xi1 = 0, T1v = 0;
-  int k = 0;
-  for (int a = a_top; a >= 0 && k < 2; --a) {
-    const double d = sc - (a + 0.5);
-    const double T = T_at(a);
-    if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
-    ++k;
-  }
-  if (k < 2) {
-    if (k == 0) { xi0 = sc; T0v = th[col]; } else { xi1 = sc; T1v = th[col]; }
-    ++k;
-  }
-  const double Gl = -one_sided(k, xi0, T0v, xi1, T1v, P.t_m);
+  // front velocity: Eq. (6) from one-sided temperature gradients, or (heat
+  // given) the heat the lattice carried into this column's front over L
+  auto gradient_velocity = [&]() -> double {
+    // liquid side: the selected nodes toward the heated wall, then the wall
+    double xi0 = 0, T0v = 0, xi1 = 0, T1v = 0;
+    int k = 0;
+    for (int a = a_top; a >= 0 && k < 2; --a) {
+      const double d = sc - (a + 0.5);
+      const double T = T_at(a);
+      if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
+      ++k;
+    }
+    if (k < 2) {
+      if (k == 0) { xi0 = sc; T0v = th[col]; } else { xi1 = sc; T1v = th[col]; }
+      ++k;
+    }
+    const double Gl = -one_sided(k, xi0, T0v, xi1, T1v, P.t_m);
 
-  // solid side: nodes beyond the front, then the cold wall (melt axis y)
-  k = 0;
-  for (int a = a_bot; a < n && k < 2; ++a) {
-    const double d = (a + 0.5) - sc;
-    const double T = T_at(a);
-    if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
-    ++k;
-  }
-  if (k < 2 && !MZ) {
-    if (k == 0) { xi0 = n - sc; T0v = P.t_c; } else { xi1 = n - sc; T1v = P.t_c; }
-    ++k;
-  }
-  const double Gs = one_sided(k, xi0, T0v, xi1, T1v, P.t_m);
+    // solid side: nodes beyond the front, then the cold wall (melt axis y)
+    k = 0;
+    for (int a = a_bot; a < n && k < 2; ++a) {
+      const double d = (a + 0.5) - sc;
+      const double T = T_at(a);
+      if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
+      ++k;
+    }
+    if (k < 2 && !MZ) {
+      if (k == 0) { xi0 = n - sc; T0v = P.t_c; } else { xi1 = n - sc; T1v = P.t_c; }
+      ++k;
+    }
+    const double Gs = one_sided(k, xi0, T0v, xi1, T1v, P.t_m);
 
-  // front slopes by central differences, mirrored at the walls
-  const double sxp = s_old[o * n + (x + 1 < n ? x + 1 : x)];
-  const double sxm = s_old[o * n + (x > 0 ? x - 1 : x)];
-  const double sop = s_old[(o + 1 < n ? o + 1 : o) * n + x];
-  const double som = s_old[(o > 0 ? o - 1 : o) * n + x];
-  const double dsx = 0.5 * (sxp - sxm), dso = 0.5 * (sop - som);
-  // Eq. (6): k_s dT_s - k_l dT_l in units of k_l (kappa = k_s / k_l)
-  const double V =
-      (1.0 + dsx * dsx + dso * dso) * P.alpha * P.ste * (P.kappa * Gs - Gl) / P.dT;
+    // front slopes by central differences, mirrored at the walls
+    const double sxp = s_old[o * n + (x + 1 < n ? x + 1 : x)];
+    const double sxm = s_old[o * n + (x > 0 ? x - 1 : x)];
+    const double sop = s_old[(o + 1 < n ? o + 1 : o) * n + x];
+    const double som = s_old[(o > 0 ? o - 1 : o) * n + x];
+    const double dsx = 0.5 * (sxp - sxm), dso = 0.5 * (sop - som);
+    // Eq. (6): k_s dT_s - k_l dT_l in units of k_l (kappa = k_s / k_l)
+    return (1.0 + dsx * dsx + dso * dso) * P.alpha * P.ste * (P.kappa * Gs - Gl) / P.dT;
+  };
+  const double V = heat ? heat[col] * P.ste / P.dT : gradient_velocity();
   double sn = sc + V;
   if (!(sn == sn)) *flag = 1;
   sn = sn < 0.0 ? 0.0 : (sn > (double)n ? (double)n : sn);
@@ -698,7 +703,7 @@ template <typename Ts>
 hipError_t front_dispatch(const KParams& P, const double* s_old, double* s_new, int* cnt,
                           const void* g, void* f, const double* th, int* melted, int* frozen,
                           int* flag, const int* replay, const int* replay_next, int* record,
-                          hipStream_t st) {
+                          const double* heat, hipStream_t st) {
   dim3 block(64, 1, 1);
   dim3 grid((P.n + 63) / 64, P.n, 1);
   auto G = static_cast<const Ts*>(g);
@@ -706,17 +711,17 @@ hipError_t front_dispatch(const KParams& P, const double* s_old, double* s_new, 
   if (P.flow) {
     if (P.melt_z)
       hipLaunchKernelGGL((k_front<Ts, true, true>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
-                         melted, frozen, flag, replay, replay_next, record, P);
+                         melted, frozen, flag, replay, replay_next, record, heat, P);
     else
       hipLaunchKernelGGL((k_front<Ts, true, false>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
-                         melted, frozen, flag, replay, replay_next, record, P);
+                         melted, frozen, flag, replay, replay_next, record, heat, P);
   } else {
     if (P.melt_z)
       hipLaunchKernelGGL((k_front<Ts, false, true>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
-                         melted, frozen, flag, replay, replay_next, record, P);
+                         melted, frozen, flag, replay, replay_next, record, heat, P);
     else
       hipLaunchKernelGGL((k_front<Ts, false, false>), grid, block, 0, st, s_old, s_new, cnt, G, F,
-                         th, melted, frozen, flag, replay, replay_next, record, P);
+                         th, melted, frozen, flag, replay, replay_next, record, heat, P);
   }
   return hipGetLastError();
 }
@@ -812,10 +817,10 @@ hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, voi
 hipError_t launch_front(int kind, const KParams& P, const double* s_old, double* s_new, int* cnt,
                         const void* g, void* f, const double* th, int* melted, int* frozen,
                         int* flag, const int* replay, const int* replay_next, int* record,
-                        hipStream_t st) {
+                        const double* heat, hipStream_t st) {
 #define CALL(T)                                                                                 \
   front_dispatch<T>(P, s_old, s_new, cnt, g, f, th, melted, frozen, flag, replay, replay_next, \
-                    record, st)
+                    record, heat, st)
   switch (kind) {
     case kF64: return CALL(double);
     case kF32: return CALL(float);

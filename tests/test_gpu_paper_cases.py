@@ -216,3 +216,39 @@ def test_unequal_conductivities_convection_matches_oracle(heating, prec):
         assert d["T"] <= 1e-11 and d["s"] <= 1e-11 and d["mask"] == 0, d
     else:
         assert d["T"] <= 1e-5 and d["s"] <= 1e-5 and d["mask"] == 0 and d["fl_rel"] <= 1e-6, d
+
+
+# ---------------------------------------------------------------- conservative front
+FLUX_CASES = [
+    dict(n=24, flow=0, alpha=0.1, ste=0.1, seed_profile=1, s0=2.0, steps=1500),
+    dict(n=24, flow=0, alpha=0.1, ste=0.1, seed_profile=2, s0=2.0, t_c=-0.5, steps=1500),
+    dict(n=40, ra=1e5, pr=1.0, ste=0.5, s0=6.3, heating="y0", steps=300),
+    dict(n=40, ra=1e5, pr=1.0, ste=0.5, s0=6.3, heating="z0", t_c=-0.3, ks_kl=2.0, steps=300),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", range(len(FLUX_CASES)))
+def test_conservative_front_matches_oracle(case, prec):
+    """front_scheme 1 (reading R19): the heat the streaming carried into each
+    column's front, gathered per column on the GPU, against the oracle (whose
+    scheme conserves sum(T) + L sum(s) minus the wall heat to round-off)."""
+    kw = dict(FLUX_CASES[case])
+    steps = kw.pop("steps")
+    orc, gpu = make_pair(steps, front_scheme=1, precision=prec, **kw)
+    d = diffs(orc, gpu)
+    if prec == "f64":
+        assert d["T"] <= 1e-11 and d["s"] <= 1e-11 and d["mask"] == 0, d
+    else:
+        assert d["T"] <= 1e-5 and d["s"] <= 1e-5 and d["mask"] == 0 and d["fl_rel"] <= 1e-6, d
+
+
+def test_conservative_front_has_no_adjoint_or_replay():
+    from paper_1604_03478_amd import Config, LbmError, Sim
+    sim = Sim(Config(n=8, flow=0, alpha=0.1, ste=0.1, front_scheme=1, precision="f64"))
+    with pytest.raises(LbmError):
+        sim.forward_ckpt(4, 2)
+    sched = np.zeros(3 * 3 * 64, dtype=np.int32)
+    with pytest.raises(LbmError):
+        sim.step_replay(sched, 2)
+    sim.close()

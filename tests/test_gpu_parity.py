@@ -22,7 +22,7 @@ def make_pair(steps=0, **kw):
     orc = OracleSim(cfg.n, ra=cfg.ra, pr=cfg.pr, ste=cfg.ste, t_h=cfg.t_h, t_c=cfg.t_c,
                     t_m=cfg.t_m, ma=cfg.ma, alpha=cfg.alpha, s0=cfg.s0,
                     heating=HEAT[cfg.heating], flow=cfg.flow, seed_profile=cfg.seed_profile,
-                    ks_kl=cfg.ks_kl)
+                    ks_kl=cfg.ks_kl, front_scheme=cfg.front_scheme)
     gpu = Sim(cfg)
     if steps:
         orc.step(steps)
