@@ -107,7 +107,7 @@ def measure(n, precision, all_liquid, steps, warmup, stream):
 
 def copy_ceiling(stream, nbytes: int = 2 << 30):
     """GB/s of torch's elementwise kernel reading and writing nbytes each
-    (dst = src * 1): a measured ceiling for a two-stream kernel on this machine."""
+    (dst = src * 1): a measured ceiling for a two-stream kernel on this GPU."""
     import torch
     with torch.cuda.stream(stream):
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -345,7 +345,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU slab decomposition is a design, not an implementation.",
               file=sys.stderr)
         sys.exit(2)
