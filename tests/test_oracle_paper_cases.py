@@ -1,7 +1,10 @@
-"""Pins of the oracle's heated-wall Nusselt number (the paper's Fig. 4(b) and
-Fig. 5(b) plot it; reading R16 defines it as -H dT/da at the wall over
-T_h - T_m), and of the conduction verification at the paper's other Stefan
-numbers (section 3.1: Ste = 0.1, 0.5, 1)."""
+"""Pins of the oracle on the paper's own workloads and their extensions: the
+heated-wall Nusselt number (the paper's Fig. 4(b) and Fig. 5(b) plot it;
+reading R16 defines it as -H dT/da at the wall over T_h - T_m), the
+conduction verification at the paper's other Stefan numbers (section 3.1:
+Ste = 0.1, 0.5, 1), and melting into a subcooled solid with equal or
+unequal phase conductivities (Eq. (6)'s solid term; readings R17, R18)
+against the two-phase Neumann solution."""
 import math
 
 import numpy as np
