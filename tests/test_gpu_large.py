@@ -86,3 +86,26 @@ def test_fp16_512_front_tracks_fp64(fp64_run):
           f"rel f_l {abs(fl16 - fl64) / fl64:.2e}")
     assert d.max() <= 3e-4
     assert abs(fl16 - fl64) / fl64 <= 1e-6
+
+
+def test_maximum_size_1024_fp16_front_is_one_dimensional():
+    """The largest lattice the library accepts in 16-bit storage, 1024^3
+    (two buffers of both distributions: 111 GB), bottom heating, Ra = 1e6,
+    300 steps: every column carries the front of the 16^3 oracle with the
+    same diffusivity (the 1-D reduction above), within the FP16 bound."""
+    from paper_1604_03478_amd import Config, Sim
+    n, steps = 1024, 300
+    sim = Sim(Config(n=n, ra=1e6, pr=1.0, ste=STE, s0=1.0, seed_profile=1, heating="z0",
+                     precision="f16s"))
+    alpha = sim.lattice()["alpha"]
+    sim.step(steps)
+    s = sim.fields(which=("s",))["s"]
+    sim.close()
+    o = OracleSim(16, heating=1, flow=0, alpha=alpha, ste=STE, seed_profile=1, s0=1.0)
+    o.step(steps)
+    ref = float(o.s[0, 0])
+    print(f"1024^3 FP16S: front mean {s.mean():.6f} max |ds| {np.abs(s - ref).max():.2e} "
+          f"(oracle 16^3 {ref:.6f})")
+    # the 512^3 noise bound scaled to 300 steps (sqrt(300/2000) of 3e-4) and
+    # 1024^2 columns (5.3 sigma): 1.5e-4; bound 3e-4
+    assert np.abs(s - ref).max() <= 3e-4
