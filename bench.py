@@ -55,12 +55,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_CELL = {"f32": 208, "f16s": 104, "bf16s": 104, "f64": 416}
-# one reverse step, FP32 storage, FP64 adjoint: transposed collision (state
-# 104 B + adjoint 208 B read, 208 B written) and transposed streaming (208 B
-# read, 208 B written) in a liquid cell; a solid cell moves only g and its
-# adjoint (28 + 56 B read, 56 B written; 56 B read, 56 B written)
-ADJ_BYTES_LIQUID = 520 + 416
-ADJ_BYTES_SOLID = 140 + 112
+# one reverse step, FP32 storage and FP32 per-cell adjoints: transposed
+# collision (state 104 B + adjoint 104 B read, 104 B written) and transposed
+# streaming (104 B read, 104 B written) in a liquid cell; a solid cell moves
+# only g and its adjoint (28 + 28 B read, 28 B written; 28 B read, 28 B written)
+ADJ_BYTES_LIQUID = 312 + 208
+ADJ_BYTES_SOLID = 84 + 56
 # sources the stream-collide kernel is compiled from
 KERNEL_SRC = [os.path.join(ROOT, "paper_1604_03478_amd", "csrc", f)
               for f in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h")]

@@ -9,8 +9,10 @@
 
 namespace lbmk {
 
-// One reverse step from the state t+1 to the state t (FP64 adjoints, dense
-// [q][n^3] and [n^2] arrays).  lg1 receives the front contributions; lf0/lg0
+// One reverse step from the state t+1 to the state t.  Per-cell adjoints
+// (lf*, lg*: dense [q][n^3] arrays) are stored in the type lambda_bytes
+// gives (FP64 for FP64 storage, FP32 otherwise); the per-column ones (ls*,
+// lth, out5, own: [n^2]) are FP64.  lg1 receives the front contributions; lf0/lg0
 // are written where they are live (f: cells liquid at t), ls0 is
 // overwritten, lth is incremented.
 struct AdjointStep {
@@ -23,19 +25,24 @@ struct AdjointStep {
   const int* cnt;    // liquid counts of state t
   const int* cmin2;  // their min / max over the 5x5 columns around each column
   const int* cmax2;
-  double* lf1;
-  double* lg1;
+  void* lf1;
+  void* lg1;
   const double* ls1;
-  double* lf0;
-  double* lg0;
+  void* lf0;
+  void* lg0;
   double* ls0;
-  double* lfh;
-  double* lgh;       // per-cell adjoint of the pulled populations
+  void* lfh;
+  void* lgh;         // per-cell adjoint of the pulled populations
   double* out5;
   double* own;       // per-column scratch of the front adjoint
   double* lth;
 };
 hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A, hipStream_t st);
 hipError_t launch_fill(double* v, size_t count, double value, hipStream_t st);
+
+// Bytes of one per-cell adjoint value for a storage kind, and a fill of such
+// an array.
+size_t lambda_bytes(int kind);
+hipError_t launch_fill_lambda(int kind, void* v, size_t count, double value, hipStream_t st);
 
 }  // namespace lbmk

@@ -25,7 +25,10 @@
 //   k_adj_interface    per column: dependence of the interpolated
 //                      anti-bounce-back on the front through the link
 //                      fractions, and of the hot-wall condition on T_h
-// Adjoint arithmetic is FP64 for every storage format.
+// Adjoint arithmetic is FP64 for every storage format.  The per-cell
+// adjoints of f and g are stored in FP64 with FP64 storage and in FP32
+// otherwise (the state they are taken at is itself FP32 or coarser); the
+// adjoints of the fronts and of T_h are FP64 throughout.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -500,10 +503,10 @@ __device__ void front_der(const Ts* g1, const double* s, const double* th, int c
 // ---------------------------------------------------------------- kernels
 // Adjoint buffers are dense FP64 arrays [q][n^3] (populations) and [n^2].
 
-template <typename Ts, bool FLOW, bool MZ>
+template <typename Ts, typename Lam, bool FLOW, bool MZ>
 __global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict__ g1,
                             const double* __restrict__ s1, const double* __restrict__ th,
-                            const double* __restrict__ ls1, double* __restrict__ lg1,
+                            const double* __restrict__ ls1, Lam* __restrict__ lg1,
                             double* __restrict__ out5, double* __restrict__ own,
                             double* __restrict__ lth, KParams P) {
   const int n = P.n;
@@ -522,7 +525,10 @@ __global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict_
   }
   own[c] = l;
   for (int k = 0; k < d.nnode; ++k)
-    for (int q = 0; q < 7; ++q) lg1[(size_t)q * nc + d.node[k]] += l * d.dT[k];
+    for (int q = 0; q < 7; ++q) {
+      Lam& v = lg1[(size_t)q * nc + d.node[k]];
+      v = (Lam)((double)v + l * d.dT[k]);
+    }
   for (int j = 0; j < 5; ++j) out5[j * nn + c] = l * d.ds[j];
   lth[c] += l * d.dth;
 }
@@ -544,13 +550,12 @@ __global__ void k_adj_front_gather(const double* __restrict__ own, const double*
   ls0[c] = acc;
 }
 
-template <typename Ts, bool FLOW, bool MZ>
+template <typename Ts, typename Lam, bool FLOW, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_collide(
     const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
     const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
-    const int* __restrict__ cmin2, const int* __restrict__ cmax2, const double* __restrict__ lf1,
-    const double* __restrict__ lg1, double* __restrict__ lfh, double* __restrict__ lgh,
-    KParams P) {
+    const int* __restrict__ cmin2, const int* __restrict__ cmax2, const Lam* __restrict__ lf1,
+    const Lam* __restrict__ lg1, Lam* __restrict__ lfh, Lam* __restrict__ lgh, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= n) return;
@@ -566,19 +571,19 @@ __global__ __launch_bounds__(256) void k_adj_collide(
   else
     pull_cell<Ts, FLOW, MZ>(f0, g0, s0, th, cnt, x, y, z, liquid, P, M);
   double lfo[19], lgo[7], lfl[19], lgl[7];
-  for (int q = 0; q < 19; ++q) lfo[q] = (FLOW && live1) ? lf1[(size_t)q * nc + i] : 0.0;
-  for (int q = 0; q < 7; ++q) lgo[q] = lg1[(size_t)q * nc + i];
+  for (int q = 0; q < 19; ++q) lfo[q] = (FLOW && live1) ? (double)lf1[(size_t)q * nc + i] : 0.0;
+  for (int q = 0; q < 7; ++q) lgo[q] = (double)lg1[(size_t)q * nc + i];
   collide_adjoint<FLOW>(M, liquid, P, lfo, lgo, lfl, lgl);
   if (FLOW && liquid)  // read only at liquid cells
-    for (int q = 0; q < 19; ++q) lfh[(size_t)q * nc + i] = lfl[q];
-  for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = lgl[q];
+    for (int q = 0; q < 19; ++q) lfh[(size_t)q * nc + i] = (Lam)lfl[q];
+  for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = (Lam)lgl[q];
 }
 
-template <typename Ts, bool FLOW, bool MZ>
+template <typename Ts, typename Lam, bool FLOW, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_stream(
     const double* __restrict__ s0, const int* __restrict__ cnt, const int* __restrict__ cmin2,
-    const int* __restrict__ cmax2, const double* __restrict__ lfh,
-    const double* __restrict__ lgh, double* __restrict__ lf0, double* __restrict__ lg0,
+    const int* __restrict__ cmax2, const Lam* __restrict__ lfh,
+    const Lam* __restrict__ lgh, Lam* __restrict__ lf0, Lam* __restrict__ lg0,
     KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
@@ -587,7 +592,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
   const size_t nc = P.ncell;
   const uint32_t i = G.cell(x, y, z);
   const bool L = liquid_at<MZ>(cnt, x, y, z, n);
-  auto LG = [&](int q, uint32_t j) { return lgh[(size_t)q * nc + j]; };
+  auto LG = [&](int q, uint32_t j) { return (double)lgh[(size_t)q * nc + j]; };
 
   if (__all(adj_fast<MZ>(cmin2, cmax2, x, y, z, n))) {
     // one phase all around: each stored population was read by the regular
@@ -597,7 +602,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
       const int ex = ex7(p);
       const bool in = (unsigned)(x + ex) < (unsigned)n;
       lg0[(size_t)p * nc + i] =
-          in ? LG(p, G.cell(x + ex, y + ey7(p), z + ez7(p))) : LG(opp7(p), i);
+          (Lam)(in ? LG(p, G.cell(x + ex, y + ey7(p), z + ez7(p))) : LG(opp7(p), i));
     }
     if (FLOW && L) {
 #pragma unroll
@@ -654,7 +659,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
         }
       }
     }
-    lg0[(size_t)p * nc + i] = acc;
+    lg0[(size_t)p * nc + i] = (Lam)acc;
   }
   // adjoint of f before the step: only liquid cells read their f (solid
   // cells hold dead data, whose adjoint is zero and is not stored)
@@ -671,9 +676,9 @@ __global__ __launch_bounds__(256) void k_adj_stream(
 // derivative of the pulled population of an interface link with respect to
 // its link fraction, times its adjoint; reader cell (x,y,z), incoming
 // direction q (its source across the front)
-template <typename Ts, bool MZ>
+template <typename Ts, typename Lam, bool MZ>
 __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, const int* cnt,
-                                            const double* lgh, int x, int y, int z, int q,
+                                            const Lam* lgh, int x, int y, int z, int q,
                                             bool L, double& dfrac, const KParams& P) {
   const int n = P.n;
   const Geo G{n, (uint32_t)n * (uint32_t)n};
@@ -682,7 +687,7 @@ __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, cons
   const int p = opp7(q);
   const double d = link_delta<MZ>(s0, x, y, z, -ex7(q), -ey7(q), -ez7(q), n);
   dfrac = d;
-  const double l = lgh[(size_t)q * nc + i];
+  const double l = (double)lgh[(size_t)q * nc + i];
   if (d < 0.5) {
     const int bx = x + ex7(q), by = y + ey7(q), bz = z + ez7(q);
     if (G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L)
@@ -694,9 +699,9 @@ __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, cons
           w * (P.t_m - P.tref) / (d * d)) * l;
 }
 
-template <typename Ts, bool MZ>
+template <typename Ts, typename Lam, bool MZ>
 __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restrict__ s0,
-                                const int* __restrict__ cnt, const double* __restrict__ lgh,
+                                const int* __restrict__ cnt, const Lam* __restrict__ lgh,
                                 double* __restrict__ ls0, double* __restrict__ lth, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
@@ -708,7 +713,7 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
   {
     const uint32_t i = cell_in_column<MZ>(c, 0, n);
     const int qin = MZ ? 5 : 3;  // +z or +y: pulled from the heated wall
-    lth[c] += 2.0 * 0.125 * lgh[(size_t)qin * nc + i];
+    lth[c] += 2.0 * 0.125 * (double)lgh[(size_t)qin * nc + i];
   }
   // lateral neighbour columns (in the box)
   int nb[4], nbx[4], nbo[4], k = 0;
@@ -742,7 +747,7 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
           continue;
         if (liquid_at<MZ>(cnt, sx, sy, sz, n) == L) continue;
         double d;
-        const double ld = link_sens<Ts, MZ>(g0, s0, cnt, lgh, cx, cy, cz, q, L, d, P);
+        const double ld = link_sens<Ts, Lam, MZ>(g0, s0, cnt, lgh, cx, cy, cz, q, L, d, P);
         const bool along = MZ ? (ez7(q) != 0) : (ey7(q) != 0);
         if (along) {
           acc += (sc > ya ? 1.0 : -1.0) * ld;
@@ -768,7 +773,7 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
       }
       if (q < 1) continue;  // every lateral neighbour has one such direction
       double d;
-      const double ld = link_sens<Ts, MZ>(g0, s0, cnt, lgh, cx, cy, cz, q, L, d, P);
+      const double ld = link_sens<Ts, Lam, MZ>(g0, s0, cnt, lgh, cx, cy, cz, q, L, d, P);
       const double sself = s0[nb[j]];
       acc += ld * (-(ya - sself)) / ((sc - sself) * (sc - sself));
     }
@@ -776,12 +781,22 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
   ls0[c] += acc;
 }
 
-__global__ void k_fill(double* __restrict__ v, size_t count, double value) {
+template <typename V>
+__global__ void k_fill(V* __restrict__ v, size_t count, double value) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) v[i] = value;
+  if (i < count) v[i] = (V)value;
 }
 
-template <typename Ts, bool FLOW, bool MZ>
+template <typename V>
+hipError_t fill_t(V* v, size_t count, double value, hipStream_t st) {
+  if (!v) return hipErrorInvalidValue;
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_fill<V>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, v,
+                     count, value);
+  return hipGetLastError();
+}
+
+template <typename Ts, typename Lam, bool FLOW, bool MZ>
 hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st) {
   const int n = P.n;
   const dim3 bcol(64, 1, 1), gcol((n + 63) / 64, n, 1);
@@ -791,46 +806,54 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   const Ts* f0 = static_cast<const Ts*>(A.f0);
   const Ts* g0 = static_cast<const Ts*>(A.g0);
   const Ts* g1 = static_cast<const Ts*>(A.g1);
-  hipLaunchKernelGGL((k_adj_front<Ts, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.s1, A.th, A.ls1,
-                     A.lg1, A.out5, A.own, A.lth, P);
+  Lam* lf1 = static_cast<Lam*>(A.lf1);
+  Lam* lg1 = static_cast<Lam*>(A.lg1);
+  Lam* lf0 = static_cast<Lam*>(A.lf0);
+  Lam* lg0 = static_cast<Lam*>(A.lg0);
+  Lam* lfh = static_cast<Lam*>(A.lfh);
+  Lam* lgh = static_cast<Lam*>(A.lgh);
+  hipLaunchKernelGGL((k_adj_front<Ts, Lam, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.s1, A.th,
+                     A.ls1, lg1, A.out5, A.own, A.lth, P);
   hipLaunchKernelGGL(k_adj_front_gather, gcol, bcol, 0, st, A.own, A.out5, A.ls0, n);
-  hipLaunchKernelGGL((k_adj_collide<Ts, FLOW, MZ>), gcell, bcell, 0, st, f0, g0, A.s0, A.s1, A.th,
-                     A.cnt, A.cmin2, A.cmax2, A.lf1, A.lg1, A.lfh, A.lgh, P);
-  hipLaunchKernelGGL((k_adj_stream<Ts, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
-                     A.cmax2, A.lfh, A.lgh,
-                     A.lf0, A.lg0, P);
-  hipLaunchKernelGGL((k_adj_interface<Ts, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, A.lgh, A.ls0,
-                     A.lth, P);
+  hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ>), gcell, bcell, 0, st, f0, g0, A.s0, A.s1,
+                     A.th, A.cnt, A.cmin2, A.cmax2, lf1, lg1, lfh, lgh, P);
+  hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
+                     A.cmax2, lfh, lgh, lf0, lg0, P);
+  hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh,
+                     A.ls0, A.lth, P);
   return hipGetLastError();
 }
 
-template <typename Ts>
+template <typename Ts, typename Lam>
 hipError_t adjoint_step_d(const KParams& P, const AdjointStep& A, hipStream_t st) {
   if (P.flow)
-    return P.melt_z ? adjoint_step_t<Ts, true, true>(P, A, st)
-                    : adjoint_step_t<Ts, true, false>(P, A, st);
-  return P.melt_z ? adjoint_step_t<Ts, false, true>(P, A, st)
-                  : adjoint_step_t<Ts, false, false>(P, A, st);
+    return P.melt_z ? adjoint_step_t<Ts, Lam, true, true>(P, A, st)
+                    : adjoint_step_t<Ts, Lam, true, false>(P, A, st);
+  return P.melt_z ? adjoint_step_t<Ts, Lam, false, true>(P, A, st)
+                  : adjoint_step_t<Ts, Lam, false, false>(P, A, st);
 }
 
 }  // namespace
 
 hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A, hipStream_t st) {
   switch (kind) {
-    case kF64: return adjoint_step_d<double>(P, A, st);
-    case kF32: return adjoint_step_d<float>(P, A, st);
-    case kF16S: return adjoint_step_d<_Float16>(P, A, st);
-    case kBF16S: return adjoint_step_d<__bf16>(P, A, st);
+    case kF64: return adjoint_step_d<double, double>(P, A, st);
+    case kF32: return adjoint_step_d<float, float>(P, A, st);
+    case kF16S: return adjoint_step_d<_Float16, float>(P, A, st);
+    case kBF16S: return adjoint_step_d<__bf16, float>(P, A, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_fill(double* v, size_t count, double value, hipStream_t st) {
-  if (!v) return hipErrorInvalidValue;
-  if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, v, count,
-                     value);
-  return hipGetLastError();
+  return fill_t(v, count, value, st);
+}
+
+size_t lambda_bytes(int kind) { return kind == kF64 ? sizeof(double) : sizeof(float); }
+
+hipError_t launch_fill_lambda(int kind, void* v, size_t count, double value, hipStream_t st) {
+  return kind == kF64 ? fill_t(static_cast<double*>(v), count, value, st)
+                      : fill_t(static_cast<float*>(v), count, value, st);
 }
 
 }  // namespace lbmk

@@ -92,8 +92,10 @@ struct AdjData {
   std::vector<double*> ss;
   int *cnt = nullptr, *cmin = nullptr, *cmax = nullptr, *melted = nullptr, *frozen = nullptr,
       *flag = nullptr, *cmin2 = nullptr, *cmax2 = nullptr;
-  double *lf[2] = {nullptr, nullptr}, *lg[2] = {nullptr, nullptr}, *ls[2] = {nullptr, nullptr};
-  double *lfh = nullptr, *lgh = nullptr, *out5 = nullptr, *own = nullptr, *lth = nullptr;
+  void *lf[2] = {nullptr, nullptr}, *lg[2] = {nullptr, nullptr};  // per-cell adjoints
+  void *lfh = nullptr, *lgh = nullptr;
+  double *ls[2] = {nullptr, nullptr};
+  double *out5 = nullptr, *own = nullptr, *lth = nullptr;
 };
 
 struct lbm_ctx {
@@ -285,6 +287,14 @@ int dalloc(T** p, size_t count) {
   if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
     *p = nullptr;
     return fail(LBM_ENOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+  }
+  return LBM_OK;
+}
+
+int dalloc_bytes(void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return fail(LBM_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
   }
   return LBM_OK;
 }
@@ -803,17 +813,19 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
     a.sg.push_back(g);
     a.ss.push_back(sp);
   }
+  const size_t lb = lbmk::lambda_bytes(c->kind);  // bytes of one per-cell adjoint value
   if (!a.lg[0]) {
     if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cmin, nn)) || (rc = dalloc(&a.cmax, nn)) ||
         (rc = dalloc(&a.cmin2, nn)) || (rc = dalloc(&a.cmax2, nn)) ||
         (rc = dalloc(&a.melted, nn)) || (rc = dalloc(&a.frozen, nn)) || (rc = dalloc(&a.flag, 1)) ||
-        (rc = dalloc(&a.lg[0], 7 * nc)) || (rc = dalloc(&a.lg[1], 7 * nc)) ||
+        (rc = dalloc_bytes(&a.lg[0], 7 * nc * lb)) || (rc = dalloc_bytes(&a.lg[1], 7 * nc * lb)) ||
         (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
-        (rc = dalloc(&a.lgh, 7 * nc)) || (rc = dalloc(&a.out5, 5 * nn)) ||
+        (rc = dalloc_bytes(&a.lgh, 7 * nc * lb)) || (rc = dalloc(&a.out5, 5 * nn)) ||
         (rc = dalloc(&a.own, nn)) || (rc = dalloc(&a.lth, nn)))
       return rc;
-    if (flow && ((rc = dalloc(&a.lf[0], 19 * nc)) || (rc = dalloc(&a.lf[1], 19 * nc)) ||
-                 (rc = dalloc(&a.lfh, 19 * nc))))
+    if (flow && ((rc = dalloc_bytes(&a.lf[0], 19 * nc * lb)) ||
+                 (rc = dalloc_bytes(&a.lf[1], 19 * nc * lb)) ||
+                 (rc = dalloc_bytes(&a.lfh, 19 * nc * lb))))
       return rc;
   }
   HIP_TRY(hipMemsetAsync(a.melted, 0, nn * sizeof(int), c->stream));
@@ -822,8 +834,8 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   // adjoint of the final state: J = dJ_dfl * sum(s) / n^3
   int cur = 1;
   HIP_TRY(lbmk::launch_fill(a.ls[cur], nn, dJ_dfl / ((double)nn * c->p.n), c->stream));
-  HIP_TRY(lbmk::launch_fill(a.lg[cur], 7 * nc, 0.0, c->stream));
-  if (flow) HIP_TRY(lbmk::launch_fill(a.lf[cur], 19 * nc, 0.0, c->stream));
+  HIP_TRY(lbmk::launch_fill_lambda(c->kind, a.lg[cur], 7 * nc, 0.0, c->stream));
+  if (flow) HIP_TRY(lbmk::launch_fill_lambda(c->kind, a.lf[cur], 19 * nc, 0.0, c->stream));
   HIP_TRY(lbmk::launch_fill(a.lth, nn, 0.0, c->stream));
   lbmk::KParams k = c->kp;
   for (int i = a.nck - 1; i >= 0; --i) {
