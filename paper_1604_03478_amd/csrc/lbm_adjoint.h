@@ -25,6 +25,7 @@ struct AdjointStep {
   const int* cnt;    // liquid counts of state t
   const int* cmin2;  // their min / max over the 5x5 columns around each column
   const int* cmax2;
+  int* rowb;         // one int: the bound of the bulk-solid row partition
   void* lf1;
   void* lg1;
   const double* ls1;

@@ -203,12 +203,6 @@ __device__ __forceinline__ double sv(const Ts* a, const KParams& P, int q, uint3
       a[((uint64_t)row * Q + q) * P.pitch + x]);
 }
 
-// stored population q of cell (x, y, z), in FP64
-template <int Q, typename Ts>
-__device__ __forceinline__ double sv_at(const Ts* a, const KParams& P, int q, int x, int y, int z) {
-  return (double)static_cast<typename Compute<Ts>::type>(a[pop_index(P, Q, q, x, y, z)]);
-}
-
 // Fast-path test of the reverse kernels: away from the y and z walls, and
 // every cell within two columns and two heights in one phase (the transposed
 // streaming reaches the source of a neighbour's link, two cells away).
@@ -234,26 +228,104 @@ struct Macro {
   }
 };
 
+// Row partition of the reverse collision and streaming.  With A = min(n - 1,
+// max liquid count + 2), a row (height a along the melt axis, o across it)
+// with A <= a < n - 1 and 0 < o < n - 1 is away from the walls and every
+// cell within two columns and two heights of it is solid: the fast path
+// with g alone.  The other rows (every height below A, the top height and
+// the two side rows in between) take the full kernels; there are
+// front_rows(A, n) of them, enumerated by front_row.
+__device__ __forceinline__ bool bulk_solid_row(int a, int o, int A, int n) {
+  return (a >= A) & (a < n - 1) & (o > 0) & (o < n - 1);
+}
+__device__ __forceinline__ int front_rows(int A, int n) { return A * n + n + 2 * (n - 1 - A); }
+__device__ __forceinline__ void front_row(int r, int A, int n, int& a, int& o) {
+  if (r < A * n) {
+    a = r / n;
+    o = r - a * n;
+  } else if (r < A * n + n) {
+    a = n - 1;
+    o = r - A * n;
+  } else {
+    const int k = r - A * n - n;
+    a = A + (k >> 1);
+    o = (k & 1) ? n - 1 : 0;
+  }
+}
+
+// the bound A of the row partition, from the liquid counts of state t (one
+// workgroup of 1024 lanes, eight independent loads per lane in flight)
+__global__ __launch_bounds__(1024) void k_adj_rows(const int* __restrict__ cnt,
+                                                   int* __restrict__ rowb, int n) {
+  __shared__ int part[1024];
+  const int nn = n * n;
+  int m = 0;
+  for (int c0 = threadIdx.x; c0 < nn; c0 += 8 * 1024) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = c0 + u * 1024 < nn ? cnt[c0 + u * 1024] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m = v[u] > m ? v[u] : m;
+  }
+  part[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w && part[threadIdx.x + w] > part[threadIdx.x])
+      part[threadIdx.x] = part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rowb[0] = part[0] + 2 < n - 1 ? part[0] + 2 : n - 1;
+}
+
 // pulled populations of a cell on the fast path: regular pulls, bounce-back
 // at the adiabatic / no-slip x walls only
+// (Each source index is selected before its load, and every load of a cell
+// is issued before the first use, so the loads are in flight together.)
 template <typename Ts, bool FLOW>
 __device__ __forceinline__ void pull_fast(const Ts* f, const Ts* g, int x, int y, int z,
                                           bool liquid, const KParams& P, Macro& M) {
+  using C = typename Compute<Ts>::type;
   const int n = P.n;
+  Ts gv[7];
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
     const int sx = x - ex7(q);
-    M.add_g(((unsigned)sx < (unsigned)n) ? sv_at<7>(g, P, q, sx, y - ey7(q), z - ez7(q))
-                                         : sv_at<7>(g, P, opp7(q), x, y, z));
+    gv[q] = g[(unsigned)sx < (unsigned)n ? pop_index(P, 7, q, sx, y - ey7(q), z - ez7(q))
+                                         : pop_index(P, 7, opp7(q), x, y, z)];
   }
+#pragma unroll
+  for (int q = 0; q < 7; ++q) M.add_g((double)static_cast<C>(gv[q]));
   if (FLOW && liquid) {
+    Ts fv[19];
 #pragma unroll
     for (int q = 1; q < 19; ++q) {  // the rest population carries no momentum
       const int sx = x - ex19(q);
-      M.add_f(q, ((unsigned)sx < (unsigned)n) ? sv_at<19>(f, P, q, sx, y - ey19(q), z - ez19(q))
-                                              : sv_at<19>(f, P, opp19(q), x, y, z));
+      fv[q] = f[(unsigned)sx < (unsigned)n ? pop_index(P, 19, q, sx, y - ey19(q), z - ez19(q))
+                                           : pop_index(P, 19, opp19(q), x, y, z)];
     }
+#pragma unroll
+    for (int q = 1; q < 19; ++q) M.add_f(q, (double)static_cast<C>(fv[q]));
   }
+}
+
+// Transposed streaming of one cell on the fast path (one phase all around):
+// stored population p before the step was read by the regular pull of the
+// neighbour x + e_p, or, at an x wall, by this cell's bounce-back into the
+// reverse direction.  Indices first, then all Q loads, then the stores.
+template <int Q, typename Lam>
+__device__ __forceinline__ void push_fast(const Lam* __restrict__ lh, Lam* __restrict__ l0,
+                                          const Geo& G, size_t nc, int x, int y, int z,
+                                          uint32_t i) {
+  Lam v[Q];
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+    const int ex = Q == 7 ? ex7(p) : ex19(p), ey = Q == 7 ? ey7(p) : ey19(p),
+              ez = Q == 7 ? ez7(p) : ez19(p), q = Q == 7 ? opp7(p) : opp19(p);
+    const bool in = (unsigned)(x + ex) < (unsigned)G.n;
+    v[p] = lh[in ? (size_t)p * nc + G.cell(x + ex, y + ey, z + ez) : (size_t)q * nc + i];
+  }
+#pragma unroll
+  for (int p = 0; p < Q; ++p) l0[(size_t)p * nc + i] = v[p];
 }
 
 // pulled (pre-collision) shifted populations of one cell (general path), in
@@ -550,15 +622,15 @@ __global__ void k_adj_front_gather(const double* __restrict__ own, const double*
   ls0[c] = acc;
 }
 
+// reverse collision of one cell (any row)
 template <typename Ts, typename Lam, bool FLOW, bool MZ>
-__global__ __launch_bounds__(256) void k_adj_collide(
+__device__ __forceinline__ void adj_collide_cell(
     const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
     const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
     const int* __restrict__ cmin2, const int* __restrict__ cmax2, const Lam* __restrict__ lf1,
-    const Lam* __restrict__ lg1, Lam* __restrict__ lfh, Lam* __restrict__ lgh, KParams P) {
+    const Lam* __restrict__ lg1, Lam* __restrict__ lfh, Lam* __restrict__ lgh, const KParams& P,
+    int x, int y, int z) {
   const int n = P.n;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-  if (x >= n) return;
   const size_t nc = P.ncell;
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
   const bool liquid = liquid_at<MZ>(cnt, x, y, z, n);
@@ -579,10 +651,52 @@ __global__ __launch_bounds__(256) void k_adj_collide(
   for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = (Lam)lgl[q];
 }
 
+// The rows outside the bulk solid, front_rows(A, n) of them, visited by a
+// grid of gridDim.y row slots (this kernel needs many registers, so its
+// waves are not spent on rows it would skip).
+template <typename Ts, typename Lam, bool FLOW, bool MZ>
+__global__ __launch_bounds__(256) void k_adj_collide(
+    const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
+    const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
+    const int* __restrict__ cmin2, const int* __restrict__ cmax2, const int* __restrict__ rowb,
+    const Lam* __restrict__ lf1, const Lam* __restrict__ lg1, Lam* __restrict__ lfh,
+    Lam* __restrict__ lgh, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int A = rowb[0], R = front_rows(A, n);
+  for (int r = blockIdx.y; r < R; r += gridDim.y) {
+    int a, o;
+    front_row(r, A, n, a, o);
+    if (x < n)
+      adj_collide_cell<Ts, Lam, FLOW, MZ>(f0, g0, s0, s1, th, cnt, cmin2, cmax2, lf1, lg1, lfh,
+                                          lgh, P, x, MZ ? o : a, MZ ? a : o);
+  }
+}
+
+// The bulk solid rows k_adj_collide leaves out: only the energy distribution
+// is reversed, with few registers, so these rows (most of a melting state)
+// run at full occupancy.
+template <typename Ts, typename Lam, bool MZ>
+__global__ __launch_bounds__(256) void k_adj_collide_solid(
+    const Ts* __restrict__ g0, const int* __restrict__ rowb, const Lam* __restrict__ lg1,
+    Lam* __restrict__ lgh, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, rowb[0], n)) return;
+  const size_t nc = P.ncell;
+  const uint32_t i = ((uint32_t)z * n + y) * n + x;
+  Macro M;
+  pull_fast<Ts, false>(static_cast<const Ts*>(nullptr), g0, x, y, z, false, P, M);
+  double lfo[19] = {}, lgo[7], lfl[19], lgl[7];
+  for (int q = 0; q < 7; ++q) lgo[q] = (double)lg1[(size_t)q * nc + i];
+  collide_adjoint<false>(M, false, P, lfo, lgo, lfl, lgl);
+  for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = (Lam)lgl[q];
+}
+
 template <typename Ts, typename Lam, bool FLOW, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_stream(
     const double* __restrict__ s0, const int* __restrict__ cnt, const int* __restrict__ cmin2,
-    const int* __restrict__ cmax2, const Lam* __restrict__ lfh,
+    const int* __restrict__ cmax2, const int* __restrict__ rowb, const Lam* __restrict__ lfh,
     const Lam* __restrict__ lgh, Lam* __restrict__ lf0, Lam* __restrict__ lg0,
     KParams P) {
   const int n = P.n;
@@ -591,28 +705,16 @@ __global__ __launch_bounds__(256) void k_adj_stream(
   const Geo G{n, (uint32_t)n * (uint32_t)n};
   const size_t nc = P.ncell;
   const uint32_t i = G.cell(x, y, z);
+  if (bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, rowb[0], n)) {
+    push_fast<7>(lgh, lg0, G, nc, x, y, z, i);  // a solid cell: g only, no phase reads
+    return;
+  }
   const bool L = liquid_at<MZ>(cnt, x, y, z, n);
   auto LG = [&](int q, uint32_t j) { return (double)lgh[(size_t)q * nc + j]; };
 
   if (__all(adj_fast<MZ>(cmin2, cmax2, x, y, z, n))) {
-    // one phase all around: each stored population was read by the regular
-    // pull of the neighbour x + e_p, or by this cell's bounce-back at an x wall
-#pragma unroll
-    for (int p = 0; p < 7; ++p) {
-      const int ex = ex7(p);
-      const bool in = (unsigned)(x + ex) < (unsigned)n;
-      lg0[(size_t)p * nc + i] =
-          (Lam)(in ? LG(p, G.cell(x + ex, y + ey7(p), z + ez7(p))) : LG(opp7(p), i));
-    }
-    if (FLOW && L) {
-#pragma unroll
-      for (int p = 0; p < 19; ++p) {
-        const int ex = ex19(p);
-        const bool in = (unsigned)(x + ex) < (unsigned)n;
-        lf0[(size_t)p * nc + i] = in ? lfh[(size_t)p * nc + G.cell(x + ex, y + ey19(p), z + ez19(p))]
-                                     : lfh[(size_t)opp19(p) * nc + i];
-      }
-    }
+    push_fast<7>(lgh, lg0, G, nc, x, y, z, i);
+    if (FLOW && L) push_fast<19>(lfh, lf0, G, nc, x, y, z, i);
     return;
   }
 
@@ -815,10 +917,15 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   hipLaunchKernelGGL((k_adj_front<Ts, Lam, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.s1, A.th,
                      A.ls1, lg1, A.out5, A.own, A.lth, P);
   hipLaunchKernelGGL(k_adj_front_gather, gcol, bcol, 0, st, A.own, A.out5, A.ls0, n);
-  hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ>), gcell, bcell, 0, st, f0, g0, A.s0, A.s1,
-                     A.th, A.cnt, A.cmin2, A.cmax2, lf1, lg1, lfh, lgh, P);
+  hipLaunchKernelGGL(k_adj_rows, dim3(1), dim3(1024), 0, st, A.cnt, A.rowb, n);
+  // row slots of the full reverse collision: at most one per row
+  const dim3 gfront((n + bx - 1) / bx, (unsigned)(n * n < 2048 ? n * n : 2048), 1);
+  hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ>), gfront, bcell, 0, st, f0, g0, A.s0,
+                     A.s1, A.th, A.cnt, A.cmin2, A.cmax2, A.rowb, lf1, lg1, lfh, lgh, P);
+  hipLaunchKernelGGL((k_adj_collide_solid<Ts, Lam, MZ>), gcell, bcell, 0, st, g0, A.rowb, lg1,
+                     lgh, P);
   hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
-                     A.cmax2, lfh, lgh, lf0, lg0, P);
+                     A.cmax2, A.rowb, lfh, lgh, lf0, lg0, P);
   hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh,
                      A.ls0, A.lth, P);
   return hipGetLastError();

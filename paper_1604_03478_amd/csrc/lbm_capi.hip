@@ -91,7 +91,7 @@ struct AdjData {
   std::vector<void*> sf, sg;  // segment states 0..K
   std::vector<double*> ss;
   int *cnt = nullptr, *cmin = nullptr, *cmax = nullptr, *melted = nullptr, *frozen = nullptr,
-      *flag = nullptr, *cmin2 = nullptr, *cmax2 = nullptr;
+      *flag = nullptr, *cmin2 = nullptr, *cmax2 = nullptr, *rowb = nullptr;
   void *lf[2] = {nullptr, nullptr}, *lg[2] = {nullptr, nullptr};  // per-cell adjoints
   void *lfh = nullptr, *lgh = nullptr;
   double *ls[2] = {nullptr, nullptr};
@@ -164,7 +164,7 @@ void release_adjoint(AdjData& a) {
   free_all(a.sf);
   free_all(a.sg);
   free_all(a.ss);
-  void* ptrs[] = {a.cnt,   a.cmin,  a.cmax,  a.cmin2, a.cmax2, a.melted, a.frozen, a.flag,
+  void* ptrs[] = {a.cnt,   a.cmin,  a.cmax,  a.cmin2, a.cmax2, a.rowb, a.melted, a.frozen, a.flag,
                   a.lf[0], a.lf[1], a.lg[0],
                   a.lg[1], a.ls[0], a.ls[1], a.lfh, a.lgh, a.out5, a.own, a.lth};
   for (void* p : ptrs)
@@ -816,7 +816,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   const size_t lb = lbmk::lambda_bytes(c->kind);  // bytes of one per-cell adjoint value
   if (!a.lg[0]) {
     if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cmin, nn)) || (rc = dalloc(&a.cmax, nn)) ||
-        (rc = dalloc(&a.cmin2, nn)) || (rc = dalloc(&a.cmax2, nn)) ||
+        (rc = dalloc(&a.cmin2, nn)) || (rc = dalloc(&a.cmax2, nn)) || (rc = dalloc(&a.rowb, 1)) ||
         (rc = dalloc(&a.melted, nn)) || (rc = dalloc(&a.frozen, nn)) || (rc = dalloc(&a.flag, 1)) ||
         (rc = dalloc_bytes(&a.lg[0], 7 * nc * lb)) || (rc = dalloc_bytes(&a.lg[1], 7 * nc * lb)) ||
         (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
@@ -870,6 +870,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
       A.cnt = a.cnt;
       A.cmin2 = a.cmin2;
       A.cmax2 = a.cmax2;
+      A.rowb = a.rowb;
       A.lf1 = a.lf[cur];
       A.lg1 = a.lg[cur];
       A.ls1 = a.ls[cur];
