@@ -67,11 +67,19 @@ typedef struct {
   int flow;         /* 0: flow frozen (g only), 1: full double MRT       */
   int seed_profile; /* 0 linear seed profile, 1 Neumann profile          */
   double seed_lambda; /* Neumann constant, used when seed_profile == 1  */
-  int periodic;     /* test mode: periodic box, no walls, no front       */
+  int periodic;     /* test modes: 1 periodic box, all liquid, no walls and
+                       no front; 2 channel: the two lateral axes periodic,
+                       the walls and the (frozen) front along the melt axis,
+                       and a uniform force body_fx along x in place of the
+                       buoyancy                                            */
   double ks_kl;     /* solid / liquid conductivity (and diffusivity: equal
                        rho c) ratio of Eq. (6); 0 or 1: equal properties   */
   int front_scheme; /* 0: Eq. (6) from temperature gradients; 1: the heat the
                        lattice carries across the interface (reading R19)  */
+  int f_wall;       /* no-slip of f at the front: 0 halfway bounce-back
+                       (reading R7); 1 bounce-back interpolated to where the
+                       front cuts each link (reading R20)                  */
+  double body_fx;   /* channel test mode only: force per unit volume along x */
 } orc_params;
 
 typedef struct {
@@ -245,7 +253,7 @@ static inline int column_of(const orc_sim *S, int x, int y, int z) {
 /* reading R1: a cell is liquid iff its centre lies strictly below the front */
 static inline int is_liquid(const orc_sim *S, const double *s, int x, int y,
                             int z) {
-  if (S->p.periodic) return 1;
+  if (S->p.periodic == 1) return 1;
   int a = melt_coord(S, x, y, z);
   return (a + 0.5) < s[column_of(S, x, y, z)];
 }
@@ -255,6 +263,17 @@ static inline int in_box(int n, int x, int y, int z) {
 }
 
 static inline int wrap(int v, int n) { return ((v % n) + n) % n; }
+
+/* channel test mode: a neighbour across a lateral face is the cell on the
+ * opposite side of the box */
+static inline void wrap_lateral(const orc_sim *S, int *x, int *y, int *z) {
+  if (S->p.periodic != 2) return;
+  *x = wrap(*x, S->n);
+  if (S->p.heating == 0)
+    *z = wrap(*z, S->n);
+  else
+    *y = wrap(*y, S->n);
+}
 
 /* ------------------------------------------------------------------------ */
 /* set-up                                                                   */
@@ -273,7 +292,7 @@ static void derive_parameters(orc_sim *S) {
     S->nu = 0.0;
     S->alpha = p->alpha_in;
   }
-  S->gbeta = p->flow ? S->u0 * S->u0 / (n * (p->t_h - p->t_m)) : 0.0;
+  S->gbeta = (p->flow && p->periodic != 2) ? S->u0 * S->u0 / (n * (p->t_h - p->t_m)) : 0.0;
   S->t0 = 0.5 * (p->t_h + p->t_c);
   S->latent = p->ste > 0.0 ? (p->t_h - p->t_m) / p->ste : 0.0;
   S->s_nu = p->flow ? 1.0 / (3.0 * S->nu + 0.5) : 1.0;
@@ -343,7 +362,7 @@ static void initial_state(orc_sim *S) {
   int n = S->n;
   const orc_params *p = &S->p;
   for (int c = 0; c < n * n; ++c) {
-    S->s[c] = p->periodic ? (double)n : p->s0;
+    S->s[c] = p->periodic == 1 ? (double)n : p->s0;
     S->th[c] = p->t_h;
   }
   for (int z = 0; z < n; ++z)
@@ -351,7 +370,7 @@ static void initial_state(orc_sim *S) {
       for (int x = 0; x < n; ++x) {
         long long i = cell_index(n, x, y, z);
         double T;
-        if (p->periodic) {
+        if (p->periodic == 1) {
           T = S->t0;
         } else if (is_liquid(S, S->s, x, y, z)) {
           double a = melt_coord(S, x, y, z) + 0.5;
@@ -428,8 +447,27 @@ static double link_fraction(const orc_sim *S, const double *s, int x, int y,
   double a = melt_coord(S, x, y, z) + 0.5;
   int along_melt = (S->p.heating == 0) ? (e[1] != 0) : (e[2] != 0);
   if (along_melt) return fabs(s[c] - a);
-  int cn = column_of(S, x + e[0], y + e[1], z + e[2]);
+  int nx = x + e[0], ny = y + e[1], nz = z + e[2];
+  wrap_lateral(S, &nx, &ny, &nz);
+  int cn = column_of(S, nx, ny, nz);
   return (a - s[c]) / (s[cn] - s[c]);
+}
+
+/* reading R20: fraction of the link from this cell's centre to the centre of
+ * the neighbour at offset e (a D3Q19 link, diagonal ones included) at which
+ * the link meets the front.  Along the link the height on the melt axis is
+ * linear, from a + 1/2 to a + 1/2 + e_a, and so is the front, from this
+ * column's s to the neighbour column's; the fraction is where the two meet.
+ * For the links of the energy lattice it is the link fraction of reading R8. */
+static double link_fraction_any(const orc_sim *S, const double *s, int x, int y,
+                                int z, const int *e) {
+  int c = column_of(S, x, y, z);
+  double a = melt_coord(S, x, y, z) + 0.5;
+  int ea = (S->p.heating == 0) ? e[1] : e[2];
+  int nx = x + e[0], ny = y + e[1], nz = z + e[2];
+  wrap_lateral(S, &nx, &ny, &nz);
+  int cn = column_of(S, nx, ny, nz);
+  return (a - s[c]) / (s[cn] - s[c] - ea);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -445,7 +483,8 @@ static void stream_cell(const orc_sim *S, const double *f, const double *g,
   for (int q = 0; q < Q7; ++q) {
     int sx = x - E7[q][0], sy = y - E7[q][1], sz = z - E7[q][2];
     int po = S->opp7[q];
-    if (p->periodic) {
+    wrap_lateral(S, &sx, &sy, &sz);
+    if (p->periodic == 1) {
       gl[q] = g[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))];
     } else if (!in_box(n, sx, sy, sz)) {
       double tw = 0.0;
@@ -463,6 +502,7 @@ static void stream_cell(const orc_sim *S, const double *f, const double *g,
       double d = link_fraction(S, s, x, y, z, ep);
       double w = S->w7[q];
       int bx = x + E7[q][0], by = y + E7[q][1], bz = z + E7[q][2];
+      wrap_lateral(S, &bx, &by, &bz);
       if (d < 0.5) {
         if (in_box(n, bx, by, bz) && is_liquid(S, s, bx, by, bz) == liquid)
           gl[q] = -(2.0 * d * g[po * nc + i] +
@@ -477,15 +517,36 @@ static void stream_cell(const orc_sim *S, const double *f, const double *g,
     }
   }
   if (p->flow && liquid) {
-    /* halfway bounce-back from walls and solid cells */
     for (int q = 0; q < Q19; ++q) {
       int sx = x - E19[q][0], sy = y - E19[q][1], sz = z - E19[q][2];
-      if (p->periodic)
+      int po = S->opp19[q];
+      wrap_lateral(S, &sx, &sy, &sz);
+      if (p->periodic == 1) {
         fl[q] = f[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))];
-      else if (in_box(n, sx, sy, sz) && is_liquid(S, s, sx, sy, sz))
+      } else if (in_box(n, sx, sy, sz) && is_liquid(S, s, sx, sy, sz)) {
         fl[q] = f[q * nc + cell_index(n, sx, sy, sz)];
-      else
-        fl[q] = f[S->opp19[q] * nc + i];
+      } else if (p->f_wall == 1 && in_box(n, sx, sy, sz)) {
+        /* reading R20: the source is solid; the wall is where the front cuts
+         * the link, at fraction d from this cell's centre.  Linear
+         * interpolation of the bounced population (the cell behind, x + e_q,
+         * for d < 1/2; this cell's own direction q for d >= 1/2), the same
+         * weights as reading R8 without its sign change and wall value. */
+        double d = link_fraction_any(S, s, x, y, z, E19[po]);
+        int bx = x + E19[q][0], by = y + E19[q][1], bz = z + E19[q][2];
+        wrap_lateral(S, &bx, &by, &bz);
+        if (d < 0.5) {
+          if (in_box(n, bx, by, bz) && is_liquid(S, s, bx, by, bz))
+            fl[q] = 2.0 * d * f[po * nc + i] +
+                    (1.0 - 2.0 * d) * f[po * nc + cell_index(n, bx, by, bz)];
+          else
+            fl[q] = f[po * nc + i];
+        } else {
+          fl[q] = f[po * nc + i] / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * f[q * nc + i];
+        }
+      } else {
+        /* halfway bounce-back from walls and solid cells (reading R7) */
+        fl[q] = f[po * nc + i];
+      }
     }
   }
 }
@@ -510,7 +571,7 @@ static void collide_cell(const orc_sim *S, int liquid, const double *fl,
       jz += E19[q][2] * fl[q];
     }
     const double rho0 = 1.0;
-    double Fx = 0.0, Fy = 0.0, Fz = S->gbeta * (T - S->t0);
+    double Fx = p->periodic == 2 ? p->body_fx : 0.0, Fy = 0.0, Fz = S->gbeta * (T - S->t0);
     ux = (jx + 0.5 * Fx) / rho0;
     uy = (jy + 0.5 * Fy) / rho0;
     uz = (jz + 0.5 * Fz) / rho0;
@@ -737,6 +798,12 @@ static double front_velocity_column(const orc_sim *S, const double *g,
     dv->scol[4] = com; dv->dV_ds[4] = -KG * dso;
   }
   return V;
+}
+
+/* reading R20 for the pin tests: fraction at which the front cuts the link
+ * from cell (x, y, z) to the source of its incoming direction q (D3Q19) */
+double orc_link_fraction19(const orc_sim *S, int x, int y, int z, int q) {
+  return link_fraction_any(S, S->s, x, y, z, E19[S->opp19[q]]);
 }
 
 void orc_front_velocity(const orc_sim *S, double *V) {
@@ -1075,7 +1142,9 @@ static void record_free(void) {
  * sizes only: (nsteps + 1) * 26 * n^3 doubles).  Returns 0 on success. */
 int orc_record(orc_sim *S, long long nsteps) {
   record_free();
-  if (S->p.front_scheme != 0) return -2; /* the reverse sweep follows Eq. (6) */
+  /* the reverse sweep follows Eq. (6), halfway bounce-back of f at the front
+   * and the cavity's walls */
+  if (S->p.front_scheme != 0 || S->p.f_wall != 0 || S->p.periodic == 2) return -2;
   const long long nc = S->ncell, nn = (long long)S->n * S->n;
   g_record.f = (double *)malloc(sizeof(double) * Q19 * nc * (nsteps + 1));
   g_record.g = (double *)malloc(sizeof(double) * Q7 * nc * (nsteps + 1));

@@ -56,6 +56,8 @@ class _Params(ctypes.Structure):
         ("periodic", ctypes.c_int),
         ("ks_kl", ctypes.c_double),
         ("front_scheme", ctypes.c_int),
+        ("f_wall", ctypes.c_int),
+        ("body_fx", ctypes.c_double),
     ]
 
 
@@ -96,6 +98,8 @@ def _load():
         lib.orc_record.argtypes = [vp, ll]
         lib.orc_adjoint.argtypes = [vp, dp, dp, dp, dp]
         lib.orc_wall_nusselt.argtypes = [vp, dp]
+        lib.orc_link_fraction19.argtypes = [vp, i, i, i, i]
+        lib.orc_link_fraction19.restype = d
         lib.orc_energy.argtypes = [vp]
         lib.orc_energy.restype = d
         lib.orc_wall_heat.argtypes = [vp]
@@ -145,13 +149,17 @@ class OracleSim:
     melting temperature ``t_m``, and the dimensionless groups ``ra``, ``pr``,
     ``ste``.  ``heating`` 0 puts the hot wall at y=0 and the cold wall at y=n;
     1 puts it at z=0 with every other wall adiabatic.  ``flow`` 0 freezes the
-    flow (energy distribution only).  ``periodic`` is a test mode: periodic
-    box, all liquid, no walls and no front.
+    flow (energy distribution only).  ``f_wall`` 0 bounces f back halfway at
+    the front, 1 interpolates the bounce-back to where the front cuts each
+    link.  ``periodic`` selects a test mode: 1 (or True) a periodic box, all
+    liquid, no walls and no front; 2 a channel, periodic across the two
+    lateral axes, with the walls and a frozen front along the melt axis and
+    the uniform force ``body_fx`` along x in place of the buoyancy.
     """
 
     def __init__(self, n, ra=1e4, pr=1.0, ste=0.1, t_h=1.0, t_c=0.0, t_m=0.0,
                  ma=0.1, alpha=0.1, s0=1.0, heating=0, flow=1, seed_profile=0,
-                 periodic=False, ks_kl=1.0, front_scheme=0):
+                 periodic=False, ks_kl=1.0, front_scheme=0, f_wall=0, body_fx=0.0):
         lib = _load()
         lam = 0.0
         if seed_profile == 1 and ste > 0:
@@ -161,7 +169,8 @@ class OracleSim:
         self.params = _Params(int(n), float(ra), float(pr), float(ste), float(t_h),
                               float(t_c), float(t_m), float(ma), float(alpha), float(s0),
                               int(heating), int(flow), int(seed_profile), float(lam),
-                              int(bool(periodic)), float(ks_kl), int(front_scheme))
+                              int(periodic), float(ks_kl), int(front_scheme), int(f_wall),
+                              float(body_fx))
         h = lib.orc_create(ctypes.byref(self.params))
         if not h:
             raise MemoryError("oracle allocation failed")
@@ -222,6 +231,11 @@ class OracleSim:
         self._lib.orc_fields(self._h, *[_dp(a) for a in out])
         T, ux, uy, uz, rho = out
         return {"T": T, "u": np.stack([ux, uy, uz]), "rho": rho, "s": self.s.copy()}
+
+    def link_fraction19(self, x: int, y: int, z: int, q: int) -> float:
+        """Fraction at which the front cuts the link from cell (x, y, z) to the
+        source of its incoming D3Q19 direction q (reading R20)."""
+        return float(self._lib.orc_link_fraction19(self._h, int(x), int(y), int(z), int(q)))
 
     def front_velocity(self) -> np.ndarray:
         V = np.zeros((self.n, self.n))
@@ -288,7 +302,8 @@ class OracleSim:
         """Step forward keeping every state (for the reverse sweep)."""
         rc = self._lib.orc_record(self._h, int(nsteps))
         if rc == -2:
-            raise ValueError("the reference adjoint follows the Eq. (6) front update only")
+            raise ValueError("the reference adjoint follows the Eq. (6) front update, halfway "
+                             "bounce-back of f and the cavity walls only")
         if rc != 0:
             raise MemoryError("oracle record allocation failed")
 
