@@ -94,6 +94,12 @@ typedef struct {
                            the interface links in each step (conserves
                            sum(T) + L sum(s) up to the wall heat; no
                            adjoint or replay)                              */
+  int32_t f_wall;       /* no-slip of f at the front: 0 halfway bounce-back;
+                           1 bounce-back interpolated linearly to the point
+                           where the front cuts each link (the link
+                           fraction of the front condition of g, extended
+                           to the diagonal links; no adjoint or replay).
+                           The walls of the box keep halfway bounce-back  */
 } lbm_params;
 
 /* Lattice units derived from the parameters (Eq. (7) time scale: the

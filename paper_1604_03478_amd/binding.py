@@ -50,6 +50,7 @@ class Params(ctypes.Structure):
         ("seed_profile", ctypes.c_int32),
         ("ks_kl", ctypes.c_double),
         ("front_scheme", ctypes.c_int32),
+        ("f_wall", ctypes.c_int32),
     ]
 
 
@@ -133,13 +134,14 @@ class Config:
     seed_profile: int = 0
     ks_kl: float = 1.0
     front_scheme: int = 0
+    f_wall: int = 0
 
     def to_c(self) -> Params:
         return Params(int(self.n), float(self.ra), float(self.pr), float(self.ste),
                       float(self.t_h), float(self.t_c), float(self.t_m), float(self.ma),
                       float(self.alpha), float(self.s0), HEATING[self.heating], int(self.flow),
                       PRECISIONS[self.precision], int(self.seed_profile), float(self.ks_kl),
-                      int(self.front_scheme))
+                      int(self.front_scheme), int(self.f_wall))
 
 
 class Sim:

@@ -213,6 +213,8 @@ int validate(const lbm_params* p) {
     return fail(LBM_EINVAL, "ks_kl must be >= 0 (0 or 1: equal phase properties)");
   if (p->front_scheme != 0 && p->front_scheme != 1)
     return fail(LBM_EINVAL, "front_scheme must be 0 (Eq. (6) gradients) or 1 (interface heat)");
+  if (p->f_wall != 0 && p->f_wall != 1)
+    return fail(LBM_EINVAL, "f_wall must be 0 (halfway bounce-back) or 1 (interpolated)");
   if (p->flow) {
     if (!(p->ra > 0.0) || !(p->pr > 0.0) || !std::isfinite(p->ra) || !std::isfinite(p->pr))
       return fail(LBM_EINVAL, "ra and pr must be positive");
@@ -345,6 +347,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   k.q_e = L.q_e;
   // solid: conductivity kappa k_l with the same rho c, diffusivity kappa alpha
   k.kappa = params->ks_kl > 0.0 ? params->ks_kl : 1.0;
+  k.f_wall = params->f_wall;
   {
     const double alpha_s = k.kappa * L.alpha;
     k.q_js = 1.0 / (4.0 * alpha_s + 0.5);
@@ -716,6 +719,8 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
   if (nsteps < 1 || every_k < 1) return fail(LBM_EINVAL, "need nsteps >= 1 and every_k >= 1");
   if (c->p.front_scheme != 0)
     return fail(LBM_EINVAL, "the adjoint follows the Eq. (6) front update (front_scheme 0)");
+  if (c->p.f_wall != 0)
+    return fail(LBM_EINVAL, "the adjoint follows halfway bounce-back of f (f_wall 0)");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   AdjData& a = c->adj;
   const size_t nn = (size_t)c->p.n * c->p.n;
@@ -911,6 +916,8 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
   if (!schedule || nsteps < 1) return fail(LBM_EINVAL, "need a schedule and nsteps >= 1");
   if (c->p.front_scheme != 0)
     return fail(LBM_EINVAL, "replay follows the Eq. (6) front update (front_scheme 0)");
+  if (c->p.f_wall != 0)
+    return fail(LBM_EINVAL, "replay follows halfway bounce-back of f (f_wall 0)");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   const int n = c->p.n;
   const size_t nn = (size_t)n * n;

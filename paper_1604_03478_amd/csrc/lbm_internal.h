@@ -31,6 +31,7 @@ struct KParams {
   double q_js;     // the same two rates in solid cells (solid diffusivity kappa * alpha)
   double q_es;
   double kappa;    // solid / liquid conductivity ratio of Eq. (6)
+  int f_wall;      // 1: no-slip of f at the front interpolated to the link fraction
   double alpha;    // thermal diffusivity (front update)
   double ste;      // Stefan number (front update)
   double dT;       // nominal t_h - t_m (front update)

@@ -353,18 +353,46 @@ __device__ __forceinline__ void update_cell(
     if (FLOW && liquid) {
 #pragma unroll
       for (int q = 0; q < 19; ++q) {
-        const int ex = ex19(q), ey = ey19(q), ez = ez19(q);
+        const int ex = ex19(q), ey = ey19(q), ez = ez19(q), p = opp19(q);
         const int sx = x - ex, sy = y - ey, sz = z - ez;
-        bool ok = (unsigned)sx < (unsigned)n && (unsigned)sy < (unsigned)n &&
-                  (unsigned)sz < (unsigned)n;
-        if (ok) {
+        const bool inb = (unsigned)sx < (unsigned)n && (unsigned)sy < (unsigned)n &&
+                         (unsigned)sz < (unsigned)n;
+        bool ok = inb;
+        int scol = 0;
+        if (inb) {
           const int sa = MZ ? sz : sy, so = MZ ? sy : sz;
-          ok = sa < cnt[so * n + sx];
+          scol = so * n + sx;
+          ok = sa < cnt[scol];
         }
         // halfway bounce-back from walls and solid cells (address select: the
         // source row of an out-of-box link is never dereferenced)
-        const Ts* src = ok ? f_src(q) + ((int)(q * pitch) + sx) : f_self + (opp19(q) * pitch + x);
-        f[q] = load_stream<C>(src, 0);
+        const Ts* src = ok ? f_src(q) + ((int)(q * pitch) + sx) : f_self + (p * pitch + x);
+        C v = load_stream<C>(src, 0);
+        if (P.f_wall && inb && !ok) {
+          // Solid source: bounce back from where the front cuts the link.  The
+          // height on the melt axis and the front (linear between the two
+          // columns) meet at fraction d of the link; the weights sum to one,
+          // so they apply to the shifted populations as stored.
+          const int ea = MZ ? ez : ey;
+          const double d = ((a + 0.5) - s_self) / ((s[scol] - s_self) + ea);
+          const C dl = (C)d;
+          if (d < 0.5) {
+            const int bx = x + ex, by = y + ey, bz = z + ez;
+            bool behind = (unsigned)bx < (unsigned)n && (unsigned)by < (unsigned)n &&
+                          (unsigned)bz < (unsigned)n;
+            if (behind) {
+              const int ba = MZ ? bz : by, bo = MZ ? by : bz;
+              behind = ba < cnt[bo * n + bx];
+            }
+            if (behind)  // else halfway bounce-back, as the front condition of g does
+              v = C(2) * dl * v +
+                  (C(1) - C(2) * dl) * load_stream<C>(row_ptr<19>(fs, P, by, bz), p * pitch + bx);
+          } else {
+            const C inv2d = C(1) / (C(2) * dl);
+            v = v * inv2d + (C(2) * dl - C(1)) * inv2d * load_stream<C>(f_self, q * pitch + x);
+          }
+        }
+        f[q] = v;
       }
     }
   }

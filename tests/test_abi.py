@@ -43,7 +43,7 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [
     dict(n=3), dict(n=2000), dict(ma=0.3), dict(ma=0.0), dict(t_c=0.5), dict(t_h=0.0),
     dict(ste=-1.0), dict(s0=17.0), dict(s0=-0.1), dict(ra=0.0), dict(pr=-1.0),
-    dict(flow=0, alpha=0.0), dict(seed_profile=1, ste=0.0), dict(seed_profile=2, ste=0.0), dict(seed_profile=3), dict(ks_kl=-1.0), dict(front_scheme=2), dict(n=1024, precision="f64"),
+    dict(flow=0, alpha=0.0), dict(seed_profile=1, ste=0.0), dict(seed_profile=2, ste=0.0), dict(seed_profile=3), dict(ks_kl=-1.0), dict(front_scheme=2), dict(f_wall=2), dict(n=1024, precision="f64"),
     dict(ra=1e12),  # viscous relaxation time too close to 1/2
 ])
 def test_invalid_parameters_are_rejected(bad):

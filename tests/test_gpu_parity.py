@@ -22,7 +22,7 @@ def make_pair(steps=0, **kw):
     orc = OracleSim(cfg.n, ra=cfg.ra, pr=cfg.pr, ste=cfg.ste, t_h=cfg.t_h, t_c=cfg.t_c,
                     t_m=cfg.t_m, ma=cfg.ma, alpha=cfg.alpha, s0=cfg.s0,
                     heating=HEAT[cfg.heating], flow=cfg.flow, seed_profile=cfg.seed_profile,
-                    ks_kl=cfg.ks_kl, front_scheme=cfg.front_scheme)
+                    ks_kl=cfg.ks_kl, front_scheme=cfg.front_scheme, f_wall=cfg.f_wall)
     gpu = Sim(cfg)
     if steps:
         orc.step(steps)
@@ -218,19 +218,20 @@ def test_convection_melting_64_full_run(prec):
         assert worst_fl <= 1e-6 and dT <= 1e-5 and dline <= 1e-5, res
 
 
-def _one_step_random(n, prec, seed, heating="y0", front=(0.0, None), flow=1):
+def _one_step_random(n, prec, seed, heating="y0", front=(0.0, None), flow=1, f_wall=0):
     """Hand the same seeded random state (rough front) to both sides, take
     one step, compare post-collision populations cell by cell."""
     from paper_1604_03478_amd import Config, Sim
     from inputs import random_state
     f, g, s = random_state(n, seed, flow=bool(flow), front=front)
-    orc = OracleSim(n, ra=1e5, pr=1.0, ste=2.0, s0=1.0, heating=HEAT[heating], flow=flow)
+    orc = OracleSim(n, ra=1e5, pr=1.0, ste=2.0, s0=1.0, heating=HEAT[heating], flow=flow,
+                    f_wall=f_wall)
     if flow:
         orc.f[:] = f
     orc.g[:] = g
     orc.s[:] = s
     gpu = Sim(Config(n=n, ra=1e5, pr=1.0, ste=2.0, s0=1.0, heating=heating, flow=flow,
-                     precision=prec))
+                     precision=prec, f_wall=f_wall))
     gpu.set_populations(f, g, s)
     del f, g
     orc.step(1)
