@@ -187,19 +187,22 @@ def adjoint_timing(stream, n: int, steps: int, every: int):
             "grad_norm": float(torch.linalg.norm(grad).item())}
 
 
-def paper_cases(n: int, stream):
+def paper_cases(n: int, stream, f_wall: int = 0):
     """The paper's convection cases (section 3.2): Pr = 0.02, Ste = 0.1,
     side-heated cube, case 1 Ra = 25000 to Fo = 1.00, case 2 Ra = 10000 to
     Fo = 1.57 (the same lattice time), FP32 storage: throughput of the whole
     run and the quantities the paper discusses (liquid fraction against Fo,
-    heated-wall Nusselt numbers, temperature stratification)."""
+    heated-wall Nusselt numbers, temperature stratification).  f_wall 1: the
+    bounce-back of f interpolated to the front's position on each link."""
     import numpy as np
     import torch
     from paper_1604_03478_amd import Config, Sim
-    out = {"mode": "paper", "n": n, "workload": f"convection melting {n}^3, side-heated, "
+    out = {"mode": "paper", "n": n, "f_wall": f_wall,
+           "workload": f"convection melting {n}^3, side-heated, "
            "Pr=0.02, Ste=0.1, fp32 storage, front seeded at s0=1"}
     for case, ra, fo_end in ((1, 25000.0, 1.00), (2, 10000.0, 1.57)):
-        sim = Sim(Config(n=n, ra=ra, pr=0.02, ste=0.1, s0=1.0, precision="f32"), stream=stream)
+        sim = Sim(Config(n=n, ra=ra, pr=0.02, ste=0.1, s0=1.0, precision="f32", f_wall=f_wall),
+                  stream=stream)
         alpha = sim.lattice()["alpha"]
         fos = [f for f in (0.25, 0.5, 0.75, 1.0, 1.25, 1.57) if f <= fo_end + 1e-9]
         done, fl, t_gpu = 0, {}, 0.0
@@ -338,6 +341,8 @@ def main():
     ap.add_argument("--precision-steps", type=int, default=100000)
     ap.add_argument("--precision", choices=["f32", "f16s", "bf16s", "f64"], default="f32",
                     help="storage precision of --mode profile")
+    ap.add_argument("--f-wall", type=int, choices=[0, 1], default=0,
+                    help="--mode paper: 1 interpolates the no-slip of f to the front")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -388,7 +393,7 @@ def main():
         return
 
     if args.mode == "paper":
-        paper_cases(args.n, stream)
+        paper_cases(args.n, stream, args.f_wall)
         return
 
     if args.mode == "adjoint":

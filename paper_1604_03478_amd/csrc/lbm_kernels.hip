@@ -221,8 +221,10 @@ __device__ __forceinline__ bool collide(C (&f)[19], G (&g)[7], bool liquid, cons
 // --------------------------------------------------------------- step kernel
 // One cell of the fused step: pull-stream f and g, collide, store.  Addresses
 // are a row pointer (64-bit, the same for a whole lattice row) plus a small
-// per-lane offset q * pitch + x.
-template <typename Ts, bool FLOW, bool MZ>
+// per-lane offset q * pitch + x.  FWALL: no-slip of f at the front
+// interpolated to the link fraction (a separate instantiation, so that the
+// default halfway rule compiles to the same code as without the option).
+template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 __device__ __forceinline__ void update_cell(
     int x, int y, int z, const Ts* __restrict__ fs, Ts* __restrict__ fd,
     const Ts* __restrict__ gs, Ts* __restrict__ gd, const int* __restrict__ cnt,
@@ -368,7 +370,7 @@ __device__ __forceinline__ void update_cell(
         // source row of an out-of-box link is never dereferenced)
         const Ts* src = ok ? f_src(q) + ((int)(q * pitch) + sx) : f_self + (p * pitch + x);
         C v = load_stream<C>(src, 0);
-        if (P.f_wall && inb && !ok) {
+        if (FWALL && inb && !ok) {
           // Solid source: bounce back from where the front cuts the link.  The
           // height on the melt axis and the front (linear between the two
           // columns) meet at fraction d of the link; the weights sum to one,
@@ -410,15 +412,15 @@ __device__ __forceinline__ void update_cell(
 
 // One lattice row per workgroup (blockIdx.y = y, blockIdx.z = z): the row
 // pointers are uniform over the workgroup.
-template <typename Ts, bool FLOW, bool MZ>
+template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 __global__ __launch_bounds__(512) void k_stream_collide(
     const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
     Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
     const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
     int* __restrict__ flag, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  update_cell<Ts, FLOW, MZ>(x, blockIdx.y, blockIdx.z, fs, fd, gs, gd, cnt, cmin, cmax, s, th,
-                            flag, P);
+  update_cell<Ts, FLOW, MZ, FWALL>(x, blockIdx.y, blockIdx.z, fs, fd, gs, gd, cnt, cmin, cmax, s,
+                                   th, flag, P);
 }
 
 // --------------------------------------------------------------- front update
@@ -709,21 +711,17 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
   const int bx = P.n >= 512 ? 512 : ((P.n + 63) / 64) * 64;
   dim3 block(bx, 1, 1);
   dim3 grid((P.n + bx - 1) / bx, P.n, P.n);
-  if (P.flow) {
-    if (P.melt_z)
-      hipLaunchKernelGGL((k_stream_collide<Ts, true, true>), grid, block, 0, st, F, Fd, G, Gd, cnt,
-                         cmin, cmax, s, th, flag, P);
-    else
-      hipLaunchKernelGGL((k_stream_collide<Ts, true, false>), grid, block, 0, st, F, Fd, G, Gd, cnt,
-                         cmin, cmax, s, th, flag, P);
+#define LAUNCH(FLOW, MZ, FWALL)                                                              \
+  hipLaunchKernelGGL((k_stream_collide<Ts, FLOW, MZ, FWALL>), grid, block, 0, st, F, Fd, G, Gd, \
+                     cnt, cmin, cmax, s, th, flag, P)
+  if (P.flow && P.f_wall) {
+    if (P.melt_z) LAUNCH(true, true, true); else LAUNCH(true, false, true);
+  } else if (P.flow) {
+    if (P.melt_z) LAUNCH(true, true, false); else LAUNCH(true, false, false);
   } else {
-    if (P.melt_z)
-      hipLaunchKernelGGL((k_stream_collide<Ts, false, true>), grid, block, 0, st, F, Fd, G, Gd, cnt,
-                         cmin, cmax, s, th, flag, P);
-    else
-      hipLaunchKernelGGL((k_stream_collide<Ts, false, false>), grid, block, 0, st, F, Fd, G, Gd,
-                         cnt, cmin, cmax, s, th, flag, P);
+    if (P.melt_z) LAUNCH(false, true, false); else LAUNCH(false, false, false);
   }
+#undef LAUNCH
   return hipGetLastError();
 }
 
