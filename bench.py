@@ -151,6 +151,45 @@ def bottom_heated_512(stream, steps: int, warmup: int):
     return out
 
 
+def large_run(stream, n: int, steps: int, sample: int = 1000):
+    """The large configuration run to its end: n^3 (512), hot wall z = 0,
+    Ra = 1e6, Pr = 1, Ste = 0.1, FP16 shifted storage, front seeded at s0 = 1.
+    Whole-run throughput, the liquid fraction against the Fourier number, and
+    HBM GB/s from the algorithmic bytes of each step: a liquid cell moves
+    104 B, a solid one the 28 B of g; the liquid share is f_l, sampled every
+    `sample` steps outside the timed part."""
+    import torch
+    from paper_1604_03478_amd import Config, Sim
+    cfg = Config(n=n, ra=1e6, pr=1.0, ste=0.1, s0=1.0, heating="z0", precision="f16s")
+    sim = Sim(cfg, stream=stream)
+    alpha = sim.lattice()["alpha"]
+    done, t_gpu, nbytes, hist = 0, 0.0, 0.0, {}
+    fl = sim.liquid_fraction()
+    while done < steps:
+        k = min(sample, steps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(k)
+        torch.cuda.synchronize()
+        t_gpu += time.perf_counter() - t0
+        fl_new = sim.liquid_fraction()
+        nbytes += k * n ** 3 * (28.0 + 76.0 * 0.5 * (fl + fl_new))
+        fl = fl_new
+        done += k
+        if done % 10000 == 0 or done == steps:
+            hist[str(done)] = round(fl, 6)
+            print(f"large: step {done} Fo {alpha * done / n ** 2:.4f} f_l {fl:.6f} "
+                  f"{n ** 3 * done / t_gpu / 1e6:.0f} MLUPS", file=sys.stderr, flush=True)
+    nu = sim.wall_nusselt()
+    sim.close()
+    return {"mode": "large", "workload": f"convection melting {n}^3, bottom-heated (hot z=0), "
+            "Ra=1e6, Pr=1, Ste=0.1, fp16 shifted storage, fp32 collide, fp64 front, s0=1",
+            "steps": done, "fo_end": round(alpha * done / n ** 2, 5), "seconds": round(t_gpu, 2),
+            "MLUPS": round(n ** 3 * done / t_gpu / 1e6, 1),
+            "algorithmic_GBps": round(nbytes / t_gpu / 1e9, 1),
+            "liquid_fraction": hist, "nu_mean_end": round(float(nu.mean()), 4)}
+
+
 def adjoint_timing(stream, n: int, steps: int, every: int):
     """Gradient of f_l after `steps` steps with respect to T_h(x, z), FP32
     storage, checkpoint every `every` steps: time of the checkpointed forward
@@ -337,7 +376,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--mode", choices=["bench", "profile", "copy", "precision", "adjoint",
-                                       "paper"], default="bench")
+                                       "paper", "large"], default="bench")
     ap.add_argument("--precision-steps", type=int, default=100000)
     ap.add_argument("--precision", choices=["f32", "f16s", "bf16s", "f64"], default="f32",
                     help="storage precision of --mode profile")
@@ -394,6 +433,10 @@ def main():
 
     if args.mode == "paper":
         paper_cases(args.n, stream, args.f_wall)
+        return
+
+    if args.mode == "large":  # --n 512 --steps 200000 for the full large configuration
+        print(json.dumps(large_run(stream, args.n, args.steps)), flush=True)
         return
 
     if args.mode == "adjoint":
