@@ -997,8 +997,8 @@ static void collide_cell_adjoint(const orc_sim *S, int liquid, const double *fl,
 /* reverse of stream_cell: scatter (lfl, lgl) of cell (x,y,z) into the
  * adjoints of the previous state (lf, lg), of the fronts (ls) and of the
  * hot-wall temperatures (lth) */
-static void stream_cell_adjoint(const orc_sim *S, const double *g, const double *s,
-                                int x, int y, int z, int liquid,
+static void stream_cell_adjoint(const orc_sim *S, const double *f, const double *g,
+                                const double *s, int x, int y, int z, int liquid,
                                 const double *lfl, const double *lgl, double *lf,
                                 double *lg, double *ls, double *lth) {
   const int n = S->n;
@@ -1061,12 +1061,45 @@ static void stream_cell_adjoint(const orc_sim *S, const double *g, const double 
   if (p->flow && liquid) {
     for (int q = 0; q < Q19; ++q) {
       int sx = x - E19[q][0], sy = y - E19[q][1], sz = z - E19[q][2];
-      if (p->periodic)
-        lf[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))] += lfl[q];
-      else if (in_box(n, sx, sy, sz) && is_liquid(S, s, sx, sy, sz))
-        lf[q * nc + cell_index(n, sx, sy, sz)] += lfl[q];
-      else
-        lf[S->opp19[q] * nc + i] += lfl[q];
+      int po = S->opp19[q];
+      double l = lfl[q];
+      if (p->periodic) {
+        lf[q * nc + cell_index(n, wrap(sx, n), wrap(sy, n), wrap(sz, n))] += l;
+      } else if (in_box(n, sx, sy, sz) && is_liquid(S, s, sx, sy, sz)) {
+        lf[q * nc + cell_index(n, sx, sy, sz)] += l;
+      } else if (p->f_wall == 1 && in_box(n, sx, sy, sz)) {
+        /* reading R20 reversed: the interpolation weights, and through the
+         * link fraction d = (a - s_c) / (s_cn - s_c - e_a) the two fronts */
+        const int *ep = E19[po];
+        double d = link_fraction_any(S, s, x, y, z, ep);
+        int bx = x + E19[q][0], by = y + E19[q][1], bz = z + E19[q][2];
+        double ld = 0.0; /* derivative of the pulled value in d, times l */
+        if (d < 0.5) {
+          if (in_box(n, bx, by, bz) && is_liquid(S, s, bx, by, bz)) {
+            long long b = cell_index(n, bx, by, bz);
+            lf[po * nc + i] += 2.0 * d * l;
+            lf[po * nc + b] += (1.0 - 2.0 * d) * l;
+            ld = (2.0 * f[po * nc + i] - 2.0 * f[po * nc + b]) * l;
+          } else {
+            lf[po * nc + i] += l;
+          }
+        } else {
+          lf[po * nc + i] += l / (2.0 * d);
+          lf[q * nc + i] += (2.0 * d - 1.0) / (2.0 * d) * l;
+          ld = (f[q * nc + i] - f[po * nc + i]) / (2.0 * d * d) * l;
+        }
+        if (ld != 0.0) {
+          int c = column_of(S, x, y, z);
+          double a = melt_coord(S, x, y, z) + 0.5;
+          int ea = (p->heating == 0) ? ep[1] : ep[2];
+          int cn = column_of(S, sx, sy, sz);
+          double D = s[cn] - s[c] - ea;
+          ls[c] += ld * (a - s[c] - D) / (D * D);
+          ls[cn] += ld * (-(a - s[c])) / (D * D);
+        }
+      } else {
+        lf[po * nc + i] += l;
+      }
     }
   }
 }
@@ -1118,7 +1151,7 @@ static void step_adjoint(const orc_sim *S, const double *f, const double *g,
         for (int q = 0; q < Q19; ++q) lfo[q] = p->flow ? lf1[q * nc + i] : 0.0;
         for (int q = 0; q < Q7; ++q) lgo[q] = lg1[q * nc + i];
         collide_cell_adjoint(S, liquid, fl, gl, lfo, lgo, lfl, lgl);
-        stream_cell_adjoint(S, g, s, x, y, z, liquid, lfl, lgl, lf, lg, ls, lth);
+        stream_cell_adjoint(S, f, g, s, x, y, z, liquid, lfl, lgl, lf, lg, ls, lth);
         if (p->flow && !liquid) /* solid cells copy f through */
           for (int q = 0; q < Q19; ++q) lf[q * nc + i] += lf1[q * nc + i];
       }
@@ -1142,9 +1175,8 @@ static void record_free(void) {
  * sizes only: (nsteps + 1) * 26 * n^3 doubles).  Returns 0 on success. */
 int orc_record(orc_sim *S, long long nsteps) {
   record_free();
-  /* the reverse sweep follows Eq. (6), halfway bounce-back of f at the front
-   * and the cavity's walls */
-  if (S->p.front_scheme != 0 || S->p.f_wall != 0 || S->p.periodic == 2) return -2;
+  /* the reverse sweep follows Eq. (6) and the cavity's walls */
+  if (S->p.front_scheme != 0 || S->p.periodic == 2) return -2;
   const long long nc = S->ncell, nn = (long long)S->n * S->n;
   g_record.f = (double *)malloc(sizeof(double) * Q19 * nc * (nsteps + 1));
   g_record.g = (double *)malloc(sizeof(double) * Q7 * nc * (nsteps + 1));
