@@ -98,7 +98,7 @@ typedef struct {
                            1 bounce-back interpolated linearly to the point
                            where the front cuts each link (the link
                            fraction of the front condition of g, extended
-                           to the diagonal links; no adjoint or replay).
+                           to the diagonal links).
                            The walls of the box keep halfway bounce-back  */
 } lbm_params;
 
@@ -211,7 +211,9 @@ int lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
  * n^2 values in the column layout of s and points to device memory if
  * on_device != 0.  lbm_adjoint needs a preceding lbm_forward_ckpt with no
  * step taken since (else LBM_ESTATE); it does not change the state.  Both
- * synchronize.  Errors: LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EDEVICE. */
+ * synchronize.  Errors: LBM_EINVAL (also for front_scheme 1: the reverse
+ * sweep follows the gradient form of Eq. (6)), LBM_ENOMEM, LBM_ESTATE,
+ * LBM_EDEVICE. */
 int lbm_forward_ckpt(lbm_ctx *ctx, int64_t nsteps, int32_t every_k, double *fl);
 int lbm_adjoint(lbm_ctx *ctx, double dJ_dfl, double *grad_th, int on_device);
 
@@ -223,7 +225,8 @@ int lbm_adjoint(lbm_ctx *ctx, double dJ_dfl, double *grad_th, int on_device);
  * nsteps steps along such a schedule (phases and node selection fixed, every
  * other quantity recomputed): the map whose derivative lbm_adjoint gives,
  * for finite-difference checks.  The schedule is host memory; both
- * synchronize. */
+ * synchronize.  lbm_step_replay returns LBM_EINVAL for front_scheme 1 and for
+ * a schedule whose node indices lie outside the lattice. */
 int lbm_get_schedule(lbm_ctx *ctx, int32_t *out, size_t count);
 int lbm_step_replay(lbm_ctx *ctx, const int32_t *schedule, int64_t nsteps);
 

@@ -194,6 +194,22 @@ __device__ __forceinline__ double link_delta(const double* s, int x, int y, int 
   return (a - s[c]) / (s[cn] - s[c]);
 }
 
+// Fraction of the link from cell (x,y,z) to the source of its incoming D3Q19
+// direction q at which the front cuts it, for the interpolated no-slip of f:
+// the height on the melt axis and the front (linear between the two columns)
+// meet there.  The forward step evaluates the same expression.  num and den
+// return its numerator and denominator, d = num / den.
+template <bool MZ>
+__device__ __forceinline__ double frac19(const double* s, int x, int y, int z, int q, int n,
+                                         double& num, double& den) {
+  const int a = melt_of<MZ>(y, z);
+  const double sc = s[col_of<MZ>(x, y, z, n)];
+  const int ea = MZ ? ez19(q) : ey19(q);
+  num = (a + 0.5) - sc;
+  den = (s[col_of<MZ>(x - ex19(q), y - ey19(q), z - ez19(q), n)] - sc) + ea;
+  return num / den;
+}
+
 // stored population q of linear cell i = (z n + y) n + x, in FP64 (the
 // row-interleaved layout of a distribution with Q directions)
 template <int Q, typename Ts>
@@ -370,8 +386,21 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
   if (FLOW && liquid) {
     for (int q = 1; q < 19; ++q) {
       const int sx = x - ex19(q), sy = y - ey19(q), sz = z - ez19(q);
-      const bool ok = G.in(sx, sy, sz) && liquid_at<MZ>(cnt, sx, sy, sz, n);
-      M.add_f(q, ok ? sv<19>(f, P, q, G.cell(sx, sy, sz)) : sv<19>(f, P, opp19(q), i));
+      const bool inb = G.in(sx, sy, sz);
+      const bool ok = inb && liquid_at<MZ>(cnt, sx, sy, sz, n);
+      double v = ok ? sv<19>(f, P, q, G.cell(sx, sy, sz)) : sv<19>(f, P, opp19(q), i);
+      if (P.f_wall && inb && !ok) {  // interpolated no-slip at the front
+        double num, den;
+        const double d = frac19<MZ>(s, x, y, z, q, n, num, den);
+        if (d < 0.5) {
+          const int bx = x + ex19(q), by = y + ey19(q), bz = z + ez19(q);
+          if (G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n))
+            v = 2.0 * d * v + (1.0 - 2.0 * d) * sv<19>(f, P, opp19(q), G.cell(bx, by, bz));
+        } else {
+          v = v / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * sv<19>(f, P, q, i);
+        }
+      }
+      M.add_f(q, v);
     }
   }
 }
@@ -766,11 +795,50 @@ __global__ __launch_bounds__(256) void k_adj_stream(
   // adjoint of f before the step: only liquid cells read their f (solid
   // cells hold dead data, whose adjoint is zero and is not stored)
   if (FLOW && L) {
+    auto LF = [&](int q, uint32_t j) { return (double)lfh[(size_t)q * nc + j]; };
     for (int p = 0; p < 19; ++p) {
-      const int yx = x + ex19(p), yy = y + ey19(p), yz = z + ez19(p);
-      const bool pulled = G.in(yx, yy, yz) && liquid_at<MZ>(cnt, yx, yy, yz, n);
-      lf0[(size_t)p * nc + i] =
-          pulled ? lfh[(size_t)p * nc + G.cell(yx, yy, yz)] : lfh[(size_t)opp19(p) * nc + i];
+      const int yx = x + ex19(p), yy = y + ey19(p), yz = z + ez19(p), q = opp19(p);
+      const bool yin = G.in(yx, yy, yz);
+      const bool pulled = yin && liquid_at<MZ>(cnt, yx, yy, yz, n);
+      if (!P.f_wall || p == 0) {
+        lf0[(size_t)p * nc + i] = (Lam)(pulled ? LF(p, G.cell(yx, yy, yz)) : LF(q, i));
+        continue;
+      }
+      // every reader of f*_p(x) under the interpolated no-slip
+      double acc = 0.0, num, den;
+      if (pulled) {  // (a) the regular pull of the neighbour x + e_p
+        acc += LF(p, G.cell(yx, yy, yz));
+      } else if (!yin) {  // (b) this cell's direction q: a box wall (halfway)
+        acc += LF(q, i);
+      } else {  // (b) ... or a solid source: the weight of f*_p(x)
+        const double d = frac19<MZ>(s0, x, y, z, q, n, num, den);
+        if (d < 0.5) {
+          const int bx = x - ex19(p), by = y - ey19(p), bz = z - ez19(p);
+          const bool behind = G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n);
+          acc += (behind ? 2.0 * d : 1.0) * LF(q, i);
+        } else {
+          acc += LF(q, i) / (2.0 * d);
+        }
+      }
+      // (c) this cell's direction p itself, when its source x - e_p is solid
+      //     and cut at d >= 1/2
+      {
+        const int sx = x - ex19(p), sy = y - ey19(p), sz = z - ez19(p);
+        if (G.in(sx, sy, sz) && !liquid_at<MZ>(cnt, sx, sy, sz, n)) {
+          const double d = frac19<MZ>(s0, x, y, z, p, n, num, den);
+          if (d >= 0.5) acc += (2.0 * d - 1.0) / (2.0 * d) * LF(p, i);
+        }
+      }
+      // (d) the neighbour x + e_p, direction q, whose source x + 2 e_p is solid
+      //     and cut at d < 1/2: this cell is the cell behind it
+      if (pulled) {
+        const int tx = yx + ex19(p), ty = yy + ey19(p), tz = yz + ez19(p);
+        if (G.in(tx, ty, tz) && !liquid_at<MZ>(cnt, tx, ty, tz, n)) {
+          const double d = frac19<MZ>(s0, yx, yy, yz, q, n, num, den);
+          if (d < 0.5) acc += (1.0 - 2.0 * d) * LF(q, G.cell(yx, yy, yz));
+        }
+      }
+      lf0[(size_t)p * nc + i] = (Lam)acc;
     }
   }
 }
@@ -801,9 +869,78 @@ __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, cons
           w * (P.t_m - P.tref) / (d * d)) * l;
 }
 
+// Interpolated no-slip of f: derivative of the pulled population q of the
+// liquid cell (x,y,z), whose source is solid, with respect to its link
+// fraction d, times that population's adjoint.  num, den: d = num / den.
+template <typename Ts, typename Lam, bool MZ>
+__device__ double flink_sens(const Ts* f0, const double* s0, const int* cnt, const Lam* lfh,
+                             int x, int y, int z, int q, double& num, double& den,
+                             const KParams& P) {
+  const int n = P.n;
+  const Geo G{n, (uint32_t)n * (uint32_t)n};
+  const uint32_t i = G.cell(x, y, z);
+  const int p = opp19(q);
+  const double d = frac19<MZ>(s0, x, y, z, q, n, num, den);
+  const double l = (double)lfh[(size_t)q * P.ncell + i];
+  if (d < 0.5) {
+    const int bx = x + ex19(q), by = y + ey19(q), bz = z + ez19(q);
+    if (!G.in(bx, by, bz) || !liquid_at<MZ>(cnt, bx, by, bz, n)) return 0.0;
+    return 2.0 * (sv<19>(f0, P, p, i) - sv<19>(f0, P, p, G.cell(bx, by, bz))) * l;
+  }
+  return (sv<19>(f0, P, q, i) - sv<19>(f0, P, p, i)) / (2.0 * d * d) * l;
+}
+
+// Sum over the f links whose link fraction depends on the front of column
+// (x, o): d = num / den with num = a + 1/2 - s_reader and den = s_source -
+// s_reader + e_a, so dd/ds_reader = (num - den) / den^2 and dd/ds_source =
+// -num / den^2.  (i) the links of this column's liquid cells, (ii) the links
+// of the 8 neighbour columns' liquid cells whose source lies in this column.
+// Every link is visited from both of its columns, so no atomics are needed.
+template <typename Ts, typename Lam, bool MZ>
+__device__ double flink_column(const Ts* f0, const double* s0, const int* cnt, const Lam* lfh,
+                               int x, int o, const KParams& P) {
+  const int n = P.n;
+  const int c = o * n + x;
+  int lo = cnt[c], hi = cnt[c];
+  for (int dd = -1; dd <= 1; ++dd)
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int xx = x + dx, oo = o + dd;
+      if (xx < 0 || xx >= n || oo < 0 || oo >= n) continue;
+      lo = cnt[oo * n + xx] < lo ? cnt[oo * n + xx] : lo;
+      hi = cnt[oo * n + xx] > hi ? cnt[oo * n + xx] : hi;
+    }
+  lo = lo - 1 < 0 ? 0 : lo - 1;
+  hi = hi - 1 > n - 1 ? n - 1 : hi - 1;
+  double acc = 0.0, num, den;
+  for (int a = lo; a <= hi; ++a) {
+    for (int dd = -1; dd <= 1; ++dd)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = x + dx, oo = o + dd;  // the reader's column
+        if (xx < 0 || xx >= n || oo < 0 || oo >= n) continue;
+        if (a >= cnt[oo * n + xx]) continue;  // the reader is liquid
+        const int ry = MZ ? oo : a, rz = MZ ? a : oo;
+        for (int q = 1; q < 19; ++q) {
+          const int sx = xx - ex19(q), sy = ry - ey19(q), sz = rz - ez19(q);
+          if ((unsigned)sx >= (unsigned)n || (unsigned)sy >= (unsigned)n ||
+              (unsigned)sz >= (unsigned)n)
+            continue;
+          if (liquid_at<MZ>(cnt, sx, sy, sz, n)) continue;  // regular pull
+          const int so = MZ ? sy : sz;
+          const bool src_here = sx == x && so == o, reader_here = dx == 0 && dd == 0;
+          if (!src_here && !reader_here) continue;
+          const double ld = flink_sens<Ts, Lam, MZ>(f0, s0, cnt, lfh, xx, ry, rz, q, num, den, P);
+          if (reader_here) acc += ld * (num - den) / (den * den);
+          if (src_here) acc += ld * (-num) / (den * den);
+        }
+      }
+  }
+  return acc;
+}
+
 template <typename Ts, typename Lam, bool MZ>
 __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restrict__ s0,
                                 const int* __restrict__ cnt, const Lam* __restrict__ lgh,
+                                const Ts* __restrict__ f0, const Lam* __restrict__ lfh,
                                 double* __restrict__ ls0, double* __restrict__ lth, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
@@ -880,6 +1017,7 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
       acc += ld * (-(ya - sself)) / ((sc - sself) * (sc - sself));
     }
   }
+  if (P.flow && P.f_wall) acc += flink_column<Ts, Lam, MZ>(f0, s0, cnt, lfh, x, o, P);
   ls0[c] += acc;
 }
 
@@ -926,8 +1064,8 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
                      lgh, P);
   hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
                      A.cmax2, A.rowb, lfh, lgh, lf0, lg0, P);
-  hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh,
-                     A.ls0, A.lth, P);
+  hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh, f0,
+                     lfh, A.ls0, A.lth, P);
   return hipGetLastError();
 }
 

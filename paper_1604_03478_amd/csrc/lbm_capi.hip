@@ -719,8 +719,6 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
   if (nsteps < 1 || every_k < 1) return fail(LBM_EINVAL, "need nsteps >= 1 and every_k >= 1");
   if (c->p.front_scheme != 0)
     return fail(LBM_EINVAL, "the adjoint follows the Eq. (6) front update (front_scheme 0)");
-  if (c->p.f_wall != 0)
-    return fail(LBM_EINVAL, "the adjoint follows halfway bounce-back of f (f_wall 0)");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   AdjData& a = c->adj;
   const size_t nn = (size_t)c->p.n * c->p.n;
@@ -916,8 +914,6 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
   if (!schedule || nsteps < 1) return fail(LBM_EINVAL, "need a schedule and nsteps >= 1");
   if (c->p.front_scheme != 0)
     return fail(LBM_EINVAL, "replay follows the Eq. (6) front update (front_scheme 0)");
-  if (c->p.f_wall != 0)
-    return fail(LBM_EINVAL, "replay follows halfway bounce-back of f (f_wall 0)");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   const int n = c->p.n;
   const size_t nn = (size_t)n * n;

@@ -167,3 +167,84 @@ def test_gradient_matches_finite_differences_64():
         errs.append(abs(fd - (grad * d).sum()) / abs((grad * d).sum()))
     print("relative errors", errs)
     assert max(errs) <= 1e-3, errs
+
+
+@pytest.mark.parametrize("heating", ["y0", "z0"])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_gradient_matches_oracle_adjoint_interpolated_bounce_back(heating, prec, tol):
+    """f_wall = 1: the reverse sweep carries the interpolation weights of the
+    bounced populations and the dependence of every cut link (diagonal ones
+    included) on the fronts of its two columns."""
+    from inputs import hot_wall_field
+    n = 16
+    kw = dict(ra=1e5, pr=1.0, ste=1.0, s0=4.6, flow=1, alpha=0.1, f_wall=1)
+    orc, gpu = _pair_from_developed(n, kw, heating, 60, prec)
+    th = hot_wall_field(n, seed=6)
+    orc.th[:] = th
+    gpu.set_hot_wall(th)
+    orc.record(40)
+    *_, g_ref = orc.adjoint()
+    gpu.forward_ckpt(40, 7)
+    g = gpu.adjoint(1.0)
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert err <= tol, err
+
+
+def test_gradient_matches_oracle_adjoint_interpolated_bounce_back_36():
+    """36^3 (bulk-solid rows, fast paths and the front rows in one sweep),
+    FP64, f_wall = 1, rough developed front."""
+    from inputs import hot_wall_field
+    n = 36
+    kw = dict(ra=1e5, pr=1.0, ste=1.0, s0=9.7, flow=1, alpha=0.1, f_wall=1)
+    orc, gpu = _pair_from_developed(n, kw, "z0", 150, "f64")
+    th = hot_wall_field(n, seed=8)
+    orc.th[:] = th
+    gpu.set_hot_wall(th)
+    orc.record(30)
+    *_, g_ref = orc.adjoint()
+    gpu.forward_ckpt(30, 8)
+    g = gpu.adjoint(1.0)
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert err <= 1e-10, err
+
+
+def test_gradient_with_interpolated_bounce_back_matches_finite_differences_32():
+    """f_wall = 1, 32^3, 400 steps from the initial state, checkpoint every
+    50: central differences along the recorded schedule (FP64) for single
+    columns and random directions, relative error <= 1e-3."""
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, Sim
+    n, steps = 32, 400
+    cfg = Config(n=n, ra=1e4, pr=1.0, ste=0.5, s0=2.3, precision="f64", f_wall=1)
+    th0 = hot_wall_field(n, seed=9)
+    base = Sim(cfg)
+    base.set_hot_wall(th0)
+    fl_base = base.forward_ckpt(steps, 50)
+    sched = base.schedule(steps)
+    grad = base.adjoint(1.0)
+    base.close()
+
+    def J(t):
+        s = Sim(cfg)
+        s.set_hot_wall(t)
+        s.step_replay(sched, steps)
+        v = s.liquid_fraction()
+        s.close()
+        return v
+
+    assert J(th0) == fl_base
+    eps = 1e-3
+    rng = np.random.default_rng(2)
+    errs = []
+    for c in [(0, 0), (16, 16), (5, 27), (31, 9)]:
+        e = np.zeros((n, n))
+        e[c] = 1.0
+        fd = (J(th0 + eps * e) - J(th0 - eps * e)) / (2 * eps)
+        errs.append(abs(fd - grad[c]) / abs(grad[c]))
+    for _ in range(3):
+        d = rng.standard_normal((n, n))
+        d /= np.linalg.norm(d)
+        fd = (J(th0 + eps * d) - J(th0 - eps * d)) / (2 * eps)
+        errs.append(abs(fd - (grad * d).sum()) / abs((grad * d).sum()))
+    print("relative errors", errs)
+    assert max(errs) <= 1e-3, errs

@@ -8,7 +8,8 @@ diagonal links included. The rough random fronts below give every kind of
 crossing link (along the melt axis, lateral, diagonal), both branches of the
 interpolation, and cells with and without a liquid cell behind them.
 Bars as for halfway bounce-back: FP64 at round-off, FP32 within
-max|dT| <= 1e-5 and relative liquid-fraction error <= 1e-6.
+max|dT| <= 1e-5 and relative liquid-fraction error <= 1e-6.  (The adjoint with
+this option is tested in test_gpu_adjoint.py.)
 """
 import numpy as np
 import pytest
@@ -62,14 +63,3 @@ def test_interpolation_differs_from_halfway_where_the_front_is_inside_a_cell():
             sim.close()
     assert np.array_equal(out[(10.0, 0)], out[(10.0, 1)])
     assert not np.array_equal(out[(10.3, 0)], out[(10.3, 1)])
-
-
-def test_interpolated_bounce_back_has_no_adjoint_or_replay():
-    from paper_1604_03478_amd import Config, LbmError, Sim
-    sim = Sim(Config(n=8, ra=1e4, ste=0.1, f_wall=1, precision="f64"))
-    with pytest.raises(LbmError):
-        sim.forward_ckpt(4, 2)
-    sched = np.zeros(3 * 3 * 64, dtype=np.int32)
-    with pytest.raises(LbmError):
-        sim.step_replay(sched, 2)
-    sim.close()
