@@ -1104,6 +1104,83 @@ static void stream_cell_adjoint(const orc_sim *S, const double *f, const double 
   }
 }
 
+/* Reverse of the front update of reading R19: s1 = clamp(s + Q(g, s) / L)
+ * with Q the heat of the interface links (front_heat).  For each interface
+ * link of cell x, incoming direction q across the front: its heat is
+ * g_p(x) - g_q received, with g_q received from the interpolated condition of
+ * reading R8.  ls1: adjoint of s1; adds into lg (adjoint of the state's g)
+ * and ls. */
+static void front_heat_adjoint(const orc_sim *S, const double *f, const double *g,
+                               const double *s, const double *ls1, double *lg, double *ls) {
+  const int n = S->n;
+  const long long nc = S->ncell;
+  const orc_params *p = &S->p;
+  double *Q = (double *)malloc(sizeof(double) * n * n);
+  double *wq = (double *)malloc(sizeof(double) * n * n);
+  /* the forward heat, for the clamp (front_heat also adds the wall heat,
+   * which is restored) */
+  orc_sim *Sm = (orc_sim *)S;
+  const double wall = Sm->wall_heat;
+  front_heat(Sm, f, g, s, Q);
+  Sm->wall_heat = wall;
+  for (int c = 0; c < n * n; ++c) {
+    double v = s[c] + Q[c] / S->latent;
+    int clamped = v < 0.0 || v > n;
+    wq[c] = clamped ? 0.0 : ls1[c] / S->latent;
+    if (!clamped) ls[c] += ls1[c];
+  }
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        long long i = cell_index(n, x, y, z);
+        int liquid = is_liquid(S, s, x, y, z);
+        for (int q = 1; q < Q7; ++q) {
+          int sx = x - E7[q][0], sy = y - E7[q][1], sz = z - E7[q][2];
+          if (!in_box(n, sx, sy, sz) || is_liquid(S, s, sx, sy, sz) == liquid) continue;
+          int po = S->opp7[q];
+          const int *ep = E7[po];
+          int along = (p->heating == 0) ? (ep[1] != 0) : (ep[2] != 0);
+          int col = (along || !liquid) ? column_of(S, x, y, z) : column_of(S, sx, sy, sz);
+          double l = wq[col];
+          if (l == 0.0) continue;
+          double d = link_fraction(S, s, x, y, z, ep);
+          double w = S->w7[q];
+          int bx = x + E7[q][0], by = y + E7[q][1], bz = z + E7[q][2];
+          double dr = 0.0; /* derivative of the received value in d */
+          lg[po * nc + i] += l; /* sent */
+          if (d < 0.5) {
+            if (in_box(n, bx, by, bz) && is_liquid(S, s, bx, by, bz) == liquid) {
+              long long b = cell_index(n, bx, by, bz);
+              lg[po * nc + i] += 2.0 * d * l;
+              lg[po * nc + b] += (1.0 - 2.0 * d) * l;
+              dr = -2.0 * g[po * nc + i] + 2.0 * g[po * nc + b];
+            } else {
+              lg[po * nc + i] += l;
+            }
+          } else {
+            lg[po * nc + i] += l / (2.0 * d);
+            lg[q * nc + i] -= (2.0 * d - 1.0) / (2.0 * d) * l;
+            dr = g[po * nc + i] / (2.0 * d * d) + g[q * nc + i] / (2.0 * d * d) -
+                 w * p->t_m / (d * d);
+          }
+          double ld = -dr * l;
+          if (ld == 0.0) continue;
+          int c = column_of(S, x, y, z);
+          double a = melt_coord(S, x, y, z) + 0.5;
+          if (along) {
+            ls[c] += (s[c] > a ? 1.0 : -1.0) * ld;
+          } else {
+            int cn = column_of(S, x + ep[0], y + ep[1], z + ep[2]);
+            double den = s[cn] - s[c];
+            ls[c] += ld * (a - s[cn]) / (den * den);
+            ls[cn] += ld * (-(a - s[c])) / (den * den);
+          }
+        }
+      }
+  free(Q);
+  free(wq);
+}
+
 /* Reverse of one whole step from the state (f, g, s) to (f1, g1, s1).  On
  * entry (lf1, lg1, ls1) hold the adjoint of the later state (modified in
  * place); on return (lf, lg, ls) hold the adjoint of the earlier state (they
@@ -1126,8 +1203,13 @@ static void step_adjoint(const orc_sim *S, const double *f, const double *g,
           long long i = cell_of_column(S, c, a);
           for (int q = 0; q < Q19; ++q) lf1[q * nc + i] = 0.0;
         }
+  /* front update s1 = clamp(s + Q(g, s) / L) of reading R19: the heat of
+   * each interface link is linear in the state's g, and depends on the
+   * fronts through its link fraction */
+  if (!p->periodic && p->front_scheme == 1)
+    front_heat_adjoint(S, f, g, s, ls1, lg, ls);
   /* front update s1 = clamp(s + V(g1, s)) */
-  if (!p->periodic)
+  if (!p->periodic && p->front_scheme == 0)
     for (int c = 0; c < n * n; ++c) {
       vderiv dv;
       double V = front_velocity_column(S, g1, s, S->th, c, &dv);
@@ -1175,8 +1257,8 @@ static void record_free(void) {
  * sizes only: (nsteps + 1) * 26 * n^3 doubles).  Returns 0 on success. */
 int orc_record(orc_sim *S, long long nsteps) {
   record_free();
-  /* the reverse sweep follows Eq. (6) and the cavity's walls */
-  if (S->p.front_scheme != 0 || S->p.periodic == 2) return -2;
+  /* the reverse sweep follows the cavity's walls */
+  if (S->p.periodic == 2) return -2;
   const long long nc = S->ncell, nn = (long long)S->n * S->n;
   g_record.f = (double *)malloc(sizeof(double) * Q19 * nc * (nsteps + 1));
   g_record.g = (double *)malloc(sizeof(double) * Q7 * nc * (nsteps + 1));

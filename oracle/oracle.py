@@ -302,8 +302,8 @@ class OracleSim:
         """Step forward keeping every state (for the reverse sweep)."""
         rc = self._lib.orc_record(self._h, int(nsteps))
         if rc == -2:
-            raise ValueError("the reference adjoint follows the Eq. (6) front update and the "
-                             "cavity walls only")
+            raise ValueError("the reference adjoint follows the cavity's walls (not the "
+                             "channel test mode)")
         if rc != 0:
             raise MemoryError("oracle record allocation failed")
 

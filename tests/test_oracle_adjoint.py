@@ -37,6 +37,8 @@ def _clone(src, kw, f, g, s, th):
     dict(flow=1, heating=0, ra=1e5, ste=1.0, s0=5.3, t_c=-0.3, ks_kl=2.0),
     dict(flow=1, heating=0, ra=1e5, ste=1.0, s0=5.3, f_wall=1),
     dict(flow=1, heating=1, ra=1e5, ste=1.0, s0=4.7, f_wall=1),
+    dict(flow=1, heating=0, ra=1e5, ste=1.0, s0=5.3, front_scheme=1),
+    dict(flow=0, heating=1, alpha=0.1, ste=1.0, s0=4.7, front_scheme=1, t_c=-0.3),
 ])
 def test_one_step_dot_product(case):
     n = 12
