@@ -93,7 +93,7 @@ typedef struct {
                            taken from the heat the lattice carries across
                            the interface links in each step (conserves
                            sum(T) + L sum(s) up to the wall heat; no
-                           adjoint or replay)                              */
+                           replay)                                         */
   int32_t f_wall;       /* no-slip of f at the front: 0 halfway bounce-back;
                            1 bounce-back interpolated linearly to the point
                            where the front cuts each link (the link
@@ -211,9 +211,8 @@ int lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
  * n^2 values in the column layout of s and points to device memory if
  * on_device != 0.  lbm_adjoint needs a preceding lbm_forward_ckpt with no
  * step taken since (else LBM_ESTATE); it does not change the state.  Both
- * synchronize.  Errors: LBM_EINVAL (also for front_scheme 1: the reverse
- * sweep follows the gradient form of Eq. (6)), LBM_ENOMEM, LBM_ESTATE,
- * LBM_EDEVICE. */
+ * synchronize.  Every front_scheme and f_wall is covered.  Errors:
+ * LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EDEVICE. */
 int lbm_forward_ckpt(lbm_ctx *ctx, int64_t nsteps, int32_t every_k, double *fl);
 int lbm_adjoint(lbm_ctx *ctx, double dJ_dfl, double *grad_th, int on_device);
 

@@ -37,6 +37,10 @@ struct AdjointStep {
   double* out5;
   double* own;       // per-column scratch of the front adjoint
   double* lth;
+  // conservative front update (front scheme 1) only, else NULL: the interface
+  // heat of state t per column, and the per-column weight d(J)/d(heat)
+  const double* heat;
+  double* wq;
 };
 hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A, hipStream_t st);
 hipError_t launch_fill(double* v, size_t count, double value, hipStream_t st);

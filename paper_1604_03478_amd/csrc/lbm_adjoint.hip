@@ -194,6 +194,18 @@ __device__ __forceinline__ double link_delta(const double* s, int x, int y, int 
   return (a - s[c]) / (s[cn] - s[c]);
 }
 
+// Conservative front update: the weight of the heat of the interface link of
+// cell (x,y,z) whose incoming D3Q7 direction q has its source across the
+// front.  A link along the melt axis is charged to its own column, a lateral
+// one to the column of its solid cell.  wq: per-column weight.
+template <bool MZ>
+__device__ __forceinline__ double heat_weight(const double* wq, int x, int y, int z, int q,
+                                              bool liquid, int n) {
+  const bool along = MZ ? (ez7(q) != 0) : (ey7(q) != 0);
+  return wq[(along || !liquid) ? col_of<MZ>(x, y, z, n)
+                               : col_of<MZ>(x - ex7(q), y - ey7(q), z - ez7(q), n)];
+}
+
 // Fraction of the link from cell (x,y,z) to the source of its incoming D3Q19
 // direction q at which the front cuts it, for the interpolated no-slip of f:
 // the height on the melt axis and the front (linear between the two columns)
@@ -637,6 +649,24 @@ __global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict_
 // s contributions: own slot 0; slot 1 of the x-1 neighbour (its x+1 is this
 // column), slot 2 of x+1, slot 3 of o-1, slot 4 of o+1; at the walls the
 // mirrored slots of the column itself
+// Reverse of the conservative front update s' = clamp(s + heat Ste / dT):
+// the direct term of s, and the weight by which each column's interface heat
+// enters J (zero where the front was clamped).  out5 is cleared so that the
+// gather below adds nothing else.
+__global__ void k_adj_front_heat(const double* __restrict__ s0, const double* __restrict__ heat,
+                                 const double* __restrict__ ls1, double* __restrict__ wq,
+                                 double* __restrict__ own, double* __restrict__ out5, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
+  if (x >= n) return;
+  const int nn = n * n, c = o * n + x;
+  const double v = s0[c] + heat[c] * P.ste / P.dT;
+  const bool clamped = v < 0.0 || v > (double)n;
+  wq[c] = clamped ? 0.0 : ls1[c] * P.ste / P.dT;
+  own[c] = clamped ? 0.0 : ls1[c];
+  for (int k = 0; k < 5; ++k) out5[(size_t)k * nn + c] = 0.0;
+}
+
 __global__ void k_adj_front_gather(const double* __restrict__ own, const double* __restrict__ out5,
                                    double* __restrict__ ls0, int n) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
@@ -727,7 +757,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
     const double* __restrict__ s0, const int* __restrict__ cnt, const int* __restrict__ cmin2,
     const int* __restrict__ cmax2, const int* __restrict__ rowb, const Lam* __restrict__ lfh,
     const Lam* __restrict__ lgh, Lam* __restrict__ lf0, Lam* __restrict__ lg0,
-    KParams P) {
+    const double* __restrict__ wq, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= n) return;
@@ -768,8 +798,11 @@ __global__ __launch_bounds__(256) void k_adj_stream(
           const int bx = x - ex, by = y - ey, bz = z - ez;
           const bool behind = G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L;
           acc += (behind ? -2.0 * d : -1.0) * LG(q, i);
+          // conservative front: the heat of this link, sent minus received
+          if (wq) acc += (behind ? 1.0 + 2.0 * d : 2.0) * heat_weight<MZ>(wq, x, y, z, q, L, n);
         } else {
           acc += -LG(q, i) / (2.0 * d);
+          if (wq) acc += (1.0 + 1.0 / (2.0 * d)) * heat_weight<MZ>(wq, x, y, z, q, L, n);
         }
       }
       // (c) this cell's direction p itself, when its source x - e_p is across
@@ -777,7 +810,10 @@ __global__ __launch_bounds__(256) void k_adj_stream(
       const int sx = x - ex, sy = y - ey, sz = z - ez;
       if (G.in(sx, sy, sz) && liquid_at<MZ>(cnt, sx, sy, sz, n) != L) {
         const double d = link_delta<MZ>(s0, x, y, z, -ex, -ey, -ez, n);
-        if (d >= 0.5) acc += (2.0 * d - 1.0) / (2.0 * d) * LG(p, i);
+        if (d >= 0.5) {
+          acc += (2.0 * d - 1.0) / (2.0 * d) * LG(p, i);
+          if (wq) acc -= (2.0 * d - 1.0) / (2.0 * d) * heat_weight<MZ>(wq, x, y, z, p, L, n);
+        }
       }
       // (d) the neighbour x + e_p, direction q, when its source x + 2 e_p is
       //     across the front with a link fraction < 1/2 (this cell is then the
@@ -786,7 +822,10 @@ __global__ __launch_bounds__(256) void k_adj_stream(
         const int tx = yx + ex, ty = yy + ey, tz = yz + ez;
         if (G.in(tx, ty, tz) && liquid_at<MZ>(cnt, tx, ty, tz, n) != L) {
           const double d = link_delta<MZ>(s0, yx, yy, yz, ex, ey, ez, n);
-          if (d < 0.5) acc += -(1.0 - 2.0 * d) * LG(q, G.cell(yx, yy, yz));
+          if (d < 0.5) {
+            acc += -(1.0 - 2.0 * d) * LG(q, G.cell(yx, yy, yz));
+            if (wq) acc += (1.0 - 2.0 * d) * heat_weight<MZ>(wq, yx, yy, yz, q, L, n);
+          }
         }
       }
     }
@@ -845,11 +884,14 @@ __global__ __launch_bounds__(256) void k_adj_stream(
 
 // derivative of the pulled population of an interface link with respect to
 // its link fraction, times its adjoint; reader cell (x,y,z), incoming
-// direction q (its source across the front)
+// direction q (its source across the front).  With the conservative front
+// update (wq not NULL) the link's heat, sent minus received, enters J with
+// the weight of its column as well.
 template <typename Ts, typename Lam, bool MZ>
 __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, const int* cnt,
-                                            const Lam* lgh, int x, int y, int z, int q,
-                                            bool L, double& dfrac, const KParams& P) {
+                                            const Lam* lgh, const double* wq, int x, int y,
+                                            int z, int q, bool L, double& dfrac,
+                                            const KParams& P) {
   const int n = P.n;
   const Geo G{n, (uint32_t)n * (uint32_t)n};
   const size_t nc = P.ncell;
@@ -857,7 +899,8 @@ __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, cons
   const int p = opp7(q);
   const double d = link_delta<MZ>(s0, x, y, z, -ex7(q), -ey7(q), -ez7(q), n);
   dfrac = d;
-  const double l = (double)lgh[(size_t)q * nc + i];
+  const double l = (double)lgh[(size_t)q * nc + i] -
+                   (wq ? heat_weight<MZ>(wq, x, y, z, q, L, n) : 0.0);
   if (d < 0.5) {
     const int bx = x + ex7(q), by = y + ey7(q), bz = z + ez7(q);
     if (G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L)
@@ -941,7 +984,8 @@ template <typename Ts, typename Lam, bool MZ>
 __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restrict__ s0,
                                 const int* __restrict__ cnt, const Lam* __restrict__ lgh,
                                 const Ts* __restrict__ f0, const Lam* __restrict__ lfh,
-                                double* __restrict__ ls0, double* __restrict__ lth, KParams P) {
+                                const double* __restrict__ wq, double* __restrict__ ls0,
+                                double* __restrict__ lth, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
   if (x >= n) return;
@@ -986,7 +1030,7 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
           continue;
         if (liquid_at<MZ>(cnt, sx, sy, sz, n) == L) continue;
         double d;
-        const double ld = link_sens<Ts, Lam, MZ>(g0, s0, cnt, lgh, cx, cy, cz, q, L, d, P);
+        const double ld = link_sens<Ts, Lam, MZ>(g0, s0, cnt, lgh, wq, cx, cy, cz, q, L, d, P);
         const bool along = MZ ? (ez7(q) != 0) : (ey7(q) != 0);
         if (along) {
           acc += (sc > ya ? 1.0 : -1.0) * ld;
@@ -1012,7 +1056,7 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
       }
       if (q < 1) continue;  // every lateral neighbour has one such direction
       double d;
-      const double ld = link_sens<Ts, Lam, MZ>(g0, s0, cnt, lgh, cx, cy, cz, q, L, d, P);
+      const double ld = link_sens<Ts, Lam, MZ>(g0, s0, cnt, lgh, wq, cx, cy, cz, q, L, d, P);
       const double sself = s0[nb[j]];
       acc += ld * (-(ya - sself)) / ((sc - sself) * (sc - sself));
     }
@@ -1052,8 +1096,13 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   Lam* lg0 = static_cast<Lam*>(A.lg0);
   Lam* lfh = static_cast<Lam*>(A.lfh);
   Lam* lgh = static_cast<Lam*>(A.lgh);
-  hipLaunchKernelGGL((k_adj_front<Ts, Lam, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.s1, A.th,
-                     A.ls1, lg1, A.out5, A.own, A.lth, P);
+  if (A.heat)  // conservative front update
+    hipLaunchKernelGGL(k_adj_front_heat, gcol, bcol, 0, st, A.s0, A.heat, A.ls1, A.wq, A.own,
+                       A.out5, P);
+  else
+    hipLaunchKernelGGL((k_adj_front<Ts, Lam, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.s1, A.th,
+                       A.ls1, lg1, A.out5, A.own, A.lth, P);
+  const double* wq = A.heat ? A.wq : nullptr;
   hipLaunchKernelGGL(k_adj_front_gather, gcol, bcol, 0, st, A.own, A.out5, A.ls0, n);
   hipLaunchKernelGGL(k_adj_rows, dim3(1), dim3(1024), 0, st, A.cnt, A.rowb, n);
   // row slots of the full reverse collision: at most one per row
@@ -1063,9 +1112,9 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   hipLaunchKernelGGL((k_adj_collide_solid<Ts, Lam, MZ>), gcell, bcell, 0, st, g0, A.rowb, lg1,
                      lgh, P);
   hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
-                     A.cmax2, A.rowb, lfh, lgh, lf0, lg0, P);
+                     A.cmax2, A.rowb, lfh, lgh, lf0, lg0, wq, P);
   hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh, f0,
-                     lfh, A.ls0, A.lth, P);
+                     lfh, wq, A.ls0, A.lth, P);
   return hipGetLastError();
 }
 

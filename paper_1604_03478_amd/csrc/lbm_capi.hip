@@ -92,6 +92,7 @@ struct AdjData {
   std::vector<double*> ss;
   int *cnt = nullptr, *cmin = nullptr, *cmax = nullptr, *melted = nullptr, *frozen = nullptr,
       *flag = nullptr, *cmin2 = nullptr, *cmax2 = nullptr, *rowb = nullptr;
+  double* wq = nullptr;  // per-column weight of the interface heat (front scheme 1)
   void *lf[2] = {nullptr, nullptr}, *lg[2] = {nullptr, nullptr};  // per-cell adjoints
   void *lfh = nullptr, *lgh = nullptr;
   double *ls[2] = {nullptr, nullptr};
@@ -166,7 +167,7 @@ void release_adjoint(AdjData& a) {
   free_all(a.ss);
   void* ptrs[] = {a.cnt,   a.cmin,  a.cmax,  a.cmin2, a.cmax2, a.rowb, a.melted, a.frozen, a.flag,
                   a.lf[0], a.lf[1], a.lg[0],
-                  a.lg[1], a.ls[0], a.ls[1], a.lfh, a.lgh, a.out5, a.own, a.lth};
+                  a.lg[1], a.ls[0], a.ls[1], a.lfh, a.lgh, a.out5, a.own, a.lth, a.wq};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   a = AdjData();
@@ -717,8 +718,6 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (nsteps < 1 || every_k < 1) return fail(LBM_EINVAL, "need nsteps >= 1 and every_k >= 1");
-  if (c->p.front_scheme != 0)
-    return fail(LBM_EINVAL, "the adjoint follows the Eq. (6) front update (front_scheme 0)");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   AdjData& a = c->adj;
   const size_t nn = (size_t)c->p.n * c->p.n;
@@ -824,7 +823,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
         (rc = dalloc_bytes(&a.lg[0], 7 * nc * lb)) || (rc = dalloc_bytes(&a.lg[1], 7 * nc * lb)) ||
         (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
         (rc = dalloc_bytes(&a.lgh, 7 * nc * lb)) || (rc = dalloc(&a.out5, 5 * nn)) ||
-        (rc = dalloc(&a.own, nn)) || (rc = dalloc(&a.lth, nn)))
+        (rc = dalloc(&a.own, nn)) || (rc = dalloc(&a.lth, nn)) || (rc = dalloc(&a.wq, nn)))
       return rc;
     if (flow && ((rc = dalloc_bytes(&a.lf[0], 19 * nc * lb)) ||
                  (rc = dalloc_bytes(&a.lf[1], 19 * nc * lb)) ||
@@ -855,14 +854,18 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
       HIP_TRY(lbmk::launch_stream_collide(c->kind, k, a.sf[t], a.sf[t + 1], a.sg[t], a.sg[t + 1],
                                           a.cnt, a.cmin, a.cmax, a.ss[t], c->th, a.flag,
                                           c->stream));
+      if (c->heat)  // conservative front: heat of the streaming from the state sg[t]
+        HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], a.cnt, c->heat, c->stream));
       HIP_TRY(lbmk::launch_front(c->kind, k, a.ss[t], a.ss[t + 1], a.cnt, a.sg[t + 1],
                                  a.sf[t + 1], c->th, a.melted, a.frozen, a.flag, nullptr, nullptr,
-                                 nullptr, nullptr, c->stream));
+                                 nullptr, c->heat, c->stream));
     }
     // reverse the segment
     for (int64_t t = len - 1; t >= 0; --t) {
       HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
       HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin2, a.cmax2, c->stream, 2));
+      if (c->heat)  // the interface heat of state t, for the reverse of the front update
+        HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], a.cnt, c->heat, c->stream));
       lbmk::AdjointStep A;
       A.f0 = a.sf[t];
       A.g0 = a.sg[t];
@@ -885,6 +888,8 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
       A.out5 = a.out5;
       A.own = a.own;
       A.lth = a.lth;
+      A.heat = c->heat;
+      A.wq = a.wq;
       HIP_TRY(lbmk::launch_adjoint_step(c->kind, c->kp, A, c->stream));
       cur = 1 - cur;
     }

@@ -248,3 +248,50 @@ def test_gradient_with_interpolated_bounce_back_matches_finite_differences_32():
         errs.append(abs(fd - (grad * d).sum()) / abs((grad * d).sum()))
     print("relative errors", errs)
     assert max(errs) <= 1e-3, errs
+
+
+@pytest.mark.parametrize("heating", ["y0", "z0"])
+@pytest.mark.parametrize("flow", [1, 0])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_gradient_matches_oracle_adjoint_conservative_front(heating, flow, prec, tol):
+    """front_scheme = 1: the front moves by the heat of its interface links,
+    which is linear in the state's g and depends on the fronts through the
+    link fractions; lateral links are charged to their solid cell's column."""
+    from inputs import hot_wall_field
+    n = 16
+    kw = dict(ra=1e5, pr=1.0, ste=1.0, s0=4.6, flow=flow, alpha=0.1, front_scheme=1)
+    orc, gpu = _pair_from_developed(n, kw, heating, 60, prec)
+    th = hot_wall_field(n, seed=7)
+    orc.th[:] = th
+    gpu.set_hot_wall(th)
+    orc.record(40)
+    *_, g_ref = orc.adjoint()
+    gpu.forward_ckpt(40, 7)
+    g = gpu.adjoint(1.0)
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert err <= tol, err
+
+
+def test_gradient_matches_oracle_adjoint_conservative_front_rough_36():
+    """36^3, FP64, front_scheme = 1, from a rough front (independent heights
+    per column: many lateral interface links)."""
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, Sim
+    n = 36
+    kw = dict(ra=1e5, pr=1.0, ste=1.0, s0=9.0, flow=1, alpha=0.1, front_scheme=1)
+    orc = OracleSim(n, heating=1, **kw)
+    orc.step(40)
+    rng = np.random.default_rng(12)
+    s = 7.2 + 4.6 * rng.random((n, n))
+    orc.s[:] = s
+    gpu = Sim(Config(n=n, heating="z0", precision="f64", **kw))
+    gpu.set_populations(orc.f.copy(), orc.g.copy(), s.copy())
+    th = hot_wall_field(n, seed=13)
+    orc.th[:] = th
+    gpu.set_hot_wall(th)
+    orc.record(25)
+    *_, g_ref = orc.adjoint()
+    gpu.forward_ckpt(25, 6)
+    g = gpu.adjoint(1.0)
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    assert err <= 1e-10, err
