@@ -92,8 +92,7 @@ typedef struct {
                            temperature gradients; 1 the same energy balance
                            taken from the heat the lattice carries across
                            the interface links in each step (conserves
-                           sum(T) + L sum(s) up to the wall heat; no
-                           replay)                                         */
+                           sum(T) + L sum(s) up to the wall heat)          */
   int32_t f_wall;       /* no-slip of f at the front: 0 halfway bounce-back;
                            1 bounce-back interpolated linearly to the point
                            where the front cuts each link (the link
@@ -224,8 +223,8 @@ int lbm_adjoint(lbm_ctx *ctx, double dJ_dfl, double *grad_th, int on_device);
  * nsteps steps along such a schedule (phases and node selection fixed, every
  * other quantity recomputed): the map whose derivative lbm_adjoint gives,
  * for finite-difference checks.  The schedule is host memory; both
- * synchronize.  lbm_step_replay returns LBM_EINVAL for front_scheme 1 and for
- * a schedule whose node indices lie outside the lattice. */
+ * synchronize.  lbm_step_replay returns LBM_EINVAL for a schedule whose
+ * counts or node indices lie outside the lattice. */
 int lbm_get_schedule(lbm_ctx *ctx, int32_t *out, size_t count);
 int lbm_step_replay(lbm_ctx *ctx, const int32_t *schedule, int64_t nsteps);
 

@@ -358,7 +358,7 @@ __device__ __forceinline__ void push_fast(const Lam* __restrict__ lh, Lam* __res
 
 // pulled (pre-collision) shifted populations of one cell (general path), in
 // FP64, reduced to T and j
-template <typename Ts, bool FLOW, bool MZ>
+template <typename Ts, bool FLOW, bool MZ, bool EXT>
 __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const double* th,
                           const int* cnt, int x, int y, int z, bool liquid, const KParams& P,
                           Macro& M) {
@@ -401,7 +401,7 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
       const bool inb = G.in(sx, sy, sz);
       const bool ok = inb && liquid_at<MZ>(cnt, sx, sy, sz, n);
       double v = ok ? sv<19>(f, P, q, G.cell(sx, sy, sz)) : sv<19>(f, P, opp19(q), i);
-      if (P.f_wall && inb && !ok) {  // interpolated no-slip at the front
+      if (EXT && P.f_wall && inb && !ok) {  // interpolated no-slip at the front
         double num, den;
         const double d = frac19<MZ>(s, x, y, z, q, n, num, den);
         if (d < 0.5) {
@@ -682,7 +682,7 @@ __global__ void k_adj_front_gather(const double* __restrict__ own, const double*
 }
 
 // reverse collision of one cell (any row)
-template <typename Ts, typename Lam, bool FLOW, bool MZ>
+template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
 __device__ __forceinline__ void adj_collide_cell(
     const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
     const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
@@ -700,7 +700,7 @@ __device__ __forceinline__ void adj_collide_cell(
   if (__all(adj_fast<MZ>(cmin2, cmax2, x, y, z, n)))
     pull_fast<Ts, FLOW>(f0, g0, x, y, z, liquid, P, M);
   else
-    pull_cell<Ts, FLOW, MZ>(f0, g0, s0, th, cnt, x, y, z, liquid, P, M);
+    pull_cell<Ts, FLOW, MZ, EXT>(f0, g0, s0, th, cnt, x, y, z, liquid, P, M);
   double lfo[19], lgo[7], lfl[19], lgl[7];
   for (int q = 0; q < 19; ++q) lfo[q] = (FLOW && live1) ? (double)lf1[(size_t)q * nc + i] : 0.0;
   for (int q = 0; q < 7; ++q) lgo[q] = (double)lg1[(size_t)q * nc + i];
@@ -713,7 +713,7 @@ __device__ __forceinline__ void adj_collide_cell(
 // The rows outside the bulk solid, front_rows(A, n) of them, visited by a
 // grid of gridDim.y row slots (this kernel needs many registers, so its
 // waves are not spent on rows it would skip).
-template <typename Ts, typename Lam, bool FLOW, bool MZ>
+template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
 __global__ __launch_bounds__(256) void k_adj_collide(
     const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
     const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
@@ -727,8 +727,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(
     int a, o;
     front_row(r, A, n, a, o);
     if (x < n)
-      adj_collide_cell<Ts, Lam, FLOW, MZ>(f0, g0, s0, s1, th, cnt, cmin2, cmax2, lf1, lg1, lfh,
-                                          lgh, P, x, MZ ? o : a, MZ ? a : o);
+      adj_collide_cell<Ts, Lam, FLOW, MZ, EXT>(f0, g0, s0, s1, th, cnt, cmin2, cmax2, lf1, lg1,
+                                               lfh, lgh, P, x, MZ ? o : a, MZ ? a : o);
   }
 }
 
@@ -752,7 +752,7 @@ __global__ __launch_bounds__(256) void k_adj_collide_solid(
   for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = (Lam)lgl[q];
 }
 
-template <typename Ts, typename Lam, bool FLOW, bool MZ>
+template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
 __global__ __launch_bounds__(256) void k_adj_stream(
     const double* __restrict__ s0, const int* __restrict__ cnt, const int* __restrict__ cmin2,
     const int* __restrict__ cmax2, const int* __restrict__ rowb, const Lam* __restrict__ lfh,
@@ -799,10 +799,11 @@ __global__ __launch_bounds__(256) void k_adj_stream(
           const bool behind = G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L;
           acc += (behind ? -2.0 * d : -1.0) * LG(q, i);
           // conservative front: the heat of this link, sent minus received
-          if (wq) acc += (behind ? 1.0 + 2.0 * d : 2.0) * heat_weight<MZ>(wq, x, y, z, q, L, n);
+          if (EXT && wq)
+            acc += (behind ? 1.0 + 2.0 * d : 2.0) * heat_weight<MZ>(wq, x, y, z, q, L, n);
         } else {
           acc += -LG(q, i) / (2.0 * d);
-          if (wq) acc += (1.0 + 1.0 / (2.0 * d)) * heat_weight<MZ>(wq, x, y, z, q, L, n);
+          if (EXT && wq) acc += (1.0 + 1.0 / (2.0 * d)) * heat_weight<MZ>(wq, x, y, z, q, L, n);
         }
       }
       // (c) this cell's direction p itself, when its source x - e_p is across
@@ -812,7 +813,8 @@ __global__ __launch_bounds__(256) void k_adj_stream(
         const double d = link_delta<MZ>(s0, x, y, z, -ex, -ey, -ez, n);
         if (d >= 0.5) {
           acc += (2.0 * d - 1.0) / (2.0 * d) * LG(p, i);
-          if (wq) acc -= (2.0 * d - 1.0) / (2.0 * d) * heat_weight<MZ>(wq, x, y, z, p, L, n);
+          if (EXT && wq)
+            acc -= (2.0 * d - 1.0) / (2.0 * d) * heat_weight<MZ>(wq, x, y, z, p, L, n);
         }
       }
       // (d) the neighbour x + e_p, direction q, when its source x + 2 e_p is
@@ -824,7 +826,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
           const double d = link_delta<MZ>(s0, yx, yy, yz, ex, ey, ez, n);
           if (d < 0.5) {
             acc += -(1.0 - 2.0 * d) * LG(q, G.cell(yx, yy, yz));
-            if (wq) acc += (1.0 - 2.0 * d) * heat_weight<MZ>(wq, yx, yy, yz, q, L, n);
+            if (EXT && wq) acc += (1.0 - 2.0 * d) * heat_weight<MZ>(wq, yx, yy, yz, q, L, n);
           }
         }
       }
@@ -833,14 +835,21 @@ __global__ __launch_bounds__(256) void k_adj_stream(
   }
   // adjoint of f before the step: only liquid cells read their f (solid
   // cells hold dead data, whose adjoint is zero and is not stored)
-  if (FLOW && L) {
+  if (FLOW && L && !(EXT && P.f_wall)) {
+    for (int p = 0; p < 19; ++p) {
+      const int yx = x + ex19(p), yy = y + ey19(p), yz = z + ez19(p);
+      const bool pulled = G.in(yx, yy, yz) && liquid_at<MZ>(cnt, yx, yy, yz, n);
+      lf0[(size_t)p * nc + i] =
+          pulled ? lfh[(size_t)p * nc + G.cell(yx, yy, yz)] : lfh[(size_t)opp19(p) * nc + i];
+    }
+  } else if (FLOW && L) {  // interpolated no-slip of f
     auto LF = [&](int q, uint32_t j) { return (double)lfh[(size_t)q * nc + j]; };
     for (int p = 0; p < 19; ++p) {
       const int yx = x + ex19(p), yy = y + ey19(p), yz = z + ez19(p), q = opp19(p);
       const bool yin = G.in(yx, yy, yz);
       const bool pulled = yin && liquid_at<MZ>(cnt, yx, yy, yz, n);
-      if (!P.f_wall || p == 0) {
-        lf0[(size_t)p * nc + i] = (Lam)(pulled ? LF(p, G.cell(yx, yy, yz)) : LF(q, i));
+      if (p == 0) {
+        lf0[(size_t)p * nc + i] = lfh[(size_t)p * nc + i];
         continue;
       }
       // every reader of f*_p(x) under the interpolated no-slip
@@ -887,7 +896,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
 // direction q (its source across the front).  With the conservative front
 // update (wq not NULL) the link's heat, sent minus received, enters J with
 // the weight of its column as well.
-template <typename Ts, typename Lam, bool MZ>
+template <typename Ts, typename Lam, bool MZ, bool EXT>
 __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, const int* cnt,
                                             const Lam* lgh, const double* wq, int x, int y,
                                             int z, int q, bool L, double& dfrac,
@@ -900,7 +909,7 @@ __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, cons
   const double d = link_delta<MZ>(s0, x, y, z, -ex7(q), -ey7(q), -ez7(q), n);
   dfrac = d;
   const double l = (double)lgh[(size_t)q * nc + i] -
-                   (wq ? heat_weight<MZ>(wq, x, y, z, q, L, n) : 0.0);
+                   ((EXT && wq) ? heat_weight<MZ>(wq, x, y, z, q, L, n) : 0.0);
   if (d < 0.5) {
     const int bx = x + ex7(q), by = y + ey7(q), bz = z + ez7(q);
     if (G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L)
@@ -980,7 +989,7 @@ __device__ double flink_column(const Ts* f0, const double* s0, const int* cnt, c
   return acc;
 }
 
-template <typename Ts, typename Lam, bool MZ>
+template <typename Ts, typename Lam, bool MZ, bool EXT>
 __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restrict__ s0,
                                 const int* __restrict__ cnt, const Lam* __restrict__ lgh,
                                 const Ts* __restrict__ f0, const Lam* __restrict__ lfh,
@@ -1030,7 +1039,8 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
           continue;
         if (liquid_at<MZ>(cnt, sx, sy, sz, n) == L) continue;
         double d;
-        const double ld = link_sens<Ts, Lam, MZ>(g0, s0, cnt, lgh, wq, cx, cy, cz, q, L, d, P);
+        const double ld =
+            link_sens<Ts, Lam, MZ, EXT>(g0, s0, cnt, lgh, wq, cx, cy, cz, q, L, d, P);
         const bool along = MZ ? (ez7(q) != 0) : (ey7(q) != 0);
         if (along) {
           acc += (sc > ya ? 1.0 : -1.0) * ld;
@@ -1056,12 +1066,12 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
       }
       if (q < 1) continue;  // every lateral neighbour has one such direction
       double d;
-      const double ld = link_sens<Ts, Lam, MZ>(g0, s0, cnt, lgh, wq, cx, cy, cz, q, L, d, P);
+      const double ld = link_sens<Ts, Lam, MZ, EXT>(g0, s0, cnt, lgh, wq, cx, cy, cz, q, L, d, P);
       const double sself = s0[nb[j]];
       acc += ld * (-(ya - sself)) / ((sc - sself) * (sc - sself));
     }
   }
-  if (P.flow && P.f_wall) acc += flink_column<Ts, Lam, MZ>(f0, s0, cnt, lfh, x, o, P);
+  if (EXT && P.flow && P.f_wall) acc += flink_column<Ts, Lam, MZ>(f0, s0, cnt, lfh, x, o, P);
   ls0[c] += acc;
 }
 
@@ -1080,7 +1090,9 @@ hipError_t fill_t(V* v, size_t count, double value, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename Ts, typename Lam, bool FLOW, bool MZ>
+// EXT: the interpolated no-slip of f or the conservative front update is on
+// (a separate instantiation, so that the default one compiles without them)
+template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
 hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st) {
   const int n = P.n;
   const dim3 bcol(64, 1, 1), gcol((n + 63) / 64, n, 1);
@@ -1107,24 +1119,30 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   hipLaunchKernelGGL(k_adj_rows, dim3(1), dim3(1024), 0, st, A.cnt, A.rowb, n);
   // row slots of the full reverse collision: at most one per row
   const dim3 gfront((n + bx - 1) / bx, (unsigned)(n * n < 2048 ? n * n : 2048), 1);
-  hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ>), gfront, bcell, 0, st, f0, g0, A.s0,
+  hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ, EXT>), gfront, bcell, 0, st, f0, g0, A.s0,
                      A.s1, A.th, A.cnt, A.cmin2, A.cmax2, A.rowb, lf1, lg1, lfh, lgh, P);
   hipLaunchKernelGGL((k_adj_collide_solid<Ts, Lam, MZ>), gcell, bcell, 0, st, g0, A.rowb, lg1,
                      lgh, P);
-  hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
+  hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ, EXT>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
                      A.cmax2, A.rowb, lfh, lgh, lf0, lg0, wq, P);
-  hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh, f0,
+  hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ, EXT>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh, f0,
                      lfh, wq, A.ls0, A.lth, P);
   return hipGetLastError();
+}
+
+template <typename Ts, typename Lam, bool FLOW, bool MZ>
+hipError_t adjoint_step_e(const KParams& P, const AdjointStep& A, hipStream_t st) {
+  if ((FLOW && P.f_wall) || A.heat) return adjoint_step_t<Ts, Lam, FLOW, MZ, true>(P, A, st);
+  return adjoint_step_t<Ts, Lam, FLOW, MZ, false>(P, A, st);
 }
 
 template <typename Ts, typename Lam>
 hipError_t adjoint_step_d(const KParams& P, const AdjointStep& A, hipStream_t st) {
   if (P.flow)
-    return P.melt_z ? adjoint_step_t<Ts, Lam, true, true>(P, A, st)
-                    : adjoint_step_t<Ts, Lam, true, false>(P, A, st);
-  return P.melt_z ? adjoint_step_t<Ts, Lam, false, true>(P, A, st)
-                  : adjoint_step_t<Ts, Lam, false, false>(P, A, st);
+    return P.melt_z ? adjoint_step_e<Ts, Lam, true, true>(P, A, st)
+                    : adjoint_step_e<Ts, Lam, true, false>(P, A, st);
+  return P.melt_z ? adjoint_step_e<Ts, Lam, false, true>(P, A, st)
+                  : adjoint_step_e<Ts, Lam, false, false>(P, A, st);
 }
 
 }  // namespace

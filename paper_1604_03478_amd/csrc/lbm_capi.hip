@@ -917,8 +917,6 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (!schedule || nsteps < 1) return fail(LBM_EINVAL, "need a schedule and nsteps >= 1");
-  if (c->p.front_scheme != 0)
-    return fail(LBM_EINVAL, "replay follows the Eq. (6) front update (front_scheme 0)");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   const int n = c->p.n;
   const size_t nn = (size_t)n * n;
@@ -956,9 +954,12 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
     HIP_TRY(lbmk::launch_stream_collide(c->kind, k, c->f[c->cur], c->f[nx], c->g[c->cur], c->g[nx],
                                         c->cnt, c->cmin, c->cmax, c->s[c->scur], c->th, c->flag,
                                         c->stream));
+    if (c->heat)  // conservative front: heat of the streaming from the state g[cur]
+      HIP_TRY(lbmk::launch_front_heat(c->kind, k, c->g[c->cur], c->s[c->scur], c->cnt, c->heat,
+                                      c->stream));
     HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
                                c->th, c->melted, c->frozen, c->flag, e, e + 3 * nn, nullptr,
-                               nullptr, c->stream));
+                               c->heat, c->stream));
     HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
     c->cur = nx;
     c->scur = sx;

@@ -295,3 +295,45 @@ def test_gradient_matches_oracle_adjoint_conservative_front_rough_36():
     g = gpu.adjoint(1.0)
     err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
     assert err <= 1e-10, err
+
+
+def test_gradient_with_conservative_front_matches_finite_differences_32():
+    """front_scheme = 1, 32^3, 400 steps from the initial state, checkpoint
+    every 50: central differences along the recorded schedule (FP64) for
+    single columns and random directions, relative error <= 1e-3."""
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, Sim
+    n, steps = 32, 400
+    cfg = Config(n=n, ra=1e4, pr=1.0, ste=0.5, s0=2.3, precision="f64", front_scheme=1)
+    th0 = hot_wall_field(n, seed=10)
+    base = Sim(cfg)
+    base.set_hot_wall(th0)
+    fl_base = base.forward_ckpt(steps, 50)
+    sched = base.schedule(steps)
+    grad = base.adjoint(1.0)
+    base.close()
+
+    def J(t):
+        s = Sim(cfg)
+        s.set_hot_wall(t)
+        s.step_replay(sched, steps)
+        v = s.liquid_fraction()
+        s.close()
+        return v
+
+    assert J(th0) == fl_base
+    eps = 1e-3
+    rng = np.random.default_rng(3)
+    errs = []
+    for c in [(0, 0), (16, 16), (5, 27), (31, 9)]:
+        e = np.zeros((n, n))
+        e[c] = 1.0
+        fd = (J(th0 + eps * e) - J(th0 - eps * e)) / (2 * eps)
+        errs.append(abs(fd - grad[c]) / abs(grad[c]))
+    for _ in range(3):
+        d = rng.standard_normal((n, n))
+        d /= np.linalg.norm(d)
+        fd = (J(th0 + eps * d) - J(th0 - eps * d)) / (2 * eps)
+        errs.append(abs(fd - (grad * d).sum()) / abs((grad * d).sum()))
+    print("relative errors", errs)
+    assert max(errs) <= 1e-3, errs

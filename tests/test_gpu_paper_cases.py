@@ -241,14 +241,3 @@ def test_conservative_front_matches_oracle(case, prec):
         assert d["T"] <= 1e-11 and d["s"] <= 1e-11 and d["mask"] == 0, d
     else:
         assert d["T"] <= 1e-5 and d["s"] <= 1e-5 and d["mask"] == 0 and d["fl_rel"] <= 1e-6, d
-
-
-def test_conservative_front_has_no_replay():
-    """The replay follows the node selection of Eq. (6); the adjoint of this
-    front update is tested in test_gpu_adjoint.py."""
-    from paper_1604_03478_amd import Config, LbmError, Sim
-    sim = Sim(Config(n=8, flow=0, alpha=0.1, ste=0.1, front_scheme=1, precision="f64"))
-    sched = np.zeros(3 * 3 * 64, dtype=np.int32)
-    with pytest.raises(LbmError):
-        sim.step_replay(sched, 2)
-    sim.close()
