@@ -11,20 +11,24 @@
 // state; the adjoint is that of the forward run's own schedule.
 //
 // Per step, in reverse order of the forward operations:
-//   k_adj_front        per column: s' = s + V(g*, s): adjoint into the node
-//                      temperatures, into s and its neighbours, into T_h
-//                      (the phase switch needs nothing: f of a solid cell
-//                      is dead data and a melting cell is refilled, so the
-//                      adjoint of f is kept only where the cell is liquid
-//                      on both sides of a step)
-//   k_adj_front_gather per column: sums the neighbour contributions to s
-//   k_adj_collide      per cell: recomputes the pulled populations and
-//                      applies the transposed collision Jacobian
-//   k_adj_stream       per cell: transposed streaming as a gather over every
-//                      reader of each stored population (no atomics)
-//   k_adj_interface    per column: dependence of the interpolated
-//                      anti-bounce-back on the front through the link
-//                      fractions, and of the hot-wall condition on T_h
+//   k_adj_rows          the bound of the bulk-solid rows (one workgroup)
+//   k_adj_front         per column: s' = s + V(g*, s): adjoint into the node
+//                       temperatures, into s and its neighbours, into T_h
+//                       (the phase switch needs nothing: f of a solid cell
+//                       is dead data and a melting cell is refilled, so the
+//                       adjoint of f is kept only where the cell is liquid
+//                       on both sides of a step); k_adj_front_heat instead
+//                       for the conservative front update
+//   k_adj_collide       per cell of the rows near the front and the walls:
+//                       recomputes the pulled populations and applies the
+//                       transposed collision Jacobian; k_adj_collide_solid
+//                       the same for the bulk-solid rows, g only
+//   k_adj_stream        per cell: transposed streaming as a gather over every
+//                       reader of each stored population (no atomics)
+//   k_adj_interface     per column: dependence of the interpolated front
+//                       conditions on the front through the link fractions,
+//                       of the hot-wall condition on T_h, and the sum of the
+//                       front part left by k_adj_front
 // Adjoint arithmetic is FP64 for every storage format.  The per-cell
 // adjoints of f and g are stored in FP64 with FP64 storage and in FP32
 // otherwise (the state they are taken at is itself FP32 or coarser); the
@@ -667,10 +671,11 @@ __global__ void k_adj_front_heat(const double* __restrict__ s0, const double* __
   for (int k = 0; k < 5; ++k) out5[(size_t)k * nn + c] = 0.0;
 }
 
-__global__ void k_adj_front_gather(const double* __restrict__ own, const double* __restrict__ out5,
-                                   double* __restrict__ ls0, int n) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
-  if (x >= n) return;
+// the front part of the adjoint of s for column (x, o): its own term and the
+// contributions its four neighbours left for it in out5
+__device__ __forceinline__ double front_gather(const double* __restrict__ own,
+                                               const double* __restrict__ out5, int x, int o,
+                                               int n) {
   const size_t nn = (size_t)n * n;
   const int c = o * n + x;
   double acc = own[c] + out5[0 * nn + c];
@@ -678,7 +683,7 @@ __global__ void k_adj_front_gather(const double* __restrict__ own, const double*
   if (x < n - 1) acc += out5[2 * nn + c + 1]; else acc += out5[1 * nn + c];
   if (o > 0) acc += out5[3 * nn + c - n]; else acc += out5[4 * nn + c];
   if (o < n - 1) acc += out5[4 * nn + c + n]; else acc += out5[3 * nn + c];
-  ls0[c] = acc;
+  return acc;
 }
 
 // reverse collision of one cell (any row)
@@ -993,7 +998,8 @@ template <typename Ts, typename Lam, bool MZ, bool EXT>
 __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restrict__ s0,
                                 const int* __restrict__ cnt, const Lam* __restrict__ lgh,
                                 const Ts* __restrict__ f0, const Lam* __restrict__ lfh,
-                                const double* __restrict__ wq, double* __restrict__ ls0,
+                                const double* __restrict__ wq, const double* __restrict__ own,
+                                const double* __restrict__ out5, double* __restrict__ ls0,
                                 double* __restrict__ lth, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
@@ -1072,7 +1078,7 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
     }
   }
   if (EXT && P.flow && P.f_wall) acc += flink_column<Ts, Lam, MZ>(f0, s0, cnt, lfh, x, o, P);
-  ls0[c] += acc;
+  ls0[c] = front_gather(own, out5, x, o, n) + acc;
 }
 
 template <typename V>
@@ -1115,7 +1121,6 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
     hipLaunchKernelGGL((k_adj_front<Ts, Lam, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.s1, A.th,
                        A.ls1, lg1, A.out5, A.own, A.lth, P);
   const double* wq = A.heat ? A.wq : nullptr;
-  hipLaunchKernelGGL(k_adj_front_gather, gcol, bcol, 0, st, A.own, A.out5, A.ls0, n);
   hipLaunchKernelGGL(k_adj_rows, dim3(1), dim3(1024), 0, st, A.cnt, A.rowb, n);
   // row slots of the full reverse collision: at most one per row
   const dim3 gfront((n + bx - 1) / bx, (unsigned)(n * n < 2048 ? n * n : 2048), 1);
@@ -1126,7 +1131,7 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ, EXT>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
                      A.cmax2, A.rowb, lfh, lgh, lf0, lg0, wq, P);
   hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ, EXT>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh, f0,
-                     lfh, wq, A.ls0, A.lth, P);
+                     lfh, wq, A.own, A.out5, A.ls0, A.lth, P);
   return hipGetLastError();
 }
 

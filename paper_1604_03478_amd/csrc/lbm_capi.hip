@@ -849,7 +849,8 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
     // recompute the segment, bit for bit as the forward run
     for (int64_t t = 0; t < len; ++t) {
       k.step = (uint32_t)(a.start + (int64_t)i * a.K + t);
-      HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
+      // the front kernel leaves the counts of the next state behind
+      if (t == 0) HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
       HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin, a.cmax, c->stream));
       HIP_TRY(lbmk::launch_stream_collide(c->kind, k, a.sf[t], a.sf[t + 1], a.sg[t], a.sg[t + 1],
                                           a.cnt, a.cmin, a.cmax, a.ss[t], c->th, a.flag,
