@@ -337,3 +337,28 @@ def test_gradient_with_conservative_front_matches_finite_differences_32():
         errs.append(abs(fd - (grad * d).sum()) / abs((grad * d).sum()))
     print("relative errors", errs)
     assert max(errs) <= 1e-3, errs
+
+
+@pytest.mark.parametrize("n,s0,kw", [
+    (4, 1.5, {}), (5, 0.0, {}), (5, 5.0, {}), (7, 3.5, {}), (6, 2.3, dict(f_wall=1)),
+    (6, 2.3, dict(front_scheme=1)),
+])
+def test_gradient_matches_oracle_adjoint_edge_sizes(n, s0, kw):
+    """Minimum and ragged sizes, all-solid and all-liquid boxes, a front on
+    a cell face: the row partition of the reverse collision and streaming
+    (bulk-solid rows against rows near the front and the walls) at its
+    edges, FP64 against the oracle's reverse sweep."""
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, Sim
+    base = dict(ra=1e3, pr=1.0, ste=0.5, s0=s0, flow=1, **kw)
+    orc = OracleSim(n, heating=0, **base)
+    gpu = Sim(Config(n=n, heating="y0", precision="f64", **base))
+    th = hot_wall_field(n, seed=n)
+    orc.th[:] = th
+    gpu.set_hot_wall(th)
+    orc.record(30)
+    *_, g_ref = orc.adjoint()
+    gpu.forward_ckpt(30, 7)
+    g = gpu.adjoint(1.0)
+    scale = max(np.linalg.norm(g_ref), 1e-300)
+    assert np.linalg.norm(g - g_ref) <= 1e-10 * scale + 1e-18, (np.linalg.norm(g - g_ref), scale)
