@@ -480,7 +480,8 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
                                c->th, c->melted, c->frozen, c->flag, nullptr, nullptr, rec,
                                c->heat, c->stream));
-    HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
+    if (lbmk::uses_neighbourhood(c->kind))
+      HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
     c->cur = nx;
     c->scur = sx;
     c->step++;
@@ -851,7 +852,8 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
       k.step = (uint32_t)(a.start + (int64_t)i * a.K + t);
       // the front kernel leaves the counts of the next state behind
       if (t == 0) HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
-      HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin, a.cmax, c->stream));
+      if (lbmk::uses_neighbourhood(c->kind))
+        HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin, a.cmax, c->stream));
       HIP_TRY(lbmk::launch_stream_collide(c->kind, k, a.sf[t], a.sf[t + 1], a.sg[t], a.sg[t + 1],
                                           a.cnt, a.cmin, a.cmax, a.ss[t], c->th, a.flag,
                                           c->stream));
@@ -961,7 +963,8 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
     HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
                                c->th, c->melted, c->frozen, c->flag, e, e + 3 * nn, nullptr,
                                c->heat, c->stream));
-    HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
+    if (lbmk::uses_neighbourhood(c->kind))
+      HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
     c->cur = nx;
     c->scur = sx;
     c->step++;

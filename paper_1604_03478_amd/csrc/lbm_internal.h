@@ -47,9 +47,15 @@ size_t store_bytes(int kind);
 // takes Q * pitch * n^2 elements.
 uint32_t row_pitch(int n, int kind);
 
+// Whether the step kernel of a storage kind reads the precomputed 3x3
+// neighbourhood min / max of the liquid counts (16-bit storage); the others
+// take it from the counts themselves.
+inline bool uses_neighbourhood(int kind) { return store_bytes(kind) == 2; }
+
 // One fused stream + collide pass over all cells: reads (fs, gs), writes
 // (fd, gd).  cnt/cmin/cmax: liquid-cell count per column and its min / max
-// over the 3x3 column neighbourhood.  s: front per column.  th: hot-wall
+// over the 3x3 column neighbourhood (cmin/cmax are read only for 16-bit
+// storage, see uses_neighbourhood).  s: front per column.  th: hot-wall
 // temperature per column.  flag: set to 1 when a non-finite value appears.
 hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, void* fd,
                                  const void* gs, void* gd, const int* cnt, const int* cmin,

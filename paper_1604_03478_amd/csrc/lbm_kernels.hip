@@ -243,8 +243,30 @@ __device__ __forceinline__ void update_cell(
   const int cc = cnt[col];
   const bool liquid = a < cc;
   const bool interior = (y > 0) & (y < n - 1) & (z > 0) & (z < n - 1);
-  const bool all_liq = (a + 1) < cmin[col];
-  const bool all_sol = (a - 1) >= cmax[col];
+  // min and max of the liquid counts over the 3x3 columns around this one:
+  // read from the precomputed arrays with 16-bit storage (its kernel is held
+  // to 64 registers), else taken from the counts here, which saves the
+  // per-step neighbourhood kernel (clamped at the walls: a repeated column
+  // leaves min and max unchanged)
+  int lo, hi;
+  if constexpr (sizeof(Ts) == 2) {
+    lo = cmin[col];
+    hi = cmax[col];
+  } else {
+    const int xm = x > 0 ? x - 1 : x, xp = x < n - 1 ? x + 1 : x;
+    const int om = o > 0 ? o - 1 : o, op = o < n - 1 ? o + 1 : o;
+    const int v[8] = {cnt[om * n + xm], cnt[om * n + x], cnt[om * n + xp], cnt[o * n + xm],
+                      cnt[o * n + xp], cnt[op * n + xm], cnt[op * n + x], cnt[op * n + xp]};
+    lo = cc;
+    hi = cc;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      lo = v[k] < lo ? v[k] : lo;
+      hi = v[k] > hi ? v[k] : hi;
+    }
+  }
+  const bool all_liq = (a + 1) < lo;
+  const bool all_sol = (a - 1) >= hi;
   const bool fast = interior & (all_liq | all_sol);
 
   const Rates<C, G> r = make_rates<C, G>(P);
