@@ -75,10 +75,10 @@ typedef struct {
   double ks_kl;     /* solid / liquid conductivity (and diffusivity: equal
                        rho c) ratio of Eq. (6); 0 or 1: equal properties   */
   int front_scheme; /* 0: Eq. (6) from temperature gradients; 1: the heat the
-                       lattice carries across the interface (reading R19)  */
-  int f_wall;       /* no-slip of f at the front: 0 halfway bounce-back
-                       (reading R7); 1 bounce-back interpolated to where the
-                       front cuts each link (reading R20)                  */
+                       lattice carries across the interface                 */
+  int f_wall;       /* no-slip of f at the front: 0 halfway bounce-back; 1
+                       bounce-back interpolated to where the front cuts each
+                       link (a reading that extends the front condition of g) */
   double body_fx;   /* channel test mode only: force per unit volume along x */
 } orc_params;
 
@@ -86,9 +86,9 @@ typedef struct {
   orc_params p;
   int n;
   long long ncell;
-  /* lattice parameters (reading R5) */
+  /* lattice parameters */
   double u0, nu, alpha, s_nu, q_j, q_e, gbeta, t0, latent;
-  double kappa, alpha_s; /* conductivity ratio, solid diffusivity (reading R18) */
+  double kappa, alpha_s; /* conductivity ratio, solid diffusivity */
   double S[Q19], QR[Q7], QRs[Q7]; /* QRs: energy rates in solid cells */
   double w19[Q19], w7[Q7];
   int opp19[Q19], opp7[Q7];
@@ -145,7 +145,7 @@ static int invert(int n, const double *a, double *inv) {
   return 0;
 }
 
-/* reading R2: orthogonal D3Q19 moment basis, one polynomial in e per row */
+/* reading: orthogonal D3Q19 moment basis, one polynomial in e per row */
 static void build_m19(double M[Q19][Q19]) {
   for (int q = 0; q < Q19; ++q) {
     double ex = E19[q][0], ey = E19[q][1], ez = E19[q][2];
@@ -172,7 +172,7 @@ static void build_m19(double M[Q19][Q19]) {
   }
 }
 
-/* reading R3: orthogonal D3Q7 moment basis */
+/* reading: orthogonal D3Q7 moment basis */
 static void build_n7(double N[Q7][Q7]) {
   for (int q = 0; q < Q7; ++q) {
     double ex = E7[q][0], ey = E7[q][1], ez = E7[q][2];
@@ -187,7 +187,7 @@ static void build_n7(double N[Q7][Q7]) {
   }
 }
 
-/* reading R2: equilibrium moments of the incompressible model, rho0 = 1 */
+/* reading: equilibrium moments of the incompressible model, rho0 = 1 */
 static void meq19(double rho, double jx, double jy, double jz, double *m) {
   const double rho0 = 1.0;
   double j2 = jx * jx + jy * jy + jz * jz;
@@ -212,7 +212,7 @@ static void meq19(double rho, double jx, double jy, double jz, double *m) {
   m[18] = 0.0;
 }
 
-/* reading R3: D3Q7 equilibrium moments, c_sT^2 = 1/4 */
+/* reading: D3Q7 equilibrium moments, c_sT^2 = 1/4 */
 static void neq7(double T, double ux, double uy, double uz, double *n) {
   n[0] = T;
   n[1] = ux * T;
@@ -223,7 +223,7 @@ static void neq7(double T, double ux, double uy, double uz, double *n) {
   n[6] = 0.0;
 }
 
-/* reading R4: Guo forcing term in velocity space (to be projected by M) */
+/* reading: Guo forcing term in velocity space (to be projected by M) */
 static void guo19(const double *w, double ux, double uy, double uz, double Fx,
                   double Fy, double Fz, double *F) {
   for (int q = 0; q < Q19; ++q) {
@@ -250,7 +250,7 @@ static inline int column_of(const orc_sim *S, int x, int y, int z) {
   return S->p.heating == 0 ? z * S->n + x : y * S->n + x;
 }
 
-/* reading R1: a cell is liquid iff its centre lies strictly below the front */
+/* reading: a cell is liquid iff its centre lies strictly below the front */
 static inline int is_liquid(const orc_sim *S, const double *s, int x, int y,
                             int z) {
   if (S->p.periodic == 1) return 1;
@@ -280,7 +280,7 @@ static inline void wrap_lateral(const orc_sim *S, int *x, int *y, int *z) {
 
 int orc_sizeof_params(void) { return (int)sizeof(orc_params); }
 
-/* reading R5: lattice parameters from Ra, Pr, Ste and Ma (Eq. (7)) */
+/* reading: lattice parameters from Ra, Pr, Ste and Ma (Eq. (7)) */
 static void derive_parameters(orc_sim *S) {
   const orc_params *p = &S->p;
   int n = p->n;
@@ -305,7 +305,7 @@ static void derive_parameters(orc_sim *S) {
   S->QR[0] = 0.0;
   S->QR[1] = S->QR[2] = S->QR[3] = S->q_j;
   S->QR[4] = S->QR[5] = S->QR[6] = S->q_e;
-  /* reading R18: the solid conducts kappa times as well as the liquid and
+  /* reading: the solid conducts kappa times as well as the liquid and
    * has the same rho c, so its diffusivity is kappa alpha */
   S->kappa = p->ks_kl > 0.0 ? p->ks_kl : 1.0;
   S->alpha_s = S->kappa * S->alpha;
@@ -355,7 +355,7 @@ static double neumann_solid_T(const orc_sim *S, double y) {
                       erfc(lam * sqrt(S->alpha / S->alpha_s));
 }
 
-/* reading R10: initial state.  f at rest equilibrium, g at equilibrium of the
+/* reading: initial state.  f at rest equilibrium, g at equilibrium of the
  * seed temperature profile, solid at the initial temperature T_c (seed
  * profile 2: the subcooled solid of the two-phase Neumann solution). */
 static void initial_state(orc_sim *S) {
@@ -432,14 +432,14 @@ static int wall_type(const orc_sim *S, const double *th, int x, int y, int z,
   if (p->heating == 0) {
     if (sy < 0) { *tw = th[column_of(S, x, y, z)]; *hot = 1; return 1; }
     if (sy >= n) { *tw = p->t_c; return 1; }
-    return 0; /* reading R6: x and z walls adiabatic; top/bottom per section 1 */
+    return 0; /* reading: x and z walls adiabatic; top/bottom per section 1 */
   }
   if (sz < 0) { *tw = th[column_of(S, x, y, z)]; *hot = 1; return 1; }
   (void)sx;
   return 0;
 }
 
-/* reading R8: link fraction from cell (x,y,z) along direction e toward the
+/* reading: link fraction from cell (x,y,z) along direction e toward the
  * neighbour on the other side of the front */
 static double link_fraction(const orc_sim *S, const double *s, int x, int y,
                             int z, const int *e) {
@@ -453,12 +453,13 @@ static double link_fraction(const orc_sim *S, const double *s, int x, int y,
   return (a - s[c]) / (s[cn] - s[c]);
 }
 
-/* reading R20: fraction of the link from this cell's centre to the centre of
+/* reading: fraction of the link from this cell's centre to the centre of
  * the neighbour at offset e (a D3Q19 link, diagonal ones included) at which
  * the link meets the front.  Along the link the height on the melt axis is
  * linear, from a + 1/2 to a + 1/2 + e_a, and so is the front, from this
  * column's s to the neighbour column's; the fraction is where the two meet.
- * For the links of the energy lattice it is the link fraction of reading R8. */
+ * For the links of the energy lattice it is the link fraction of the front
+ * condition of g. */
 static double link_fraction_any(const orc_sim *S, const double *s, int x, int y,
                                 int z, const int *e) {
   int c = column_of(S, x, y, z);
@@ -496,7 +497,7 @@ static void stream_cell(const orc_sim *S, const double *f, const double *g,
     } else if (is_liquid(S, s, sx, sy, sz) == liquid) {
       gl[q] = g[q * nc + cell_index(n, sx, sy, sz)];
     } else {
-      /* reading R8: interpolated anti-bounce-back at the front, wall value
+      /* reading: interpolated anti-bounce-back at the front, wall value
        * T_m; the link direction p points from this cell toward the front */
       const int *ep = E7[po];
       double d = link_fraction(S, s, x, y, z, ep);
@@ -526,11 +527,12 @@ static void stream_cell(const orc_sim *S, const double *f, const double *g,
       } else if (in_box(n, sx, sy, sz) && is_liquid(S, s, sx, sy, sz)) {
         fl[q] = f[q * nc + cell_index(n, sx, sy, sz)];
       } else if (p->f_wall == 1 && in_box(n, sx, sy, sz)) {
-        /* reading R20: the source is solid; the wall is where the front cuts
+        /* reading: the source is solid; the wall is where the front cuts
          * the link, at fraction d from this cell's centre.  Linear
          * interpolation of the bounced population (the cell behind, x + e_q,
          * for d < 1/2; this cell's own direction q for d >= 1/2), the same
-         * weights as reading R8 without its sign change and wall value. */
+         * weights as the front condition of g without its sign change and
+         * wall value. */
         double d = link_fraction_any(S, s, x, y, z, E19[po]);
         int bx = x + E19[q][0], by = y + E19[q][1], bz = z + E19[q][2];
         wrap_lateral(S, &bx, &by, &bz);
@@ -544,7 +546,7 @@ static void stream_cell(const orc_sim *S, const double *f, const double *g,
           fl[q] = f[po * nc + i] / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * f[q * nc + i];
         }
       } else {
-        /* halfway bounce-back from walls and solid cells (reading R7) */
+        /* halfway bounce-back from walls and solid cells */
         fl[q] = f[po * nc + i];
       }
     }
@@ -697,7 +699,7 @@ typedef struct {
   double dV_ds[5];
 } vderiv;
 
-/* reading R9: front velocity of column c from Eq. (6), from the temperatures
+/* reading: front velocity of column c from Eq. (6), from the temperatures
  * of post-collision populations g and the fronts s (explicit, Jacobi). */
 static double front_velocity_column(const orc_sim *S, const double *g,
                                     const double *s, const double *th, int c,
@@ -800,7 +802,7 @@ static double front_velocity_column(const orc_sim *S, const double *g,
   return V;
 }
 
-/* reading R20 for the pin tests: fraction at which the front cuts the link
+/* for the pin tests: fraction at which the front cuts the link
  * from cell (x, y, z) to the source of its incoming direction q (D3Q19) */
 double orc_link_fraction19(const orc_sim *S, int x, int y, int z, int q) {
   return link_fraction_any(S, S->s, x, y, z, E19[S->opp19[q]]);
@@ -812,7 +814,7 @@ void orc_front_velocity(const orc_sim *S, double *V) {
     V[c] = S->p.periodic ? 0.0 : front_velocity_column(S, S->g, S->s, S->th, c, NULL);
 }
 
-/* reading R19: the energy the lattice carries into the interface during the
+/* reading: the energy the lattice carries into the interface during the
  * streaming that produced the current state, per column.  The streaming
  * moves every population of a cell to a neighbour except across a boundary
  * link, where the population the cell sends toward the wall or the front is
@@ -866,7 +868,7 @@ static void front_update(orc_sim *S) {
     S->sn[c] = v;
   }
   free(V);
-  /* reading R10: phase switch.  Newly liquid cells get the rest equilibrium of
+  /* reading: phase switch.  Newly liquid cells get the rest equilibrium of
    * f, their energy populations are kept; newly solid cells drop f. */
   for (int c = 0; c < n * n; ++c) {
     for (int a = 0; a < n; ++a) {
@@ -1068,7 +1070,7 @@ static void stream_cell_adjoint(const orc_sim *S, const double *f, const double 
       } else if (in_box(n, sx, sy, sz) && is_liquid(S, s, sx, sy, sz)) {
         lf[q * nc + cell_index(n, sx, sy, sz)] += l;
       } else if (p->f_wall == 1 && in_box(n, sx, sy, sz)) {
-        /* reading R20 reversed: the interpolation weights, and through the
+        /* the interpolated bounce-back reversed: the weights, and through the
          * link fraction d = (a - s_c) / (s_cn - s_c - e_a) the two fronts */
         const int *ep = E19[po];
         double d = link_fraction_any(S, s, x, y, z, ep);
@@ -1104,12 +1106,12 @@ static void stream_cell_adjoint(const orc_sim *S, const double *f, const double 
   }
 }
 
-/* Reverse of the front update of reading R19: s1 = clamp(s + Q(g, s) / L)
+/* Reverse of the conservative front update: s1 = clamp(s + Q(g, s) / L)
  * with Q the heat of the interface links (front_heat).  For each interface
  * link of cell x, incoming direction q across the front: its heat is
  * g_p(x) - g_q received, with g_q received from the interpolated condition of
- * reading R8.  ls1: adjoint of s1; adds into lg (adjoint of the state's g)
- * and ls. */
+ * the front (the anti-bounce-back of g).  ls1: adjoint of s1; adds into lg
+ * (adjoint of the state's g) and ls. */
 static void front_heat_adjoint(const orc_sim *S, const double *f, const double *g,
                                const double *s, const double *ls1, double *lg, double *ls) {
   const int n = S->n;
@@ -1203,7 +1205,7 @@ static void step_adjoint(const orc_sim *S, const double *f, const double *g,
           long long i = cell_of_column(S, c, a);
           for (int q = 0; q < Q19; ++q) lf1[q * nc + i] = 0.0;
         }
-  /* front update s1 = clamp(s + Q(g, s) / L) of reading R19: the heat of
+  /* front update s1 = clamp(s + Q(g, s) / L) (conservative scheme): the heat of
    * each interface link is linear in the state's g, and depends on the
    * fronts through its link fraction */
   if (!p->periodic && p->front_scheme == 1)
@@ -1308,7 +1310,7 @@ int orc_adjoint(orc_sim *S, double *lf, double *lg, double *ls, double *lth) {
 /* ------------------------------------------------------------------------ */
 /* outputs                                                                  */
 
-/* reading R11: liquid fraction from the front heights */
+/* reading: liquid fraction from the front heights */
 /* thermal energy of the cavity: sum of T over the cells (rho c = 1 per cell)
  * plus the latent heat of the melted layers, L sum of s over the columns */
 double orc_energy(const orc_sim *S) {
@@ -1477,7 +1479,7 @@ static double lagrange_derivative(int m, const double *x, const double *v, doubl
 }
 
 /* Local Nusselt number of every column on the heated wall.  The paper plots
- * it without defining it; reading R16: Nu = -H (dT/da)(a = 0) / (T_h - T_m)
+ * it without defining it; reading: Nu = -H (dT/da)(a = 0) / (T_h - T_m)
  * with H = n and a the melt-axis coordinate.  dT/da is the derivative of the
  * quadratic through the wall point (0, T_w) and the first two cell centres
  * (1/2 and 3/2) when both are liquid (s > 3/2); for a thinner liquid layer

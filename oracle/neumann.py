@@ -67,7 +67,7 @@ def seed_time(s0: float, alpha: float, ste: float) -> float:
 # Melting of a semi-infinite solid initially subcooled to T_c < T_m.  The
 # solid conducts kappa times as well as the liquid with the same rho c
 # (diffusivities alpha and alpha_s = kappa alpha; kappa = 1: equal
-# properties, reading R9).  Front s = 2 lam sqrt(alpha t); liquid
+# properties).  Front s = 2 lam sqrt(alpha t); liquid
 # T = T_h - (T_h - T_m) erf(eta) / erf(lam) with eta = y / (2 sqrt(alpha t));
 # solid T = T_c + (T_m - T_c) erfc(eta_s) / erfc(nu lam) with
 # eta_s = y / (2 sqrt(alpha_s t)), nu = sqrt(alpha / alpha_s).  The Stefan

@@ -234,7 +234,7 @@ class OracleSim:
 
     def link_fraction19(self, x: int, y: int, z: int, q: int) -> float:
         """Fraction at which the front cuts the link from cell (x, y, z) to the
-        source of its incoming D3Q19 direction q (reading R20)."""
+        source of its incoming D3Q19 direction q."""
         return float(self._lib.orc_link_fraction19(self._h, int(x), int(y), int(z), int(q)))
 
     def front_velocity(self) -> np.ndarray:

@@ -2,7 +2,7 @@
 melting at the other Stefan numbers it verifies (Ste = 0.5, 1), its two
 convection cases (Pr = 0.02, Ra = 25000 and 10000, Ste = 0.1, run to
 Fo = 1.00 and 1.57, the same lattice time), and the heated-wall Nusselt
-number it plots for them (reading R16).
+number it plots for them.
 
 Parity with the oracle is element by element at sizes the oracle finishes in
 seconds.  The convection figures (Fig. 4, Fig. 5) are not available, so the
@@ -230,7 +230,7 @@ FLUX_CASES = [
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("case", range(len(FLUX_CASES)))
 def test_conservative_front_matches_oracle(case, prec):
-    """front_scheme 1 (reading R19): the heat the streaming carried into each
+    """front_scheme 1: the heat the streaming carried into each
     column's front, gathered per column on the GPU, against the oracle (whose
     scheme conserves sum(T) + L sum(s) minus the wall heat to round-off)."""
     kw = dict(FLUX_CASES[case])

@@ -1,4 +1,4 @@
-"""Pins of the oracle's interpolated no-slip of f at the front (reading R20).
+"""Pins of the oracle's interpolated no-slip of f at the front.
 
 With f_wall = 1, a population whose source cell is solid bounces back from
 the point where the front cuts the link, at fraction d of the link from the
@@ -23,12 +23,12 @@ import pytest
 
 from oracle import OracleSim
 
-U0 = 0.1 / np.sqrt(3.0)  # Ma = 0.1 (reading R5)
+U0 = 0.1 / np.sqrt(3.0)  # Ma = 0.1
 
 
 def channel(n, s0, f_wall, heating=1, nu=1.0 / 6.0, umax=0.02):
     """Steady channel profile (mean over the lateral axes) and its closed form."""
-    ra = (U0 * n / nu) ** 2  # reading R5 with Pr = 1: nu = U0 n sqrt(Pr / Ra)
+    ra = (U0 * n / nu) ** 2  # with Pr = 1: nu = U0 n sqrt(Pr / Ra)
     fx = 8.0 * nu * umax / s0 ** 2
     o = OracleSim(n, ra=ra, pr=1.0, ste=0.0, s0=s0, heating=heating, flow=1, periodic=2,
                   f_wall=f_wall, body_fx=fx)

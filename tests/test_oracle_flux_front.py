@@ -1,4 +1,4 @@
-"""Pins of the oracle's conservative front update (reading R19): the front
+"""Pins of the oracle's conservative front update: the front
 of each column moves by the heat the lattice itself carried into the
 interface (sent minus received over the interface links of the streaming),
 divided by the latent heat L = (T_h - T_m) / Ste.  An alternative to the

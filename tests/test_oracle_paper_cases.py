@@ -1,9 +1,9 @@
 """Pins of the oracle on the paper's own workloads and their extensions: the
 heated-wall Nusselt number (the paper's Fig. 4(b) and Fig. 5(b) plot it;
-reading R16 defines it as -H dT/da at the wall over T_h - T_m), the
+read as -H dT/da at the wall over T_h - T_m), the
 conduction verification at the paper's other Stefan numbers (section 3.1:
 Ste = 0.1, 0.5, 1), and melting into a subcooled solid with equal or
-unequal phase conductivities (Eq. (6)'s solid term; readings R17, R18)
+unequal phase conductivities (Eq. (6)'s solid term)
 against the two-phase Neumann solution."""
 import math
 
@@ -51,7 +51,7 @@ def test_thin_layer_uses_the_chord_to_the_front_and_no_liquid_gives_zero():
     sim.th[:] = 1.0
     _set_profile(sim, 0, lambda a: np.full((n, n), 0.5), s=1.2)
     sim.s[0, 0] = 0.0
-    sim.s[1, 1] = 1.5  # the second centre is not liquid (strict phase, R1)
+    sim.s[1, 1] = 1.5  # the second centre is not liquid (strict phase rule)
     nu = sim.wall_nusselt()
     assert nu[0, 0] == 0.0
     assert abs(nu[1, 1] - n / 1.5) <= 1e-12
