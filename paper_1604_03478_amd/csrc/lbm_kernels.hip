@@ -249,22 +249,39 @@ __device__ __forceinline__ void update_cell(
   // per-step neighbourhood kernel (clamped at the walls: a repeated column
   // leaves min and max unchanged)
   int lo, hi;
+  int nb[9];  // counts of the 3x3 columns, [(o offset + 1) * 3 + x offset + 1]
   if constexpr (sizeof(Ts) == 2) {
     lo = cmin[col];
     hi = cmax[col];
   } else {
     const int xm = x > 0 ? x - 1 : x, xp = x < n - 1 ? x + 1 : x;
     const int om = o > 0 ? o - 1 : o, op = o < n - 1 ? o + 1 : o;
-    const int v[8] = {cnt[om * n + xm], cnt[om * n + x], cnt[om * n + xp], cnt[o * n + xm],
-                      cnt[o * n + xp], cnt[op * n + xm], cnt[op * n + x], cnt[op * n + xp]};
+    nb[0] = cnt[om * n + xm];
+    nb[1] = cnt[om * n + x];
+    nb[2] = cnt[om * n + xp];
+    nb[3] = cnt[o * n + xm];
+    nb[4] = cc;
+    nb[5] = cnt[o * n + xp];
+    nb[6] = cnt[op * n + xm];
+    nb[7] = cnt[op * n + x];
+    nb[8] = cnt[op * n + xp];
     lo = cc;
     hi = cc;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      lo = v[k] < lo ? v[k] : lo;
-      hi = v[k] > hi ? v[k] : hi;
+    for (int k = 0; k < 9; ++k) {
+      lo = nb[k] < lo ? nb[k] : lo;
+      hi = nb[k] > hi ? nb[k] : hi;
     }
   }
+  // liquid count of the in-box column at offset (dx, do) from this one: from
+  // the registers above (the offsets are constants of the unrolled loops), or
+  // loaded for 16-bit storage
+  auto count_at = [&](int dx, int dob) -> int {
+    if constexpr (sizeof(Ts) == 2)
+      return cnt[(o + dob) * n + x + dx];
+    else
+      return nb[(dob + 1) * 3 + dx + 1];
+  };
   const bool all_liq = (a + 1) < lo;
   const bool all_sol = (a - 1) >= hi;
   const bool fast = interior & (all_liq | all_sol);
@@ -337,7 +354,7 @@ __device__ __forceinline__ void update_cell(
       } else {
         const int sa = MZ ? sz : sy, so = MZ ? sy : sz;
         const int scol = so * n + sx;
-        const bool src_liq = sa < cnt[scol];
+        const bool src_liq = sa < count_at(-ex, MZ ? -ey : -ez);
         if (src_liq == liquid) {
           v = load_stream<G>(g_src(q), q * pitch + sx);
         } else {
@@ -356,8 +373,8 @@ __device__ __forceinline__ void update_cell(
             bool behind = (unsigned)bx < (unsigned)n && (unsigned)by < (unsigned)n &&
                           (unsigned)bz < (unsigned)n;
             if (behind) {
-              const int ba = MZ ? bz : by, bo = MZ ? by : bz;
-              behind = (ba < cnt[bo * n + bx]) == liquid;
+              const int ba = MZ ? bz : by;
+              behind = (ba < count_at(ex, MZ ? ey : ez)) == liquid;
             }
             if (behind) {
               const G gb = load_stream<G>(row_ptr<7>(gs, P, by, bz), p * pitch + bx);
@@ -386,7 +403,7 @@ __device__ __forceinline__ void update_cell(
         if (inb) {
           const int sa = MZ ? sz : sy, so = MZ ? sy : sz;
           scol = so * n + sx;
-          ok = sa < cnt[scol];
+          ok = sa < count_at(-ex, MZ ? -ey : -ez);
         }
         // halfway bounce-back from walls and solid cells (address select: the
         // source row of an out-of-box link is never dereferenced)
@@ -405,8 +422,8 @@ __device__ __forceinline__ void update_cell(
             bool behind = (unsigned)bx < (unsigned)n && (unsigned)by < (unsigned)n &&
                           (unsigned)bz < (unsigned)n;
             if (behind) {
-              const int ba = MZ ? bz : by, bo = MZ ? by : bz;
-              behind = ba < cnt[bo * n + bx];
+              const int ba = MZ ? bz : by;
+              behind = ba < count_at(ex, MZ ? ey : ez);
             }
             if (behind)  // else halfway bounce-back, as the front condition of g does
               v = C(2) * dl * v +
