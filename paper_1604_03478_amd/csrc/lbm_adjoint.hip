@@ -370,6 +370,20 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
   const int n = P.n;
   const uint32_t i = G.cell(x, y, z);
   const double w = 0.125, wTm = w * (P.t_m - P.tref);
+  // liquid counts of the 3x3 columns around this one, loaded together
+  // (clamped at the walls; only in-box cells are asked for); the offsets are
+  // constants of the unrolled loops, so each phase test reads a register
+  const int o = MZ ? y : z;
+  int nbc[9];
+  {
+    auto cl = [&](int v) { return v < 0 ? 0 : (v > n - 1 ? n - 1 : v); };
+#pragma unroll
+    for (int k = 0; k < 9; ++k) nbc[k] = cnt[cl(o + k / 3 - 1) * n + cl(x + k % 3 - 1)];
+  }
+  auto liq = [&](int X, int Y, int Z) -> bool {
+    return melt_of<MZ>(Y, Z) < nbc[((MZ ? Y : Z) - o + 1) * 3 + (X - x) + 1];
+  };
+#pragma unroll
   for (int q = 0; q < 7; ++q) {
     const int ex = ex7(q), ey = ey7(q), ez = ez7(q), p = opp7(q);
     const int sx = x - ex, sy = y - ey, sz = z - ez;
@@ -383,14 +397,14 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
         v = -gp + 2.0 * w * (P.t_c - P.tref);
       else
         v = gp;
-    } else if (liquid_at<MZ>(cnt, sx, sy, sz, n) == liquid) {
+    } else if (liq(sx, sy, sz) == liquid) {
       v = sv<7>(g, P, q, G.cell(sx, sy, sz));
     } else {
       const double d = link_delta<MZ>(s, x, y, z, -ex, -ey, -ez, n);
       const double gp = sv<7>(g, P, p, i);
       if (d < 0.5) {
         const int bx = x + ex, by = y + ey, bz = z + ez;
-        const bool behind = G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == liquid;
+        const bool behind = G.in(bx, by, bz) && liq(bx, by, bz) == liquid;
         v = behind ? -(2.0 * d * gp + (1.0 - 2.0 * d) * sv<7>(g, P, p, G.cell(bx, by, bz))) + 2.0 * wTm
                    : -gp + 2.0 * wTm;
       } else {
@@ -400,17 +414,18 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
     M.add_g(v);
   }
   if (FLOW && liquid) {
+#pragma unroll
     for (int q = 1; q < 19; ++q) {
       const int sx = x - ex19(q), sy = y - ey19(q), sz = z - ez19(q);
       const bool inb = G.in(sx, sy, sz);
-      const bool ok = inb && liquid_at<MZ>(cnt, sx, sy, sz, n);
+      const bool ok = inb && liq(sx, sy, sz);
       double v = ok ? sv<19>(f, P, q, G.cell(sx, sy, sz)) : sv<19>(f, P, opp19(q), i);
       if (EXT && P.f_wall && inb && !ok) {  // interpolated no-slip at the front
         double num, den;
         const double d = frac19<MZ>(s, x, y, z, q, n, num, den);
         if (d < 0.5) {
           const int bx = x + ex19(q), by = y + ey19(q), bz = z + ez19(q);
-          if (G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n))
+          if (G.in(bx, by, bz) && liq(bx, by, bz))
             v = 2.0 * d * v + (1.0 - 2.0 * d) * sv<19>(f, P, opp19(q), G.cell(bx, by, bz));
         } else {
           v = v / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * sv<19>(f, P, q, i);
@@ -782,13 +797,38 @@ __global__ __launch_bounds__(256) void k_adj_stream(
     return;
   }
 
+  // The liquid counts the phase tests below ask for, loaded together: the
+  // 3x3 columns around this one and the four at distance two along the
+  // lateral axes (indices clamped at the walls; only in-box columns are
+  // asked for).  The offsets are constants of the unrolled loops, so each
+  // test reads a register.
+  const int o = MZ ? y : z;
+  int nbc[13];
+  {
+    auto cl = [&](int v) { return v < 0 ? 0 : (v > n - 1 ? n - 1 : v); };
+#pragma unroll
+    for (int k = 0; k < 9; ++k) nbc[k] = cnt[cl(o + k / 3 - 1) * n + cl(x + k % 3 - 1)];
+    nbc[9] = cnt[o * n + cl(x - 2)];
+    nbc[10] = cnt[o * n + cl(x + 2)];
+    nbc[11] = cnt[cl(o - 2) * n + x];
+    nbc[12] = cnt[cl(o + 2) * n + x];
+  }
+  // phase of the in-box cell (X, Y, Z) within those columns
+  auto liq = [&](int X, int Y, int Z) -> bool {
+    const int dx = X - x, dob = (MZ ? Y : Z) - o;
+    const int k = dx == -2 ? 9 : dx == 2 ? 10 : dob == -2 ? 11 : dob == 2 ? 12
+                                                                      : (dob + 1) * 3 + dx + 1;
+    return melt_of<MZ>(Y, Z) < nbc[k];
+  };
+
+#pragma unroll
   for (int p = 0; p < 7; ++p) {
     const int ex = ex7(p), ey = ey7(p), ez = ez7(p), q = opp7(p);
     double acc = 0.0;
     // (a) regular pull of direction p by the neighbour x + e_p
     const int yx = x + ex, yy = y + ey, yz = z + ez;
     const bool yin = G.in(yx, yy, yz);
-    const bool ysame = yin && liquid_at<MZ>(cnt, yx, yy, yz, n) == L;
+    const bool ysame = yin && liq(yx, yy, yz) == L;
     if (ysame) acc += LG(p, G.cell(yx, yy, yz));
     // (b) this cell's direction q = opp(p), whose source x + e_p is a wall or
     //     across the front
@@ -801,7 +841,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
         const double d = link_delta<MZ>(s0, x, y, z, ex, ey, ez, n);
         if (d < 0.5) {
           const int bx = x - ex, by = y - ey, bz = z - ez;
-          const bool behind = G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L;
+          const bool behind = G.in(bx, by, bz) && liq(bx, by, bz) == L;
           acc += (behind ? -2.0 * d : -1.0) * LG(q, i);
           // conservative front: the heat of this link, sent minus received
           if (EXT && wq)
@@ -814,7 +854,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
       // (c) this cell's direction p itself, when its source x - e_p is across
       //     the front with a link fraction >= 1/2
       const int sx = x - ex, sy = y - ey, sz = z - ez;
-      if (G.in(sx, sy, sz) && liquid_at<MZ>(cnt, sx, sy, sz, n) != L) {
+      if (G.in(sx, sy, sz) && liq(sx, sy, sz) != L) {
         const double d = link_delta<MZ>(s0, x, y, z, -ex, -ey, -ez, n);
         if (d >= 0.5) {
           acc += (2.0 * d - 1.0) / (2.0 * d) * LG(p, i);
@@ -827,7 +867,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
       //     cell behind it)
       if (ysame) {
         const int tx = yx + ex, ty = yy + ey, tz = yz + ez;
-        if (G.in(tx, ty, tz) && liquid_at<MZ>(cnt, tx, ty, tz, n) != L) {
+        if (G.in(tx, ty, tz) && liq(tx, ty, tz) != L) {
           const double d = link_delta<MZ>(s0, yx, yy, yz, ex, ey, ez, n);
           if (d < 0.5) {
             acc += -(1.0 - 2.0 * d) * LG(q, G.cell(yx, yy, yz));
@@ -841,9 +881,10 @@ __global__ __launch_bounds__(256) void k_adj_stream(
   // adjoint of f before the step: only liquid cells read their f (solid
   // cells hold dead data, whose adjoint is zero and is not stored)
   if (FLOW && L && !(EXT && P.f_wall)) {
+#pragma unroll
     for (int p = 0; p < 19; ++p) {
       const int yx = x + ex19(p), yy = y + ey19(p), yz = z + ez19(p);
-      const bool pulled = G.in(yx, yy, yz) && liquid_at<MZ>(cnt, yx, yy, yz, n);
+      const bool pulled = G.in(yx, yy, yz) && liq(yx, yy, yz);
       lf0[(size_t)p * nc + i] =
           pulled ? lfh[(size_t)p * nc + G.cell(yx, yy, yz)] : lfh[(size_t)opp19(p) * nc + i];
     }
