@@ -22,7 +22,8 @@
 //   k_adj_collide       per cell of the rows near the front and the walls:
 //                       recomputes the pulled populations and applies the
 //                       transposed collision Jacobian; k_adj_collide_solid
-//                       the same for the bulk-solid rows, g only
+//                       the same for the bulk-solid rows, g only and
+//                       without the state (linear at rest)
 //   k_adj_stream        per cell: transposed streaming as a gather over every
 //                       reader of each stored population (no atomics)
 //   k_adj_interface     per column: dependence of the interpolated front
@@ -754,18 +755,19 @@ __global__ __launch_bounds__(256) void k_adj_collide(
 
 // The bulk solid rows k_adj_collide leaves out: only the energy distribution
 // is reversed, with few registers, so these rows (most of a melting state)
-// run at full occupancy.
-template <typename Ts, typename Lam, bool MZ>
+// run at full occupancy.  A solid cell is at rest, and at u = 0 the heat
+// collision is linear in g: its transpose needs no state, so the kernel reads
+// the 7 adjoints and writes 7 (56 B per cell in FP32).
+template <typename Lam, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_collide_solid(
-    const Ts* __restrict__ g0, const int* __restrict__ rowb, const Lam* __restrict__ lg1,
-    Lam* __restrict__ lgh, KParams P) {
+    const int* __restrict__ rowb, const Lam* __restrict__ lg1, Lam* __restrict__ lgh,
+    KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, rowb[0], n)) return;
   const size_t nc = P.ncell;
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
-  Macro M;
-  pull_fast<Ts, false>(static_cast<const Ts*>(nullptr), g0, x, y, z, false, P, M);
+  const Macro M;  // T enters only the flow part, which a solid cell skips
   double lfo[19] = {}, lgo[7], lfl[19], lgl[7];
   for (int q = 0; q < 7; ++q) lgo[q] = (double)lg1[(size_t)q * nc + i];
   collide_adjoint<false>(M, false, P, lfo, lgo, lfl, lgl);
@@ -1167,8 +1169,7 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   const dim3 gfront((n + bx - 1) / bx, (unsigned)(n * n < 2048 ? n * n : 2048), 1);
   hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ, EXT>), gfront, bcell, 0, st, f0, g0, A.s0,
                      A.s1, A.th, A.cnt, A.cmin2, A.cmax2, A.rowb, lf1, lg1, lfh, lgh, P);
-  hipLaunchKernelGGL((k_adj_collide_solid<Ts, Lam, MZ>), gcell, bcell, 0, st, g0, A.rowb, lg1,
-                     lgh, P);
+  hipLaunchKernelGGL((k_adj_collide_solid<Lam, MZ>), gcell, bcell, 0, st, A.rowb, lg1, lgh, P);
   hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ, EXT>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
                      A.cmax2, A.rowb, lfh, lgh, lf0, lg0, wq, P);
   hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ, EXT>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh, f0,
