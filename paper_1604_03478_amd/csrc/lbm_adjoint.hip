@@ -638,8 +638,7 @@ __device__ void front_der(const Ts* g1, const double* s, const double* th, int c
 
 template <typename Ts, typename Lam, bool FLOW, bool MZ>
 __global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict__ g1,
-                            const double* __restrict__ s1, const double* __restrict__ th,
-                            const double* __restrict__ ls1, Lam* __restrict__ lg1,
+                            const double* __restrict__ th, const double* __restrict__ ls1, Lam* __restrict__ lg1,
                             double* __restrict__ out5, double* __restrict__ own,
                             double* __restrict__ lth, KParams P) {
   const int n = P.n;
@@ -649,7 +648,7 @@ __global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict_
   const size_t nc = P.ncell, nn = (size_t)n * n;
   VDer d;
   front_der<Ts, MZ>(g1, s0, th, c, P, d);
-  const double v = s0[c] + d.V;
+  const double v = s0[c] + d.V;  // the unclamped update, recomputed as the step did
   const double l = ls1[c];
   if (v < 0.0 || v > (double)n) {  // clamped: no dependence
     own[c] = 0.0;
@@ -659,8 +658,8 @@ __global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict_
   own[c] = l;
   for (int k = 0; k < d.nnode; ++k)
     for (int q = 0; q < 7; ++q) {
-      Lam& v = lg1[(size_t)q * nc + d.node[k]];
-      v = (Lam)((double)v + l * d.dT[k]);
+      Lam& lv = lg1[(size_t)q * nc + d.node[k]];
+      lv = (Lam)((double)lv + l * d.dT[k]);
     }
   for (int j = 0; j < 5; ++j) out5[j * nn + c] = l * d.ds[j];
   lth[c] += l * d.dth;
@@ -1161,8 +1160,8 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
     hipLaunchKernelGGL(k_adj_front_heat, gcol, bcol, 0, st, A.s0, A.heat, A.ls1, A.wq, A.own,
                        A.out5, P);
   else
-    hipLaunchKernelGGL((k_adj_front<Ts, Lam, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.s1, A.th,
-                       A.ls1, lg1, A.out5, A.own, A.lth, P);
+    hipLaunchKernelGGL((k_adj_front<Ts, Lam, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.th, A.ls1,
+                       lg1, A.out5, A.own, A.lth, P);
   const double* wq = A.heat ? A.wq : nullptr;
   hipLaunchKernelGGL(k_adj_rows, dim3(1), dim3(1024), 0, st, A.cnt, A.rowb, n);
   // row slots of the full reverse collision: at most one per row
