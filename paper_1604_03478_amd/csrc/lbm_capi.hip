@@ -430,7 +430,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
       hipMemsetAsync(c->flag, 0, sizeof(int), c->stream))
     return dev(fail(LBM_EDEVICE, "initial upload failed"));
   if ((rc = refresh_masks(c))) return bail(rc);
-  if (lbmk::launch_init(c->kind, k, c->cnt, c->seedT, c->f[0], c->g[0], c->stream) != hipSuccess)
+  if (lbmk::launch_init(c->kind, k, c->seedT, c->f[0], c->g[0], c->stream) != hipSuccess)
     return bail(fail(LBM_EDEVICE, "init kernel launch failed"));
   if (hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(fail(LBM_EDEVICE, "initialisation failed on the device"));

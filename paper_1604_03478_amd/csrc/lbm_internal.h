@@ -86,8 +86,8 @@ hipError_t launch_counts(const KParams& P, const double* s, int* cnt, hipStream_
 
 // Initial state: f at rest, g at equilibrium of seedT[a] (a the melt-axis
 // coordinate; the host fills solid heights with t_c or the subcooled profile).
-hipError_t launch_init(int kind, const KParams& P, const int* cnt, const double* seedT, void* f,
-                       void* g, hipStream_t st);
+hipError_t launch_init(int kind, const KParams& P, const double* seedT, void* f, void* g,
+                       hipStream_t st);
 
 // Macroscopic fields in FP64 (any output may be null).
 hipError_t launch_fields(int kind, const KParams& P, const void* f, const void* g, const int* cnt,

@@ -652,8 +652,8 @@ __global__ void k_neighbourhood(const int* __restrict__ cnt, int* __restrict__ c
 
 // --------------------------------------------------------------- init, fields
 template <typename Ts, bool MZ>
-__global__ void k_init(const int* __restrict__ cnt, const double* __restrict__ seedT,
-                       Ts* __restrict__ f, Ts* __restrict__ g, KParams P) {
+__global__ void k_init(const double* __restrict__ seedT, Ts* __restrict__ f, Ts* __restrict__ g,
+                       KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
@@ -836,15 +836,14 @@ hipError_t front_dispatch(const KParams& P, const double* s_old, double* s_new, 
 }
 
 template <typename Ts>
-hipError_t init_dispatch(const KParams& P, const int* cnt, const double* seedT, void* f, void* g,
-                         hipStream_t st) {
+hipError_t init_dispatch(const KParams& P, const double* seedT, void* f, void* g, hipStream_t st) {
   dim3 block(64, 1, 1);
   dim3 grid((P.n + 63) / 64, P.n, P.n);
   if (P.melt_z)
-    hipLaunchKernelGGL((k_init<Ts, true>), grid, block, 0, st, cnt, seedT, static_cast<Ts*>(f),
+    hipLaunchKernelGGL((k_init<Ts, true>), grid, block, 0, st, seedT, static_cast<Ts*>(f),
                        static_cast<Ts*>(g), P);
   else
-    hipLaunchKernelGGL((k_init<Ts, false>), grid, block, 0, st, cnt, seedT, static_cast<Ts*>(f),
+    hipLaunchKernelGGL((k_init<Ts, false>), grid, block, 0, st, seedT, static_cast<Ts*>(f),
                        static_cast<Ts*>(g), P);
   return hipGetLastError();
 }
@@ -955,9 +954,9 @@ hipError_t launch_counts(const KParams& P, const double* s, int* cnt, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_init(int kind, const KParams& P, const int* cnt, const double* seedT, void* f,
-                       void* g, hipStream_t st) {
-#define CALL(T) init_dispatch<T>(P, cnt, seedT, f, g, st)
+hipError_t launch_init(int kind, const KParams& P, const double* seedT, void* f, void* g,
+                       hipStream_t st) {
+#define CALL(T) init_dispatch<T>(P, seedT, f, g, st)
   switch (kind) {
     case kF64: return CALL(double);
     case kF32: return CALL(float);
