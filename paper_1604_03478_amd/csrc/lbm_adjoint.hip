@@ -509,9 +509,12 @@ __device__ void collide_adjoint(const Macro& M, bool liquid, const KParams& P,
 }
 
 // ---- front velocity and its derivatives (node selection frozen) ----
+// Every array below is indexed by constants once the loops are unrolled, so
+// the whole record stays in registers.  Node slots 0 and 1 hold the liquid
+// side, 2 and 3 the solid side; a slot taken by a wall point is not used.
 struct VDer {
   double V;
-  int nnode;
+  bool use[4];
   uint32_t node[4];
   double dT[4];
   double dth;
@@ -519,32 +522,36 @@ struct VDer {
   double ds[5];
 };
 
-__device__ __forceinline__ double slope_der(int k, const double* xi, const double* Tv, double tm,
-                                            double* dT, double* dxi) {
-  dT[0] = dT[1] = dxi[0] = dxi[1] = 0.0;
+// Slope at xi = 0 of the one-sided quadratic through (0, tm), (xi0, T0),
+// (xi1, T1) (k = 2), or of the chord to (xi0, T0) (k = 1), with its
+// derivatives with respect to the node temperatures and distances.
+__device__ __forceinline__ double slope_der(int k, double xi0, double xi1, double T0, double T1,
+                                            double tm, double& dT0, double& dT1, double& dxi0,
+                                            double& dxi1) {
+  dT0 = dT1 = dxi0 = dxi1 = 0.0;
   if (k >= 2) {
-    const double A = Tv[0] - tm, B = Tv[1] - tm;
-    const double D = xi[0] * xi[1] * (xi[1] - xi[0]);
-    const double num = A * xi[1] * xi[1] - B * xi[0] * xi[0];
-    const double dD0 = xi[1] * xi[1] - 2.0 * xi[0] * xi[1];
-    const double dD1 = 2.0 * xi[0] * xi[1] - xi[0] * xi[0];
-    dT[0] = xi[1] * xi[1] / D;
-    dT[1] = -xi[0] * xi[0] / D;
-    dxi[0] = (-2.0 * B * xi[0] * D - num * dD0) / (D * D);
-    dxi[1] = (2.0 * A * xi[1] * D - num * dD1) / (D * D);
+    const double A = T0 - tm, B = T1 - tm;
+    const double D = xi0 * xi1 * (xi1 - xi0);
+    const double num = A * xi1 * xi1 - B * xi0 * xi0;
+    const double dD0 = xi1 * xi1 - 2.0 * xi0 * xi1;
+    const double dD1 = 2.0 * xi0 * xi1 - xi0 * xi0;
+    dT0 = xi1 * xi1 / D;
+    dT1 = -xi0 * xi0 / D;
+    dxi0 = (-2.0 * B * xi0 * D - num * dD0) / (D * D);
+    dxi1 = (2.0 * A * xi1 * D - num * dD1) / (D * D);
     return num / D;
   }
-  if (k == 1 && xi[0] > 0.0) {
-    dT[0] = 1.0 / xi[0];
-    dxi[0] = -(Tv[0] - tm) / (xi[0] * xi[0]);
-    return (Tv[0] - tm) / xi[0];
+  if (k == 1 && xi0 > 0.0) {
+    dT0 = 1.0 / xi0;
+    dxi0 = -(T0 - tm) / (xi0 * xi0);
+    return (T0 - tm) / xi0;
   }
   return 0.0;
 }
 
 template <typename Ts, bool MZ>
-__device__ void front_der(const Ts* g1, const double* s, const double* th, int c,
-                          const KParams& P, VDer& d) {
+__device__ __forceinline__ void front_der(const Ts* g1, const double* s, const double* th, int c,
+                                          const KParams& P, VDer& d) {
   const int n = P.n;
   const double sc = s[c];
   const int cnt = count_liquid(sc, n);
@@ -553,48 +560,60 @@ __device__ void front_der(const Ts* g1, const double* s, const double* th, int c
     for (int q = 0; q < 7; ++q) acc += sv<7>(g1, P, q, i);
     return acc + P.tref;
   };
-  double xi[2], Tv[2], dT[2], dxi[2];
-  uint32_t nd[2] = {0, 0};
-  int k = 0, wall = -1;
+  // liquid side: the nearest centres at distance >= 1/2 toward the heated
+  // wall, then the wall itself
+  double xi0 = 0.0, xi1 = 0.0, T0 = 0.0, T1 = 0.0;
+  uint32_t nd0 = 0, nd1 = 0;
+  int k = 0, wall_l = -1;
   for (int a = cnt - 1; a >= 0 && k < 2; --a) {
     const double dd = sc - (a + 0.5);
     if (dd >= 0.5) {
-      xi[k] = dd;
-      nd[k] = cell_in_column<MZ>(c, a, n);
-      Tv[k] = Tcell(nd[k]);
+      const uint32_t node = cell_in_column<MZ>(c, a, n);
+      const double T = Tcell(node);
+      if (k == 0) { xi0 = dd; nd0 = node; T0 = T; } else { xi1 = dd; nd1 = node; T1 = T; }
       ++k;
     }
   }
   if (k < 2) {
-    xi[k] = sc;
-    Tv[k] = th[c];
-    wall = k;
+    if (k == 0) { xi0 = sc; T0 = th[c]; } else { xi1 = sc; T1 = th[c]; }
+    wall_l = k;
     ++k;
   }
   const int kl = k;
-  double dTl[2], dxil[2];
-  const double sl = slope_der(kl, xi, Tv, P.t_m, dTl, dxil);
-  const uint32_t ndl[2] = {nd[0], nd[1]};
-  const int wall_l = wall;
+  double dTl0, dTl1, dxil0, dxil1;
+  const double sl = slope_der(kl, xi0, xi1, T0, T1, P.t_m, dTl0, dTl1, dxil0, dxil1);
+  d.use[0] = kl > 0 && wall_l != 0;
+  d.use[1] = kl > 1 && wall_l != 1;
+  d.node[0] = nd0;
+  d.node[1] = nd1;
+
+  // solid side: centres beyond the front, then the cold wall (melt axis y)
+  xi0 = xi1 = T0 = T1 = 0.0;
+  nd0 = nd1 = 0;
   k = 0;
-  wall = -1;
+  int wall_s = -1;
   for (int a = cnt; a < n && k < 2; ++a) {
     const double dd = (a + 0.5) - sc;
     if (dd >= 0.5) {
-      xi[k] = dd;
-      nd[k] = cell_in_column<MZ>(c, a, n);
-      Tv[k] = Tcell(nd[k]);
+      const uint32_t node = cell_in_column<MZ>(c, a, n);
+      const double T = Tcell(node);
+      if (k == 0) { xi0 = dd; nd0 = node; T0 = T; } else { xi1 = dd; nd1 = node; T1 = T; }
       ++k;
     }
   }
   if (k < 2 && !MZ) {
-    xi[k] = n - sc;
-    Tv[k] = P.t_c;
-    wall = k;
+    if (k == 0) { xi0 = n - sc; T0 = P.t_c; } else { xi1 = n - sc; T1 = P.t_c; }
+    wall_s = k;
     ++k;
   }
   const int ks = k;
-  const double ss = slope_der(ks, xi, Tv, P.t_m, dT, dxi);
+  double dTs0, dTs1, dxis0, dxis1;
+  const double ss = slope_der(ks, xi0, xi1, T0, T1, P.t_m, dTs0, dTs1, dxis0, dxis1);
+  d.use[2] = ks > 0 && wall_s != 0;
+  d.use[3] = ks > 1 && wall_s != 1;
+  d.node[2] = nd0;
+  d.node[3] = nd1;
+
   const int x = c % n, o = c / n;
   const int cxp = o * n + (x + 1 < n ? x + 1 : x), cxm = o * n + (x > 0 ? x - 1 : x);
   const int cop = (o + 1 < n ? o + 1 : o) * n + x, com = (o > 0 ? o - 1 : o) * n + x;
@@ -602,24 +621,14 @@ __device__ void front_der(const Ts* g1, const double* s, const double* th, int c
   const double Pf = 1.0 + dsx * dsx + dso * dso;
   const double K = P.alpha * P.ste / P.dT, kap = P.kappa;  // Eq. (6): kappa on the solid side
   d.V = Pf * K * (kap * ss + sl);
-  d.nnode = 0;
-  d.dth = 0.0;
-  for (int j = 0; j < kl; ++j) {
-    if (j == wall_l) {
-      d.dth += Pf * K * dTl[j];
-    } else {
-      d.node[d.nnode] = ndl[j];
-      d.dT[d.nnode++] = Pf * K * dTl[j];
-    }
-  }
-  for (int j = 0; j < ks; ++j) {
-    if (j == wall) continue;
-    d.node[d.nnode] = nd[j];
-    d.dT[d.nnode++] = Pf * K * kap * dT[j];
-  }
-  double dself = 0.0;
-  for (int j = 0; j < kl; ++j) dself += dxil[j];
-  for (int j = 0; j < ks; ++j) dself -= kap * dxi[j];
+  d.dT[0] = Pf * K * dTl0;
+  d.dT[1] = Pf * K * dTl1;
+  d.dT[2] = Pf * K * kap * dTs0;
+  d.dT[3] = Pf * K * kap * dTs1;
+  // the hot-wall temperature enters through the liquid side's wall point
+  d.dth = wall_l == 0 ? Pf * K * dTl0 : (wall_l == 1 ? Pf * K * dTl1 : 0.0);
+  // unused slopes and distances are zero, so every sum keeps its terms in order
+  const double dself = dxil0 + dxil1 - kap * dxis0 - kap * dxis1;
   const double KG = K * (kap * ss + sl);
   d.col[0] = c;
   d.ds[0] = Pf * K * dself;
@@ -637,7 +646,7 @@ __device__ void front_der(const Ts* g1, const double* s, const double* th, int c
 // Adjoint buffers are dense FP64 arrays [q][n^3] (populations) and [n^2].
 
 template <typename Ts, typename Lam, bool FLOW, bool MZ>
-__global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict__ g1,
+__global__ __launch_bounds__(64) void k_adj_front(const double* __restrict__ s0, const Ts* __restrict__ g1,
                             const double* __restrict__ th, const double* __restrict__ ls1, Lam* __restrict__ lg1,
                             double* __restrict__ out5, double* __restrict__ own,
                             double* __restrict__ lth, KParams P) {
@@ -656,11 +665,13 @@ __global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict_
     return;
   }
   own[c] = l;
-  for (int k = 0; k < d.nnode; ++k)
-    for (int q = 0; q < 7; ++q) {
-      Lam& lv = lg1[(size_t)q * nc + d.node[k]];
-      lv = (Lam)((double)lv + l * d.dT[k]);
-    }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (d.use[k])
+      for (int q = 0; q < 7; ++q) {
+        Lam& lv = lg1[(size_t)q * nc + d.node[k]];
+        lv = (Lam)((double)lv + l * d.dT[k]);
+      }
   for (int j = 0; j < 5; ++j) out5[j * nn + c] = l * d.ds[j];
   lth[c] += l * d.dth;
 }
@@ -672,7 +683,7 @@ __global__ void k_adj_front(const double* __restrict__ s0, const Ts* __restrict_
 // the direct term of s, and the weight by which each column's interface heat
 // enters J (zero where the front was clamped).  out5 is cleared so that the
 // gather below adds nothing else.
-__global__ void k_adj_front_heat(const double* __restrict__ s0, const double* __restrict__ heat,
+__global__ __launch_bounds__(64) void k_adj_front_heat(const double* __restrict__ s0, const double* __restrict__ heat,
                                  const double* __restrict__ ls1, double* __restrict__ wq,
                                  double* __restrict__ own, double* __restrict__ out5, KParams P) {
   const int n = P.n;
@@ -1037,7 +1048,7 @@ __device__ double flink_column(const Ts* f0, const double* s0, const int* cnt, c
 }
 
 template <typename Ts, typename Lam, bool MZ, bool EXT>
-__global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restrict__ s0,
+__global__ __launch_bounds__(64) void k_adj_interface(const Ts* __restrict__ g0, const double* __restrict__ s0,
                                 const int* __restrict__ cnt, const Lam* __restrict__ lgh,
                                 const Ts* __restrict__ f0, const Lam* __restrict__ lfh,
                                 const double* __restrict__ wq, const double* __restrict__ own,
@@ -1055,21 +1066,26 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
     const int qin = MZ ? 5 : 3;  // +z or +y: pulled from the heated wall
     lth[c] += 2.0 * 0.125 * (double)lgh[(size_t)qin * nc + i];
   }
-  // lateral neighbour columns (in the box)
-  int nb[4], nbx[4], nbo[4], k = 0;
+  // lateral neighbour columns, one fixed slot each (constant indices once the
+  // loops are unrolled, so the slots live in registers); ok: in the box
+  int nb[4], nbx[4], nbo[4], nbc[4];
+  bool ok[4];
   const int dx[4] = {1, -1, 0, 0}, dob[4] = {0, 0, 1, -1};
+#pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int xx = x + dx[j], oo = o + dob[j];
-    if (xx < 0 || xx >= n || oo < 0 || oo >= n) continue;
-    nb[k] = oo * n + xx;
-    nbx[k] = xx;
-    nbo[k] = oo;
-    ++k;
+    ok[j] = xx >= 0 && xx < n && oo >= 0 && oo < n;
+    nbx[j] = xx;
+    nbo[j] = oo;
+    nb[j] = ok[j] ? oo * n + xx : c;
+    nbc[j] = cnt[nb[j]];
   }
   int lo = cnt[c], hi = cnt[c];
-  for (int j = 0; j < k; ++j) {
-    lo = cnt[nb[j]] < lo ? cnt[nb[j]] : lo;
-    hi = cnt[nb[j]] > hi ? cnt[nb[j]] : hi;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (!ok[j]) continue;
+    lo = nbc[j] < lo ? nbc[j] : lo;
+    hi = nbc[j] > hi ? nbc[j] : hi;
   }
   lo = lo - 1 < 0 ? 0 : lo - 1;
   hi = hi > n - 1 ? n - 1 : hi;
@@ -1100,9 +1116,11 @@ __global__ void k_adj_interface(const Ts* __restrict__ g0, const double* __restr
     }
     // (ii) lateral links of the neighbours' cells at height a that point into
     //      this column
-    for (int j = 0; j < k; ++j) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (!ok[j]) continue;
       const int cx = nbx[j], cy = MZ ? nbo[j] : a, cz = MZ ? a : nbo[j];
-      const bool L = a < cnt[nb[j]];
+      const bool L = a < nbc[j];
       if ((a < cnt[c]) == L) continue;
       // incoming direction of the neighbour whose source is this column
       const int ddx = x - nbx[j], ddo = o - nbo[j];
