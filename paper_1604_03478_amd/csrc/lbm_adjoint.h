@@ -25,7 +25,7 @@ struct AdjointStep {
   const int* cnt;    // liquid counts of state t
   const int* cmin2;  // their min / max over the 5x5 columns around each column
   const int* cmax2;
-  int* rowb;         // one int: the bound of the bulk-solid row partition
+  const int* rowb;   // one int: the largest liquid count of state t
   void* lf1;
   void* lg1;
   const double* ls1;
@@ -43,6 +43,12 @@ struct AdjointStep {
   double* wq;
 };
 hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A, hipStream_t st);
+// Liquid counts of the fronts s (cnt), their min / max over the 5x5 columns
+// around each column (cmin2, cmax2) and the largest count, merged into
+// rmax[slot], which must be zero; rmax[1 - slot] is cleared for the next
+// reverse step.  rmax holds two ints.
+hipError_t launch_adj_partition(const KParams& P, const double* s, int* cnt, int* cmin2,
+                                int* cmax2, int* rmax, int slot, hipStream_t st);
 hipError_t launch_fill(double* v, size_t count, double value, hipStream_t st);
 
 // Bytes of one per-cell adjoint value for a storage kind, and a fill of such

@@ -11,7 +11,9 @@
 // state; the adjoint is that of the forward run's own schedule.
 //
 // Per step, in reverse order of the forward operations:
-//   k_adj_rows          the bound of the bulk-solid rows (one workgroup)
+//   k_adj_partition     per column: liquid counts of state t, their extremes
+//                       over 5x5 columns, and the largest count (the bound of
+//                       the bulk-solid rows); launched by the host loop
 //   k_adj_front         per column: s' = s + V(g*, s): adjoint into the node
 //                       temperatures, into s and its neighbours, into T_h
 //                       (the phase switch needs nothing: f of a solid cell
@@ -286,28 +288,66 @@ __device__ __forceinline__ void front_row(int r, int A, int n, int& a, int& o) {
   }
 }
 
-// the bound A of the row partition, from the liquid counts of state t (one
-// workgroup of 1024 lanes, eight independent loads per lane in flight)
-__global__ __launch_bounds__(1024) void k_adj_rows(const int* __restrict__ cnt,
-                                                   int* __restrict__ rowb, int n) {
-  __shared__ int part[1024];
-  const int nn = n * n;
-  int m = 0;
-  for (int c0 = threadIdx.x; c0 < nn; c0 += 8 * 1024) {
-    int v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = c0 + u * 1024 < nn ? cnt[c0 + u * 1024] : 0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) m = v[u] > m ? v[u] : m;
+// The bound A of the row partition from the largest liquid count m of the
+// lattice.
+__device__ __forceinline__ int row_bound(int m, int n) { return m + 2 < n - 1 ? m + 2 : n - 1; }
+
+// Phase bookkeeping of state t in one pass over the columns: the liquid count
+// of each column (from its front), the minimum and maximum count over the 5x5
+// columns around it (the columns in the box), and the largest count of the
+// lattice.  A workgroup covers kPartRows x 64 columns; its largest count is
+// reduced in LDS and merged into rmax[p] by one atomic maximum (device-scope
+// atomics on one address serialize, so there is one per workgroup), so
+// rmax[p] must be zero at launch.  The same launch clears rmax[1 - p] for the
+// next reverse step: every kernel that read it ran earlier on the same stream
+// and has finished.
+constexpr int kPartRows = 8;
+__global__ __launch_bounds__(64 * kPartRows) void k_adj_partition(
+    const double* __restrict__ s, int* __restrict__ cnt, int* __restrict__ cmin2,
+    int* __restrict__ cmax2, int* __restrict__ rmax, int p, int n) {
+  // counts of the (kPartRows + 4) x (64 + 4) columns the windows cover, each
+  // computed once; -1 marks a column outside the box
+  __shared__ int tile[kPartRows + 4][64 + 4];
+  __shared__ int wmax[kPartRows];
+  const int x0 = blockIdx.x * 64, o0 = blockIdx.y * kPartRows;
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  for (int i = tid; i < (kPartRows + 4) * (64 + 4); i += 64 * kPartRows) {
+    const int r = i / (64 + 4), j = i - r * (64 + 4);
+    const int oo = o0 + r - 2, xx = x0 + j - 2;
+    const bool in = oo >= 0 && oo < n && xx >= 0 && xx < n;
+    tile[r][j] = in ? count_liquid(s[oo * n + xx], n) : -1;
   }
-  part[threadIdx.x] = m;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w && part[threadIdx.x + w] > part[threadIdx.x])
-      part[threadIdx.x] = part[threadIdx.x + w];
-    __syncthreads();
+  const int x = x0 + threadIdx.x, o = o0 + threadIdx.y;
+  int own = 0;
+  if (x < n && o < n) {
+    int lo = n, hi = 0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+      for (int dx = 0; dx < 5; ++dx) {
+        const int c = tile[threadIdx.y + r][threadIdx.x + dx];
+        if (c < 0) continue;
+        lo = c < lo ? c : lo;
+        hi = c > hi ? c : hi;
+      }
+    own = tile[threadIdx.y + 2][threadIdx.x + 2];
+    cnt[o * n + x] = own;
+    cmin2[o * n + x] = lo;
+    cmax2[o * n + x] = hi;
   }
-  if (threadIdx.x == 0) rowb[0] = part[0] + 2 < n - 1 ? part[0] + 2 : n - 1;
+  int m = own;  // lanes outside the box hold 0, below every count's maximum
+  for (int w = 32; w > 0; w >>= 1) {
+    const int v = __shfl_xor(m, w);
+    m = v > m ? v : m;
+  }
+  if (threadIdx.x == 0) wmax[threadIdx.y] = m;
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < kPartRows; ++w) m = wmax[w] > m ? wmax[w] : m;
+    atomicMax(rmax + p, m);
+    if (blockIdx.x == 0 && blockIdx.y == 0) rmax[1 - p] = 0;
+  }
 }
 
 // pulled populations of a cell on the fast path: regular pulls, bounce-back
@@ -753,7 +793,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(
     Lam* __restrict__ lgh, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int A = rowb[0], R = front_rows(A, n);
+  const int A = row_bound(rowb[0], n), R = front_rows(A, n);
   for (int r = blockIdx.y; r < R; r += gridDim.y) {
     int a, o;
     front_row(r, A, n, a, o);
@@ -774,7 +814,7 @@ __global__ __launch_bounds__(256) void k_adj_collide_solid(
     KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-  if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, rowb[0], n)) return;
+  if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, row_bound(rowb[0], n), n)) return;
   const size_t nc = P.ncell;
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
   const Macro M;  // T enters only the flow part, which a solid cell skips
@@ -796,7 +836,7 @@ __global__ __launch_bounds__(256) void k_adj_stream(
   const Geo G{n, (uint32_t)n * (uint32_t)n};
   const size_t nc = P.ncell;
   const uint32_t i = G.cell(x, y, z);
-  if (bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, rowb[0], n)) {
+  if (bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, row_bound(rowb[0], n), n)) {
     push_fast<7>(lgh, lg0, G, nc, x, y, z, i);  // a solid cell: g only, no phase reads
     return;
   }
@@ -1181,7 +1221,6 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
     hipLaunchKernelGGL((k_adj_front<Ts, Lam, FLOW, MZ>), gcol, bcol, 0, st, A.s0, g1, A.th, A.ls1,
                        lg1, A.out5, A.own, A.lth, P);
   const double* wq = A.heat ? A.wq : nullptr;
-  hipLaunchKernelGGL(k_adj_rows, dim3(1), dim3(1024), 0, st, A.cnt, A.rowb, n);
   // row slots of the full reverse collision: at most one per row
   const dim3 gfront((n + bx - 1) / bx, (unsigned)(n * n < 2048 ? n * n : 2048), 1);
   hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ, EXT>), gfront, bcell, 0, st, f0, g0, A.s0,
@@ -1219,6 +1258,14 @@ hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A,
     case kBF16S: return adjoint_step_d<__bf16, float>(P, A, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_adj_partition(const KParams& P, const double* s, int* cnt, int* cmin2,
+                                int* cmax2, int* rmax, int slot, hipStream_t st) {
+  const int n = P.n;
+  hipLaunchKernelGGL(k_adj_partition, dim3((n + 63) / 64, (n + kPartRows - 1) / kPartRows, 1),
+                     dim3(64, kPartRows, 1), 0, st, s, cnt, cmin2, cmax2, rmax, slot, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(double* v, size_t count, double value, hipStream_t st) {

@@ -819,7 +819,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   const size_t lb = lbmk::lambda_bytes(c->kind);  // bytes of one per-cell adjoint value
   if (!a.lg[0]) {
     if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cmin, nn)) || (rc = dalloc(&a.cmax, nn)) ||
-        (rc = dalloc(&a.cmin2, nn)) || (rc = dalloc(&a.cmax2, nn)) || (rc = dalloc(&a.rowb, 1)) ||
+        (rc = dalloc(&a.cmin2, nn)) || (rc = dalloc(&a.cmax2, nn)) || (rc = dalloc(&a.rowb, 2)) ||
         (rc = dalloc(&a.melted, nn)) || (rc = dalloc(&a.frozen, nn)) || (rc = dalloc(&a.flag, 1)) ||
         (rc = dalloc_bytes(&a.lg[0], 7 * nc * lb)) || (rc = dalloc_bytes(&a.lg[1], 7 * nc * lb)) ||
         (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
@@ -834,6 +834,8 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   HIP_TRY(hipMemsetAsync(a.melted, 0, nn * sizeof(int), c->stream));
   HIP_TRY(hipMemsetAsync(a.frozen, 0, nn * sizeof(int), c->stream));
   HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(int), c->stream));
+  HIP_TRY(hipMemsetAsync(a.rowb, 0, 2 * sizeof(int), c->stream));  // both partition slots
+  int64_t rev = 0;  // reverse steps taken; its parity picks the partition slot
   // adjoint of the final state: J = dJ_dfl * sum(s) / n^3
   int cur = 1;
   HIP_TRY(lbmk::launch_fill(a.ls[cur], nn, dJ_dfl / ((double)nn * c->p.n), c->stream));
@@ -864,9 +866,10 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
                                  nullptr, c->heat, c->stream));
     }
     // reverse the segment
-    for (int64_t t = len - 1; t >= 0; --t) {
-      HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
-      HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin2, a.cmax2, c->stream, 2));
+    for (int64_t t = len - 1; t >= 0; --t, ++rev) {
+      const int slot = (int)(rev & 1);
+      HIP_TRY(lbmk::launch_adj_partition(k, a.ss[t], a.cnt, a.cmin2, a.cmax2, a.rowb, slot,
+                                         c->stream));
       if (c->heat)  // the interface heat of state t, for the reverse of the front update
         HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], a.cnt, c->heat, c->stream));
       lbmk::AdjointStep A;
@@ -879,7 +882,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
       A.cnt = a.cnt;
       A.cmin2 = a.cmin2;
       A.cmax2 = a.cmax2;
-      A.rowb = a.rowb;
+      A.rowb = a.rowb + slot;
       A.lf1 = a.lf[cur];
       A.lg1 = a.lg[cur];
       A.ls1 = a.ls[cur];
