@@ -594,28 +594,53 @@ __device__ __forceinline__ void front_der(const Ts* g1, const double* s, const d
                                           const KParams& P, VDer& d) {
   const int n = P.n;
   const double sc = s[c];
+  // front slopes by central differences, mirrored at the walls, and the
+  // hot-wall temperature: loads that depend on nothing else, issued first
+  const int x = c % n, o = c / n;
+  const int cxp = o * n + (x + 1 < n ? x + 1 : x), cxm = o * n + (x > 0 ? x - 1 : x);
+  const int cop = (o + 1 < n ? o + 1 : o) * n + x, com = (o > 0 ? o - 1 : o) * n + x;
+  const double dsx = 0.5 * (s[cxp] - s[cxm]), dso = 0.5 * (s[cop] - s[com]);
+  const double thc = th[c];
   const int cnt = count_liquid(sc, n);
   auto Tcell = [&](uint32_t i) {
     double acc = 0.0;
     for (int q = 0; q < 7; ++q) acc += sv<7>(g1, P, q, i);
     return acc + P.tref;
   };
-  // liquid side: the nearest centres at distance >= 1/2 toward the heated
-  // wall, then the wall itself
+  // The nodes: on each side the two nearest centres at distance >= 1/2 from
+  // the front.  The nearest liquid one is at height cnt - 1 or, if that
+  // centre is closer than 1/2, cnt - 2; the nearest solid one at cnt or
+  // cnt + 1.  The four candidate cells are known from the front alone, so
+  // their temperatures are loaded together (heights clamped into the box;
+  // a candidate outside it is not used).
+  int at = cnt - 1;
+  if (at >= 0 && sc - (at + 0.5) < 0.5) --at;
+  int ab = cnt;
+  if (ab < n && (ab + 0.5) - sc < 0.5) ++ab;
+  auto cell_at = [&](int a) {
+    return cell_in_column<MZ>(c, a < 0 ? 0 : (a > n - 1 ? n - 1 : a), n);
+  };
+  const uint32_t cl0 = cell_at(at), cl1 = cell_at(at - 1), cs0 = cell_at(ab), cs1 = cell_at(ab + 1);
+  const double Tl0 = Tcell(cl0), Tl1 = Tcell(cl1), Ts0 = Tcell(cs0), Ts1 = Tcell(cs1);
+
+  // liquid side: those nodes toward the heated wall, then the wall itself
   double xi0 = 0.0, xi1 = 0.0, T0 = 0.0, T1 = 0.0;
   uint32_t nd0 = 0, nd1 = 0;
   int k = 0, wall_l = -1;
-  for (int a = cnt - 1; a >= 0 && k < 2; --a) {
-    const double dd = sc - (a + 0.5);
-    if (dd >= 0.5) {
-      const uint32_t node = cell_in_column<MZ>(c, a, n);
-      const double T = Tcell(node);
-      if (k == 0) { xi0 = dd; nd0 = node; T0 = T; } else { xi1 = dd; nd1 = node; T1 = T; }
-      ++k;
+  if (at >= 0) {
+    xi0 = sc - (at + 0.5);
+    nd0 = cl0;
+    T0 = Tl0;
+    k = 1;
+    if (at - 1 >= 0) {
+      xi1 = sc - ((at - 1) + 0.5);
+      nd1 = cl1;
+      T1 = Tl1;
+      k = 2;
     }
   }
   if (k < 2) {
-    if (k == 0) { xi0 = sc; T0 = th[c]; } else { xi1 = sc; T1 = th[c]; }
+    if (k == 0) { xi0 = sc; T0 = thc; } else { xi1 = sc; T1 = thc; }
     wall_l = k;
     ++k;
   }
@@ -627,18 +652,21 @@ __device__ __forceinline__ void front_der(const Ts* g1, const double* s, const d
   d.node[0] = nd0;
   d.node[1] = nd1;
 
-  // solid side: centres beyond the front, then the cold wall (melt axis y)
+  // solid side: the nodes beyond the front, then the cold wall (melt axis y)
   xi0 = xi1 = T0 = T1 = 0.0;
   nd0 = nd1 = 0;
   k = 0;
   int wall_s = -1;
-  for (int a = cnt; a < n && k < 2; ++a) {
-    const double dd = (a + 0.5) - sc;
-    if (dd >= 0.5) {
-      const uint32_t node = cell_in_column<MZ>(c, a, n);
-      const double T = Tcell(node);
-      if (k == 0) { xi0 = dd; nd0 = node; T0 = T; } else { xi1 = dd; nd1 = node; T1 = T; }
-      ++k;
+  if (ab < n) {
+    xi0 = (ab + 0.5) - sc;
+    nd0 = cs0;
+    T0 = Ts0;
+    k = 1;
+    if (ab + 1 < n) {
+      xi1 = ((ab + 1) + 0.5) - sc;
+      nd1 = cs1;
+      T1 = Ts1;
+      k = 2;
     }
   }
   if (k < 2 && !MZ) {
@@ -654,10 +682,6 @@ __device__ __forceinline__ void front_der(const Ts* g1, const double* s, const d
   d.node[2] = nd0;
   d.node[3] = nd1;
 
-  const int x = c % n, o = c / n;
-  const int cxp = o * n + (x + 1 < n ? x + 1 : x), cxm = o * n + (x > 0 ? x - 1 : x);
-  const int cop = (o + 1 < n ? o + 1 : o) * n + x, com = (o > 0 ? o - 1 : o) * n + x;
-  const double dsx = 0.5 * (s[cxp] - s[cxm]), dso = 0.5 * (s[cop] - s[com]);
   const double Pf = 1.0 + dsx * dsx + dso * dso;
   const double K = P.alpha * P.ste / P.dT, kap = P.kappa;  // Eq. (6): kappa on the solid side
   d.V = Pf * K * (kap * ss + sl);
@@ -705,13 +729,21 @@ __global__ __launch_bounds__(64) void k_adj_front(const double* __restrict__ s0,
     return;
   }
   own[c] = l;
+  // The 28 updated values are distinct (other direction or other cell of this
+  // column, and no other column touches these cells): all loads are issued
+  // before the first store, instead of one load-add-store round trip each.
+  // An unused slot loads cell 0 (its node index stays 0) and stores nothing.
+  Lam old[4][7];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int q = 0; q < 7; ++q) old[k][q] = lg1[(size_t)q * nc + d.node[k]];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     if (d.use[k])
-      for (int q = 0; q < 7; ++q) {
-        Lam& lv = lg1[(size_t)q * nc + d.node[k]];
-        lv = (Lam)((double)lv + l * d.dT[k]);
-      }
+#pragma unroll
+      for (int q = 0; q < 7; ++q)
+        lg1[(size_t)q * nc + d.node[k]] = (Lam)((double)old[k][q] + l * d.dT[k]);
   for (int j = 0; j < 5; ++j) out5[j * nn + c] = l * d.ds[j];
   lth[c] += l * d.dth;
 }
