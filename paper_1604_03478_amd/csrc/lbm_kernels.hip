@@ -566,28 +566,50 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
   // front velocity: Eq. (6) from one-sided temperature gradients, or (heat
   // given) the heat the lattice carried into this column's front over L
   auto gradient_velocity = [&]() -> double {
-    // liquid side: the selected nodes toward the heated wall, then the wall
+    // The nodes are a_top, a_top - 1 (liquid side) and a_bot, a_bot + 1
+    // (solid side) where they lie in the box.  Their temperatures, the
+    // neighbouring fronts and the hot-wall temperature are loaded together
+    // (heights clamped into the box; a candidate outside it is not used).
+    auto in_box = [&](int a) { return a < 0 ? 0 : (a > n - 1 ? n - 1 : a); };
+    const double Tl0 = T_at(in_box(a_top)), Tl1 = T_at(in_box(a_top - 1));
+    const double Ts0 = T_at(in_box(a_bot)), Ts1 = T_at(in_box(a_bot + 1));
+    const double thc = th[col];
+    // front slopes by central differences, mirrored at the walls
+    const double sxp = s_old[o * n + (x + 1 < n ? x + 1 : x)];
+    const double sxm = s_old[o * n + (x > 0 ? x - 1 : x)];
+    const double sop = s_old[(o + 1 < n ? o + 1 : o) * n + x];
+    const double som = s_old[(o > 0 ? o - 1 : o) * n + x];
+
+    // liquid side: the nodes toward the heated wall, then the wall
     double xi0 = 0, T0v = 0, xi1 = 0, T1v = 0;
     int k = 0;
-    for (int a = a_top; a >= 0 && k < 2; --a) {
-      const double d = sc - (a + 0.5);
-      const double T = T_at(a);
-      if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
-      ++k;
+    if (a_top >= 0) {
+      xi0 = sc - (a_top + 0.5);
+      T0v = Tl0;
+      k = 1;
+      if (a_top - 1 >= 0) {
+        xi1 = sc - ((a_top - 1) + 0.5);
+        T1v = Tl1;
+        k = 2;
+      }
     }
     if (k < 2) {
-      if (k == 0) { xi0 = sc; T0v = th[col]; } else { xi1 = sc; T1v = th[col]; }
+      if (k == 0) { xi0 = sc; T0v = thc; } else { xi1 = sc; T1v = thc; }
       ++k;
     }
     const double Gl = -one_sided(k, xi0, T0v, xi1, T1v, P.t_m);
 
     // solid side: nodes beyond the front, then the cold wall (melt axis y)
     k = 0;
-    for (int a = a_bot; a < n && k < 2; ++a) {
-      const double d = (a + 0.5) - sc;
-      const double T = T_at(a);
-      if (k == 0) { xi0 = d; T0v = T; } else { xi1 = d; T1v = T; }
-      ++k;
+    if (a_bot < n) {
+      xi0 = (a_bot + 0.5) - sc;
+      T0v = Ts0;
+      k = 1;
+      if (a_bot + 1 < n) {
+        xi1 = ((a_bot + 1) + 0.5) - sc;
+        T1v = Ts1;
+        k = 2;
+      }
     }
     if (k < 2 && !MZ) {
       if (k == 0) { xi0 = n - sc; T0v = P.t_c; } else { xi1 = n - sc; T1v = P.t_c; }
@@ -595,11 +617,6 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
     }
     const double Gs = one_sided(k, xi0, T0v, xi1, T1v, P.t_m);
 
-    // front slopes by central differences, mirrored at the walls
-    const double sxp = s_old[o * n + (x + 1 < n ? x + 1 : x)];
-    const double sxm = s_old[o * n + (x > 0 ? x - 1 : x)];
-    const double sop = s_old[(o + 1 < n ? o + 1 : o) * n + x];
-    const double som = s_old[(o > 0 ? o - 1 : o) * n + x];
     const double dsx = 0.5 * (sxp - sxm), dso = 0.5 * (sop - som);
     // Eq. (6): k_s dT_s - k_l dT_l in units of k_l (kappa = k_s / k_l)
     return (1.0 + dsx * dsx + dso * dso) * P.alpha * P.ste * (P.kappa * Gs - Gl) / P.dT;
