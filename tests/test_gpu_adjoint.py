@@ -341,13 +341,15 @@ def test_gradient_with_conservative_front_matches_finite_differences_32():
 
 @pytest.mark.parametrize("n,s0,kw", [
     (4, 1.5, {}), (5, 0.0, {}), (5, 5.0, {}), (7, 3.5, {}), (6, 2.3, dict(f_wall=1)),
-    (6, 2.3, dict(front_scheme=1)),
+    (6, 2.3, dict(front_scheme=1)), (70, 3.3, {}),
 ])
 def test_gradient_matches_oracle_adjoint_edge_sizes(n, s0, kw):
     """Minimum and ragged sizes, all-solid and all-liquid boxes, a front on
     a cell face: the row partition of the reverse collision and streaming
     (bulk-solid rows against rows near the front and the walls) at its
-    edges, FP64 against the oracle's reverse sweep."""
+    edges, FP64 against the oracle's reverse sweep.  n = 70 spans two
+    64-column blocks of the partition kernel, the second one ragged, and a
+    ragged last block of 8 rows."""
     from inputs import hot_wall_field
     from paper_1604_03478_amd import Config, Sim
     base = dict(ra=1e3, pr=1.0, ste=0.5, s0=s0, flow=1, **kw)
