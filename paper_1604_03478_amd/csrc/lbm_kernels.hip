@@ -276,12 +276,12 @@ __device__ __forceinline__ void update_cell(
   // With 16-bit storage the general path packs the phases of the 3x3x3
   // stencil into one register instead (bit ((da + 1) * 3 + do + 1) * 3 + dx +
   // 1 for the cell at offsets dx, do and da along the melt axis); nine live
-  // counts would spill under that kernel's register cap.  Measured at 256^3,
-  // FP16 with the melt axis y: 346 -> 322 us all-liquid, 203 -> 167 us
-  // melting.  For the melt axis z, and for BF16, the mask raised the spill
-  // from 12 to 32 bytes per lane and cost 18-50 %, so those instantiations
-  // load each count.
-  constexpr bool kMask = __is_same(Ts, _Float16) && !MZ;
+  // counts would spill under that kernel's register cap.  Against a load of
+  // the count per link, measured at 256^3 (all-liquid / melting, us per step):
+  // FP16 with the melt axis y 346 / 203 -> 322 / 167; BF16 with the melt axis
+  // y 345 / 203 -> 323 / 162; either format with the melt axis z 341 / 154 ->
+  // 323 / 146 (those three at 7 waves, where the mask does not spill).
+  constexpr bool kMask = sizeof(Ts) == 2;
   uint32_t phase27 = 0;
   // phase of the in-box cell at offsets (dx, do) across and da along the melt
   // axis; the offsets are constants of the unrolled loops
@@ -483,14 +483,19 @@ __global__ __launch_bounds__(512) void k_stream_collide(
                                    th, flag, P);
 }
 
-// The same for 16-bit storage, held to 8 waves per SIMD.  Its instruction
-// stream is long for the bytes it moves (conversions and the rounding of 26
-// values), and two more resident waves hide more of it: at 256^3 the step
-// takes 5 % less time all-liquid and 9 % less in the melting state, although
-// the register limit spills 12 bytes per lane.  (For FP32 the same limit
-// spills 60 bytes and costs 24 %.)
+// The same for 16-bit storage, held to 7 or 8 resident waves per SIMD.  Its
+// instruction stream is long for the bytes it moves (conversions and the
+// rounding of 26 values), and more resident waves hide more of it.  FP16 with
+// the melt axis y and the halfway no-slip of f fits 8 waves (64 VGPRs, a
+// 12-byte spill per lane), and so does the conduction-only step (g alone).
+// Every other instantiation needs 65 VGPRs for the phase mask of its general
+// path: it spills 32 bytes at 8 waves and none at 7, and runs 5-20 % faster
+// at 7.  (For FP32 an 8-wave limit spills 60 bytes and costs 24 %.)
 template <typename Ts, bool FLOW, bool MZ, bool FWALL>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8, 8))) void
+constexpr int kWaves16 = !FLOW || (__is_same(Ts, _Float16) && !MZ && !FWALL) ? 8 : 7;
+template <typename Ts, bool FLOW, bool MZ, bool FWALL>
+__global__ __launch_bounds__(512) __attribute__((
+    amdgpu_waves_per_eu(kWaves16<Ts, FLOW, MZ, FWALL>, kWaves16<Ts, FLOW, MZ, FWALL>))) void
 k_stream_collide_h(const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
                    Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
                    const int* __restrict__ cmax, const double* __restrict__ s,
