@@ -27,7 +27,9 @@
 //                       the same for the bulk-solid rows, g only and
 //                       without the state (linear at rest)
 //   k_adj_stream        per cell: transposed streaming as a gather over every
-//                       reader of each stored population (no atomics)
+//                       reader of each stored population (no atomics), on
+//                       row slots over the rows outside the bulk solid;
+//                       k_adj_stream_solid the bulk-solid rows (g only)
 //   k_adj_interface     per column: dependence of the interpolated front
 //                       conditions on the front through the link fractions,
 //                       of the hot-wall condition on T_h, and the sum of the
@@ -856,22 +858,17 @@ __global__ __launch_bounds__(256) void k_adj_collide_solid(
   for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = (Lam)lgl[q];
 }
 
+// Transposed streaming of one cell outside the bulk-solid rows.
 template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
-__global__ __launch_bounds__(256) void k_adj_stream(
+__device__ __forceinline__ void adj_stream_cell(
     const double* __restrict__ s0, const int* __restrict__ cnt, const int* __restrict__ cmin2,
-    const int* __restrict__ cmax2, const int* __restrict__ rowb, const Lam* __restrict__ lfh,
-    const Lam* __restrict__ lgh, Lam* __restrict__ lf0, Lam* __restrict__ lg0,
-    const double* __restrict__ wq, KParams P) {
+    const int* __restrict__ cmax2, const Lam* __restrict__ lfh, const Lam* __restrict__ lgh,
+    Lam* __restrict__ lf0, Lam* __restrict__ lg0, const double* __restrict__ wq,
+    const KParams& P, int x, int y, int z) {
   const int n = P.n;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-  if (x >= n) return;
   const Geo G{n, (uint32_t)n * (uint32_t)n};
   const size_t nc = P.ncell;
   const uint32_t i = G.cell(x, y, z);
-  if (bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, row_bound(rowb[0], n), n)) {
-    push_fast<7>(lgh, lg0, G, nc, x, y, z, i);  // a solid cell: g only, no phase reads
-    return;
-  }
   const bool L = liquid_at<MZ>(cnt, x, y, z, n);
   auto LG = [&](int q, uint32_t j) { return (double)lgh[(size_t)q * nc + j]; };
 
@@ -1019,6 +1016,39 @@ __global__ __launch_bounds__(256) void k_adj_stream(
       lf0[(size_t)p * nc + i] = (Lam)acc;
     }
   }
+}
+
+// The rows outside the bulk solid, visited by row slots as in k_adj_collide
+// (its general path needs more registers than the bulk rows should pay for).
+template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
+__global__ __launch_bounds__(256) void k_adj_stream(
+    const double* __restrict__ s0, const int* __restrict__ cnt, const int* __restrict__ cmin2,
+    const int* __restrict__ cmax2, const int* __restrict__ rowb, const Lam* __restrict__ lfh,
+    const Lam* __restrict__ lgh, Lam* __restrict__ lf0, Lam* __restrict__ lg0,
+    const double* __restrict__ wq, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int A = row_bound(rowb[0], n), R = front_rows(A, n);
+  for (int r = blockIdx.y; r < R; r += gridDim.y) {
+    int a, o;
+    front_row(r, A, n, a, o);
+    if (x < n)
+      adj_stream_cell<Ts, Lam, FLOW, MZ, EXT>(s0, cnt, cmin2, cmax2, lfh, lgh, lf0, lg0, wq, P, x,
+                                              MZ ? o : a, MZ ? a : o);
+  }
+}
+
+// The bulk-solid rows: g alone, gathered from the neighbours with no phase
+// reads, at full occupancy.
+template <typename Lam, bool MZ>
+__global__ __launch_bounds__(256) void k_adj_stream_solid(const int* __restrict__ rowb,
+                                                          const Lam* __restrict__ lgh,
+                                                          Lam* __restrict__ lg0, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, row_bound(rowb[0], n), n)) return;
+  const Geo G{n, (uint32_t)n * (uint32_t)n};
+  push_fast<7>(lgh, lg0, G, P.ncell, x, y, z, G.cell(x, y, z));
 }
 
 // derivative of the pulled population of an interface link with respect to
@@ -1258,8 +1288,9 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ, EXT>), gfront, bcell, 0, st, f0, g0, A.s0,
                      A.s1, A.th, A.cnt, A.cmin2, A.cmax2, A.rowb, lf1, lg1, lfh, lgh, P);
   hipLaunchKernelGGL((k_adj_collide_solid<Lam, MZ>), gcell, bcell, 0, st, A.rowb, lg1, lgh, P);
-  hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ, EXT>), gcell, bcell, 0, st, A.s0, A.cnt, A.cmin2,
-                     A.cmax2, A.rowb, lfh, lgh, lf0, lg0, wq, P);
+  hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ, EXT>), gfront, bcell, 0, st, A.s0, A.cnt,
+                     A.cmin2, A.cmax2, A.rowb, lfh, lgh, lf0, lg0, wq, P);
+  hipLaunchKernelGGL((k_adj_stream_solid<Lam, MZ>), gcell, bcell, 0, st, A.rowb, lgh, lg0, P);
   hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ, EXT>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh, f0,
                      lfh, wq, A.own, A.out5, A.ls0, A.lth, P);
   return hipGetLastError();
