@@ -470,8 +470,32 @@ __device__ __forceinline__ void update_cell(
   for (int q = 0; q < 7; ++q) store_stream(gr, q * pitch + x, g[q], rs);
 }
 
-// One lattice row per workgroup (blockIdx.y = y, blockIdx.z = z): the row
-// pointers are uniform over the workgroup.
+// One lattice row per workgroup, so the row pointers are uniform over it.
+// The workgroups of the n x n rows are numbered r = blockIdx.z * n +
+// blockIdx.y, the order in which they are dispatched.  The 4n - 4 rows on the
+// y and z walls, which always take the general path, come first; the
+// interior rows follow in z-major order.  In plane order the wall plane
+// z = n - 1 came last, and its slow rows formed a tail: at 256^3 the melting
+// step took 214 instead of 179 us (FP32), 167 instead of 141 us (FP16).
+__device__ __forceinline__ void step_row(int n, int& y, int& z) {
+  const int r = blockIdx.z * n + blockIdx.y, nw = 4 * n - 4;
+  if (r < n) {
+    y = r;
+    z = 0;
+  } else if (r < 2 * n) {
+    y = r - n;
+    z = n - 1;
+  } else if (r < nw) {  // the y walls of the planes 0 < z < n - 1
+    const int k = r - 2 * n;
+    z = 1 + (k >> 1);
+    y = (k & 1) ? n - 1 : 0;
+  } else {
+    const int k = r - nw;
+    z = 1 + k / (n - 2);
+    y = 1 + (k - (z - 1) * (n - 2));
+  }
+}
+
 template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 __global__ __launch_bounds__(512) void k_stream_collide(
     const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
@@ -479,8 +503,9 @@ __global__ __launch_bounds__(512) void k_stream_collide(
     const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
     int* __restrict__ flag, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  update_cell<Ts, FLOW, MZ, FWALL>(x, blockIdx.y, blockIdx.z, fs, fd, gs, gd, cnt, cmin, cmax, s,
-                                   th, flag, P);
+  int y, z;
+  step_row(P.n, y, z);
+  update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, cmin, cmax, s, th, flag, P);
 }
 
 // The same for 16-bit storage, held to 7 or 8 resident waves per SIMD.  Its
@@ -501,8 +526,9 @@ k_stream_collide_h(const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __r
                    const int* __restrict__ cmax, const double* __restrict__ s,
                    const double* __restrict__ th, int* __restrict__ flag, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  update_cell<Ts, FLOW, MZ, FWALL>(x, blockIdx.y, blockIdx.z, fs, fd, gs, gd, cnt, cmin, cmax, s,
-                                   th, flag, P);
+  int y, z;
+  step_row(P.n, y, z);
+  update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, cmin, cmax, s, th, flag, P);
 }
 
 // --------------------------------------------------------------- front update
