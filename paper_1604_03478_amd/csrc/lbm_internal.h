@@ -76,10 +76,10 @@ hipError_t launch_front(int kind, const KParams& P, const double* s_old, double*
                         int* frozen, int* flag, const int* replay, const int* replay_next,
                         int* record, const double* heat, hipStream_t st);
 
-// cmin/cmax: min and max of cnt over the (2 radius + 1)^2 columns around each
-// column (radius 1 for the step kernel, 2 for the adjoint's fast path).
+// cmin/cmax: min and max of cnt over the 3x3 columns around each column (the
+// columns in the box), for the fast-path test of the 16-bit step kernel.
 hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
-                                hipStream_t st, int radius = 1);
+                                hipStream_t st);
 
 // cnt from s.
 hipError_t launch_counts(const KParams& P, const double* s, int* cnt, hipStream_t st);

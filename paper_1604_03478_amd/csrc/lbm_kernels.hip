@@ -678,15 +678,15 @@ __global__ void k_counts(const double* __restrict__ s, int* __restrict__ cnt, in
 }
 
 __global__ void k_neighbourhood(const int* __restrict__ cnt, int* __restrict__ cmin,
-                                int* __restrict__ cmax, int n, int radius) {
+                                int* __restrict__ cmax, int n) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int o = blockIdx.y;
   if (x >= n) return;
   int lo = 0x7fffffff, hi = -1;
-  for (int d_o = -radius; d_o <= radius; ++d_o) {
+  for (int d_o = -1; d_o <= 1; ++d_o) {
     const int oo = o + d_o;
     if (oo < 0 || oo >= n) continue;
-    for (int dx = -radius; dx <= radius; ++dx) {
+    for (int dx = -1; dx <= 1; ++dx) {
       const int xx = x + dx;
       if (xx < 0 || xx >= n) continue;
       const int c = cnt[oo * n + xx];
@@ -988,11 +988,10 @@ hipError_t launch_front(int kind, const KParams& P, const double* s_old, double*
 }
 
 hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
-                                hipStream_t st, int radius) {
-  if (radius < 1 || radius > 2) return hipErrorInvalidValue;
+                                hipStream_t st) {
   dim3 block(64, 1, 1);
   dim3 grid((P.n + 63) / 64, P.n, 1);
-  hipLaunchKernelGGL(k_neighbourhood, grid, block, 0, st, cnt, cmin, cmax, P.n, radius);
+  hipLaunchKernelGGL(k_neighbourhood, grid, block, 0, st, cnt, cmin, cmax, P.n);
   return hipGetLastError();
 }
 
