@@ -902,33 +902,53 @@ __device__ __forceinline__ void adj_stream_cell(
     return melt_of<MZ>(Y, Z) < nbc[k];
   };
 
+  // Every value the terms below may read is loaded before the tests that
+  // pick them (indices selected or clamped into the box), so the loads of a
+  // direction are in flight together: the adjoints at this cell and at
+  // x + e_p, and the fronts of this column and of the columns at x + e_p,
+  // x - e_p and x + 2 e_p (this column itself for a link along the melt
+  // axis).  The link fractions are those of link_delta, term for term.
+  const double s_own = s0[col_of<MZ>(x, y, z, n)];
+  auto s_at = [&](int X, int Y, int Z) {
+    X = X < 0 ? 0 : (X > n - 1 ? n - 1 : X);
+    Y = Y < 0 ? 0 : (Y > n - 1 ? n - 1 : Y);
+    Z = Z < 0 ? 0 : (Z > n - 1 ? n - 1 : Z);
+    return s0[col_of<MZ>(X, Y, Z, n)];
+  };
+  const double a0 = melt_of<MZ>(y, z) + 0.5;
 #pragma unroll
   for (int p = 0; p < 7; ++p) {
     const int ex = ex7(p), ey = ey7(p), ez = ez7(p), q = opp7(p);
-    double acc = 0.0;
-    // (a) regular pull of direction p by the neighbour x + e_p
+    const bool along = MZ ? (ez != 0) : (ey != 0);
     const int yx = x + ex, yy = y + ey, yz = z + ez;
     const bool yin = G.in(yx, yy, yz);
     const bool ysame = yin && liq(yx, yy, yz) == L;
-    if (ysame) acc += LG(p, G.cell(yx, yy, yz));
+    const uint32_t cy = yin ? G.cell(yx, yy, yz) : i;
+    const double la = LG(p, cy), lq = LG(q, i), lp = LG(p, i), lqy = LG(q, cy);
+    const double s_p1 = along ? s_own : s_at(x + ex, y + ey, z + ez);
+    const double s_m1 = along ? s_own : s_at(x - ex, y - ey, z - ez);
+    const double s_p2 = along ? s_own : s_at(x + 2 * ex, y + 2 * ey, z + 2 * ez);
+    double acc = 0.0;
+    // (a) regular pull of direction p by the neighbour x + e_p
+    if (ysame) acc += la;
     // (b) this cell's direction q = opp(p), whose source x + e_p is a wall or
     //     across the front
     if (p != 0) {
       if (!yin) {
         const int sa = melt_of<MZ>(yy, yz);
         const bool dirichlet = sa < 0 || (!MZ && sa >= n);
-        acc += (dirichlet ? -1.0 : 1.0) * LG(q, i);
+        acc += (dirichlet ? -1.0 : 1.0) * lq;
       } else if (!ysame) {
-        const double d = link_delta<MZ>(s0, x, y, z, ex, ey, ez, n);
+        const double d = along ? fabs(s_own - a0) : (a0 - s_own) / (s_p1 - s_own);
         if (d < 0.5) {
           const int bx = x - ex, by = y - ey, bz = z - ez;
           const bool behind = G.in(bx, by, bz) && liq(bx, by, bz) == L;
-          acc += (behind ? -2.0 * d : -1.0) * LG(q, i);
+          acc += (behind ? -2.0 * d : -1.0) * lq;
           // conservative front: the heat of this link, sent minus received
           if (EXT && wq)
             acc += (behind ? 1.0 + 2.0 * d : 2.0) * heat_weight<MZ>(wq, x, y, z, q, L, n);
         } else {
-          acc += -LG(q, i) / (2.0 * d);
+          acc += -lq / (2.0 * d);
           if (EXT && wq) acc += (1.0 + 1.0 / (2.0 * d)) * heat_weight<MZ>(wq, x, y, z, q, L, n);
         }
       }
@@ -936,9 +956,9 @@ __device__ __forceinline__ void adj_stream_cell(
       //     the front with a link fraction >= 1/2
       const int sx = x - ex, sy = y - ey, sz = z - ez;
       if (G.in(sx, sy, sz) && liq(sx, sy, sz) != L) {
-        const double d = link_delta<MZ>(s0, x, y, z, -ex, -ey, -ez, n);
+        const double d = along ? fabs(s_own - a0) : (a0 - s_own) / (s_m1 - s_own);
         if (d >= 0.5) {
-          acc += (2.0 * d - 1.0) / (2.0 * d) * LG(p, i);
+          acc += (2.0 * d - 1.0) / (2.0 * d) * lp;
           if (EXT && wq)
             acc -= (2.0 * d - 1.0) / (2.0 * d) * heat_weight<MZ>(wq, x, y, z, p, L, n);
         }
@@ -949,9 +969,10 @@ __device__ __forceinline__ void adj_stream_cell(
       if (ysame) {
         const int tx = yx + ex, ty = yy + ey, tz = yz + ez;
         if (G.in(tx, ty, tz) && liq(tx, ty, tz) != L) {
-          const double d = link_delta<MZ>(s0, yx, yy, yz, ex, ey, ez, n);
+          const double ay = melt_of<MZ>(yy, yz) + 0.5;
+          const double d = along ? fabs(s_own - ay) : (ay - s_p1) / (s_p2 - s_p1);
           if (d < 0.5) {
-            acc += -(1.0 - 2.0 * d) * LG(q, G.cell(yx, yy, yz));
+            acc += -(1.0 - 2.0 * d) * lqy;
             if (EXT && wq) acc += (1.0 - 2.0 * d) * heat_weight<MZ>(wq, yx, yy, yz, q, L, n);
           }
         }
