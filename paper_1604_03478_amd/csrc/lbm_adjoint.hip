@@ -1087,19 +1087,23 @@ __device__ __forceinline__ double link_sens(const Ts* g0, const double* s0, cons
   const size_t nc = P.ncell;
   const uint32_t i = G.cell(x, y, z);
   const int p = opp7(q);
+  // every value either branch may read, loaded first (the cell behind
+  // replaced by this one where it is outside the box)
+  const int bx = x + ex7(q), by = y + ey7(q), bz = z + ez7(q);
+  const bool bin = G.in(bx, by, bz);
+  const uint32_t ib = bin ? G.cell(bx, by, bz) : i;
+  const double gp = sv<7>(g0, P, p, i), gq = sv<7>(g0, P, q, i), gpb = sv<7>(g0, P, p, ib);
+  const int cb = cnt[bin ? col_of<MZ>(bx, by, bz, n) : col_of<MZ>(x, y, z, n)];
+  const double lg = (double)lgh[(size_t)q * nc + i];
   const double d = link_delta<MZ>(s0, x, y, z, -ex7(q), -ey7(q), -ez7(q), n);
   dfrac = d;
-  const double l = (double)lgh[(size_t)q * nc + i] -
-                   ((EXT && wq) ? heat_weight<MZ>(wq, x, y, z, q, L, n) : 0.0);
+  const double l = lg - ((EXT && wq) ? heat_weight<MZ>(wq, x, y, z, q, L, n) : 0.0);
   if (d < 0.5) {
-    const int bx = x + ex7(q), by = y + ey7(q), bz = z + ez7(q);
-    if (G.in(bx, by, bz) && liquid_at<MZ>(cnt, bx, by, bz, n) == L)
-      return (-2.0 * sv<7>(g0, P, p, i) + 2.0 * sv<7>(g0, P, p, G.cell(bx, by, bz))) * l;
+    if (bin && (melt_of<MZ>(by, bz) < cb) == L) return (-2.0 * gp + 2.0 * gpb) * l;
     return 0.0;
   }
   const double w = 0.125;
-  return (sv<7>(g0, P, p, i) / (2.0 * d * d) + sv<7>(g0, P, q, i) / (2.0 * d * d) -
-          w * (P.t_m - P.tref) / (d * d)) * l;
+  return (gp / (2.0 * d * d) + gq / (2.0 * d * d) - w * (P.t_m - P.tref) / (d * d)) * l;
 }
 
 // Interpolated no-slip of f: derivative of the pulled population q of the
