@@ -439,27 +439,16 @@ static int wall_type(const orc_sim *S, const double *th, int x, int y, int z,
   return 0;
 }
 
-/* reading: link fraction from cell (x,y,z) along direction e toward the
- * neighbour on the other side of the front */
-static double link_fraction(const orc_sim *S, const double *s, int x, int y,
-                            int z, const int *e) {
-  int c = column_of(S, x, y, z);
-  double a = melt_coord(S, x, y, z) + 0.5;
-  int along_melt = (S->p.heating == 0) ? (e[1] != 0) : (e[2] != 0);
-  if (along_melt) return fabs(s[c] - a);
-  int nx = x + e[0], ny = y + e[1], nz = z + e[2];
-  wrap_lateral(S, &nx, &ny, &nz);
-  int cn = column_of(S, nx, ny, nz);
-  return (a - s[c]) / (s[cn] - s[c]);
-}
-
 /* reading: fraction of the link from this cell's centre to the centre of
- * the neighbour at offset e (a D3Q19 link, diagonal ones included) at which
- * the link meets the front.  Along the link the height on the melt axis is
- * linear, from a + 1/2 to a + 1/2 + e_a, and so is the front, from this
- * column's s to the neighbour column's; the fraction is where the two meet.
- * For the links of the energy lattice it is the link fraction of the front
- * condition of g. */
+ * the neighbour at offset e at which the link meets the front (section 2:
+ * the interface condition T = T_m that Eq. (6) moves).  Along the link the
+ * height on the melt axis is linear, from a + 1/2 to a + 1/2 + e_a, and so
+ * is the front, from this column's s to the neighbour column's; the
+ * fraction is where the two meet.  Every interface link goes through here:
+ * the D3Q7 links of the front condition of g (along the melt axis this is
+ * |s - (a + 1/2)|, across columns (a + 1/2 - s_c) / (s_nbr - s_c)), from
+ * liquid and from solid cells, and the D3Q19 links of the interpolated
+ * no-slip of f, diagonal ones included. */
 static double link_fraction_any(const orc_sim *S, const double *s, int x, int y,
                                 int z, const int *e) {
   int c = column_of(S, x, y, z);
@@ -500,7 +489,7 @@ static void stream_cell(const orc_sim *S, const double *f, const double *g,
       /* reading: interpolated anti-bounce-back at the front, wall value
        * T_m; the link direction p points from this cell toward the front */
       const int *ep = E7[po];
-      double d = link_fraction(S, s, x, y, z, ep);
+      double d = link_fraction_any(S, s, x, y, z, ep);
       double w = S->w7[q];
       int bx = x + E7[q][0], by = y + E7[q][1], bz = z + E7[q][2];
       wrap_lateral(S, &bx, &by, &bz);
@@ -808,6 +797,12 @@ double orc_link_fraction19(const orc_sim *S, int x, int y, int z, int q) {
   return link_fraction_any(S, S->s, x, y, z, E19[S->opp19[q]]);
 }
 
+/* the same for the incoming D3Q7 direction q of the energy lattice, as its
+ * front condition takes it (from a liquid or a solid cell) */
+double orc_link_fraction7(const orc_sim *S, int x, int y, int z, int q) {
+  return link_fraction_any(S, S->s, x, y, z, E7[S->opp7[q]]);
+}
+
 void orc_front_velocity(const orc_sim *S, double *V) {
   const int n = S->n;
   for (int c = 0; c < n * n; ++c)
@@ -1026,7 +1021,7 @@ static void stream_cell_adjoint(const orc_sim *S, const double *f, const double 
       lg[q * nc + cell_index(n, sx, sy, sz)] += l;
     } else {
       const int *ep = E7[po];
-      double d = link_fraction(S, s, x, y, z, ep);
+      double d = link_fraction_any(S, s, x, y, z, ep);
       double w = S->w7[q];
       int bx = x + E7[q][0], by = y + E7[q][1], bz = z + E7[q][2];
       double ld = 0.0;
@@ -1145,7 +1140,7 @@ static void front_heat_adjoint(const orc_sim *S, const double *f, const double *
           int col = (along || !liquid) ? column_of(S, x, y, z) : column_of(S, sx, sy, sz);
           double l = wq[col];
           if (l == 0.0) continue;
-          double d = link_fraction(S, s, x, y, z, ep);
+          double d = link_fraction_any(S, s, x, y, z, ep);
           double w = S->w7[q];
           int bx = x + E7[q][0], by = y + E7[q][1], bz = z + E7[q][2];
           double dr = 0.0; /* derivative of the received value in d */

@@ -26,14 +26,24 @@ def oracle_library_path() -> str:
     return _LIB
 
 
+# gcc flags of the oracle: plain -O2, IEEE semantics (no fast-math, no
+# contraction into fused multiply-adds), OpenMP over independent cells
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+          "-std=c11"]
+
+
+def compile_oracle(src: str, out: str, extra=()) -> str:
+    """Compile an oracle source file into the shared library ``out``."""
+    tmp = out + ".tmp"
+    subprocess.run(["gcc", *CFLAGS, *extra, "-o", tmp, src, "-lm"], check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def build_oracle(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, IEEE semantics, OpenMP)."""
+    """Compile the oracle with gcc (CFLAGS)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-               "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+        compile_oracle(_SRC, _LIB)
     return _LIB
 
 
@@ -61,15 +71,18 @@ class _Params(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def _load(path=None):
+    """The oracle library (ctypes handle), loaded once per path.  ``path``
+    names another build of the oracle source, for the tests that plant a
+    mistake in a copy of it and check that a pin catches the mistake."""
+    key = path or _LIB
+    if key not in _libs:
+        if path is None and not os.path.exists(_LIB):
             build_oracle()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(key)
         P = ctypes.POINTER
         d, i, ll, vp = ctypes.c_double, ctypes.c_int, ctypes.c_longlong, ctypes.c_void_p
         dp = P(d)
@@ -98,8 +111,9 @@ def _load():
         lib.orc_record.argtypes = [vp, ll]
         lib.orc_adjoint.argtypes = [vp, dp, dp, dp, dp]
         lib.orc_wall_nusselt.argtypes = [vp, dp]
-        lib.orc_link_fraction19.argtypes = [vp, i, i, i, i]
-        lib.orc_link_fraction19.restype = d
+        for name in ("orc_link_fraction19", "orc_link_fraction7"):
+            getattr(lib, name).argtypes = [vp, i, i, i, i]
+            getattr(lib, name).restype = d
         lib.orc_energy.argtypes = [vp]
         lib.orc_energy.restype = d
         lib.orc_wall_heat.argtypes = [vp]
@@ -107,8 +121,8 @@ def _load():
         lib.orc_threads.restype = i
         lib.orc_set_threads.argtypes = [i]
         assert lib.orc_sizeof_params() == ctypes.sizeof(_Params), "oracle params layout mismatch"
-        _lib = lib
-    return _lib
+        _libs[key] = lib
+    return _libs[key]
 
 
 def threads() -> int:
@@ -159,8 +173,9 @@ class OracleSim:
 
     def __init__(self, n, ra=1e4, pr=1.0, ste=0.1, t_h=1.0, t_c=0.0, t_m=0.0,
                  ma=0.1, alpha=0.1, s0=1.0, heating=0, flow=1, seed_profile=0,
-                 periodic=False, ks_kl=1.0, front_scheme=0, f_wall=0, body_fx=0.0):
-        lib = _load()
+                 periodic=False, ks_kl=1.0, front_scheme=0, f_wall=0, body_fx=0.0,
+                 library=None):
+        lib = _load(library)
         lam = 0.0
         if seed_profile == 1 and ste > 0:
             lam = neumann.stefan_lambda(ste)
@@ -236,6 +251,11 @@ class OracleSim:
         """Fraction at which the front cuts the link from cell (x, y, z) to the
         source of its incoming D3Q19 direction q."""
         return float(self._lib.orc_link_fraction19(self._h, int(x), int(y), int(z), int(q)))
+
+    def link_fraction7(self, x: int, y: int, z: int, q: int) -> float:
+        """Fraction at which the front cuts the link from cell (x, y, z) to the
+        source of its incoming D3Q7 direction q (the front condition of g)."""
+        return float(self._lib.orc_link_fraction7(self._h, int(x), int(y), int(z), int(q)))
 
     def front_velocity(self) -> np.ndarray:
         V = np.zeros((self.n, self.n))
