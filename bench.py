@@ -14,8 +14,14 @@ and moves 208 B (FP32).  The melting state of the same configuration
 (front near the heated wall) is timed as well and reported separately.
 
 Also reported: the 512^3 bottom-heated configuration in FP16 shifted storage
-(`bottom512`), the adjoint timings (`adjoint`), and the measured ceiling of a
-two-stream elementwise kernel (`roofline.copy_ceiling_GBps`).
+(`bottom512`), the adjoint timings (`adjoint`), two measured bandwidth
+ceilings from the library's own kernels (`roofline.copy_ceiling_GBps`: a
+float4 copy; `roofline.pattern_ceiling_GBps`: the bare access pattern of the
+all-liquid step in the same layout and launch), and the equal-error leg
+(`equal_error`: the melting run of the same configuration in FP64, FP32, FP16
+and BF16 storage side by side for 2e4 steps, each format's liquid-fraction and
+temperature errors against FP64 beside its throughput, and the
+discretization band from FP64 at half resolution).
 
 Output: one JSON line (see the contract in the repository notes).  The
 roofline object uses the stream-collide kernel's average duration measured
@@ -25,8 +31,9 @@ kernel source (else null).
 
 Modes:
   (default)       the benchmark line
-  --mode profile  a short run of the all-liquid workload only (for rocprofv3;
-                  FP32 unless --precision says otherwise)
+  --mode profile  a short run of one workload only, for rocprofv3: the
+                  all-liquid benchmark state by default; --precision, --melting,
+                  --case bottom512 --n 512 select the others
   --mode copy     a plain device copy of known size (counter calibration)
   --mode adjoint  the checkpointed forward run and the reverse sweep alone
                   (64^3 x 2000 steps with a checkpoint every 100, and
@@ -105,25 +112,19 @@ def measure(n, precision, all_liquid, steps, warmup, stream):
     return ms, kms, fl
 
 
-def copy_ceiling(stream, nbytes: int = 2 << 30):
-    """GB/s of torch's elementwise kernel reading and writing nbytes each
-    (dst = src * 1): a measured ceiling for a two-stream kernel on this GPU."""
-    import torch
-    with torch.cuda.stream(stream):
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(10):
-            torch.mul(src, 1.0, out=dst)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        del src, dst
-    return 2 * nbytes / (e0.elapsed_time(e1) / 10) / 1e6
+def ceilings(n: int, stream, reps: int = 20):
+    """Measured bandwidth ceilings (GB/s) from the library's ceiling kernels:
+    a float4 copy of distribution-sized buffers, and the bare access pattern
+    of the all-liquid step (every population pulled and stored, no
+    arithmetic) in the step kernel's layout and launch, FP32 and FP16."""
+    from paper_1604_03478_amd.binding import bandwidth_ceiling
+    out = {}
+    for key, which, prec in (("copy_f32", "copy", "f32"), ("pattern_f32", "pattern", "f32"),
+                             ("pattern_f16s", "pattern", "f16s")):
+        ms, nbytes = bandwidth_ceiling(which, n, prec, 1, reps, stream=stream)
+        out[key] = {"GBps": round(nbytes / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 5),
+                    "bytes": nbytes}
+    return out
 
 
 def bottom_heated_512(stream, steps: int, warmup: int):
@@ -314,59 +315,96 @@ def cpu_baseline(n: int, steps: int):
     orc.step(1)
     el1 = time.perf_counter() - t1
     orc_mod.set_threads(cores)
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    cpu = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n ** 3 * steps / el / 1e6, "unit": "MLUPS", "cores": cores,
             "kind": "oracle", "value_1thread": n ** 3 / el1 / 1e6,
+            "cpu_model": cpu, "host_cpus": os.cpu_count(),
+            "oracle_build": "gcc " + " ".join(orc_mod.CFLAGS),
             "sample": f"{steps} steps of the {n}^3 all-liquid double-MRT state on {cores} "
                       f"threads ({n ** 3 * steps / 1e6:.1f}M FP64 cell updates, {el:.1f} s), "
                       f"then 1 step on 1 thread ({el1:.1f} s)"}
 
 
-def precision_study(n: int, steps: int, stream):
+def precision_study(n: int, steps: int, stream, samples: int = 20, emit: bool = True):
     """Same melting run (side-heated, Ra = 1e5, Pr = 1, Ste = 0.1, front seeded
-    at s0 = 1) in FP64, FP32, FP16 and BF16 storage; errors against FP64."""
+    at s0 = 1) in FP64, FP32, FP16 and BF16 storage side by side; errors
+    against the FP64 run.  At every sample: the liquid fraction, and for each
+    format the largest temperature difference; at the end, where it sits (its
+    cell, its distance along the melt axis to the FP64 front, the largest
+    difference more than two cells from the front) and the first sample at
+    which it exceeded 1e-5.  The discretization band is the FP64 run at half
+    resolution and the same Fourier number (half the steps)."""
     import numpy as np
     import torch
     from paper_1604_03478_amd import Sim
-    every = max(1, steps // 20)
-    runs = {}
-    for prec in ("f64", "f32", "f16s", "bf16s"):
-        sim = Sim(workload_config(n, prec, False), stream=stream)
-        fl, t_gpu = [], 0.0
-        for k in range(steps // every):
+    every = max(1, steps // samples)
+    precs = ("f64", "f32", "f16s", "bf16s")
+    sims = {p: Sim(workload_config(n, p, False), stream=stream) for p in precs}
+    t_gpu = {p: 0.0 for p in precs}
+    fl = {p: [] for p in precs}
+    first_1e5 = {p: None for p in precs[1:]}
+    done = 0
+    T = {}
+    while done < steps:
+        k = min(every, steps - done)
+        for p in precs:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sim.step(every)
+            sims[p].step(k)
             torch.cuda.synchronize()
-            t_gpu += time.perf_counter() - t0
-            fl.append(sim.liquid_fraction())
-            print(f"precision: {prec} step {(k + 1) * every} fl {fl[-1]:.9f}", file=sys.stderr,
-                  flush=True)
-        T = sim.fields()["T"]
-        runs[prec] = {"fl": fl, "T": T, "mlups": n ** 3 * steps / t_gpu / 1e6}
-        sim.close()
+            t_gpu[p] += time.perf_counter() - t0
+            fl[p].append(sims[p].liquid_fraction())
+        done += k
+        T = {p: sims[p].fields(which=("T",))["T"] for p in precs}
+        for p in precs[1:]:
+            if first_1e5[p] is None and float(np.abs(T[p] - T["f64"]).max()) > 1e-5:
+                first_1e5[p] = done
+        print(f"precision: step {done} fl " +
+              " ".join(f"{p} {fl[p][-1]:.9f}" for p in precs), file=sys.stderr, flush=True)
+    s64 = sims["f64"].fields(which=("s",))["s"]  # [z][x], melt axis y
+    for p in precs:
+        sims[p].close()
     # discretization band: FP64 at n/2, same Fourier number (t scales with n)
     half = n // 2
     sim = Sim(workload_config(half, "f64", False), stream=stream)
     sim.step(steps // 2)
     fl_half = sim.liquid_fraction()
     sim.close()
-    ref = runs["f64"]
+    ref = fl["f64"]
     out = {"mode": "precision", "n": n, "steps": steps, "workload":
            f"convection melting {n}^3, side-heated, Ra=1e5, Pr=1, Ste=0.1, s0=1",
-           "fl_f64": ref["fl"][-1], "fl_f64_half_resolution": fl_half,
-           "discretization_rel": abs(fl_half - ref["fl"][-1]) / ref["fl"][-1]}
-    for prec in ("f32", "f16s", "bf16s"):
-        r = runs[prec]
-        rel = [abs(a - b) / b for a, b in zip(r["fl"], ref["fl"])]
-        out[prec] = {"fl_rel_err_final": rel[-1], "fl_rel_err_max": max(rel),
-                     "max_abs_dT": float(np.abs(r["T"] - ref["T"]).max()),
-                     "mlups_melting_state": round(r["mlups"], 1)}
-    out["f64_mlups_melting_state"] = round(ref["mlups"], 1)
+           "fl_f64": ref[-1], "fl_f64_half_resolution": fl_half,
+           "discretization_rel": abs(fl_half - ref[-1]) / ref[-1]}
+    h = np.arange(n) + 0.5
+    dist = np.abs(h[None, :, None] - s64[:, None, :])  # [z][y][x]: melt-axis distance to the front
+    for p in precs[1:]:
+        rel = [abs(a - b) / b for a, b in zip(fl[p], ref)]
+        dT = np.abs(T[p] - T["f64"])
+        z, y, x = np.unravel_index(int(np.argmax(dT)), dT.shape)
+        far = dist > 2.0
+        out[p] = {"fl_rel_err_final": rel[-1], "fl_rel_err_max": max(rel),
+                  "max_abs_dT": float(dT.max()),
+                  "max_abs_dT_at": {"x": int(x), "y": int(y), "z": int(z),
+                                    "melt_axis_distance_to_front": round(float(dist[z, y, x]), 3)},
+                  "max_abs_dT_beyond_2_cells_of_front": float(dT[far].max()),
+                  "first_sample_dT_above_1e-5": first_1e5[p],
+                  "mlups_melting_state": round(n ** 3 * steps / t_gpu[p] / 1e6, 1)}
+    out["f64_mlups_melting_state"] = round(n ** 3 * steps / t_gpu["f64"] / 1e6, 1)
     band = max(out["f32"]["fl_rel_err_max"], 0.1 * out["discretization_rel"])
     out["equal_error_band"] = band
-    for prec in ("f16s", "bf16s"):
-        out[prec]["within_band"] = out[prec]["fl_rel_err_max"] <= band
-    print(json.dumps(out), flush=True)
+    for p in ("f16s", "bf16s"):
+        out[p]["within_band"] = out[p]["fl_rel_err_max"] <= band
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -380,12 +418,23 @@ def main():
     ap.add_argument("--precision-steps", type=int, default=100000)
     ap.add_argument("--precision", choices=["f32", "f16s", "bf16s", "f64"], default="f32",
                     help="storage precision of --mode profile")
+    ap.add_argument("--case", choices=["side256", "bottom512"], default="side256",
+                    help="--mode profile: the side-heated benchmark configuration (Ra = 1e5) "
+                         "or the bottom-heated large one (Ra = 1e6); --n sets the size")
+    ap.add_argument("--melting", action="store_true",
+                    help="--mode profile: the melting state (front at s0 = 1) instead of the "
+                         "all-liquid one")
     ap.add_argument("--f-wall", type=int, choices=[0, 1], default=0,
                     help="--mode paper: 1 interpolates the no-slip of f to the front")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 512^3 and adjoint legs")
+    ap.add_argument("--no-equal-error", action="store_true",
+                    help="skip the bounded precision (equal-error) leg")
+    ap.add_argument("--equal-error-steps", type=int, default=20000,
+                    help="steps of the equal-error leg at 256^3 (its 128^3 FP64 run takes "
+                         "half as many)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -419,12 +468,19 @@ def main():
         return
 
     if args.mode == "profile":
-        from paper_1604_03478_amd import Sim
-        sim = Sim(workload_config(args.n, args.precision, True), stream=stream)
+        from paper_1604_03478_amd import Config, Sim
+        if args.case == "bottom512":  # the large configuration, hot wall z = 0
+            cfg = Config(n=args.n, ra=1e6, pr=1.0, ste=0.1, s0=1.0 if args.melting else
+                         float(args.n), heating="z0", precision=args.precision)
+        else:
+            cfg = workload_config(args.n, args.precision, not args.melting)
+        sim = Sim(cfg, stream=stream)
         sim.step(args.warmup)
         ms = time_steps(sim, stream, args.steps)
-        print(json.dumps({"mode": "profile", "n": args.n, "precision": args.precision,
-                          "steps": args.steps, "ms_per_step": ms}), flush=True)
+        print(json.dumps({"mode": "profile", "case": args.case, "n": args.n,
+                          "precision": args.precision, "melting": bool(args.melting),
+                          "steps": args.steps, "ms_per_step": ms,
+                          "liquid_fraction": sim.liquid_fraction()}), flush=True)
         return
 
     if args.mode == "precision":
@@ -499,10 +555,20 @@ def main():
             "note": "front near the heated wall: solid cells move only g (56 B)",
         },
     }
-    print("bench: copy ceiling, 512^3 bottom-heated fp16, adjoint", file=sys.stderr, flush=True)
-    ceiling = copy_ceiling(stream)
-    line["roofline"]["copy_ceiling_GBps"] = round(ceiling, 1)
-    line["roofline"]["frac_of_copy"] = round(achieved / ceiling, 4)
+    print("bench: bandwidth ceilings, equal-error leg, 512^3 bottom-heated fp16, adjoint",
+          file=sys.stderr, flush=True)
+    ceil = ceilings(n, stream)
+    line["roofline"]["copy_ceiling_GBps"] = ceil["copy_f32"]["GBps"]
+    line["roofline"]["frac_of_copy"] = round(achieved / ceil["copy_f32"]["GBps"], 4)
+    line["roofline"]["pattern_ceiling_GBps"] = ceil["pattern_f32"]["GBps"]
+    line["roofline"]["frac_of_pattern"] = round(achieved / ceil["pattern_f32"]["GBps"], 4)
+    line["roofline"]["ceilings"] = ceil
+    line["fp16s"]["pattern_ceiling_GBps"] = ceil["pattern_f16s"]["GBps"]
+    line["fp16s"]["frac_of_pattern"] = round(
+        line["fp16s"]["achieved_GBps"] / ceil["pattern_f16s"]["GBps"], 4)
+    if not args.no_equal_error:
+        line["equal_error"] = precision_study(n, args.equal_error_steps, stream, samples=10,
+                                              emit=False)
     if not args.no_extras:
         line["bottom512"] = bottom_heated_512(stream, 100, 20)
         line["adjoint"] = [adjoint_timing(stream, 64, 2000, 100),

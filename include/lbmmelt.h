@@ -114,10 +114,13 @@ typedef struct {
   double q_e;     /* remaining relaxation rate of g                        */
 } lbm_lattice;
 
-/* Create a context: validates *params, maps them to lattice units, allocates
- * the double-buffered distributions in HBM and writes the initial state
- * (f at rest, g at equilibrium of the seed temperature profile, front at
- * s0).  hip_stream is a hipStream_t, or NULL for a stream the library
+/* Create a context: validates *params (the problem statement of section 1:
+ * cube of edge n, hot wall t_h, cold wall t_c <= t_m, adiabatic top and
+ * bottom, no slip everywhere, and Ra, Pr, Ste; Mach number below 0.3 as
+ * section 3.2 allows), maps them to lattice units (the time scale of
+ * Eq. (7)), allocates the double-buffered distributions in HBM and writes
+ * the initial state (f at rest, g at equilibrium of the seed temperature
+ * profile, front at s0).  hip_stream is a hipStream_t, or NULL for a stream the library
  * creates and owns.  On success *out receives the context.
  * Errors: LBM_EINVAL (bad parameter; e.g. n out of range, t_c > t_m,
  * ma >= 0.3, derived viscous relaxation time <= 0.5 + 1e-3),
@@ -140,7 +143,9 @@ int lbm_step(lbm_ctx *ctx, int64_t nsteps);
  * any step so far. */
 int lbm_liquid_fraction(lbm_ctx *ctx, double *fl);
 
-/* Copy the macroscopic fields of the current state to host memory, in FP64.
+/* Copy the macroscopic fields of the current state to host memory, in FP64
+ * (section 2: T is the sum of the D3Q7 populations of Eq. (4), rho the sum of
+ * the D3Q19 populations of Eq. (1), u the first moment of f).
  * T and rho: n^3 values each; u: 3*n^3 values (u_x, u_y, u_z planes);
  * s: n^2 values.  Any pointer may be NULL.  Solid cells report rho = 0 and
  * u = 0.  u is the velocity the collision used (momentum plus half the
@@ -209,7 +214,9 @@ int lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
  * gradient of the piecewise-smooth map along that schedule).  grad_th has
  * n^2 values in the column layout of s and points to device memory if
  * on_device != 0.  lbm_adjoint needs a preceding lbm_forward_ckpt with no
- * step taken since (else LBM_ESTATE); it does not change the state.  Both
+ * lbm_step, lbm_step_replay, lbm_set_hot_wall, lbm_set_populations or
+ * lbm_load_state since (else LBM_ESTATE): the recompute between checkpoints
+ * uses the current hot wall; it does not change the state.  Both
  * synchronize.  Every front_scheme and f_wall is covered.  Errors:
  * LBM_EINVAL, LBM_ENOMEM, LBM_ESTATE, LBM_EDEVICE. */
 int lbm_forward_ckpt(lbm_ctx *ctx, int64_t nsteps, int32_t every_k, double *fl);
@@ -236,6 +243,28 @@ int lbm_step_replay(lbm_ctx *ctx, const int32_t *schedule, int64_t nsteps);
  * steps. */
 int lbm_kernel_timing(lbm_ctx *ctx, int enable);
 int lbm_kernel_time(lbm_ctx *ctx, double *ms, int64_t *launches);
+
+/* Bandwidth ceilings for the measurement of the step kernel (a measurement
+ * aid, not part of the method; no context needed).  Kernels:
+ *   LBM_CEIL_COPY     a float4 copy of buffers the size of one step's
+ *                     distributions at (n, precision, flow), each byte read
+ *                     once and written once (non-temporal stores);
+ *   LBM_CEIL_PATTERN  the bare access pattern of the all-liquid step in the
+ *                     step kernel's row-interleaved layout, launch shape and
+ *                     row order: every population pulled from its source
+ *                     (bounce-back addresses at the walls) and stored, with
+ *                     no arithmetic.
+ * The buffers (four distribution-sized device allocations) are allocated,
+ * zero-filled and freed here.  Two untimed launches, then reps >= 1 launches
+ * timed with HIP events on hip_stream (a hipStream_t; NULL is the default
+ * stream): *ms_per_launch their average duration, *bytes_per_launch the bytes
+ * one launch moves (for the pattern the algorithmic 2 (19 + 7) n^3 element
+ * bytes; without flow 2 * 7 n^3).  Synchronizes.  Errors: LBM_EINVAL,
+ * LBM_ENOMEM, LBM_EDEVICE. */
+typedef enum { LBM_CEIL_COPY = 0, LBM_CEIL_PATTERN = 1 } lbm_ceiling;
+int lbm_bandwidth_ceiling(int32_t which, int32_t n, int32_t precision, int32_t flow,
+                          int32_t reps, void *hip_stream, double *ms_per_launch,
+                          double *bytes_per_launch);
 
 /* Thread-local message describing the last error of this thread. */
 const char *lbm_last_error(void);

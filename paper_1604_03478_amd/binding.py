@@ -63,8 +63,8 @@ EXPORTS = ("lbm_init", "lbm_destroy", "lbm_step", "lbm_liquid_fraction", "lbm_fi
            "lbm_get_lattice", "lbm_get_step", "lbm_set_hot_wall", "lbm_set_populations",
            "lbm_get_populations", "lbm_diagnostics", "lbm_save_state", "lbm_load_state",
            "lbm_forward_ckpt", "lbm_adjoint", "lbm_get_schedule", "lbm_step_replay",
-           "lbm_wall_nusselt",
-           "lbm_kernel_timing", "lbm_kernel_time", "lbm_last_error")
+           "lbm_wall_nusselt", "lbm_kernel_timing", "lbm_kernel_time",
+           "lbm_bandwidth_ceiling", "lbm_last_error")
 
 _lib = None
 
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_step_replay.argtypes = [vp, vp, i64]
     lib.lbm_kernel_timing.argtypes = [vp, i32]
     lib.lbm_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.lbm_bandwidth_ceiling.argtypes = [i32, i32, i32, i32, i32, vp, dp, dp]
     lib.lbm_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("lbm_destroy", "lbm_last_error"):
@@ -306,6 +307,26 @@ class Sim:
     def load_state(self, blob: bytes) -> None:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(self._lib.lbm_load_state(self._h, buf, len(blob)))
+
+
+CEILINGS = {"copy": 0, "pattern": 1}
+
+
+def bandwidth_ceiling(which: str, n: int, precision: str = "f32", flow: int = 1, reps: int = 10,
+                      stream=None):
+    """(ms per launch, bytes per launch) of a bandwidth-ceiling kernel:
+    "copy" (float4 copy of distribution-sized buffers) or "pattern" (the
+    bare access pattern of the all-liquid step in its layout and launch)."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("lbmmelt needs a HIP GPU; none is visible")
+    lib = load_library()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    ms, nbytes = ctypes.c_double(), ctypes.c_double()
+    _check(lib.lbm_bandwidth_ceiling(CEILINGS[which], int(n), PRECISIONS[precision], int(flow),
+                                     int(reps), ctypes.c_void_p(stream.cuda_stream),
+                                     ctypes.byref(ms), ctypes.byref(nbytes)))
+    return ms.value, nbytes.value
 
 
 class LiquidFraction(torch.autograd.Function):

@@ -11,7 +11,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbmmelt.so")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("lbm_kernels.hip", "lbm_adjoint.hip", "lbm_diag.hip", "lbm_front_heat.hip",
-            "lbm_capi.hip")]
+            "lbm_ceiling.hip", "lbm_capi.hip")]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.  Code
 # object v5 keeps the library loadable by the HIP runtime that ships with the

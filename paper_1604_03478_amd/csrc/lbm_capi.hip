@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "lbm_adjoint.h"
+#include "lbm_ceiling.h"
 #include "lbm_diag.h"
 #include "lbm_front_heat.h"
 #include "lbm_internal.h"
@@ -116,13 +117,15 @@ struct lbm_ctx {
   int* cnt = nullptr;
   int* cmin = nullptr;
   int* cmax = nullptr;
+  int* rowmax = nullptr;  // largest cmax per row of columns (16-bit storage)
   int* melted = nullptr;
   int* frozen = nullptr;
   int* flag = nullptr;
   double* th = nullptr;
   double* red = nullptr;
+  double* dpart = nullptr;   // partial sums of the diagnostics reductions
   double* seedT = nullptr;
-  double* fields = nullptr;  // 5 * n^3 FP64 scratch for fields and diagnostics
+  double* fields = nullptr;  // 5 * n^3 FP64 scratch for the field output
   double* wall = nullptr;    // n^2 FP64 scratch of per-column wall diagnostics
   double* heat = nullptr;    // n^2 FP64 front heat of a step (front_scheme 1)
   int64_t step = 0;
@@ -179,7 +182,7 @@ void release(lbm_ctx* c) {
   release_adjoint(c->adj);
   void* ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->s[0], c->s[1], c->cnt,  c->cmin,
                   c->cmax, c->melted, c->frozen, c->flag, c->th,  c->red,  c->seedT, c->fields,
-                  c->sched, c->replay, c->wall, c->heat};
+                  c->sched, c->replay, c->wall, c->heat, c->dpart, c->rowmax};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -253,7 +256,7 @@ int derive(const lbm_params* p, lbm_lattice* L) {
 
 int refresh_masks(lbm_ctx* c) {
   HIP_TRY(lbmk::launch_counts(c->kp, c->s[c->scur], c->cnt, c->stream));
-  HIP_TRY(lbmk::launch_neighbourhood(c->kp, c->cnt, c->cmin, c->cmax, c->stream));
+  HIP_TRY(lbmk::launch_neighbourhood(c->kp, c->cnt, c->cmin, c->cmax, c->rowmax, c->stream));
   return LBM_OK;
 }
 
@@ -387,9 +390,11 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
     }
   if ((rc = dalloc(&c->s[0], nn)) || (rc = dalloc(&c->s[1], nn)) || (rc = dalloc(&c->cnt, nn)) ||
       (rc = dalloc(&c->cmin, nn)) || (rc = dalloc(&c->cmax, nn)) ||
+      (rc = dalloc(&c->rowmax, (size_t)n)) ||
       (rc = dalloc(&c->melted, nn)) || (rc = dalloc(&c->frozen, nn)) ||
       (rc = dalloc(&c->flag, 1)) || (rc = dalloc(&c->th, nn)) || (rc = dalloc(&c->red, 8)) ||
       (rc = dalloc(&c->seedT, (size_t)n)) ||
+      (rc = dalloc(&c->dpart, lbmk::diag_scratch_doubles(n))) ||
       (params->front_scheme == 1 && (rc = dalloc(&c->heat, nn))))
     return bail(rc);
 
@@ -465,8 +470,8 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
       HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
     }
     HIP_TRY(lbmk::launch_stream_collide(c->kind, k, c->f[c->cur], c->f[nx], c->g[c->cur], c->g[nx],
-                                        c->cnt, c->cmin, c->cmax, c->s[c->scur], c->th, c->flag,
-                                        c->stream));
+                                        c->cnt, c->cmin, c->cmax, c->rowmax, c->s[c->scur], c->th,
+                                        c->flag, c->stream));
     if (c->timing) {
       HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
       c->ev_used += 2;
@@ -481,7 +486,7 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
                                c->th, c->melted, c->frozen, c->flag, nullptr, nullptr, rec,
                                c->heat, c->stream));
     if (lbmk::uses_neighbourhood(c->kind))
-      HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
+      HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->rowmax, c->stream));
     c->cur = nx;
     c->scur = sx;
     c->step++;
@@ -558,6 +563,7 @@ int lbm_set_hot_wall(lbm_ctx* c, const double* th, int on_device) {
   if (rc) return rc;
   if (!th) return fail(LBM_EINVAL, "th is NULL");
   const size_t nn = (size_t)c->p.n * c->p.n;
+  c->adj.ready = false;  // a recorded run no longer matches the wall it ran with
   HIP_TRY(hipMemcpyAsync(c->th, th, nn * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
   if (!on_device) HIP_TRY(hipStreamSynchronize(c->stream));  // host buffer may be reused
@@ -570,6 +576,7 @@ int lbm_set_populations(lbm_ctx* c, const double* f, const double* g, const doub
   if (c->p.flow && !f) return fail(LBM_EINVAL, "f is required when flow == 1");
   if (!g || !s) return fail(LBM_EINVAL, "g and s are required");
   const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
+  c->adj.ready = false;  // the state no longer ends a recorded run
   double* tmp = nullptr;
   if ((rc = dalloc(&tmp, (c->p.flow ? 19 : 7) * nc))) return rc;
   auto done = [&](int code) {
@@ -623,25 +630,11 @@ int lbm_diagnostics(lbm_ctx* c, double out[5]) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (!out) return fail(LBM_EINVAL, "out is NULL");
-  if ((rc = ensure_fields(c))) return rc;
-  const size_t nc = c->kp.ncell, nn = (size_t)c->p.n * c->p.n;
-  double* d = c->fields;
-  HIP_TRY(lbmk::launch_fields(c->kind, c->kp, c->f[c->cur], c->g[c->cur], c->cnt, d, nullptr,
-                              nullptr, nullptr, d + 4 * nc, c->stream));
-  // each reduction over its own array length: rho and T have n^3 values, s has n^2
-  HIP_TRY(lbmk::launch_sum(d + 4 * nc, (int64_t)nc, c->red + 0, c->stream));
-  HIP_TRY(lbmk::launch_sum(d, (int64_t)nc, c->red + 1, c->stream));
-  HIP_TRY(lbmk::launch_sum(c->s[c->scur], (int64_t)nn, c->red + 2, c->stream));
-  HIP_TRY(lbmk::launch_sum_int(c->melted, (int64_t)nn, c->red + 4, c->stream));
-  HIP_TRY(lbmk::launch_sum_int(c->frozen, (int64_t)nn, c->red + 5, c->stream));
-  double h[8];
-  HIP_TRY(hipMemcpyAsync(h, c->red, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(lbmk::launch_diag_sums(c->kind, c->kp, c->f[c->cur], c->g[c->cur], c->cnt,
+                                 c->s[c->scur], c->melted, c->frozen, c->dpart, c->stream));
+  HIP_TRY(hipMemcpyAsync(out, c->dpart + 5 * (size_t)lbmk::diag_blocks(c->p.n),
+                         5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  out[0] = h[0];
-  out[1] = h[1] - (double)nc * c->p.t_m;
-  out[2] = h[2];
-  out[3] = h[4];
-  out[4] = h[5];
   return check_unstable(c);
 }
 
@@ -697,6 +690,7 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes) {
   if (h.n != c->p.n || h.precision != c->p.precision || h.flow != c->p.flow ||
       h.heating != c->p.heating || h.ncell != nc)
     return fail(LBM_EINVAL, "state blob was made by an incompatible context");
+  c->adj.ready = false;  // the state no longer ends a recorded run
   const char* b = static_cast<const char*>(host_buf) + sizeof(h);
   if (fb) HIP_TRY(hipMemcpyAsync(c->f[c->cur], b, fb, hipMemcpyHostToDevice, c->stream));
   b += fb;
@@ -798,7 +792,8 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   if (!grad_th) return fail(LBM_EINVAL, "grad_th is NULL");
   AdjData& a = c->adj;
   if (!a.ready || c->step != a.end)
-    return fail(LBM_ESTATE, "lbm_adjoint needs lbm_forward_ckpt with no step taken since");
+    return fail(LBM_ESTATE, "lbm_adjoint needs lbm_forward_ckpt with no step, state change "
+                "or hot-wall change since");
   const size_t nn = (size_t)c->p.n * c->p.n, nc = c->kp.ncell;
   const bool flow = c->p.flow != 0;
   const size_t fb = flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
@@ -855,9 +850,10 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
       // the front kernel leaves the counts of the next state behind
       if (t == 0) HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
       if (lbmk::uses_neighbourhood(c->kind))
-        HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin, a.cmax, c->stream));
+        HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin, a.cmax, nullptr, c->stream));
+      // the one-cell path throughout (no row maxima): bit for bit the forward run
       HIP_TRY(lbmk::launch_stream_collide(c->kind, k, a.sf[t], a.sf[t + 1], a.sg[t], a.sg[t + 1],
-                                          a.cnt, a.cmin, a.cmax, a.ss[t], c->th, a.flag,
+                                          a.cnt, a.cmin, a.cmax, nullptr, a.ss[t], c->th, a.flag,
                                           c->stream));
       if (c->heat)  // conservative front: heat of the streaming from the state sg[t]
         HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], a.cnt, c->heat, c->stream));
@@ -952,14 +948,15 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
   HIP_TRY(hipMemcpyAsync(c->cnt, c->replay, nn * sizeof(int), hipMemcpyDeviceToDevice,
                          c->stream));
   lbmk::KParams& k = c->kp;
-  HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
+  HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->rowmax, c->stream));
   for (int64_t t = 0; t < nsteps; ++t) {
     const int nx = c->cur ^ 1, sx = c->scur ^ 1;
     const int* e = c->replay + (size_t)t * 3 * nn;
     k.step = (uint32_t)c->step;
+    // the one-cell path throughout (no row maxima): bit for bit the recorded run
     HIP_TRY(lbmk::launch_stream_collide(c->kind, k, c->f[c->cur], c->f[nx], c->g[c->cur], c->g[nx],
-                                        c->cnt, c->cmin, c->cmax, c->s[c->scur], c->th, c->flag,
-                                        c->stream));
+                                        c->cnt, c->cmin, c->cmax, nullptr, c->s[c->scur], c->th,
+                                        c->flag, c->stream));
     if (c->heat)  // conservative front: heat of the streaming from the state g[cur]
       HIP_TRY(lbmk::launch_front_heat(c->kind, k, c->g[c->cur], c->s[c->scur], c->cnt, c->heat,
                                       c->stream));
@@ -967,7 +964,7 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
                                c->th, c->melted, c->frozen, c->flag, e, e + 3 * nn, nullptr,
                                c->heat, c->stream));
     if (lbmk::uses_neighbourhood(c->kind))
-      HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->stream));
+      HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->rowmax, c->stream));
     c->cur = nx;
     c->scur = sx;
     c->step++;
@@ -998,6 +995,72 @@ int lbm_kernel_time(lbm_ctx* c, double* ms, int64_t* launches) {
   *launches = (int64_t)(c->ev_used / 2);
   c->ev_used = 0;
   return LBM_OK;
+}
+
+int lbm_bandwidth_ceiling(int32_t which, int32_t n, int32_t precision, int32_t flow,
+                          int32_t reps, void* hip_stream, double* ms_per_launch,
+                          double* bytes_per_launch) {
+  if (which != LBM_CEIL_COPY && which != LBM_CEIL_PATTERN)
+    return fail(LBM_EINVAL, "which = %d is not an lbm_ceiling", which);
+  if (n < 4 || n > 1024) return fail(LBM_EINVAL, "n = %d outside [4, 1024]", n);
+  if (precision < LBM_F64 || precision > LBM_BF16S)
+    return fail(LBM_EINVAL, "precision = %d is not an lbm_precision", precision);
+  if (flow != 0 && flow != 1) return fail(LBM_EINVAL, "flow must be 0 or 1");
+  if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
+  if (!ms_per_launch || !bytes_per_launch)
+    return fail(LBM_EINVAL, "ms_per_launch and bytes_per_launch are required");
+  lbmk::KParams k{};
+  k.n = n;
+  k.ncell = (uint32_t)((size_t)n * n * n);
+  k.pitch = lbmk::row_pitch(n, precision);
+  k.flow = flow;
+  const size_t esz = lbmk::store_bytes(precision), nn = (size_t)n * n;
+  const size_t fb = flow ? 19 * (size_t)k.pitch * nn * esz : 0, gb = 7 * (size_t)k.pitch * nn * esz;
+  hipStream_t st = (hipStream_t)hip_stream;
+  void* buf[4] = {nullptr, nullptr, nullptr, nullptr};  // fs, fd, gs, gd
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  auto done = [&](int code) {
+    (void)hipStreamSynchronize(st);
+    for (void* p : buf)
+      if (p) (void)hipFree(p);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    return code;
+  };
+  const size_t sizes[4] = {fb, fb, gb, gb};
+  for (int b = 0; b < 4; ++b) {
+    if (!sizes[b]) continue;
+    if (hipMalloc(&buf[b], sizes[b]) != hipSuccess) {
+      buf[b] = nullptr;
+      return done(fail(LBM_ENOMEM, "cannot allocate %zu bytes", sizes[b]));
+    }
+    if (hipMemsetAsync(buf[b], 0, sizes[b], st) != hipSuccess)
+      return done(fail(LBM_EDEVICE, "hipMemsetAsync failed"));
+  }
+  auto launch = [&]() -> hipError_t {
+    if (which == LBM_CEIL_PATTERN)
+      return lbmk::launch_pull_pattern(precision, k, buf[0], buf[1], buf[2], buf[3], st);
+    hipError_t e = lbmk::launch_copy4(buf[2], buf[3], gb, st);  // g rows, then f rows
+    if (e == hipSuccess && fb) e = lbmk::launch_copy4(buf[0], buf[1], fb, st);
+    return e;
+  };
+  for (int w = 0; w < 2; ++w)
+    if (launch() != hipSuccess) return done(fail(LBM_EDEVICE, "ceiling kernel launch failed"));
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+    return done(fail(LBM_EDEVICE, "hipEventCreate failed"));
+  if (hipEventRecord(ev[0], st) != hipSuccess) return done(fail(LBM_EDEVICE, "event record"));
+  for (int r = 0; r < reps; ++r)
+    if (launch() != hipSuccess) return done(fail(LBM_EDEVICE, "ceiling kernel launch failed"));
+  if (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess)
+    return done(fail(LBM_EDEVICE, "ceiling kernels failed on the device"));
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
+    return done(fail(LBM_EDEVICE, "hipEventElapsedTime failed"));
+  *ms_per_launch = (double)ms / reps;
+  *bytes_per_launch = which == LBM_CEIL_PATTERN
+                          ? 2.0 * ((flow ? 19.0 : 0.0) + 7.0) * (double)k.ncell * (double)esz
+                          : 2.0 * (double)(fb + gb);
+  return done(LBM_OK);
 }
 
 }  // extern "C"

@@ -168,6 +168,37 @@ static_assert(opp19(8) == 9 && opp19(11) == 14 && opp19(12) == 13 && opp19(15) =
 constexpr double kW7Axis = 0.125;  // D3Q7 weight of the six moving directions
 constexpr double kW7Rest = 0.25;
 
+// --------------------------------------------------------------- launch order
+// Largest workgroup of the step kernel (one lattice row, or part of one, per
+// workgroup) for a storage format of `bytes` per value.
+__host__ __device__ constexpr int step_block_max(size_t bytes) { return bytes == 2 ? 256 : 512; }
+
+// One lattice row per workgroup, so the row pointers are uniform over it.
+// The workgroups of the n x n rows are numbered r = blockIdx.z * n +
+// blockIdx.y, the order in which they are dispatched.  The 4n - 4 rows on the
+// y and z walls, which always take the general path, come first; the
+// interior rows follow in z-major order.  In plane order the wall plane
+// z = n - 1 came last, and its slow rows formed a tail: at 256^3 the melting
+// step took 214 instead of 179 us (FP32), 167 instead of 141 us (FP16).
+__device__ __forceinline__ void step_row(int n, int& y, int& z) {
+  const int r = blockIdx.z * n + blockIdx.y, nw = 4 * n - 4;
+  if (r < n) {
+    y = r;
+    z = 0;
+  } else if (r < 2 * n) {
+    y = r - n;
+    z = n - 1;
+  } else if (r < nw) {  // the y walls of the planes 0 < z < n - 1
+    const int k = r - 2 * n;
+    z = 1 + (k >> 1);
+    y = (k & 1) ? n - 1 : 0;
+  } else {
+    const int k = r - nw;
+    z = 1 + k / (n - 2);
+    y = 1 + (k - (z - 1) * (n - 2));
+  }
+}
+
 // number of cells a in [0, n) with a + 1/2 < s (exact: s - 1/2 is exact in FP64)
 __device__ __forceinline__ int count_liquid(double sv, int n) {
   double c = ceil(sv - 0.5);

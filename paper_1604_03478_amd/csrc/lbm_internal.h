@@ -55,12 +55,15 @@ inline bool uses_neighbourhood(int kind) { return store_bytes(kind) == 2; }
 // One fused stream + collide pass over all cells: reads (fs, gs), writes
 // (fd, gd).  cnt/cmin/cmax: liquid-cell count per column and its min / max
 // over the 3x3 column neighbourhood (cmin/cmax are read only for 16-bit
-// storage, see uses_neighbourhood).  s: front per column.  th: hot-wall
+// storage, see uses_neighbourhood).  rowmax (16-bit storage, may be null):
+// the largest cmax of every row of columns, from launch_neighbourhood; with
+// it the lattice rows whose stencils are all solid skip the per-cell phase
+// loads (the same results bit for bit).  s: front per column.  th: hot-wall
 // temperature per column.  flag: set to 1 when a non-finite value appears.
 hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, void* fd,
                                  const void* gs, void* gd, const int* cnt, const int* cmin,
-                                 const int* cmax, const double* s, const double* th, int* flag,
-                                 hipStream_t st);
+                                 const int* cmax, const int* rowmax, const double* s,
+                                 const double* th, int* flag, hipStream_t st);
 
 // Interface update (Eq. (6)) of every column from the post-collision g, then
 // the phase switch: s_new, cnt (in place), refill of f in newly liquid cells,
@@ -77,9 +80,11 @@ hipError_t launch_front(int kind, const KParams& P, const double* s_old, double*
                         int* record, const double* heat, hipStream_t st);
 
 // cmin/cmax: min and max of cnt over the 3x3 columns around each column (the
-// columns in the box), for the fast-path test of the 16-bit step kernel.
+// columns in the box), for the fast-path test of the 16-bit step kernel;
+// rowmax (n values, may be null): the largest cmax over each row of columns
+// (all x for one value of the other lateral index).
 hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
-                                hipStream_t st);
+                                int* rowmax, hipStream_t st);
 
 // cnt from s.
 hipError_t launch_counts(const KParams& P, const double* s, int* cnt, hipStream_t st);
@@ -104,6 +109,5 @@ hipError_t launch_from_storage(int kind, const KParams& P, int q_count, const vo
 // Deterministic FP64 sum (fixed order; no atomics) of v[0..count) into
 // out[0].  count must not exceed the number of elements v points to.
 hipError_t launch_sum(const double* v, int64_t count, double* out, hipStream_t st);
-hipError_t launch_sum_int(const int* v, int64_t count, double* out, hipStream_t st);
 
 }  // namespace lbmk

@@ -470,30 +470,49 @@ __device__ __forceinline__ void update_cell(
   for (int q = 0; q < 7; ++q) store_stream(gr, q * pitch + x, g[q], rs);
 }
 
-// One lattice row per workgroup, so the row pointers are uniform over it.
-// The workgroups of the n x n rows are numbered r = blockIdx.z * n +
-// blockIdx.y, the order in which they are dispatched.  The 4n - 4 rows on the
-// y and z walls, which always take the general path, come first; the
-// interior rows follow in z-major order.  In plane order the wall plane
-// z = n - 1 came last, and its slow rows formed a tail: at 256^3 the melting
-// step took 214 instead of 179 us (FP32), 167 instead of 141 us (FP16).
-__device__ __forceinline__ void step_row(int n, int& y, int& z) {
-  const int r = blockIdx.z * n + blockIdx.y, nw = 4 * n - 4;
-  if (r < n) {
-    y = r;
-    z = 0;
-  } else if (r < 2 * n) {
-    y = r - n;
-    z = n - 1;
-  } else if (r < nw) {  // the y walls of the planes 0 < z < n - 1
-    const int k = r - 2 * n;
-    z = 1 + (k >> 1);
-    y = (k & 1) ? n - 1 : 0;
-  } else {
-    const int k = r - nw;
-    z = 1 + k / (n - 2);
-    y = 1 + (k - (z - 1) * (n - 2));
+// A cell of a lattice row whose cells and 3x3x3 stencils are all solid, off
+// the y and z walls (16-bit storage): only g moves.  The row is known to be
+// such a row from one uniform load (the row maximum of the liquid counts), so
+// the cell issues its 7 population loads at once, without first loading the
+// liquid counts of its column and their neighbourhood extremes.  Those solid
+// cells are latency-bound (14 bytes of loads per cell); the round trip saved
+// is a quarter of their time.  The arithmetic, the x-wall bounce-back and
+// the rounding stream are those of the fast path of update_cell, so the
+// results are the same bit for bit.
+template <typename Ts, bool FLOW, bool MZ>
+__device__ __forceinline__ void solid_cell(int x, int y, int z, const Ts* __restrict__ gs,
+                                           Ts* __restrict__ gd, int* __restrict__ flag,
+                                           const KParams& P) {
+  using C = typename Compute<Ts>::type;
+  using G = typename Compute<Ts>::gtype;
+  const int n = P.n;
+  if (x >= n) return;
+  const uint32_t pitch = P.pitch;
+  const Ts* gb = row_ptr<7>(gs, P, y - 1, z - 1);  // y, z are interior rows
+  const uint32_t un = (uint32_t)n;
+  auto row_ofs = [&](uint32_t Q, int dy, int dz) {  // row (y + dy, z + dz)
+    return ((uint32_t)(1 + dz) * un + (uint32_t)(1 + dy)) * (Q * pitch);
+  };
+  G g[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const int ex = ex7(q);
+    uint32_t i = row_ofs(7, -ey7(q), -ez7(q)) + q * pitch + (uint32_t)(x - ex);
+    if (ex != 0) {  // adiabatic x wall: bounce-back
+      const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
+      i = wall ? row_ofs(7, 0, 0) + opp7(q) * pitch + x : i;
+    }
+    g[q] = load_stream<G>(gb, i);
   }
+  const Rates<C, G> r = make_rates<C, G>(P);
+  C fdummy[19];  // not read: the cell is solid
+  if (collide<FLOW>(fdummy, g, false, r)) *flag = 1;
+  const uint32_t nn = (uint32_t)n * (uint32_t)n;
+  const uint32_t self = (uint32_t)z * nn + (uint32_t)y * (uint32_t)n + (uint32_t)x;
+  uint32_t rs = mix32(self * 0x9e3779b1u + P.step * 0x85ebca77u);
+  Ts* gr = row_ptr<7>(gd, P, y, z);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) store_stream(gr, q * pitch + x, g[q], rs);
 }
 
 template <typename Ts, bool FLOW, bool MZ, bool FWALL>
@@ -510,24 +529,36 @@ __global__ __launch_bounds__(512) void k_stream_collide(
 
 // The same for 16-bit storage, held to 7 or 8 resident waves per SIMD.  Its
 // instruction stream is long for the bytes it moves (conversions and the
-// rounding of 26 values), and more resident waves hide more of it.  FP16 with
-// the melt axis y and the halfway no-slip of f fits 8 waves (64 VGPRs, a
-// 12-byte spill per lane), and so does the conduction-only step (g alone).
-// Every other instantiation needs 65 VGPRs for the phase mask of its general
-// path: it spills 32 bytes at 8 waves and none at 7, and runs 5-20 % faster
-// at 7.  (For FP32 an 8-wave limit spills 60 bytes and costs 24 %.)
+// rounding of 26 values), and more resident waves hide more of it.  The
+// conduction-only step (g alone) fits 8 waves.  With flow the general path
+// needs 65 VGPRs for its phase mask: at 8 waves it spills, at 7 nothing
+// does.  FP16 with the melt axis y once ran at 8 with a 12-byte spill; with
+// the solid-row path (solid_cell) that spill grew to 32 bytes and the
+// all-liquid 256^3 step went from 305 to 404 us, while at 7 waves it takes
+// 304 us.  (For FP32 an 8-wave limit spills 60 bytes and costs 24 %.)
 template <typename Ts, bool FLOW, bool MZ, bool FWALL>
-constexpr int kWaves16 = !FLOW || (__is_same(Ts, _Float16) && !MZ && !FWALL) ? 8 : 7;
+constexpr int kWaves16 = !FLOW ? 8 : 7;
 template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 __global__ __launch_bounds__(512) __attribute__((
     amdgpu_waves_per_eu(kWaves16<Ts, FLOW, MZ, FWALL>, kWaves16<Ts, FLOW, MZ, FWALL>))) void
 k_stream_collide_h(const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
                    Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
-                   const int* __restrict__ cmax, const double* __restrict__ s,
-                   const double* __restrict__ th, int* __restrict__ flag, KParams P) {
+                   const int* __restrict__ cmax, const int* __restrict__ rowmax,
+                   const double* __restrict__ s, const double* __restrict__ th,
+                   int* __restrict__ flag, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y, z;
   step_row(P.n, y, z);
+  if (rowmax) {
+    // rowmax[o]: the largest liquid count over the 3x3 neighbourhoods of the
+    // columns with this other-lateral index, so every stencil of the row is
+    // solid when its height a satisfies a - 1 >= rowmax[o] (uniform)
+    const int n = P.n, a = MZ ? z : y, o = MZ ? y : z;
+    if (a - 1 >= rowmax[o] && a <= n - 2 && o >= 1 && o <= n - 2) {
+      solid_cell<Ts, FLOW, MZ>(x, y, z, gs, gd, flag, P);
+      return;
+    }
+  }
   update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, cmin, cmax, s, th, flag, P);
 }
 
@@ -677,25 +708,46 @@ __global__ void k_counts(const double* __restrict__ s, int* __restrict__ cnt, in
   if (i < n * n) cnt[i] = count_liquid(s[i], n);
 }
 
-__global__ void k_neighbourhood(const int* __restrict__ cnt, int* __restrict__ cmin,
-                                int* __restrict__ cmax, int n) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int o = blockIdx.y;
-  if (x >= n) return;
-  int lo = 0x7fffffff, hi = -1;
-  for (int d_o = -1; d_o <= 1; ++d_o) {
-    const int oo = o + d_o;
-    if (oo < 0 || oo >= n) continue;
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int xx = x + dx;
-      if (xx < 0 || xx >= n) continue;
-      const int c = cnt[oo * n + xx];
-      lo = c < lo ? c : lo;
-      hi = c > hi ? c : hi;
+// One workgroup per row of columns o: cmin / cmax of every column's 3x3
+// neighbourhood, and (rowmax != null) the largest cmax of the row, which
+// bounds the liquid counts near every cell of the lattice rows with this o.
+constexpr int kNbThreads = 256;
+__global__ __launch_bounds__(kNbThreads) void k_neighbourhood(const int* __restrict__ cnt,
+                                                              int* __restrict__ cmin,
+                                                              int* __restrict__ cmax,
+                                                              int* __restrict__ rowmax, int n) {
+  __shared__ int sh[kNbThreads / 64];
+  const int o = blockIdx.x;
+  int rmax = -1;
+  for (int x = threadIdx.x; x < n; x += kNbThreads) {
+    int lo = 0x7fffffff, hi = -1;
+    for (int d_o = -1; d_o <= 1; ++d_o) {
+      const int oo = o + d_o;
+      if (oo < 0 || oo >= n) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xx = x + dx;
+        if (xx < 0 || xx >= n) continue;
+        const int c = cnt[oo * n + xx];
+        lo = c < lo ? c : lo;
+        hi = c > hi ? c : hi;
+      }
     }
+    cmin[o * n + x] = lo;
+    cmax[o * n + x] = hi;
+    rmax = hi > rmax ? hi : rmax;
   }
-  cmin[o * n + x] = lo;
-  cmax[o * n + x] = hi;
+  if (!rowmax) return;  // uniform
+  for (int off = 32; off > 0; off >>= 1) {
+    const int v = __shfl_down(rmax, off, 64);
+    rmax = v > rmax ? v : rmax;
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = rmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int m = sh[0];
+    for (int w = 1; w < kNbThreads / 64; ++w) m = sh[w] > m ? sh[w] : m;
+    rowmax[o] = m;
+  }
 }
 
 // --------------------------------------------------------------- init, fields
@@ -812,35 +864,31 @@ __global__ __launch_bounds__(kSumThreads) void k_sum(const double* __restrict__ 
   if (threadIdx.x == 0) out[0] = t;
 }
 
-__global__ __launch_bounds__(kSumThreads) void k_sum_int(const int* __restrict__ v, int64_t count,
-                                                         double* __restrict__ out) {
-  __shared__ double sh[kSumThreads / 64];
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += kSumThreads) acc += (double)v[i];
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[0] = t;
-}
-
 // --------------------------------------------------------------- dispatch
 template <typename Ts>
 hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* gs, void* gd,
-                       const int* cnt, const int* cmin, const int* cmax, const double* s,
-                       const double* th, int* flag, hipStream_t st) {
+                       const int* cnt, const int* cmin, const int* cmax, const int* rowmax,
+                       const double* s, const double* th, int* flag, hipStream_t st) {
   auto F = static_cast<const Ts*>(fs);
   auto Fd = static_cast<Ts*>(fd);
   auto G = static_cast<const Ts*>(gs);
   auto Gd = static_cast<Ts*>(gd);
-  // one whole x row per workgroup (up to 512 cells): the +-1-shifted loads of
-  // a row hit cache lines the same workgroup fetches, and the row pointers are
-  // uniform
-  const int bx = P.n >= 512 ? 512 : ((P.n + 63) / 64) * 64;
+  // one whole x row per workgroup (up to 512 cells; 256 with 16-bit
+  // storage): the +-1-shifted loads of a row hit cache lines the same
+  // workgroup fetches, and the row pointers are uniform.  The 16-bit kernels
+  // run 7 waves per SIMD, 28 per compute unit: workgroups of 8 waves leave 4
+  // of those slots empty, workgroups of 4 fill all of them (512^3,
+  // bottom-heated FP16: melting state 786 -> 713 us, all-liquid 2520 -> 2445
+  // us per step, two runs each)
+  const int bmax = step_block_max(sizeof(Ts));
+  const int bx = P.n >= bmax ? bmax : ((P.n + 63) / 64) * 64;
   dim3 block(bx, 1, 1);
   dim3 grid((P.n + bx - 1) / bx, P.n, P.n);
 #define LAUNCH(FLOW, MZ, FWALL)                                                                \
   do {                                                                                          \
     if constexpr (sizeof(Ts) == 2)                                                              \
       hipLaunchKernelGGL((k_stream_collide_h<Ts, FLOW, MZ, FWALL>), grid, block, 0, st, F, Fd, \
-                         G, Gd, cnt, cmin, cmax, s, th, flag, P);                               \
+                         G, Gd, cnt, cmin, cmax, rowmax, s, th, flag, P);                       \
     else                                                                                        \
       hipLaunchKernelGGL((k_stream_collide<Ts, FLOW, MZ, FWALL>), grid, block, 0, st, F, Fd, G, \
                          Gd, cnt, cmin, cmax, s, th, flag, P);                                  \
@@ -957,9 +1005,9 @@ size_t store_bytes(int kind) {
 
 hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, void* fd,
                                  const void* gs, void* gd, const int* cnt, const int* cmin,
-                                 const int* cmax, const double* s, const double* th, int* flag,
-                                 hipStream_t st) {
-#define CALL(T) sc_dispatch<T>(P, fs, fd, gs, gd, cnt, cmin, cmax, s, th, flag, st)
+                                 const int* cmax, const int* rowmax, const double* s,
+                                 const double* th, int* flag, hipStream_t st) {
+#define CALL(T) sc_dispatch<T>(P, fs, fd, gs, gd, cnt, cmin, cmax, rowmax, s, th, flag, st)
   switch (kind) {
     case kF64: return CALL(double);
     case kF32: return CALL(float);
@@ -988,10 +1036,9 @@ hipError_t launch_front(int kind, const KParams& P, const double* s_old, double*
 }
 
 hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
-                                hipStream_t st) {
-  dim3 block(64, 1, 1);
-  dim3 grid((P.n + 63) / 64, P.n, 1);
-  hipLaunchKernelGGL(k_neighbourhood, grid, block, 0, st, cnt, cmin, cmax, P.n);
+                                int* rowmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_neighbourhood, dim3(P.n), dim3(kNbThreads), 0, st, cnt, cmin, cmax,
+                     rowmax, P.n);
   return hipGetLastError();
 }
 
@@ -1060,10 +1107,5 @@ hipError_t launch_sum(const double* v, int64_t count, double* out, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_sum_int(const int* v, int64_t count, double* out, hipStream_t st) {
-  if (!v || !out || count < 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sum_int, dim3(1), dim3(kSumThreads), 0, st, v, count, out);
-  return hipGetLastError();
-}
 
 }  // namespace lbmk
