@@ -8,7 +8,8 @@ linear seed profile, 20000 steps.  Values come from the FP64 CPU oracle only
 
 Output (text): the liquid fraction every 500 steps, the front of every column
 at the end, and the temperature at 2048 seeded cell indices plus the full
-mid-plane line x = z = 32 at the end.
+mid-plane line x = z = 32 at the end.  Output (binary, numpy .npy, FP64): the
+whole final temperature field, [z][y][x].
 """
 import os
 import sys
@@ -23,6 +24,7 @@ from oracle import OracleSim  # noqa: E402
 
 N, STEPS, EVERY = 64, 20000, 500
 OUT = os.path.join(HERE, "conv64_ra1e4_oracle.txt")
+OUT_T = os.path.join(HERE, "conv64_ra1e4_oracle_T.npy")
 
 
 def sample_cells(n, k=2048, seed=12345):
@@ -55,7 +57,8 @@ def main():
             fh.write(f"T {c} {T[c]:.17e}\n")
         for y, v in enumerate(line):
             fh.write(f"Tline {y} {v:.17e}\n")
-    print("wrote", OUT)
+    np.save(OUT_T, np.ascontiguousarray(F["T"], dtype=np.float64), allow_pickle=False)
+    print("wrote", OUT, OUT_T)
 
 
 if __name__ == "__main__":

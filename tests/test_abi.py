@@ -69,3 +69,16 @@ def test_null_arguments_are_rejected():
     assert lib.lbm_step_replay(None, None, 1) == LBM_EINVAL
     assert lib.lbm_wall_nusselt(None, None) == LBM_EINVAL
     lib.lbm_destroy(None)
+
+
+def test_bandwidth_ceiling_rejects_invalid_arguments():
+    from paper_1604_03478_amd.binding import LBM_EINVAL, load_library
+    lib = load_library()
+    ms, nb = ctypes.c_double(), ctypes.c_double()
+    args = (ctypes.byref(ms), ctypes.byref(nb))
+    assert lib.lbm_bandwidth_ceiling(2, 64, 1, 1, 1, None, *args) == LBM_EINVAL
+    assert lib.lbm_bandwidth_ceiling(0, 3, 1, 1, 1, None, *args) == LBM_EINVAL
+    assert lib.lbm_bandwidth_ceiling(1, 64, 4, 1, 1, None, *args) == LBM_EINVAL
+    assert lib.lbm_bandwidth_ceiling(1, 64, 1, 2, 1, None, *args) == LBM_EINVAL
+    assert lib.lbm_bandwidth_ceiling(1, 64, 1, 1, 0, None, *args) == LBM_EINVAL
+    assert lib.lbm_bandwidth_ceiling(1, 64, 1, 1, 1, None, None, None) == LBM_EINVAL

@@ -68,33 +68,35 @@ def test_gradient_matches_oracle_adjoint_subcooled_unequal_conductivities(prec, 
     assert err <= tol, err
 
 
-def test_replay_reproduces_recorded_run():
+@pytest.mark.parametrize("prec,heating", [("f64", "y0"), ("f32", "y0"), ("f16s", "z0"),
+                                          ("bf16s", "y0")])
+def test_replay_reproduces_recorded_run(prec, heating):
     """Stepping along the recorded schedule with unchanged inputs gives the
-    recorded run bit for bit (FP64 and FP32 storage), through a melting
-    front that switches cells."""
+    recorded run bit for bit, through a melting front that switches cells.
+    With 16-bit storage the forward step takes the rows whose stencils are
+    all solid on a path of their own (no per-cell phase loads), the replay
+    on the general one: the two paths agree bit for bit."""
     from inputs import hot_wall_field
+    from live_state import states_equal
     from paper_1604_03478_amd import Config, Sim
-    for prec in ("f64", "f32"):
-        cfg = Config(n=24, ra=1e5, pr=1.0, ste=1.0, s0=5.45, precision=prec)
-        th = hot_wall_field(24, seed=2)
-        a = Sim(cfg)
-        a.set_hot_wall(th)
-        a.step(50)
-        st = a.save_state()
-        fl = a.forward_ckpt(120, 13)
-        sched = a.schedule(120)
-        b = Sim(cfg)
-        b.set_hot_wall(th)
-        b.load_state(st)
-        b.step_replay(sched, 120)
-        assert b.liquid_fraction() == fl
-        fa, ga, sa = a.get_populations()
-        fb, gb, sb = b.get_populations()
-        assert np.array_equal(fa, fb) and np.array_equal(ga, gb) and np.array_equal(sa, sb)
-        counts = sched.reshape(121, 3, 24, 24)[:, 0]
-        assert (counts[-1] != counts[0]).any()  # the front moved across cells
-        a.close()
-        b.close()
+    cfg = Config(n=24, ra=1e5, pr=1.0, ste=1.0, s0=5.45, precision=prec, heating=heating)
+    th = hot_wall_field(24, seed=2)
+    a = Sim(cfg)
+    a.set_hot_wall(th)
+    a.step(50)
+    st = a.save_state()
+    fl = a.forward_ckpt(120, 13)
+    sched = a.schedule(120)
+    b = Sim(cfg)
+    b.set_hot_wall(th)
+    b.load_state(st)
+    b.step_replay(sched, 120)
+    assert b.liquid_fraction() == fl
+    assert states_equal(a.get_populations(), b.get_populations(), heating)
+    counts = sched.reshape(121, 3, 24, 24)[:, 0]
+    assert (counts[-1] != counts[0]).any()  # the front moved across cells
+    a.close()
+    b.close()
 
 
 def test_replay_rejects_out_of_lattice_nodes():
@@ -111,6 +113,51 @@ def test_replay_rejects_out_of_lattice_nodes():
     with pytest.raises(LbmError):
         s.step_replay(bad, 3)
     s.close()
+
+
+def _golden_adj64():
+    import os
+    from conftest import golden_path
+    path = golden_path("adj64_ra1e4_oracle_grad.txt")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing")
+    fl, g = None, {}
+    for ln in open(path):
+        if ln.startswith("#"):
+            continue
+        parts = ln.split()
+        if parts[0] == "fl":
+            fl = float(parts[1])
+        else:
+            g[int(parts[1])] = float(parts[2])
+    return fl, np.array([g[c] for c in range(len(g))]).reshape(64, 64)
+
+
+@pytest.mark.parametrize("prec,dtype,tol", [("f32", "float32", 1e-4), ("f64", "float64", 1e-10)])
+def test_adjoint_at_the_64_configuration_matches_the_oracle(prec, dtype, tol):
+    """The 64^3 adjoint configuration (Ra = 1e4, Pr = 1, Ste = 0.1, from the
+    initial state; T_h = 1 + 0.1 N(0, 1) seeded, as a 64 x 64 tensor of the
+    given dtype through torch.autograd), 100 steps with a checkpoint every
+    10, against the oracle's reverse sweep of the same run (FP64, written by
+    tests/golden/make_adj64_golden.py): relative L2 error of d f_l / d T_h
+    <= 1e-4 in FP32 storage (the FP32 bar of the 16^3 comparisons), round-off
+    in FP64 storage.  The FP32 tensor rounds T_h to FP32 (relative 3e-8),
+    which moves f_l and the gradient far below these bars."""
+    import torch
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, LiquidFraction
+    fl_ref, g_ref = _golden_adj64()
+    cfg = Config(n=64, ra=1e4, pr=1.0, ste=0.1, s0=1.0, precision=prec)
+    th = torch.tensor(hot_wall_field(64, seed=0), dtype=getattr(torch, dtype), device="cuda",
+                      requires_grad=True)
+    fl = LiquidFraction.apply(th, cfg, 100, 10)
+    fl.backward()
+    assert th.grad.dtype == th.dtype
+    g = th.grad.detach().double().cpu().numpy()
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"{prec}: f_l {float(fl.detach()):.12f} (oracle {fl_ref:.12f}), gradient rel. L2 error {err:.3e}")
+    assert abs(float(fl.detach()) - fl_ref) <= (1e-13 if prec == "f64" else 1e-6) * fl_ref
+    assert err <= tol, err
 
 
 def test_gradient_matches_finite_differences_64():
@@ -139,7 +186,7 @@ def test_gradient_matches_finite_differences_64():
     sched = base.schedule(steps)
     grad = base.adjoint(1.0)
     base.close()
-    assert fl_base == float(fl)
+    assert fl_base == float(fl.detach())
     assert np.array_equal(grad, grad_autograd)
 
     def J(t):
@@ -154,19 +201,36 @@ def test_gradient_matches_finite_differences_64():
     eps = 1e-3
     rng = np.random.default_rng(1)
     cols = [(0, 0), (32, 32), (10, 50), (63, 17), (5, 5), (40, 1), (22, 60), (63, 63)]
-    errs = []
+    errs, fds, dirs = [], [], []
     for c in cols:
         e = np.zeros((n, n))
         e[c] = 1.0
         fd = (J(th0 + eps * e) - J(th0 - eps * e)) / (2 * eps)
+        fds.append(fd)
         errs.append(abs(fd - grad[c]) / abs(grad[c]))
     for _ in range(4):
         d = rng.standard_normal((n, n))
         d /= np.linalg.norm(d)
+        dirs.append(d)
         fd = (J(th0 + eps * d) - J(th0 - eps * d)) / (2 * eps)
+        fds.append(fd)
         errs.append(abs(fd - (grad * d).sum()) / abs((grad * d).sum()))
     print("relative errors", errs)
     assert max(errs) <= 1e-3, errs
+
+    # the same configuration in FP32 storage with an FP32 T_h tensor (its
+    # own run and schedule): against the same central differences
+    th32 = torch.tensor(th0, dtype=torch.float32, device="cuda", requires_grad=True)
+    fl32 = LiquidFraction.apply(th32, Config(n=n, ra=1e4, pr=1.0, ste=0.1, s0=1.0,
+                                             precision="f32"), steps, 100)
+    fl32.backward()
+    g32 = th32.grad.detach().double().cpu().numpy()
+    errs32 = [abs(fd - g32[c]) / abs(fd) for c, fd in zip(cols, fds[:len(cols)])]
+    errs32 += [abs(fd - (g32 * d).sum()) / abs(fd) for d, fd in zip(dirs, fds[len(cols):])]
+    rel32 = np.linalg.norm(g32 - grad) / np.linalg.norm(grad)
+    print("FP32: f_l", float(fl32.detach()), "relative errors", errs32, "rel. L2 to FP64", rel32)
+    assert abs(float(fl32.detach()) - fl_base) <= 1e-6 * fl_base
+    assert max(errs32) <= 1e-3, errs32
 
 
 @pytest.mark.parametrize("heating", ["y0", "z0"])
