@@ -192,6 +192,22 @@ int lbm_get_populations(lbm_ctx *ctx, double *f, double *g, double *s);
  * that changed from liquid to solid since init.  Synchronizes. */
 int lbm_diagnostics(lbm_ctx *ctx, double out[5]);
 
+/* The same reductions as lbm_diagnostics, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): this call allocates nothing.  The partial
+ * sums of its reduction live in a fixed device array of the library
+ * (5 * 1024 + 5 FP64 values, 41 KB on every GPU the library runs on, held
+ * until the process ends), enough for every lattice lbm_init accepts; a
+ * larger need would be rejected with LBM_EINVAL.  out: 5 values as for
+ * lbm_diagnostics.  on_device != 0: out is device memory and the call only
+ * enqueues on the context stream (no synchronization; the instability flag
+ * is not read).  on_device == 0: out is host memory, the call synchronizes
+ * and reports LBM_EUNSTABLE as lbm_diagnostics does.  Every call on one GPU
+ * uses that GPU's one array, whose contents each call overwrites: calls that
+ * overlap on one GPU (unordered streams or threads) race and give wrong
+ * sums.  Errors: LBM_EINVAL, LBM_EDEVICE, LBM_EUNSTABLE. */
+int lbm_diagnostics_noalloc(lbm_ctx *ctx, double *out, int on_device);
+
 /* Checkpoint.  With host_buf == NULL, *bytes receives the size needed.
  * Otherwise the state (distributions in storage precision, front, counters,
  * step) is copied into host_buf, which must hold *bytes bytes.

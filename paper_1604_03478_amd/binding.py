@@ -64,7 +64,7 @@ EXPORTS = ("lbm_init", "lbm_destroy", "lbm_step", "lbm_liquid_fraction", "lbm_fi
            "lbm_get_populations", "lbm_diagnostics", "lbm_save_state", "lbm_load_state",
            "lbm_forward_ckpt", "lbm_adjoint", "lbm_get_schedule", "lbm_step_replay",
            "lbm_wall_nusselt", "lbm_kernel_timing", "lbm_kernel_time",
-           "lbm_bandwidth_ceiling", "lbm_last_error")
+           "lbm_bandwidth_ceiling", "lbm_diagnostics_noalloc", "lbm_last_error")
 
 _lib = None
 
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_kernel_timing.argtypes = [vp, i32]
     lib.lbm_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lbm_bandwidth_ceiling.argtypes = [i32, i32, i32, i32, i32, vp, dp, dp]
+    lib.lbm_diagnostics_noalloc.argtypes = [vp, vp, i32]
     lib.lbm_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("lbm_destroy", "lbm_last_error"):
@@ -221,6 +222,20 @@ class Sim:
     def diagnostics(self) -> dict:
         out = np.zeros(5)
         _check(self._lib.lbm_diagnostics(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return {"mass": out[0], "energy": out[1], "front_sum": out[2], "melted": int(out[3]),
+                "frozen": int(out[4])}
+
+    def diagnostics_noalloc(self, device: bool = False):
+        """lbm_diagnostics through the allocation-free entry point: a dict as
+        diagnostics(), or (device=True) the 5 values in an FP64 tensor on the
+        current device (enqueued on the context stream, not synchronized)."""
+        if device:
+            out = torch.empty(5, dtype=torch.float64,
+                              device=torch.device("cuda", torch.cuda.current_device()))
+            _check(self._lib.lbm_diagnostics_noalloc(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        out = np.zeros(5)
+        _check(self._lib.lbm_diagnostics_noalloc(self._h, _ptr(out), 0))
         return {"mass": out[0], "energy": out[1], "front_sum": out[2], "melted": int(out[3]),
                 "frozen": int(out[4])}
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -124,6 +125,7 @@ struct lbm_ctx {
   double* th = nullptr;
   double* red = nullptr;
   double* dpart = nullptr;   // partial sums of the diagnostics reductions
+  double* scratch = nullptr; // this device's address of the no-allocation scratch
   double* seedT = nullptr;
   double* fields = nullptr;  // 5 * n^3 FP64 scratch for the field output
   double* wall = nullptr;    // n^2 FP64 scratch of per-column wall diagnostics
@@ -305,6 +307,35 @@ int dalloc_bytes(void** p, size_t bytes) {
   return LBM_OK;
 }
 
+// Scratch of lbm_diagnostics_noalloc: the partial sums of its two-pass
+// reduction, in a file-scope device array (one copy per GPU, held until the
+// process ends), so that the call allocates nothing.  In host code the name
+// `scratch` is only a stand-in for the symbol: its address on each device
+// comes from hipGetSymbolAddress, taken once per device at lbm_init with that
+// device current, and only that address is handed to kernels.
+constexpr size_t kScratchDoubles = 5 * (size_t)lbmk::kDiagBlocks + 5;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address of `device` (the current device), looked up once.
+int scratch_address(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(LBM_EDEVICE, "device %d beyond the %d the library tracks", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LBM_EDEVICE, "hipGetSymbolAddress of the scratch array failed: %s",
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return LBM_OK;
+}
+
 struct StateHeader {
   char magic[8];
   int32_t n, precision, flow, heating;
@@ -367,6 +398,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
     return code;
   };
   if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(LBM_EDEVICE, "no HIP device"));
+  if ((rc = scratch_address(c->device, &c->scratch))) return bail(rc);
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -634,6 +666,26 @@ int lbm_diagnostics(lbm_ctx* c, double out[5]) {
                                  c->s[c->scur], c->melted, c->frozen, c->dpart, c->stream));
   HIP_TRY(hipMemcpyAsync(out, c->dpart + 5 * (size_t)lbmk::diag_blocks(c->p.n),
                          5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return check_unstable(c);
+}
+
+int lbm_diagnostics_noalloc(lbm_ctx* c, double* out, int on_device) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  const size_t need = lbmk::diag_scratch_doubles(c->p.n);
+  if (need > kScratchDoubles)
+    return fail(LBM_EINVAL, "n = %d needs %zu scratch values, the array holds %zu", c->p.n, need,
+                kScratchDoubles);
+  HIP_TRY(lbmk::launch_diag_sums(c->kind, c->kp, c->f[c->cur], c->g[c->cur], c->cnt,
+                                 c->s[c->scur], c->melted, c->frozen, c->scratch, c->stream));
+  const double* res = c->scratch + 5 * (size_t)lbmk::diag_blocks(c->p.n);
+  if (on_device) {
+    HIP_TRY(hipMemcpyAsync(out, res, 5 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(out, res, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return check_unstable(c);
 }
