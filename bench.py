@@ -191,6 +191,36 @@ def large_run(stream, n: int, steps: int, sample: int = 1000):
             "liquid_fraction": hist, "nu_mean_end": round(float(nu.mean()), 4)}
 
 
+def graph_timing(stream, reps: int = 3):
+    """Steps launched kernel by kernel against the same steps run as replays
+    of a captured graph (lbm_set_graph): ms per step, the two modes
+    alternating `reps` times on a context each (the two stay in the same
+    state) and each keeping its best."""
+    from paper_1604_03478_amd import Sim
+    out = []
+    for n, prec, liquid, steps, chunk in ((64, "f32", False, 2000, 100),
+                                          (64, "f16s", False, 2000, 100),
+                                          (256, "f32", True, 200, 100),
+                                          (256, "f16s", True, 200, 100)):
+        sims = {m: Sim(workload_config(n, prec, liquid), stream=stream)
+                for m in ("launch", "graph")}
+        sims["graph"].set_graph(chunk)
+        for sim in sims.values():
+            sim.step(chunk)  # warm-up, and the capture
+        best = {m: float("inf") for m in sims}
+        for _ in range(reps):
+            for m, sim in sims.items():
+                best[m] = min(best[m], time_steps(sim, stream, steps))
+        for sim in sims.values():
+            sim.close()
+        out.append({"n": n, "precision": prec, "state": "all-liquid" if liquid else "melting",
+                    "steps": steps, "chunk": chunk,
+                    "launch_ms_per_step": round(best["launch"], 5),
+                    "graph_ms_per_step": round(best["graph"], 5),
+                    "graph_speedup": round(best["launch"] / best["graph"], 4)})
+    return out
+
+
 def adjoint_timing(stream, n: int, steps: int, every: int):
     """Gradient of f_l after `steps` steps with respect to T_h(x, z), FP32
     storage, checkpoint every `every` steps: time of the checkpointed forward
@@ -414,7 +444,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--mode", choices=["bench", "profile", "copy", "precision", "adjoint",
-                                       "paper", "large"], default="bench")
+                                       "paper", "large", "graph"], default="bench")
     ap.add_argument("--precision-steps", type=int, default=100000)
     ap.add_argument("--precision", choices=["f32", "f16s", "bf16s", "f64"], default="f32",
                     help="storage precision of --mode profile")
@@ -495,6 +525,10 @@ def main():
         print(json.dumps(large_run(stream, args.n, args.steps)), flush=True)
         return
 
+    if args.mode == "graph":
+        print(json.dumps({"mode": "graph", "runs": graph_timing(stream)}), flush=True)
+        return
+
     if args.mode == "adjoint":
         print(json.dumps({"mode": "adjoint",
                           "runs": [adjoint_timing(stream, 64, 2000, 100),
@@ -573,6 +607,7 @@ def main():
         line["bottom512"] = bottom_heated_512(stream, 100, 20)
         line["adjoint"] = [adjoint_timing(stream, 64, 2000, 100),
                            adjoint_timing(stream, 256, 100, 10)]
+        line["graph"] = graph_timing(stream)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_steps)

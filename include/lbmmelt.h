@@ -137,6 +137,23 @@ void lbm_destroy(lbm_ctx *ctx);
  * LBM_EUNSTABLE and no lbm_load_state followed), LBM_EDEVICE. */
 int lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
+/* Graph replays of the step loop (a launch-overhead option, not part of the
+ * method).  steps = 0 (the default): lbm_step launches every kernel of every
+ * step.  steps = an even number in [2, 4096]: lbm_step runs whole chunks of
+ * that many steps as replays of one captured HIP graph (the same kernels in
+ * the same order, captured on first use and again after the buffer parity
+ * changed, e.g. by an odd remainder) and the remaining steps one by one; the
+ * step counter that seeds the stochastic rounding lives in device memory
+ * while a chunk runs, so the results are the same bit for bit either way.
+ * Replays are not used while kernel timing is on or inside lbm_forward_ckpt,
+ * lbm_step_replay and lbm_adjoint.  The graph holds pointers into the
+ * context only; it lives until the next lbm_set_graph or lbm_destroy.  Costs
+ * 4 bytes of device memory and one capture stream.  Synchronizes the
+ * context's stream when the setting changes.
+ * Errors: LBM_EINVAL (steps odd, negative or above 4096), LBM_ENOMEM,
+ * LBM_EDEVICE (capture failures are reported by the lbm_step that captures). */
+int lbm_set_graph(lbm_ctx *ctx, int32_t steps);
+
 /* Liquid fraction: sum of the column fronts over n^3, in FP64 (the quantity
  * plotted against the Fourier number in the paper's Fig. 2 and Fig. 4(d)).
  * Synchronizes.  Returns LBM_EUNSTABLE if a non-finite value was detected in

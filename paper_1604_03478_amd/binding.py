@@ -64,7 +64,8 @@ EXPORTS = ("lbm_init", "lbm_destroy", "lbm_step", "lbm_liquid_fraction", "lbm_fi
            "lbm_get_populations", "lbm_diagnostics", "lbm_save_state", "lbm_load_state",
            "lbm_forward_ckpt", "lbm_adjoint", "lbm_get_schedule", "lbm_step_replay",
            "lbm_wall_nusselt", "lbm_kernel_timing", "lbm_kernel_time",
-           "lbm_bandwidth_ceiling", "lbm_diagnostics_noalloc", "lbm_last_error")
+           "lbm_bandwidth_ceiling", "lbm_diagnostics_noalloc", "lbm_set_graph",
+           "lbm_last_error")
 
 _lib = None
 
@@ -101,6 +102,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_kernel_time.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.lbm_bandwidth_ceiling.argtypes = [i32, i32, i32, i32, i32, vp, dp, dp]
     lib.lbm_diagnostics_noalloc.argtypes = [vp, vp, i32]
+    lib.lbm_set_graph.argtypes = [vp, i32]
     lib.lbm_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("lbm_destroy", "lbm_last_error"):
@@ -274,6 +276,10 @@ class Sim:
     # ---- measurement ----
     def kernel_timing(self, enable: bool) -> None:
         _check(self._lib.lbm_kernel_timing(self._h, int(bool(enable))))
+
+    def set_graph(self, steps: int) -> None:
+        """Run step() in chunks of `steps` (even; 0: off) as HIP graph replays."""
+        _check(self._lib.lbm_set_graph(self._h, int(steps)))
 
     def kernel_time(self):
         """(summed milliseconds, launches) of the timed stream-collide kernels."""

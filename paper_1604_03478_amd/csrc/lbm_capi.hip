@@ -101,6 +101,14 @@ struct AdjData {
   double *out5 = nullptr, *own = nullptr, *lth = nullptr;
 };
 
+// A captured chunk of steps (lbm_set_graph): `steps` (even) steps that start
+// and end at buffer parity (cur, scur).
+struct StepGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int cur = -1, scur = -1;
+};
+
 struct lbm_ctx {
   lbm_params p{};
   lbm_lattice lat{};
@@ -143,6 +151,11 @@ struct lbm_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed kernels
   size_t ev_used = 0;
+  // graph replays of the step loop (lbm_set_graph)
+  int graph_steps = 0;           // steps per captured chunk, 0: launch every kernel
+  StepGraph sgraph;
+  hipStream_t cap = nullptr;     // capture stream (never runs work)
+  uint32_t* step_dev = nullptr;  // the step counter that graph replays advance
 };
 
 namespace {
@@ -178,7 +191,16 @@ void release_adjoint(AdjData& a) {
   a = AdjData();
 }
 
+void release_graph(StepGraph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = StepGraph();
+}
+
 void release(lbm_ctx* c) {
+  release_graph(c->sgraph);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->step_dev) (void)hipFree(c->step_dev);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
   release_adjoint(c->adj);
@@ -482,15 +504,97 @@ void lbm_destroy(lbm_ctx* c) {
   delete c;
 }
 
+namespace {
+
+// The kernels of one step from buffer parity (cur, scur) on stream st: the
+// same launches whether they run at once or are captured into a graph.
+// rec: schedule slot to record (or null).  step_ctr: the device step counter
+// to advance (graph replays, else null).  ev0/ev1 (or null):
+// events recorded around the stream-collide kernel.
+hipError_t enqueue_step(lbm_ctx* c, const lbmk::KParams& k, int cur, int scur, int* rec,
+                        uint32_t* step_ctr, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
+  const int nx = cur ^ 1, sx = scur ^ 1;
+  hipError_t e;
+  if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+  if ((e = lbmk::launch_stream_collide(c->kind, k, c->f[cur], c->f[nx], c->g[cur], c->g[nx],
+                                       c->cnt, c->cmin, c->cmax, c->rowmax, c->s[scur], c->th,
+                                       c->flag, st)) != hipSuccess)
+    return e;
+  if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
+  if (c->heat &&  // conservative front: heat of the streaming from the state g[cur]
+      (e = lbmk::launch_front_heat(c->kind, k, c->g[cur], c->s[scur], c->cnt, c->heat, st)) !=
+          hipSuccess)
+    return e;
+  if ((e = lbmk::launch_front(c->kind, k, c->s[scur], c->s[sx], c->cnt, c->g[nx], c->f[nx], c->th,
+                              c->melted, c->frozen, c->flag, nullptr, nullptr, rec, c->heat,
+                              step_ctr, st)) != hipSuccess)
+    return e;
+  if (lbmk::uses_neighbourhood(c->kind) &&
+      (e = lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->rowmax, st)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
+// Captures c->graph_steps steps from the current buffer parity.  Nothing
+// runs during the capture.  The stream-collide kernels of the graph read the
+// step (the seed of the stochastic rounding of FP32 and 16-bit storage) from
+// c->step_dev, which each step's front kernel advances, so a replay rounds
+// with the same per-step random streams as launches one by one.
+int build_step_graph(lbm_ctx* c) {
+  release_graph(c->sgraph);
+  if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  lbmk::KParams k = c->kp;
+  k.step_dev = c->step_dev;
+  HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  int cur = c->cur, scur = c->scur;
+  for (int i = 0; i < c->graph_steps && e == hipSuccess; ++i) {
+    e = enqueue_step(c, k, cur, scur, nullptr, c->step_dev, nullptr, nullptr, c->cap);
+    cur ^= 1;
+    scur ^= 1;
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(c->cap, &g);
+  if (e != hipSuccess || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(LBM_EDEVICE, "capture of the step graph failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : ee));
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(LBM_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+  }
+  c->sgraph.graph = g;
+  c->sgraph.exec = x;
+  c->sgraph.cur = c->cur;
+  c->sgraph.scur = c->scur;
+  return LBM_OK;
+}
+
+}  // namespace
+
 int lbm_step(lbm_ctx* c, int64_t nsteps) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   lbmk::KParams& k = c->kp;
+  // whole chunks as graph replays (an even number of steps returns the
+  // buffers to their parity, so one graph serves every chunk)
+  if (c->graph_steps > 0 && !c->timing && c->rec_start < 0 && nsteps >= c->graph_steps) {
+    if (!c->sgraph.exec || c->sgraph.cur != c->cur || c->sgraph.scur != c->scur)
+      if ((rc = build_step_graph(c))) return rc;
+    HIP_TRY(lbmk::launch_set_u32(c->step_dev, (uint32_t)c->step, c->stream));
+    const int64_t reps = nsteps / c->graph_steps;
+    for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(c->sgraph.exec, c->stream));
+    c->step += reps * c->graph_steps;
+    nsteps -= reps * c->graph_steps;
+  }
   for (int64_t i = 0; i < nsteps; ++i) {
     k.step = (uint32_t)c->step;
-    const int nx = c->cur ^ 1, sx = c->scur ^ 1;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (c->timing) {
       if (c->ev_used + 2 > c->ev.size()) {
         for (int e = 0; e < 2; ++e) {
@@ -499,30 +603,35 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
           c->ev.push_back(h);
         }
       }
-      HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
-    }
-    HIP_TRY(lbmk::launch_stream_collide(c->kind, k, c->f[c->cur], c->f[nx], c->g[c->cur], c->g[nx],
-                                        c->cnt, c->cmin, c->cmax, c->rowmax, c->s[c->scur], c->th,
-                                        c->flag, c->stream));
-    if (c->timing) {
-      HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+      ev0 = c->ev[c->ev_used];
+      ev1 = c->ev[c->ev_used + 1];
       c->ev_used += 2;
     }
     int* rec = c->rec_start >= 0
                    ? c->sched + (size_t)(c->step - c->rec_start) * 3 * ((size_t)c->p.n * c->p.n)
                    : nullptr;
-    if (c->heat)  // conservative front: heat of the streaming from the state g[cur]
-      HIP_TRY(lbmk::launch_front_heat(c->kind, k, c->g[c->cur], c->s[c->scur], c->cnt, c->heat,
-                                      c->stream));
-    HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
-                               c->th, c->melted, c->frozen, c->flag, nullptr, nullptr, rec,
-                               c->heat, c->stream));
-    if (lbmk::uses_neighbourhood(c->kind))
-      HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->rowmax, c->stream));
-    c->cur = nx;
-    c->scur = sx;
+    HIP_TRY(enqueue_step(c, k, c->cur, c->scur, rec, nullptr, ev0, ev1, c->stream));
+    c->cur ^= 1;
+    c->scur ^= 1;
     c->step++;
   }
+  return LBM_OK;
+}
+
+int lbm_set_graph(lbm_ctx* c, int32_t steps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (steps < 0 || steps > 4096 || (steps & 1))
+    return fail(LBM_EINVAL, "graph chunk of %d steps: need 0 or an even number up to 4096",
+                (int)steps);
+  if (steps == c->graph_steps) return LBM_OK;
+  if (steps && !c->step_dev && hipMalloc((void**)&c->step_dev, sizeof(uint32_t)) != hipSuccess) {
+    c->step_dev = nullptr;
+    return fail(LBM_ENOMEM, "cannot allocate the step counter");
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));  // no replay of the old graph is pending
+  release_graph(c->sgraph);
+  c->graph_steps = steps;
   return LBM_OK;
 }
 
@@ -911,7 +1020,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
         HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], a.cnt, c->heat, c->stream));
       HIP_TRY(lbmk::launch_front(c->kind, k, a.ss[t], a.ss[t + 1], a.cnt, a.sg[t + 1],
                                  a.sf[t + 1], c->th, a.melted, a.frozen, a.flag, nullptr, nullptr,
-                                 nullptr, c->heat, c->stream));
+                                 nullptr, c->heat, nullptr, c->stream));
     }
     // reverse the segment
     for (int64_t t = len - 1; t >= 0; --t, ++rev) {
@@ -1014,7 +1123,7 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
                                       c->stream));
     HIP_TRY(lbmk::launch_front(c->kind, k, c->s[c->scur], c->s[sx], c->cnt, c->g[nx], c->f[nx],
                                c->th, c->melted, c->frozen, c->flag, e, e + 3 * nn, nullptr,
-                               c->heat, c->stream));
+                               c->heat, nullptr, c->stream));
     if (lbmk::uses_neighbourhood(c->kind))
       HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->rowmax, c->stream));
     c->cur = nx;

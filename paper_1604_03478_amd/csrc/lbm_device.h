@@ -47,7 +47,10 @@ template <> struct Compute<float> { using type = LBM_F32_FLOW_T; using gtype = L
 // stores (each adds the 32-bit golden-ratio constant).  Every value's offset
 // is uniform over the hash, so its rounding error has zero mean; within a
 // cell the offsets are spread evenly (low discrepancy), and advancing the
-// stream costs one integer add instead of a 32-bit multiply.
+// stream costs one integer add instead of a 32-bit multiply.  The hash is
+// C. Wellons' published 32-bit integer mixer "lowbias32" (found by his
+// hash-prospector search): two xor-shift / multiply rounds and a final
+// xor-shift, with his shift amounts and multipliers.
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -55,6 +58,11 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x *= 0x846ca68bu;
   x ^= x >> 16;
   return x;
+}
+// The step that seeds a cell's hash: the kernel argument, or the counter in
+// device memory that graph replays advance (a uniform scalar load).
+__device__ __forceinline__ uint32_t step_of(const KParams& P) {
+  return P.step_dev ? *P.step_dev : P.step;
 }
 __device__ __forceinline__ uint32_t next_rand(uint32_t& st) {
   st += 0x9e3779b9u;

@@ -36,6 +36,9 @@ struct KParams {
   double ste;      // Stefan number (front update)
   double dT;       // nominal t_h - t_m (front update)
   uint32_t step;   // step counter (seeds the per-cell random stream of rounding)
+  // Graph replays: the step counter in device memory, advanced by each step's
+  // front kernel (launch_front's step_ctr); null: use step.
+  const uint32_t* step_dev;
 };
 
 size_t store_bytes(int kind);
@@ -74,10 +77,12 @@ hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, voi
 // replay_next (the following entry) instead of the new fronts.  heat != null
 // (n^2 values from launch_front_heat) moves every front by heat * Ste /
 // (t_h - t_m), the conservative form of the same balance, instead of Eq. (6).
+// step_ctr (may be null): a device step counter that this launch advances by
+// one; no kernel after it in the step reads the counter.
 hipError_t launch_front(int kind, const KParams& P, const double* s_old, double* s_new,
                         int* cnt, const void* g, void* f, const double* th, int* melted,
                         int* frozen, int* flag, const int* replay, const int* replay_next,
-                        int* record, const double* heat, hipStream_t st);
+                        int* record, const double* heat, uint32_t* step_ctr, hipStream_t st);
 
 // cmin/cmax: min and max of cnt over the 3x3 columns around each column (the
 // columns in the box), for the fast-path test of the 16-bit step kernel;
@@ -85,6 +90,9 @@ hipError_t launch_front(int kind, const KParams& P, const double* s_old, double*
 // (all x for one value of the other lateral index).
 hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
                                 int* rowmax, hipStream_t st);
+
+// *p = v (one thread).
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t st);
 
 // cnt from s.
 hipError_t launch_counts(const KParams& P, const double* s, int* cnt, hipStream_t st);

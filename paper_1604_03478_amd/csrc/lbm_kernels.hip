@@ -459,7 +459,7 @@ __device__ __forceinline__ void update_cell(
     }
   }
   if (collide<FLOW>(f, g, liquid, r)) *flag = 1;
-  uint32_t rs = mix32(self * 0x9e3779b1u + P.step * 0x85ebca77u);
+  uint32_t rs = mix32(self * 0x9e3779b1u + step_of(P) * 0x85ebca77u);
   if (FLOW && liquid) {
     Ts* fr = row_ptr<19>(fd, P, y, z);
 #pragma unroll
@@ -509,7 +509,7 @@ __device__ __forceinline__ void solid_cell(int x, int y, int z, const Ts* __rest
   if (collide<FLOW>(fdummy, g, false, r)) *flag = 1;
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
   const uint32_t self = (uint32_t)z * nn + (uint32_t)y * (uint32_t)n + (uint32_t)x;
-  uint32_t rs = mix32(self * 0x9e3779b1u + P.step * 0x85ebca77u);
+  uint32_t rs = mix32(self * 0x9e3779b1u + step_of(P) * 0x85ebca77u);
   Ts* gr = row_ptr<7>(gd, P, y, z);
 #pragma unroll
   for (int q = 0; q < 7; ++q) store_stream(gr, q * pitch + x, g[q], rs);
@@ -594,10 +594,13 @@ __global__ __launch_bounds__(256) void k_front(const double* __restrict__ s_old,
                                                const int* __restrict__ replay,
                                                const int* __restrict__ replay_next,
                                                int* __restrict__ record,
-                                               const double* __restrict__ heat, KParams P) {
+                                               const double* __restrict__ heat,
+                                               uint32_t* __restrict__ step_ctr, KParams P) {
   const int n = P.n;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int o = blockIdx.y;
+  // the step counter of graph replays: no later kernel of this step reads it
+  if (step_ctr && x == 0 && o == 0) *step_ctr += 1u;
   if (x >= n) return;
   const int col = o * n + x;
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
@@ -908,26 +911,26 @@ template <typename Ts>
 hipError_t front_dispatch(const KParams& P, const double* s_old, double* s_new, int* cnt,
                           const void* g, void* f, const double* th, int* melted, int* frozen,
                           int* flag, const int* replay, const int* replay_next, int* record,
-                          const double* heat, hipStream_t st) {
+                          const double* heat, uint32_t* step_ctr, hipStream_t st) {
   dim3 block(64, 1, 1);
   dim3 grid((P.n + 63) / 64, P.n, 1);
   auto G = static_cast<const Ts*>(g);
   auto F = static_cast<Ts*>(f);
+#define LAUNCH(FLOW, MZ)                                                                   \
+  hipLaunchKernelGGL((k_front<Ts, FLOW, MZ>), grid, block, 0, st, s_old, s_new, cnt, G, F, th, \
+                     melted, frozen, flag, replay, replay_next, record, heat, step_ctr, P)
   if (P.flow) {
     if (P.melt_z)
-      hipLaunchKernelGGL((k_front<Ts, true, true>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
-                         melted, frozen, flag, replay, replay_next, record, heat, P);
+      LAUNCH(true, true);
     else
-      hipLaunchKernelGGL((k_front<Ts, true, false>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
-                         melted, frozen, flag, replay, replay_next, record, heat, P);
+      LAUNCH(true, false);
   } else {
     if (P.melt_z)
-      hipLaunchKernelGGL((k_front<Ts, false, true>), grid, block, 0, st, s_old, s_new, cnt, G, F, th,
-                         melted, frozen, flag, replay, replay_next, record, heat, P);
+      LAUNCH(false, true);
     else
-      hipLaunchKernelGGL((k_front<Ts, false, false>), grid, block, 0, st, s_old, s_new, cnt, G, F,
-                         th, melted, frozen, flag, replay, replay_next, record, heat, P);
+      LAUNCH(false, false);
   }
+#undef LAUNCH
   return hipGetLastError();
 }
 
@@ -1021,10 +1024,10 @@ hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, voi
 hipError_t launch_front(int kind, const KParams& P, const double* s_old, double* s_new, int* cnt,
                         const void* g, void* f, const double* th, int* melted, int* frozen,
                         int* flag, const int* replay, const int* replay_next, int* record,
-                        const double* heat, hipStream_t st) {
+                        const double* heat, uint32_t* step_ctr, hipStream_t st) {
 #define CALL(T)                                                                                 \
   front_dispatch<T>(P, s_old, s_new, cnt, g, f, th, melted, frozen, flag, replay, replay_next, \
-                    record, heat, st)
+                    record, heat, step_ctr, st)
   switch (kind) {
     case kF64: return CALL(double);
     case kF32: return CALL(float);
@@ -1039,6 +1042,13 @@ hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int
                                 int* rowmax, hipStream_t st) {
   hipLaunchKernelGGL(k_neighbourhood, dim3(P.n), dim3(kNbThreads), 0, st, cnt, cmin, cmax,
                      rowmax, P.n);
+  return hipGetLastError();
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, st, p, v);
   return hipGetLastError();
 }
 
