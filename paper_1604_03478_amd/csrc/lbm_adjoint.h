@@ -43,12 +43,13 @@ struct AdjointStep {
   double* wq;
 };
 hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A, hipStream_t st);
-// Liquid counts of the fronts s (cnt), their min / max over the 5x5 columns
+// For each of `count` states (device array `states` of their fronts, n^2
+// values each): the liquid counts (cnt), their min / max over the 5x5 columns
 // around each column (cmin2, cmax2) and the largest count, merged into
-// rmax[slot], which must be zero; rmax[1 - slot] is cleared for the next
-// reverse step.  rmax holds two ints.
-hipError_t launch_adj_partition(const KParams& P, const double* s, int* cnt, int* cmin2,
-                                int* cmax2, int* rmax, int slot, hipStream_t st);
+// rmax[t], which must be zero.  The outputs of state t start at t n^2 and at
+// rmax[t].
+hipError_t launch_adj_partition(const KParams& P, const double* const* states, int count,
+                                int* cnt, int* cmin2, int* cmax2, int* rmax, hipStream_t st);
 hipError_t launch_fill(double* v, size_t count, double value, hipStream_t st);
 
 // Bytes of one per-cell adjoint value for a storage kind, and a fill of such

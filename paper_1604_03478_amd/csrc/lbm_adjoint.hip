@@ -294,25 +294,28 @@ __device__ __forceinline__ void front_row(int r, int A, int n, int& a, int& o) {
 // lattice.
 __device__ __forceinline__ int row_bound(int m, int n) { return m + 2 < n - 1 ? m + 2 : n - 1; }
 
-// Phase bookkeeping of state t in one pass over the columns: the liquid count
-// of each column (from its front), the minimum and maximum count over the 5x5
-// columns around it (the columns in the box), and the largest count of the
-// lattice.  A workgroup covers kPartRows x 64 columns; its largest count is
-// reduced in LDS and merged into rmax[p] by one atomic maximum (device-scope
-// atomics on one address serialize, so there is one per workgroup), so
-// rmax[p] must be zero at launch.  The same launch clears rmax[1 - p] for the
-// next reverse step: every kernel that read it ran earlier on the same stream
-// and has finished.
+// Phase bookkeeping of the states of a segment, one state per grid plane z
+// (state s[z]), in one pass over its columns: the liquid count of each column
+// (from its front), the minimum and maximum count over the 5x5 columns around
+// it (the columns in the box), and the largest count of the lattice.  The
+// outputs of state z start at z n^2 (cnt, cmin2, cmax2) and at rmax[z].  None
+// of this depends on the adjoints, so one launch serves a whole segment once
+// its states are recomputed.  A workgroup covers kPartRows x 64 columns; its
+// largest count is reduced in LDS and merged into rmax[z] by one atomic
+// maximum (device-scope atomics on one address serialize, so there is one
+// per workgroup), so rmax must be zero at launch.
 constexpr int kPartRows = 8;
 __global__ __launch_bounds__(64 * kPartRows) void k_adj_partition(
-    const double* __restrict__ s, int* __restrict__ cnt, int* __restrict__ cmin2,
-    int* __restrict__ cmax2, int* __restrict__ rmax, int p, int n) {
+    const double* const* __restrict__ states, int* __restrict__ cnt, int* __restrict__ cmin2,
+    int* __restrict__ cmax2, int* __restrict__ rmax, int n) {
   // counts of the (kPartRows + 4) x (64 + 4) columns the windows cover, each
   // computed once; -1 marks a column outside the box
   __shared__ int tile[kPartRows + 4][64 + 4];
   __shared__ int wmax[kPartRows];
   const int x0 = blockIdx.x * 64, o0 = blockIdx.y * kPartRows;
   const int tid = threadIdx.y * 64 + threadIdx.x;
+  const size_t nn = (size_t)n * n, zofs = blockIdx.z * nn;
+  const double* __restrict__ s = states[blockIdx.z];
   for (int i = tid; i < (kPartRows + 4) * (64 + 4); i += 64 * kPartRows) {
     const int r = i / (64 + 4), j = i - r * (64 + 4);
     const int oo = o0 + r - 2, xx = x0 + j - 2;
@@ -334,9 +337,9 @@ __global__ __launch_bounds__(64 * kPartRows) void k_adj_partition(
         hi = c > hi ? c : hi;
       }
     own = tile[threadIdx.y + 2][threadIdx.x + 2];
-    cnt[o * n + x] = own;
-    cmin2[o * n + x] = lo;
-    cmax2[o * n + x] = hi;
+    cnt[zofs + o * n + x] = own;
+    cmin2[zofs + o * n + x] = lo;
+    cmax2[zofs + o * n + x] = hi;
   }
   int m = own;  // lanes outside the box hold 0, below every count's maximum
   for (int w = 32; w > 0; w >>= 1) {
@@ -347,8 +350,7 @@ __global__ __launch_bounds__(64 * kPartRows) void k_adj_partition(
   __syncthreads();
   if (tid == 0) {
     for (int w = 1; w < kPartRows; ++w) m = wmax[w] > m ? wmax[w] : m;
-    atomicMax(rmax + p, m);
-    if (blockIdx.x == 0 && blockIdx.y == 0) rmax[1 - p] = 0;
+    atomicMax(rmax + blockIdx.z, m);
   }
 }
 
@@ -819,16 +821,15 @@ __device__ __forceinline__ void adj_collide_cell(
 // grid of gridDim.y row slots (this kernel needs many registers, so its
 // waves are not spent on rows it would skip).
 template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
-__global__ __launch_bounds__(256) void k_adj_collide(
-    const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
-    const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
-    const int* __restrict__ cmin2, const int* __restrict__ cmax2, const int* __restrict__ rowb,
-    const Lam* __restrict__ lf1, const Lam* __restrict__ lg1, Lam* __restrict__ lfh,
-    Lam* __restrict__ lgh, KParams P) {
+__device__ __forceinline__ void adj_collide_rows(
+    int slot, int nslots, int x, const Ts* __restrict__ f0, const Ts* __restrict__ g0,
+    const double* __restrict__ s0, const double* __restrict__ s1, const double* __restrict__ th,
+    const int* __restrict__ cnt, const int* __restrict__ cmin2, const int* __restrict__ cmax2,
+    const int* __restrict__ rowb, const Lam* __restrict__ lf1, const Lam* __restrict__ lg1,
+    Lam* __restrict__ lfh, Lam* __restrict__ lgh, const KParams& P) {
   const int n = P.n;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int A = row_bound(rowb[0], n), R = front_rows(A, n);
-  for (int r = blockIdx.y; r < R; r += gridDim.y) {
+  for (int r = slot; r < R; r += nslots) {
     int a, o;
     front_row(r, A, n, a, o);
     if (x < n)
@@ -837,17 +838,29 @@ __global__ __launch_bounds__(256) void k_adj_collide(
   }
 }
 
+template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
+__global__ __launch_bounds__(256) void k_adj_collide(
+    const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
+    const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
+    const int* __restrict__ cmin2, const int* __restrict__ cmax2, const int* __restrict__ rowb,
+    const Lam* __restrict__ lf1, const Lam* __restrict__ lg1, Lam* __restrict__ lfh,
+    Lam* __restrict__ lgh, KParams P) {
+  adj_collide_rows<Ts, Lam, FLOW, MZ, EXT>(blockIdx.y, gridDim.y,
+                                           blockIdx.x * blockDim.x + threadIdx.x, f0, g0, s0, s1,
+                                           th, cnt, cmin2, cmax2, rowb, lf1, lg1, lfh, lgh, P);
+}
+
 // The bulk solid rows k_adj_collide leaves out: only the energy distribution
 // is reversed, with few registers, so these rows (most of a melting state)
 // run at full occupancy.  A solid cell is at rest, and at u = 0 the heat
 // collision is linear in g: its transpose needs no state, so the kernel reads
 // the 7 adjoints and writes 7 (56 B per cell in FP32).
 template <typename Lam, bool MZ>
-__global__ __launch_bounds__(256) void k_adj_collide_solid(
-    const int* __restrict__ rowb, const Lam* __restrict__ lg1, Lam* __restrict__ lgh,
-    KParams P) {
+__device__ __forceinline__ void adj_collide_solid_row(int x, int y, int z,
+                                                      const int* __restrict__ rowb,
+                                                      const Lam* __restrict__ lg1,
+                                                      Lam* __restrict__ lgh, const KParams& P) {
   const int n = P.n;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, row_bound(rowb[0], n), n)) return;
   const size_t nc = P.ncell;
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
@@ -856,6 +869,14 @@ __global__ __launch_bounds__(256) void k_adj_collide_solid(
   for (int q = 0; q < 7; ++q) lgo[q] = (double)lg1[(size_t)q * nc + i];
   collide_adjoint<false>(M, false, P, lfo, lgo, lfl, lgl);
   for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = (Lam)lgl[q];
+}
+
+template <typename Lam, bool MZ>
+__global__ __launch_bounds__(256) void k_adj_collide_solid(
+    const int* __restrict__ rowb, const Lam* __restrict__ lg1, Lam* __restrict__ lgh,
+    KParams P) {
+  adj_collide_solid_row<Lam, MZ>(blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, blockIdx.z,
+                                 rowb, lg1, lgh, P);
 }
 
 // Transposed streaming of one cell outside the bulk-solid rows.
@@ -1042,15 +1063,14 @@ __device__ __forceinline__ void adj_stream_cell(
 // The rows outside the bulk solid, visited by row slots as in k_adj_collide
 // (its general path needs more registers than the bulk rows should pay for).
 template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
-__global__ __launch_bounds__(256) void k_adj_stream(
-    const double* __restrict__ s0, const int* __restrict__ cnt, const int* __restrict__ cmin2,
-    const int* __restrict__ cmax2, const int* __restrict__ rowb, const Lam* __restrict__ lfh,
-    const Lam* __restrict__ lgh, Lam* __restrict__ lf0, Lam* __restrict__ lg0,
-    const double* __restrict__ wq, KParams P) {
+__device__ __forceinline__ void adj_stream_rows(
+    int slot, int nslots, int x, const double* __restrict__ s0, const int* __restrict__ cnt,
+    const int* __restrict__ cmin2, const int* __restrict__ cmax2, const int* __restrict__ rowb,
+    const Lam* __restrict__ lfh, const Lam* __restrict__ lgh, Lam* __restrict__ lf0,
+    Lam* __restrict__ lg0, const double* __restrict__ wq, const KParams& P) {
   const int n = P.n;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int A = row_bound(rowb[0], n), R = front_rows(A, n);
-  for (int r = blockIdx.y; r < R; r += gridDim.y) {
+  for (int r = slot; r < R; r += nslots) {
     int a, o;
     front_row(r, A, n, a, o);
     if (x < n)
@@ -1059,17 +1079,36 @@ __global__ __launch_bounds__(256) void k_adj_stream(
   }
 }
 
+template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
+__global__ __launch_bounds__(256) void k_adj_stream(
+    const double* __restrict__ s0, const int* __restrict__ cnt, const int* __restrict__ cmin2,
+    const int* __restrict__ cmax2, const int* __restrict__ rowb, const Lam* __restrict__ lfh,
+    const Lam* __restrict__ lgh, Lam* __restrict__ lf0, Lam* __restrict__ lg0,
+    const double* __restrict__ wq, KParams P) {
+  adj_stream_rows<Ts, Lam, FLOW, MZ, EXT>(blockIdx.y, gridDim.y,
+                                          blockIdx.x * blockDim.x + threadIdx.x, s0, cnt, cmin2,
+                                          cmax2, rowb, lfh, lgh, lf0, lg0, wq, P);
+}
+
 // The bulk-solid rows: g alone, gathered from the neighbours with no phase
 // reads, at full occupancy.
+template <typename Lam, bool MZ>
+__device__ __forceinline__ void adj_stream_solid_row(int x, int y, int z,
+                                                     const int* __restrict__ rowb,
+                                                     const Lam* __restrict__ lgh,
+                                                     Lam* __restrict__ lg0, const KParams& P) {
+  const int n = P.n;
+  if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, row_bound(rowb[0], n), n)) return;
+  const Geo G{n, (uint32_t)n * (uint32_t)n};
+  push_fast<7>(lgh, lg0, G, P.ncell, x, y, z, G.cell(x, y, z));
+}
+
 template <typename Lam, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_stream_solid(const int* __restrict__ rowb,
                                                           const Lam* __restrict__ lgh,
                                                           Lam* __restrict__ lg0, KParams P) {
-  const int n = P.n;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-  if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, row_bound(rowb[0], n), n)) return;
-  const Geo G{n, (uint32_t)n * (uint32_t)n};
-  push_fast<7>(lgh, lg0, G, P.ncell, x, y, z, G.cell(x, y, z));
+  adj_stream_solid_row<Lam, MZ>(blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, blockIdx.z,
+                                rowb, lgh, lg0, P);
 }
 
 // derivative of the pulled population of an interface link with respect to
@@ -1175,14 +1214,13 @@ __device__ double flink_column(const Ts* f0, const double* s0, const int* cnt, c
 }
 
 template <typename Ts, typename Lam, bool MZ, bool EXT>
-__global__ __launch_bounds__(64) void k_adj_interface(const Ts* __restrict__ g0, const double* __restrict__ s0,
-                                const int* __restrict__ cnt, const Lam* __restrict__ lgh,
-                                const Ts* __restrict__ f0, const Lam* __restrict__ lfh,
-                                const double* __restrict__ wq, const double* __restrict__ own,
-                                const double* __restrict__ out5, double* __restrict__ ls0,
-                                double* __restrict__ lth, KParams P) {
+__device__ __forceinline__ void adj_interface_column(
+    int x, int o, const Ts* __restrict__ g0, const double* __restrict__ s0,
+    const int* __restrict__ cnt, const Lam* __restrict__ lgh, const Ts* __restrict__ f0,
+    const Lam* __restrict__ lfh, const double* __restrict__ wq, const double* __restrict__ own,
+    const double* __restrict__ out5, double* __restrict__ ls0, double* __restrict__ lth,
+    const KParams& P) {
   const int n = P.n;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x, o = blockIdx.y;
   if (x >= n) return;
   const int c = o * n + x;
   const size_t nc = P.ncell;
@@ -1268,6 +1306,67 @@ __global__ __launch_bounds__(64) void k_adj_interface(const Ts* __restrict__ g0,
   ls0[c] = front_gather(own, out5, x, o, n) + acc;
 }
 
+template <typename Ts, typename Lam, bool MZ, bool EXT>
+__global__ __launch_bounds__(64) void k_adj_interface(
+    const Ts* __restrict__ g0, const double* __restrict__ s0, const int* __restrict__ cnt,
+    const Lam* __restrict__ lgh, const Ts* __restrict__ f0, const Lam* __restrict__ lfh,
+    const double* __restrict__ wq, const double* __restrict__ own,
+    const double* __restrict__ out5, double* __restrict__ ls0, double* __restrict__ lth,
+    KParams P) {
+  adj_interface_column<Ts, Lam, MZ, EXT>(blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, g0,
+                                         s0, cnt, lgh, f0, lfh, wq, own, out5, ls0, lth, P);
+}
+
+// Small lattices, where each kernel of the reverse step is latency bound
+// (one row or one column of work per wave, fewer waves than SIMDs): the
+// independent kernels share a launch, each workgroup taking one role by its
+// index, so their latencies overlap instead of adding up.  The same cell and
+// column functions as the separate kernels: the same results bit for bit.
+// Collision: row slots of the rows outside the bulk solid first (the longer
+// chain), then the bulk-solid rows.
+template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
+__global__ __launch_bounds__(256) void k_adj_collide_all(
+    const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,
+    const double* __restrict__ s1, const double* __restrict__ th, const int* __restrict__ cnt,
+    const int* __restrict__ cmin2, const int* __restrict__ cmax2, const int* __restrict__ rowb,
+    const Lam* __restrict__ lf1, const Lam* __restrict__ lg1, Lam* __restrict__ lfh,
+    Lam* __restrict__ lgh, int nslots, KParams P) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+  if (b < nslots) {
+    adj_collide_rows<Ts, Lam, FLOW, MZ, EXT>(b, nslots, x, f0, g0, s0, s1, th, cnt, cmin2, cmax2,
+                                             rowb, lf1, lg1, lfh, lgh, P);
+  } else {
+    const int r = b - nslots;  // row (y, z) = (r mod n, r / n)
+    adj_collide_solid_row<Lam, MZ>(x, r % P.n, r / P.n, rowb, lg1, lgh, P);
+  }
+}
+
+// Streaming and interface: the interface columns first, then the row slots
+// of the rows outside the bulk solid, then the bulk-solid rows.  64-lane
+// workgroups (the interface needs the registers a 64-lane bound allows).
+template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
+__global__ __launch_bounds__(64) void k_adj_stream_all(
+    const Ts* __restrict__ g0, const Ts* __restrict__ f0, const double* __restrict__ s0,
+    const int* __restrict__ cnt, const int* __restrict__ cmin2, const int* __restrict__ cmax2,
+    const int* __restrict__ rowb, const Lam* __restrict__ lfh, const Lam* __restrict__ lgh,
+    Lam* __restrict__ lf0, Lam* __restrict__ lg0, const double* __restrict__ wq,
+    const double* __restrict__ own, const double* __restrict__ out5, double* __restrict__ ls0,
+    double* __restrict__ lth, int nslots, KParams P) {
+  const int n = P.n;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  int b = blockIdx.y;
+  if (b < n) {
+    adj_interface_column<Ts, Lam, MZ, EXT>(x, b, g0, s0, cnt, lgh, f0, lfh, wq, own, out5, ls0,
+                                           lth, P);
+  } else if ((b -= n) < nslots) {
+    adj_stream_rows<Ts, Lam, FLOW, MZ, EXT>(b, nslots, x, s0, cnt, cmin2, cmax2, rowb, lfh, lgh,
+                                            lf0, lg0, wq, P);
+  } else {
+    b -= nslots;
+    adj_stream_solid_row<Lam, MZ>(x, b % n, b / n, rowb, lgh, lg0, P);
+  }
+}
+
 template <typename V>
 __global__ void k_fill(V* __restrict__ v, size_t count, double value) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1285,6 +1384,9 @@ hipError_t fill_t(V* v, size_t count, double value, hipStream_t st) {
 
 // EXT: the interpolated no-slip of f or the conservative front update is on
 // (a separate instantiation, so that the default one compiles without them)
+// Largest lattice whose reverse step uses the two shared launches.
+constexpr int kAdjFuseMaxN = 128;
+
 template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
 hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st) {
   const int n = P.n;
@@ -1309,7 +1411,20 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
                        lg1, A.out5, A.own, A.lth, P);
   const double* wq = A.heat ? A.wq : nullptr;
   // row slots of the full reverse collision: at most one per row
-  const dim3 gfront((n + bx - 1) / bx, (unsigned)(n * n < 2048 ? n * n : 2048), 1);
+  const int nslots = n * n < 2048 ? n * n : 2048;
+  if (n <= kAdjFuseMaxN) {  // two launches, each over all its independent parts
+    const int gx = (n + 63) / 64;
+    hipLaunchKernelGGL((k_adj_collide_all<Ts, Lam, FLOW, MZ, EXT>),
+                       dim3(gx, (unsigned)(nslots + n * n), 1), dim3(64, 1, 1), 0, st, f0, g0,
+                       A.s0, A.s1, A.th, A.cnt, A.cmin2, A.cmax2, A.rowb, lf1, lg1, lfh, lgh,
+                       nslots, P);
+    hipLaunchKernelGGL((k_adj_stream_all<Ts, Lam, FLOW, MZ, EXT>),
+                       dim3(gx, (unsigned)(n + nslots + n * n), 1), dim3(64, 1, 1), 0, st, g0, f0,
+                       A.s0, A.cnt, A.cmin2, A.cmax2, A.rowb, lfh, lgh, lf0, lg0, wq, A.own,
+                       A.out5, A.ls0, A.lth, nslots, P);
+    return hipGetLastError();
+  }
+  const dim3 gfront((n + bx - 1) / bx, (unsigned)nslots, 1);
   hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ, EXT>), gfront, bcell, 0, st, f0, g0, A.s0,
                      A.s1, A.th, A.cnt, A.cmin2, A.cmax2, A.rowb, lf1, lg1, lfh, lgh, P);
   hipLaunchKernelGGL((k_adj_collide_solid<Lam, MZ>), gcell, bcell, 0, st, A.rowb, lg1, lgh, P);
@@ -1348,12 +1463,21 @@ hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A,
   }
 }
 
-hipError_t launch_adj_partition(const KParams& P, const double* s, int* cnt, int* cmin2,
-                                int* cmax2, int* rmax, int slot, hipStream_t st) {
+hipError_t launch_adj_partition(const KParams& P, const double* const* states, int count,
+                                int* cnt, int* cmin2, int* cmax2, int* rmax, hipStream_t st) {
   const int n = P.n;
-  hipLaunchKernelGGL(k_adj_partition, dim3((n + 63) / 64, (n + kPartRows - 1) / kPartRows, 1),
-                     dim3(64, kPartRows, 1), 0, st, s, cnt, cmin2, cmax2, rmax, slot, n);
-  return hipGetLastError();
+  const size_t nn = (size_t)n * n;
+  constexpr int kMaxPlanes = 65535;  // grid z limit
+  for (int t0 = 0; t0 < count; t0 += kMaxPlanes) {
+    const int planes = count - t0 < kMaxPlanes ? count - t0 : kMaxPlanes;
+    hipLaunchKernelGGL(k_adj_partition,
+                       dim3((n + 63) / 64, (n + kPartRows - 1) / kPartRows, planes),
+                       dim3(64, kPartRows, 1), 0, st, states + t0, cnt + t0 * nn,
+                       cmin2 + t0 * nn, cmax2 + t0 * nn, rmax + t0, n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_fill(double* v, size_t count, double value, hipStream_t st) {

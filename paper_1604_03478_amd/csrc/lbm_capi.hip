@@ -93,7 +93,14 @@ struct AdjData {
   std::vector<void*> sf, sg;  // segment states 0..K
   std::vector<double*> ss;
   int *cnt = nullptr, *cmin = nullptr, *cmax = nullptr, *melted = nullptr, *frozen = nullptr,
-      *flag = nullptr, *cmin2 = nullptr, *cmax2 = nullptr, *rowb = nullptr;
+      *flag = nullptr;
+  // phase bookkeeping of the states of a segment (launch_adj_partition), for
+  // up to pcap states: counts, their 5x5 extremes (pcap n^2 each), the
+  // largest count of each state, and the device array of their fronts
+  int *cnt2 = nullptr, *cmin2 = nullptr, *cmax2 = nullptr, *rowb = nullptr;
+  const double** sptr = nullptr;
+  std::vector<const double*> sptr_host;  // source of the last upload of sptr
+  int pcap = 0;
   double* wq = nullptr;  // per-column weight of the interface heat (front scheme 1)
   void *lf[2] = {nullptr, nullptr}, *lg[2] = {nullptr, nullptr};  // per-cell adjoints
   void *lfh = nullptr, *lgh = nullptr;
@@ -183,9 +190,10 @@ void release_adjoint(AdjData& a) {
   free_all(a.sf);
   free_all(a.sg);
   free_all(a.ss);
-  void* ptrs[] = {a.cnt,   a.cmin,  a.cmax,  a.cmin2, a.cmax2, a.rowb, a.melted, a.frozen, a.flag,
-                  a.lf[0], a.lf[1], a.lg[0],
-                  a.lg[1], a.ls[0], a.ls[1], a.lfh, a.lgh, a.out5, a.own, a.lth, a.wq};
+  void* ptrs[] = {a.cnt,   a.cmin,   a.cmax,  a.cnt2,  a.cmin2, a.cmax2, a.rowb,
+                  a.sptr,  a.melted, a.frozen, a.flag, a.lf[0], a.lf[1], a.lg[0],
+                  a.lg[1], a.ls[0],  a.ls[1], a.lfh,   a.lgh,   a.out5,  a.own,
+                  a.lth,   a.wq};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   a = AdjData();
@@ -975,7 +983,6 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   const size_t lb = lbmk::lambda_bytes(c->kind);  // bytes of one per-cell adjoint value
   if (!a.lg[0]) {
     if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cmin, nn)) || (rc = dalloc(&a.cmax, nn)) ||
-        (rc = dalloc(&a.cmin2, nn)) || (rc = dalloc(&a.cmax2, nn)) || (rc = dalloc(&a.rowb, 2)) ||
         (rc = dalloc(&a.melted, nn)) || (rc = dalloc(&a.frozen, nn)) || (rc = dalloc(&a.flag, 1)) ||
         (rc = dalloc_bytes(&a.lg[0], 7 * nc * lb)) || (rc = dalloc_bytes(&a.lg[1], 7 * nc * lb)) ||
         (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
@@ -990,8 +997,24 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   HIP_TRY(hipMemsetAsync(a.melted, 0, nn * sizeof(int), c->stream));
   HIP_TRY(hipMemsetAsync(a.frozen, 0, nn * sizeof(int), c->stream));
   HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(int), c->stream));
-  HIP_TRY(hipMemsetAsync(a.rowb, 0, 2 * sizeof(int), c->stream));  // both partition slots
-  int64_t rev = 0;  // reverse steps taken; its parity picks the partition slot
+  if (a.pcap < a.K) {  // per-state phase bookkeeping of a segment
+    void* ptrs[] = {a.cnt2, a.cmin2, a.cmax2, a.rowb, a.sptr};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    a.cnt2 = a.cmin2 = a.cmax2 = a.rowb = nullptr;
+    a.sptr = nullptr;
+    a.pcap = 0;
+    const size_t np = (size_t)a.K * nn;
+    if ((rc = dalloc(&a.cnt2, np)) || (rc = dalloc(&a.cmin2, np)) || (rc = dalloc(&a.cmax2, np)) ||
+        (rc = dalloc(&a.rowb, (size_t)a.K)) ||
+        (rc = dalloc_bytes((void**)&a.sptr, (size_t)a.K * sizeof(double*))))
+      return rc;
+    a.pcap = a.K;
+  }
+  // the fronts of the segment states 0..K-1, for the batched partition
+  a.sptr_host.assign(a.ss.begin(), a.ss.begin() + a.K);
+  HIP_TRY(hipMemcpyAsync(a.sptr, a.sptr_host.data(), (size_t)a.K * sizeof(double*),
+                         hipMemcpyHostToDevice, c->stream));
   // adjoint of the final state: J = dJ_dfl * sum(s) / n^3
   int cur = 1;
   HIP_TRY(lbmk::launch_fill(a.ls[cur], nn, dJ_dfl / ((double)nn * c->p.n), c->stream));
@@ -1022,13 +1045,15 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
                                  a.sf[t + 1], c->th, a.melted, a.frozen, a.flag, nullptr, nullptr,
                                  nullptr, c->heat, nullptr, c->stream));
     }
+    // phase bookkeeping of the segment's states, all in one launch
+    HIP_TRY(hipMemsetAsync(a.rowb, 0, (size_t)len * sizeof(int), c->stream));
+    HIP_TRY(lbmk::launch_adj_partition(k, a.sptr, (int)len, a.cnt2, a.cmin2, a.cmax2, a.rowb,
+                                       c->stream));
     // reverse the segment
-    for (int64_t t = len - 1; t >= 0; --t, ++rev) {
-      const int slot = (int)(rev & 1);
-      HIP_TRY(lbmk::launch_adj_partition(k, a.ss[t], a.cnt, a.cmin2, a.cmax2, a.rowb, slot,
-                                         c->stream));
+    for (int64_t t = len - 1; t >= 0; --t) {
+      const int* cnt_t = a.cnt2 + (size_t)t * nn;
       if (c->heat)  // the interface heat of state t, for the reverse of the front update
-        HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], a.cnt, c->heat, c->stream));
+        HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], cnt_t, c->heat, c->stream));
       lbmk::AdjointStep A;
       A.f0 = a.sf[t];
       A.g0 = a.sg[t];
@@ -1036,10 +1061,10 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
       A.g1 = a.sg[t + 1];
       A.s1 = a.ss[t + 1];
       A.th = c->th;
-      A.cnt = a.cnt;
-      A.cmin2 = a.cmin2;
-      A.cmax2 = a.cmax2;
-      A.rowb = a.rowb + slot;
+      A.cnt = cnt_t;
+      A.cmin2 = a.cmin2 + (size_t)t * nn;
+      A.cmax2 = a.cmax2 + (size_t)t * nn;
+      A.rowb = a.rowb + t;
       A.lf1 = a.lf[cur];
       A.lg1 = a.lg[cur];
       A.ls1 = a.ls[cur];
