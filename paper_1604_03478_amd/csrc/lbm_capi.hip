@@ -92,8 +92,8 @@ struct AdjData {
   std::vector<double*> cks;
   std::vector<void*> sf, sg;  // segment states 0..K
   std::vector<double*> ss;
-  int *cnt = nullptr, *cmin = nullptr, *cmax = nullptr, *melted = nullptr, *frozen = nullptr,
-      *flag = nullptr;
+  int *cnt = nullptr, *melted = nullptr, *frozen = nullptr, *flag = nullptr;
+  uint32_t* cext = nullptr;  // 3x3 count extremes of the recompute (16-bit storage)
   // phase bookkeeping of the states of a segment (launch_adj_partition), for
   // up to pcap states: counts, their 5x5 extremes (pcap n^2 each), the
   // largest count of each state, and the device array of their fronts
@@ -131,9 +131,8 @@ struct lbm_ctx {
   double* s[2] = {nullptr, nullptr};
   int scur = 0;
   int* cnt = nullptr;
-  int* cmin = nullptr;
-  int* cmax = nullptr;
-  int* rowmax = nullptr;  // largest cmax per row of columns (16-bit storage)
+  uint32_t* cext = nullptr;  // min | max << 16 of the counts over 3x3 columns (16-bit storage)
+  int* rowmax = nullptr;     // largest such max per row of columns (16-bit storage)
   int* melted = nullptr;
   int* frozen = nullptr;
   int* flag = nullptr;
@@ -190,10 +189,10 @@ void release_adjoint(AdjData& a) {
   free_all(a.sf);
   free_all(a.sg);
   free_all(a.ss);
-  void* ptrs[] = {a.cnt,   a.cmin,   a.cmax,  a.cnt2,  a.cmin2, a.cmax2, a.rowb,
-                  a.sptr,  a.melted, a.frozen, a.flag, a.lf[0], a.lf[1], a.lg[0],
-                  a.lg[1], a.ls[0],  a.ls[1], a.lfh,   a.lgh,   a.out5,  a.own,
-                  a.lth,   a.wq};
+  void* ptrs[] = {a.cnt,   a.cext,   a.cnt2,   a.cmin2, a.cmax2, a.rowb,  a.sptr,
+                  a.melted, a.frozen, a.flag,  a.lf[0], a.lf[1], a.lg[0], a.lg[1],
+                  a.ls[0],  a.ls[1],  a.lfh,   a.lgh,   a.out5,  a.own,   a.lth,
+                  a.wq};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   a = AdjData();
@@ -212,8 +211,8 @@ void release(lbm_ctx* c) {
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
   release_adjoint(c->adj);
-  void* ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->s[0], c->s[1], c->cnt,  c->cmin,
-                  c->cmax, c->melted, c->frozen, c->flag, c->th,  c->red,  c->seedT, c->fields,
+  void* ptrs[] = {c->f[0], c->f[1], c->g[0], c->g[1], c->s[0], c->s[1], c->cnt,  c->cext,
+                  c->melted, c->frozen, c->flag, c->th,  c->red,  c->seedT, c->fields,
                   c->sched, c->replay, c->wall, c->heat, c->dpart, c->rowmax};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -288,7 +287,7 @@ int derive(const lbm_params* p, lbm_lattice* L) {
 
 int refresh_masks(lbm_ctx* c) {
   HIP_TRY(lbmk::launch_counts(c->kp, c->s[c->scur], c->cnt, c->stream));
-  HIP_TRY(lbmk::launch_neighbourhood(c->kp, c->cnt, c->cmin, c->cmax, c->rowmax, c->stream));
+  HIP_TRY(lbmk::launch_neighbourhood(c->kp, c->cnt, c->cext, c->rowmax, c->stream));
   return LBM_OK;
 }
 
@@ -451,7 +450,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
       return bail(fail(LBM_ENOMEM, "cannot allocate g (%zu bytes)", gbytes));
     }
   if ((rc = dalloc(&c->s[0], nn)) || (rc = dalloc(&c->s[1], nn)) || (rc = dalloc(&c->cnt, nn)) ||
-      (rc = dalloc(&c->cmin, nn)) || (rc = dalloc(&c->cmax, nn)) ||
+      (rc = dalloc(&c->cext, nn)) ||
       (rc = dalloc(&c->rowmax, (size_t)n)) ||
       (rc = dalloc(&c->melted, nn)) || (rc = dalloc(&c->frozen, nn)) ||
       (rc = dalloc(&c->flag, 1)) || (rc = dalloc(&c->th, nn)) || (rc = dalloc(&c->red, 8)) ||
@@ -525,7 +524,7 @@ hipError_t enqueue_step(lbm_ctx* c, const lbmk::KParams& k, int cur, int scur, i
   hipError_t e;
   if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
   if ((e = lbmk::launch_stream_collide(c->kind, k, c->f[cur], c->f[nx], c->g[cur], c->g[nx],
-                                       c->cnt, c->cmin, c->cmax, c->rowmax, c->s[scur], c->th,
+                                       c->cnt, c->cext, c->rowmax, c->s[scur], c->th,
                                        c->flag, st)) != hipSuccess)
     return e;
   if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
@@ -538,7 +537,7 @@ hipError_t enqueue_step(lbm_ctx* c, const lbmk::KParams& k, int cur, int scur, i
                               step_ctr, st)) != hipSuccess)
     return e;
   if (lbmk::uses_neighbourhood(c->kind) &&
-      (e = lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->rowmax, st)) != hipSuccess)
+      (e = lbmk::launch_neighbourhood(k, c->cnt, c->cext, c->rowmax, st)) != hipSuccess)
     return e;
   return hipSuccess;
 }
@@ -982,7 +981,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   }
   const size_t lb = lbmk::lambda_bytes(c->kind);  // bytes of one per-cell adjoint value
   if (!a.lg[0]) {
-    if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cmin, nn)) || (rc = dalloc(&a.cmax, nn)) ||
+    if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cext, nn)) ||
         (rc = dalloc(&a.melted, nn)) || (rc = dalloc(&a.frozen, nn)) || (rc = dalloc(&a.flag, 1)) ||
         (rc = dalloc_bytes(&a.lg[0], 7 * nc * lb)) || (rc = dalloc_bytes(&a.lg[1], 7 * nc * lb)) ||
         (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
@@ -1034,10 +1033,10 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
       // the front kernel leaves the counts of the next state behind
       if (t == 0) HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
       if (lbmk::uses_neighbourhood(c->kind))
-        HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cmin, a.cmax, nullptr, c->stream));
+        HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cext, nullptr, c->stream));
       // the one-cell path throughout (no row maxima): bit for bit the forward run
       HIP_TRY(lbmk::launch_stream_collide(c->kind, k, a.sf[t], a.sf[t + 1], a.sg[t], a.sg[t + 1],
-                                          a.cnt, a.cmin, a.cmax, nullptr, a.ss[t], c->th, a.flag,
+                                          a.cnt, a.cext, nullptr, a.ss[t], c->th, a.flag,
                                           c->stream));
       if (c->heat)  // conservative front: heat of the streaming from the state sg[t]
         HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], a.cnt, c->heat, c->stream));
@@ -1134,14 +1133,14 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
   HIP_TRY(hipMemcpyAsync(c->cnt, c->replay, nn * sizeof(int), hipMemcpyDeviceToDevice,
                          c->stream));
   lbmk::KParams& k = c->kp;
-  HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->rowmax, c->stream));
+  HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cext, c->rowmax, c->stream));
   for (int64_t t = 0; t < nsteps; ++t) {
     const int nx = c->cur ^ 1, sx = c->scur ^ 1;
     const int* e = c->replay + (size_t)t * 3 * nn;
     k.step = (uint32_t)c->step;
     // the one-cell path throughout (no row maxima): bit for bit the recorded run
     HIP_TRY(lbmk::launch_stream_collide(c->kind, k, c->f[c->cur], c->f[nx], c->g[c->cur], c->g[nx],
-                                        c->cnt, c->cmin, c->cmax, nullptr, c->s[c->scur], c->th,
+                                        c->cnt, c->cext, nullptr, c->s[c->scur], c->th,
                                         c->flag, c->stream));
     if (c->heat)  // conservative front: heat of the streaming from the state g[cur]
       HIP_TRY(lbmk::launch_front_heat(c->kind, k, c->g[c->cur], c->s[c->scur], c->cnt, c->heat,
@@ -1150,7 +1149,7 @@ int lbm_step_replay(lbm_ctx* c, const int32_t* schedule, int64_t nsteps) {
                                c->th, c->melted, c->frozen, c->flag, e, e + 3 * nn, nullptr,
                                c->heat, nullptr, c->stream));
     if (lbmk::uses_neighbourhood(c->kind))
-      HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cmin, c->cmax, c->rowmax, c->stream));
+      HIP_TRY(lbmk::launch_neighbourhood(k, c->cnt, c->cext, c->rowmax, c->stream));
     c->cur = nx;
     c->scur = sx;
     c->step++;

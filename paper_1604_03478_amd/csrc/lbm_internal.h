@@ -51,22 +51,22 @@ size_t store_bytes(int kind);
 uint32_t row_pitch(int n, int kind);
 
 // Whether the step kernel of a storage kind reads the precomputed 3x3
-// neighbourhood min / max of the liquid counts (16-bit storage); the others
-// take it from the counts themselves.
+// neighbourhood min / max of the liquid counts (16-bit storage, one packed
+// word per column); the others take it from the counts themselves.
 inline bool uses_neighbourhood(int kind) { return store_bytes(kind) == 2; }
 
 // One fused stream + collide pass over all cells: reads (fs, gs), writes
-// (fd, gd).  cnt/cmin/cmax: liquid-cell count per column and its min / max
-// over the 3x3 column neighbourhood (cmin/cmax are read only for 16-bit
-// storage, see uses_neighbourhood).  rowmax (16-bit storage, may be null):
-// the largest cmax of every row of columns, from launch_neighbourhood; with
+// (fd, gd).  cnt: liquid-cell count per column; cext: its min | max << 16
+// over the 3x3 column neighbourhood (from launch_neighbourhood; read only
+// for 16-bit storage, see uses_neighbourhood).  rowmax (16-bit storage, may be null):
+// the largest 3x3 maximum of every row of columns, from launch_neighbourhood; with
 // it the lattice rows whose stencils are all solid skip the per-cell phase
 // loads (the same results bit for bit).  s: front per column.  th: hot-wall
 // temperature per column.  flag: set to 1 when a non-finite value appears.
 hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, void* fd,
-                                 const void* gs, void* gd, const int* cnt, const int* cmin,
-                                 const int* cmax, const int* rowmax, const double* s,
-                                 const double* th, int* flag, hipStream_t st);
+                                 const void* gs, void* gd, const int* cnt, const uint32_t* cext,
+                                 const int* rowmax, const double* s, const double* th, int* flag,
+                                 hipStream_t st);
 
 // Interface update (Eq. (6)) of every column from the post-collision g, then
 // the phase switch: s_new, cnt (in place), refill of f in newly liquid cells,
@@ -84,12 +84,12 @@ hipError_t launch_front(int kind, const KParams& P, const double* s_old, double*
                         int* frozen, int* flag, const int* replay, const int* replay_next,
                         int* record, const double* heat, uint32_t* step_ctr, hipStream_t st);
 
-// cmin/cmax: min and max of cnt over the 3x3 columns around each column (the
+// cext: min | max << 16 of cnt over the 3x3 columns around each column (the
 // columns in the box), for the fast-path test of the 16-bit step kernel;
-// rowmax (n values, may be null): the largest cmax over each row of columns
+// rowmax (n values, may be null): the largest max over each row of columns
 // (all x for one value of the other lateral index).
-hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
-                                int* rowmax, hipStream_t st);
+hipError_t launch_neighbourhood(const KParams& P, const int* cnt, uint32_t* cext, int* rowmax,
+                                hipStream_t st);
 
 // *p = v (one thread).
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t st);

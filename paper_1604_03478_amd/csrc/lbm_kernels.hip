@@ -228,7 +228,7 @@ template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 __device__ __forceinline__ void update_cell(
     int x, int y, int z, const Ts* __restrict__ fs, Ts* __restrict__ fd,
     const Ts* __restrict__ gs, Ts* __restrict__ gd, const int* __restrict__ cnt,
-    const int* __restrict__ cmin, const int* __restrict__ cmax, const double* __restrict__ s,
+    const uint32_t* __restrict__ cext, const double* __restrict__ s,
     const double* __restrict__ th, int* __restrict__ flag, const KParams& P) {
   using C = typename Compute<Ts>::type;
   using G = typename Compute<Ts>::gtype;
@@ -240,20 +240,25 @@ __device__ __forceinline__ void update_cell(
   const int a = MZ ? z : y;  // coordinate along the melt axis
   const int o = MZ ? y : z;  // the other lateral coordinate
   const int col = o * n + x;
-  const int cc = cnt[col];
-  const bool liquid = a < cc;
   const bool interior = (y > 0) & (y < n - 1) & (z > 0) & (z < n - 1);
   // min and max of the liquid counts over the 3x3 columns around this one:
-  // read from the precomputed arrays with 16-bit storage (its kernel is held
+  // with 16-bit storage one precomputed word per column (its kernel is held
   // to 64 registers), else taken from the counts here, which saves the
   // per-step neighbourhood kernel (clamped at the walls: a repeated column
-  // leaves min and max unchanged)
-  int lo, hi;
+  // leaves min and max unchanged).  The column's own count cc decides the
+  // phase; with 16-bit storage it is loaded on the general path only (on the
+  // fast path the extremes decide it), which saves one of the two column
+  // loads per cell.
+  int cc = 0, lo, hi;
+  bool liquid = false;
   int nb[9];  // counts of the 3x3 columns, [(o offset + 1) * 3 + x offset + 1]
   if constexpr (sizeof(Ts) == 2) {
-    lo = cmin[col];
-    hi = cmax[col];
+    const uint32_t w = cext[col];
+    lo = (int)(w & 0xffffu);
+    hi = (int)(w >> 16);
   } else {
+    cc = cnt[col];
+    liquid = a < cc;
     const int xm = x > 0 ? x - 1 : x, xp = x < n - 1 ? x + 1 : x;
     const int om = o > 0 ? o - 1 : o, op = o < n - 1 ? o + 1 : o;
     nb[0] = cnt[om * n + xm];
@@ -304,6 +309,7 @@ __device__ __forceinline__ void update_cell(
 
   if (__all(fast)) {
     // ---------- fast path: one phase, only x walls possible ----------
+    if constexpr (sizeof(Ts) == 2) liquid = all_liq;  // a + 1 < lo <= cc, or a - 1 >= hi >= cc
     // Every source row lies in the 3x3 block of rows around (y, z).  Offsets
     // are counted from the block's first row (y - 1, z - 1), so all loads of
     // a distribution share one uniform base and differ by a 32-bit lane
@@ -339,6 +345,10 @@ __device__ __forceinline__ void update_cell(
     }
   } else {
     // ---------- general path: walls and the front, link by link ----------
+    if constexpr (sizeof(Ts) == 2) {
+      cc = cnt[col];
+      liquid = a < cc;
+    }
     if constexpr (kMask) {
       const int xm = x > 0 ? x - 1 : x, xp = x < n - 1 ? x + 1 : x;
       const int om = o > 0 ? o - 1 : o, op = o < n - 1 ? o + 1 : o;
@@ -518,13 +528,12 @@ __device__ __forceinline__ void solid_cell(int x, int y, int z, const Ts* __rest
 template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 __global__ __launch_bounds__(512) void k_stream_collide(
     const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
-    Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
-    const int* __restrict__ cmax, const double* __restrict__ s, const double* __restrict__ th,
-    int* __restrict__ flag, KParams P) {
+    Ts* __restrict__ gd, const int* __restrict__ cnt, const double* __restrict__ s,
+    const double* __restrict__ th, int* __restrict__ flag, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y, z;
   step_row(P.n, y, z);
-  update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, cmin, cmax, s, th, flag, P);
+  update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, nullptr, s, th, flag, P);
 }
 
 // The same for 16-bit storage, held to 7 or 8 resident waves per SIMD.  Its
@@ -542,8 +551,8 @@ template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 __global__ __launch_bounds__(512) __attribute__((
     amdgpu_waves_per_eu(kWaves16<Ts, FLOW, MZ, FWALL>, kWaves16<Ts, FLOW, MZ, FWALL>))) void
 k_stream_collide_h(const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
-                   Ts* __restrict__ gd, const int* __restrict__ cnt, const int* __restrict__ cmin,
-                   const int* __restrict__ cmax, const int* __restrict__ rowmax,
+                   Ts* __restrict__ gd, const int* __restrict__ cnt,
+                   const uint32_t* __restrict__ cext, const int* __restrict__ rowmax,
                    const double* __restrict__ s, const double* __restrict__ th,
                    int* __restrict__ flag, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -559,7 +568,7 @@ k_stream_collide_h(const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __r
       return;
     }
   }
-  update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, cmin, cmax, s, th, flag, P);
+  update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, cext, s, th, flag, P);
 }
 
 // --------------------------------------------------------------- front update
@@ -711,13 +720,14 @@ __global__ void k_counts(const double* __restrict__ s, int* __restrict__ cnt, in
   if (i < n * n) cnt[i] = count_liquid(s[i], n);
 }
 
-// One workgroup per row of columns o: cmin / cmax of every column's 3x3
-// neighbourhood, and (rowmax != null) the largest cmax of the row, which
-// bounds the liquid counts near every cell of the lattice rows with this o.
+// One workgroup per row of columns o: the min and max liquid count of every
+// column's 3x3 neighbourhood, packed into one word (min in the low 16 bits,
+// max in the high; counts are at most n <= 1024), and (rowmax != null) the
+// largest max of the row, which bounds the liquid counts near every cell of
+// the lattice rows with this o.
 constexpr int kNbThreads = 256;
 __global__ __launch_bounds__(kNbThreads) void k_neighbourhood(const int* __restrict__ cnt,
-                                                              int* __restrict__ cmin,
-                                                              int* __restrict__ cmax,
+                                                              uint32_t* __restrict__ cext,
                                                               int* __restrict__ rowmax, int n) {
   __shared__ int sh[kNbThreads / 64];
   const int o = blockIdx.x;
@@ -735,8 +745,7 @@ __global__ __launch_bounds__(kNbThreads) void k_neighbourhood(const int* __restr
         hi = c > hi ? c : hi;
       }
     }
-    cmin[o * n + x] = lo;
-    cmax[o * n + x] = hi;
+    cext[o * n + x] = (uint32_t)lo | ((uint32_t)hi << 16);
     rmax = hi > rmax ? hi : rmax;
   }
   if (!rowmax) return;  // uniform
@@ -870,7 +879,7 @@ __global__ __launch_bounds__(kSumThreads) void k_sum(const double* __restrict__ 
 // --------------------------------------------------------------- dispatch
 template <typename Ts>
 hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* gs, void* gd,
-                       const int* cnt, const int* cmin, const int* cmax, const int* rowmax,
+                       const int* cnt, const uint32_t* cext, const int* rowmax,
                        const double* s, const double* th, int* flag, hipStream_t st) {
   auto F = static_cast<const Ts*>(fs);
   auto Fd = static_cast<Ts*>(fd);
@@ -891,10 +900,10 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
   do {                                                                                          \
     if constexpr (sizeof(Ts) == 2)                                                              \
       hipLaunchKernelGGL((k_stream_collide_h<Ts, FLOW, MZ, FWALL>), grid, block, 0, st, F, Fd, \
-                         G, Gd, cnt, cmin, cmax, rowmax, s, th, flag, P);                       \
+                         G, Gd, cnt, cext, rowmax, s, th, flag, P);                             \
     else                                                                                        \
       hipLaunchKernelGGL((k_stream_collide<Ts, FLOW, MZ, FWALL>), grid, block, 0, st, F, Fd, G, \
-                         Gd, cnt, cmin, cmax, s, th, flag, P);                                  \
+                         Gd, cnt, s, th, flag, P);                                              \
   } while (0)
   if (P.flow && P.f_wall) {
     if (P.melt_z) LAUNCH(true, true, true); else LAUNCH(true, false, true);
@@ -1007,10 +1016,10 @@ size_t store_bytes(int kind) {
 }
 
 hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, void* fd,
-                                 const void* gs, void* gd, const int* cnt, const int* cmin,
-                                 const int* cmax, const int* rowmax, const double* s,
-                                 const double* th, int* flag, hipStream_t st) {
-#define CALL(T) sc_dispatch<T>(P, fs, fd, gs, gd, cnt, cmin, cmax, rowmax, s, th, flag, st)
+                                 const void* gs, void* gd, const int* cnt, const uint32_t* cext,
+                                 const int* rowmax, const double* s, const double* th, int* flag,
+                                 hipStream_t st) {
+#define CALL(T) sc_dispatch<T>(P, fs, fd, gs, gd, cnt, cext, rowmax, s, th, flag, st)
   switch (kind) {
     case kF64: return CALL(double);
     case kF32: return CALL(float);
@@ -1038,10 +1047,10 @@ hipError_t launch_front(int kind, const KParams& P, const double* s_old, double*
 #undef CALL
 }
 
-hipError_t launch_neighbourhood(const KParams& P, const int* cnt, int* cmin, int* cmax,
-                                int* rowmax, hipStream_t st) {
-  hipLaunchKernelGGL(k_neighbourhood, dim3(P.n), dim3(kNbThreads), 0, st, cnt, cmin, cmax,
-                     rowmax, P.n);
+hipError_t launch_neighbourhood(const KParams& P, const int* cnt, uint32_t* cext, int* rowmax,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_neighbourhood, dim3(P.n), dim3(kNbThreads), 0, st, cnt, cext, rowmax,
+                     P.n);
   return hipGetLastError();
 }
 
