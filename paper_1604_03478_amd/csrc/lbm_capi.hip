@@ -83,6 +83,19 @@ double two_phase_constant(double ste_l, double ste_s, double kappa) {
 
 }  // namespace
 
+// The recomputed states of one segment (0..K) and their phase bookkeeping
+// (launch_adj_partition), for up to pcap states: counts, their 5x5 extremes
+// (pcap n^2 each), the largest count of each state, and the device array of
+// their fronts.
+struct SegSet {
+  std::vector<void*> sf, sg;
+  std::vector<double*> ss;
+  int *cnt2 = nullptr, *cmin2 = nullptr, *cmax2 = nullptr, *rowb = nullptr;
+  const double** sptr = nullptr;
+  std::vector<const double*> sptr_host;  // source of the last upload of sptr
+  int pcap = 0;
+};
+
 // Checkpoints of a forward run and the buffers of its reverse sweep.
 struct AdjData {
   bool ready = false;
@@ -90,17 +103,15 @@ struct AdjData {
   int K = 0, nck = 0;
   std::vector<void*> ckf, ckg;
   std::vector<double*> cks;
-  std::vector<void*> sf, sg;  // segment states 0..K
-  std::vector<double*> ss;
+  // one segment set, or two: then the recompute of the next segment (on the
+  // side stream) overlaps the reverse sweep of the current one
+  SegSet set[2];
+  hipStream_t side = nullptr;
+  hipEvent_t ev_start = nullptr, ev_rc[2] = {nullptr, nullptr}, ev_rv[2] = {nullptr, nullptr};
+  // recompute scratch (only the recompute uses these)
   int *cnt = nullptr, *melted = nullptr, *frozen = nullptr, *flag = nullptr;
   uint32_t* cext = nullptr;  // 3x3 count extremes of the recompute (16-bit storage)
-  // phase bookkeeping of the states of a segment (launch_adj_partition), for
-  // up to pcap states: counts, their 5x5 extremes (pcap n^2 each), the
-  // largest count of each state, and the device array of their fronts
-  int *cnt2 = nullptr, *cmin2 = nullptr, *cmax2 = nullptr, *rowb = nullptr;
-  const double** sptr = nullptr;
-  std::vector<const double*> sptr_host;  // source of the last upload of sptr
-  int pcap = 0;
+  double* heat_rc = nullptr;  // interface heat of a recomputed step (front scheme 1)
   double* wq = nullptr;  // per-column weight of the interface heat (front scheme 1)
   void *lf[2] = {nullptr, nullptr}, *lg[2] = {nullptr, nullptr};  // per-cell adjoints
   void *lfh = nullptr, *lgh = nullptr;
@@ -182,19 +193,35 @@ void free_all(std::vector<double*>& v) {
   v.clear();
 }
 
+void release_states(SegSet& s) {
+  free_all(s.sf);
+  free_all(s.sg);
+  free_all(s.ss);
+}
+
+void release_set(SegSet& s) {
+  release_states(s);
+  void* ptrs[] = {s.cnt2, s.cmin2, s.cmax2, s.rowb, s.sptr};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  s = SegSet();
+}
+
 void release_adjoint(AdjData& a) {
   free_all(a.ckf);
   free_all(a.ckg);
   free_all(a.cks);
-  free_all(a.sf);
-  free_all(a.sg);
-  free_all(a.ss);
-  void* ptrs[] = {a.cnt,   a.cext,   a.cnt2,   a.cmin2, a.cmax2, a.rowb,  a.sptr,
-                  a.melted, a.frozen, a.flag,  a.lf[0], a.lf[1], a.lg[0], a.lg[1],
-                  a.ls[0],  a.ls[1],  a.lfh,   a.lgh,   a.out5,  a.own,   a.lth,
-                  a.wq};
+  release_set(a.set[0]);
+  release_set(a.set[1]);
+  void* ptrs[] = {a.cnt,   a.cext,  a.heat_rc, a.melted, a.frozen, a.flag, a.lf[0], a.lf[1],
+                  a.lg[0], a.lg[1], a.ls[0],   a.ls[1],  a.lfh,    a.lgh,  a.out5,  a.own,
+                  a.lth,   a.wq};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  hipEvent_t evs[] = {a.ev_start, a.ev_rc[0], a.ev_rc[1], a.ev_rv[0], a.ev_rv[1]};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
+  if (a.side) (void)hipStreamDestroy(a.side);
   a = AdjData();
 }
 
@@ -888,9 +915,8 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
   const int nck = (int)((nsteps + every_k - 1) / every_k);
   a.ready = false;
   if (a.K != every_k) {  // the segment buffers are sized by every_k
-    free_all(a.sf);
-    free_all(a.sg);
-    free_all(a.ss);
+    release_states(a.set[0]);
+    release_states(a.set[1]);
   }
   while ((int)a.ckg.size() > nck) {
     if (a.ckf.back()) (void)hipFree(a.ckf.back());
@@ -954,6 +980,124 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
   return LBM_OK;
 }
 
+namespace {
+
+// Device bytes of one segment set: K + 1 states and the bookkeeping of K.
+size_t segset_bytes(const lbm_ctx* c, int K) {
+  const size_t nn = (size_t)c->p.n * c->p.n;
+  const size_t fb = c->p.flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
+  return (size_t)(K + 1) * (fb + gb + nn * sizeof(double)) +
+         (size_t)K * (3 * nn * sizeof(int) + sizeof(int) + sizeof(double*));
+}
+
+// Fill a segment set up to K + 1 states and K bookkeeping entries.
+int alloc_segset(lbm_ctx* c, SegSet& S, int K) {
+  const size_t nn = (size_t)c->p.n * c->p.n;
+  const size_t fb = c->p.flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
+  while ((int)S.sg.size() < K + 1) {
+    void *f = nullptr, *g = nullptr;
+    double* sp = nullptr;
+    if ((fb && hipMalloc(&f, fb) != hipSuccess) || hipMalloc(&g, gb) != hipSuccess ||
+        hipMalloc((void**)&sp, nn * sizeof(double)) != hipSuccess) {
+      if (f) (void)hipFree(f);
+      if (g) (void)hipFree(g);
+      return fail(LBM_ENOMEM, "cannot allocate the recompute segment (%d states)", K + 1);
+    }
+    S.sf.push_back(f);
+    S.sg.push_back(g);
+    S.ss.push_back(sp);
+  }
+  if (S.pcap < K) {
+    void* ptrs[] = {S.cnt2, S.cmin2, S.cmax2, S.rowb, S.sptr};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    S.cnt2 = S.cmin2 = S.cmax2 = S.rowb = nullptr;
+    S.sptr = nullptr;
+    S.pcap = 0;
+    const size_t np = (size_t)K * nn;
+    int rc;
+    if ((rc = dalloc(&S.cnt2, np)) || (rc = dalloc(&S.cmin2, np)) || (rc = dalloc(&S.cmax2, np)) ||
+        (rc = dalloc(&S.rowb, (size_t)K)) ||
+        (rc = dalloc_bytes((void**)&S.sptr, (size_t)K * sizeof(double*))))
+      return rc;
+    S.pcap = K;
+  }
+  return LBM_OK;
+}
+
+// Recompute segment i of the recorded run into set S on stream st, bit for
+// bit as the forward run, then its phase bookkeeping (one launch).
+int enqueue_recompute(lbm_ctx* c, int i, SegSet& S, hipStream_t st) {
+  AdjData& a = c->adj;
+  const size_t nn = (size_t)c->p.n * c->p.n;
+  const size_t fb = c->p.flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
+  const int64_t len = std::min<int64_t>(a.K, a.nsteps - (int64_t)i * a.K);
+  lbmk::KParams k = c->kp;
+  if (fb) HIP_TRY(hipMemcpyAsync(S.sf[0], a.ckf[i], fb, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(S.sg[0], a.ckg[i], gb, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(S.ss[0], a.cks[i], nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int64_t t = 0; t < len; ++t) {
+    k.step = (uint32_t)(a.start + (int64_t)i * a.K + t);
+    // the front kernel leaves the counts of the next state behind
+    if (t == 0) HIP_TRY(lbmk::launch_counts(k, S.ss[t], a.cnt, st));
+    if (lbmk::uses_neighbourhood(c->kind))
+      HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cext, nullptr, st));
+    // the one-cell path throughout (no row maxima): bit for bit the forward run
+    HIP_TRY(lbmk::launch_stream_collide(c->kind, k, S.sf[t], S.sf[t + 1], S.sg[t], S.sg[t + 1],
+                                        a.cnt, a.cext, nullptr, S.ss[t], c->th, a.flag, st));
+    if (c->heat)  // conservative front: heat of the streaming from the state sg[t]
+      HIP_TRY(lbmk::launch_front_heat(c->kind, k, S.sg[t], S.ss[t], a.cnt, a.heat_rc, st));
+    HIP_TRY(lbmk::launch_front(c->kind, k, S.ss[t], S.ss[t + 1], a.cnt, S.sg[t + 1],
+                               S.sf[t + 1], c->th, a.melted, a.frozen, a.flag, nullptr, nullptr,
+                               nullptr, c->heat ? a.heat_rc : nullptr, nullptr, st));
+  }
+  HIP_TRY(hipMemsetAsync(S.rowb, 0, (size_t)len * sizeof(int), st));
+  HIP_TRY(lbmk::launch_adj_partition(k, S.sptr, (int)len, S.cnt2, S.cmin2, S.cmax2, S.rowb, st));
+  return LBM_OK;
+}
+
+// The reverse steps of segment i from set S on stream st; cur: the slot of
+// the per-cell adjoints of the newest state, updated.
+int enqueue_reverse(lbm_ctx* c, int i, SegSet& S, int& cur, hipStream_t st) {
+  AdjData& a = c->adj;
+  const size_t nn = (size_t)c->p.n * c->p.n;
+  const int64_t len = std::min<int64_t>(a.K, a.nsteps - (int64_t)i * a.K);
+  for (int64_t t = len - 1; t >= 0; --t) {
+    const int* cnt_t = S.cnt2 + (size_t)t * nn;
+    if (c->heat)  // the interface heat of state t, for the reverse of the front update
+      HIP_TRY(lbmk::launch_front_heat(c->kind, c->kp, S.sg[t], S.ss[t], cnt_t, c->heat, st));
+    lbmk::AdjointStep A;
+    A.f0 = S.sf[t];
+    A.g0 = S.sg[t];
+    A.s0 = S.ss[t];
+    A.g1 = S.sg[t + 1];
+    A.s1 = S.ss[t + 1];
+    A.th = c->th;
+    A.cnt = cnt_t;
+    A.cmin2 = S.cmin2 + (size_t)t * nn;
+    A.cmax2 = S.cmax2 + (size_t)t * nn;
+    A.rowb = S.rowb + t;
+    A.lf1 = a.lf[cur];
+    A.lg1 = a.lg[cur];
+    A.ls1 = a.ls[cur];
+    A.lf0 = a.lf[1 - cur];
+    A.lg0 = a.lg[1 - cur];
+    A.ls0 = a.ls[1 - cur];
+    A.lfh = a.lfh;
+    A.lgh = a.lgh;
+    A.out5 = a.out5;
+    A.own = a.own;
+    A.lth = a.lth;
+    A.heat = c->heat;
+    A.wq = a.wq;
+    HIP_TRY(lbmk::launch_adjoint_step(c->kind, c->kp, A, st));
+    cur = 1 - cur;
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
 int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -964,21 +1108,25 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
                 "or hot-wall change since");
   const size_t nn = (size_t)c->p.n * c->p.n, nc = c->kp.ncell;
   const bool flow = c->p.flow != 0;
-  const size_t fb = flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
-  // segment states and scratch
-  while ((int)a.sg.size() < a.K + 1) {
-    void *f = nullptr, *g = nullptr;
-    double* sp = nullptr;
-    if ((fb && hipMalloc(&f, fb) != hipSuccess) || hipMalloc(&g, gb) != hipSuccess ||
-        hipMalloc((void**)&sp, nn * sizeof(double)) != hipSuccess) {
-      if (f) (void)hipFree(f);
-      if (g) (void)hipFree(g);
-      return fail(LBM_ENOMEM, "cannot allocate the recompute segment (%d states)", a.K + 1);
+  // segment sets: a second one when the run has several segments and the set
+  // fits with room to spare, so that the recompute of each segment overlaps
+  // the reverse sweep of the one after it
+  if ((rc = alloc_segset(c, a.set[0], a.K))) return rc;
+  if (a.nck > 1) {
+    if (a.set[1].sg.empty()) {
+      size_t free_b = 0, total_b = 0;
+      const size_t need = segset_bytes(c, a.K);
+      if (hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+          free_b > need + need / 4 + ((size_t)4 << 30) &&
+          alloc_segset(c, a.set[1], a.K) != LBM_OK) {
+        release_set(a.set[1]);  // not enough after all: one set
+        (void)hipGetLastError();
+      }
+    } else if ((rc = alloc_segset(c, a.set[1], a.K))) {
+      return rc;
     }
-    a.sf.push_back(f);
-    a.sg.push_back(g);
-    a.ss.push_back(sp);
   }
+  const int nsets = a.nck > 1 && !a.set[1].sg.empty() ? 2 : 1;
   const size_t lb = lbmk::lambda_bytes(c->kind);  // bytes of one per-cell adjoint value
   if (!a.lg[0]) {
     if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cext, nn)) ||
@@ -986,104 +1134,74 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
         (rc = dalloc_bytes(&a.lg[0], 7 * nc * lb)) || (rc = dalloc_bytes(&a.lg[1], 7 * nc * lb)) ||
         (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
         (rc = dalloc_bytes(&a.lgh, 7 * nc * lb)) || (rc = dalloc(&a.out5, 5 * nn)) ||
-        (rc = dalloc(&a.own, nn)) || (rc = dalloc(&a.lth, nn)) || (rc = dalloc(&a.wq, nn)))
+        (rc = dalloc(&a.own, nn)) || (rc = dalloc(&a.lth, nn)) || (rc = dalloc(&a.wq, nn)) ||
+        (c->heat && (rc = dalloc(&a.heat_rc, nn))))
       return rc;
     if (flow && ((rc = dalloc_bytes(&a.lf[0], 19 * nc * lb)) ||
                  (rc = dalloc_bytes(&a.lf[1], 19 * nc * lb)) ||
                  (rc = dalloc_bytes(&a.lfh, 19 * nc * lb))))
       return rc;
   }
-  HIP_TRY(hipMemsetAsync(a.melted, 0, nn * sizeof(int), c->stream));
-  HIP_TRY(hipMemsetAsync(a.frozen, 0, nn * sizeof(int), c->stream));
-  HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(int), c->stream));
-  if (a.pcap < a.K) {  // per-state phase bookkeeping of a segment
-    void* ptrs[] = {a.cnt2, a.cmin2, a.cmax2, a.rowb, a.sptr};
-    for (void* p : ptrs)
-      if (p) (void)hipFree(p);
-    a.cnt2 = a.cmin2 = a.cmax2 = a.rowb = nullptr;
-    a.sptr = nullptr;
-    a.pcap = 0;
-    const size_t np = (size_t)a.K * nn;
-    if ((rc = dalloc(&a.cnt2, np)) || (rc = dalloc(&a.cmin2, np)) || (rc = dalloc(&a.cmax2, np)) ||
-        (rc = dalloc(&a.rowb, (size_t)a.K)) ||
-        (rc = dalloc_bytes((void**)&a.sptr, (size_t)a.K * sizeof(double*))))
-      return rc;
-    a.pcap = a.K;
+  const bool two = nsets == 2;
+  if (two && !a.side) {
+    HIP_TRY(hipStreamCreateWithFlags(&a.side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&a.ev_start, hipEventDisableTiming));
+    for (int b = 0; b < 2; ++b) {
+      HIP_TRY(hipEventCreateWithFlags(&a.ev_rc[b], hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&a.ev_rv[b], hipEventDisableTiming));
+    }
   }
+  // the recompute runs on the side stream (after everything enqueued so far)
+  const hipStream_t rs = two ? a.side : c->stream;
+  if (two) {
+    HIP_TRY(hipEventRecord(a.ev_start, c->stream));
+    HIP_TRY(hipStreamWaitEvent(rs, a.ev_start, 0));
+  }
+  HIP_TRY(hipMemsetAsync(a.melted, 0, nn * sizeof(int), rs));
+  HIP_TRY(hipMemsetAsync(a.frozen, 0, nn * sizeof(int), rs));
+  HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(int), rs));
   // the fronts of the segment states 0..K-1, for the batched partition
-  a.sptr_host.assign(a.ss.begin(), a.ss.begin() + a.K);
-  HIP_TRY(hipMemcpyAsync(a.sptr, a.sptr_host.data(), (size_t)a.K * sizeof(double*),
-                         hipMemcpyHostToDevice, c->stream));
+  for (int b = 0; b < nsets; ++b) {
+    SegSet& S = a.set[b];
+    S.sptr_host.assign(S.ss.begin(), S.ss.begin() + a.K);
+    HIP_TRY(hipMemcpyAsync(S.sptr, S.sptr_host.data(), (size_t)a.K * sizeof(double*),
+                           hipMemcpyHostToDevice, rs));
+  }
   // adjoint of the final state: J = dJ_dfl * sum(s) / n^3
   int cur = 1;
   HIP_TRY(lbmk::launch_fill(a.ls[cur], nn, dJ_dfl / ((double)nn * c->p.n), c->stream));
   HIP_TRY(lbmk::launch_fill_lambda(c->kind, a.lg[cur], 7 * nc, 0.0, c->stream));
   if (flow) HIP_TRY(lbmk::launch_fill_lambda(c->kind, a.lf[cur], 19 * nc, 0.0, c->stream));
   HIP_TRY(lbmk::launch_fill(a.lth, nn, 0.0, c->stream));
-  lbmk::KParams k = c->kp;
-  for (int i = a.nck - 1; i >= 0; --i) {
-    const int64_t len = std::min<int64_t>(a.K, a.nsteps - (int64_t)i * a.K);
-    if (fb) HIP_TRY(hipMemcpyAsync(a.sf[0], a.ckf[i], fb, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(a.sg[0], a.ckg[i], gb, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(a.ss[0], a.cks[i], nn * sizeof(double), hipMemcpyDeviceToDevice,
-                           c->stream));
-    // recompute the segment, bit for bit as the forward run
-    for (int64_t t = 0; t < len; ++t) {
-      k.step = (uint32_t)(a.start + (int64_t)i * a.K + t);
-      // the front kernel leaves the counts of the next state behind
-      if (t == 0) HIP_TRY(lbmk::launch_counts(k, a.ss[t], a.cnt, c->stream));
-      if (lbmk::uses_neighbourhood(c->kind))
-        HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cext, nullptr, c->stream));
-      // the one-cell path throughout (no row maxima): bit for bit the forward run
-      HIP_TRY(lbmk::launch_stream_collide(c->kind, k, a.sf[t], a.sf[t + 1], a.sg[t], a.sg[t + 1],
-                                          a.cnt, a.cext, nullptr, a.ss[t], c->th, a.flag,
-                                          c->stream));
-      if (c->heat)  // conservative front: heat of the streaming from the state sg[t]
-        HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], a.cnt, c->heat, c->stream));
-      HIP_TRY(lbmk::launch_front(c->kind, k, a.ss[t], a.ss[t + 1], a.cnt, a.sg[t + 1],
-                                 a.sf[t + 1], c->th, a.melted, a.frozen, a.flag, nullptr, nullptr,
-                                 nullptr, c->heat, nullptr, c->stream));
+  if (!two) {
+    for (int i = a.nck - 1; i >= 0; --i) {
+      if ((rc = enqueue_recompute(c, i, a.set[0], c->stream))) return rc;
+      if ((rc = enqueue_reverse(c, i, a.set[0], cur, c->stream))) return rc;
     }
-    // phase bookkeeping of the segment's states, all in one launch
-    HIP_TRY(hipMemsetAsync(a.rowb, 0, (size_t)len * sizeof(int), c->stream));
-    HIP_TRY(lbmk::launch_adj_partition(k, a.sptr, (int)len, a.cnt2, a.cmin2, a.cmax2, a.rowb,
-                                       c->stream));
-    // reverse the segment
-    for (int64_t t = len - 1; t >= 0; --t) {
-      const int* cnt_t = a.cnt2 + (size_t)t * nn;
-      if (c->heat)  // the interface heat of state t, for the reverse of the front update
-        HIP_TRY(lbmk::launch_front_heat(c->kind, k, a.sg[t], a.ss[t], cnt_t, c->heat, c->stream));
-      lbmk::AdjointStep A;
-      A.f0 = a.sf[t];
-      A.g0 = a.sg[t];
-      A.s0 = a.ss[t];
-      A.g1 = a.sg[t + 1];
-      A.s1 = a.ss[t + 1];
-      A.th = c->th;
-      A.cnt = cnt_t;
-      A.cmin2 = a.cmin2 + (size_t)t * nn;
-      A.cmax2 = a.cmax2 + (size_t)t * nn;
-      A.rowb = a.rowb + t;
-      A.lf1 = a.lf[cur];
-      A.lg1 = a.lg[cur];
-      A.ls1 = a.ls[cur];
-      A.lf0 = a.lf[1 - cur];
-      A.lg0 = a.lg[1 - cur];
-      A.ls0 = a.ls[1 - cur];
-      A.lfh = a.lfh;
-      A.lgh = a.lgh;
-      A.out5 = a.out5;
-      A.own = a.own;
-      A.lth = a.lth;
-      A.heat = c->heat;
-      A.wq = a.wq;
-      HIP_TRY(lbmk::launch_adjoint_step(c->kind, c->kp, A, c->stream));
-      cur = 1 - cur;
+  } else {
+    // segment i uses set (nck - 1 - i) mod 2.  The side stream recomputes
+    // segment i - 1 into the other set as soon as the reverse sweep of
+    // segment i + 1 has released it; the main stream reverses segment i once
+    // its recompute is done.
+    const int last = a.nck - 1;
+    if ((rc = enqueue_recompute(c, last, a.set[0], rs))) return rc;
+    HIP_TRY(hipEventRecord(a.ev_rc[0], rs));
+    for (int i = last; i >= 0; --i) {
+      const int b = (last - i) & 1;
+      if (i > 0) {
+        if (i < last) HIP_TRY(hipStreamWaitEvent(rs, a.ev_rv[1 - b], 0));
+        if ((rc = enqueue_recompute(c, i - 1, a.set[1 - b], rs))) return rc;
+        HIP_TRY(hipEventRecord(a.ev_rc[1 - b], rs));
+      }
+      HIP_TRY(hipStreamWaitEvent(c->stream, a.ev_rc[b], 0));
+      if ((rc = enqueue_reverse(c, i, a.set[b], cur, c->stream))) return rc;
+      HIP_TRY(hipEventRecord(a.ev_rv[b], c->stream));
     }
   }
   HIP_TRY(hipMemcpyAsync(grad_th, a.lth, nn * sizeof(double),
                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  if (two) HIP_TRY(hipStreamSynchronize(rs));
   return LBM_OK;
 }
 

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(512) void k_pull_pattern(const Ts* __restrict__ fs,
                                                       Ts* __restrict__ gd, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y, z;
-  step_row(P.n, y, z);
+  step_row<row_run<Ts>()>(P.n, y, z);
   if (x >= P.n) return;
   move_pulled<7>(gs, gd, P, x, y, z);
   if (P.flow) move_pulled<19>(fs, fd, P, x, y, z);

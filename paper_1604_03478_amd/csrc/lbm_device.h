@@ -183,13 +183,55 @@ __host__ __device__ constexpr int step_block_max(size_t bytes) { return bytes ==
 
 // One lattice row per workgroup, so the row pointers are uniform over it.
 // The workgroups of the n x n rows are numbered r = blockIdx.z * n +
-// blockIdx.y, the order in which they are dispatched.  The 4n - 4 rows on the
-// y and z walls, which always take the general path, come first; the
+// blockIdx.y, the order in which they are dispatched; workgroup w runs on
+// XCD w mod 8 (round-robin dispatch), each XCD with its own L2.
+//
+// Neighbouring rows share cache lines: at an x wall a cell bounces back its
+// own outgoing population, the first or last value of a direction row whose
+// other values a neighbouring row (y +- 1 or z +- 1, for the 8 diagonal
+// directions with an x component) pulls.  On different XCDs those 8 lines
+// per row are fetched twice (256^3: reads 1.041x the algorithmic bytes in
+// FP32, 1.084x in FP16).  So where a workgroup covers a whole row
+// (gridDim.x == 1) and n is a multiple of 8 L: the two z-wall planes first,
+// then the planes z = 1 .. n-2 in order; within a plane, the workgroup at
+// position j (on XCD j mod 8) takes a row of the XCD's runs of L consecutive
+// rows (y = 8 L (m / L) + L c + m mod L, m = j / 8, c the XCD's run), so a
+// row and most of its y neighbours share an L2, and the plane's workgroup
+// count n, a multiple of 8, keeps its z neighbours on the same XCD.  The run
+// an XCD takes rotates every 8 planes (c = (j + z / 8) mod 8): a front along
+// y and the y walls put their slow rows in a few runs, and fixed runs per
+// XCD left those XCDs with the slow rows of every plane (256^3 melting state
+// 176 -> 210 us per step).  L = 0 stands for L = n / 8, one run per XCD and
+// plane.  Measured against the order below, one box, medians of three:
+// FP32 (L = 4) 256^3 all-liquid 601.6 -> 598.1 us, melting 178.5 -> 175.2,
+// 64^3 melting 13.2 -> 11.7, reads 1.010x; FP16 (L = 0) all-liquid 290.6 ->
+// 290.9 us, melting 103.4 -> 103.8, reads 1.012x (FP16 with L = 4: +0.7 and
+// +1.5 %).
+//
+// Otherwise (several workgroups per row, or other n): the 4n - 4 rows on the
+// y and z walls, which always take the general path, come first, and the
 // interior rows follow in z-major order.  In plane order the wall plane
 // z = n - 1 came last, and its slow rows formed a tail: at 256^3 the melting
 // step took 214 instead of 179 us (FP32), 167 instead of 141 us (FP16).
+template <int L>
 __device__ __forceinline__ void step_row(int n, int& y, int& z) {
-  const int r = blockIdx.z * n + blockIdx.y, nw = 4 * n - 4;
+  const int r = blockIdx.z * n + blockIdx.y;
+  const int run = L > 0 ? L : n >> 3;
+  if (gridDim.x == 1 && (n & 7) == 0 && ((n >> 3) % run) == 0) {
+    if (r < 2 * n) {
+      y = r < n ? r : r - n;
+      z = r < n ? 0 : n - 1;
+      return;
+    }
+    const int k = r - 2 * n;
+    z = 1 + k / n;
+    const int j = k - (z - 1) * n;            // position in the plane; XCD j mod 8
+    const int c = ((j & 7) + (z >> 3)) & 7;   // the XCD's run in this plane
+    const int m = j >> 3;
+    y = (m / run) * (run << 3) + c * run + (m - (m / run) * run);
+    return;
+  }
+  const int nw = 4 * n - 4;
   if (r < n) {
     y = r;
     z = 0;
@@ -206,6 +248,12 @@ __device__ __forceinline__ void step_row(int n, int& y, int& z) {
     y = 1 + (k - (z - 1) * (n - 2));
   }
 }
+
+// The run length of the step kernels' row order for a storage format of
+// `bytes` per value: 4 for FP32 and FP64, one run per XCD and plane for
+// 16-bit storage.
+template <typename Ts>
+__host__ __device__ constexpr int row_run() { return sizeof(Ts) == 2 ? 0 : 4; }
 
 // number of cells a in [0, n) with a + 1/2 < s (exact: s - 1/2 is exact in FP64)
 __device__ __forceinline__ int count_liquid(double sv, int n) {

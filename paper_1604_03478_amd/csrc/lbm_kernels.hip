@@ -532,7 +532,7 @@ __global__ __launch_bounds__(512) void k_stream_collide(
     const double* __restrict__ th, int* __restrict__ flag, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y, z;
-  step_row(P.n, y, z);
+  step_row<row_run<Ts>()>(P.n, y, z);
   update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, nullptr, s, th, flag, P);
 }
 
@@ -557,7 +557,7 @@ k_stream_collide_h(const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __r
                    int* __restrict__ flag, KParams P) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y, z;
-  step_row(P.n, y, z);
+  step_row<row_run<Ts>()>(P.n, y, z);
   if (rowmax) {
     // rowmax[o]: the largest liquid count over the 3x3 neighbourhoods of the
     // columns with this other-lateral index, so every stencil of the row is
