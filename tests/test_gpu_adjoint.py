@@ -428,3 +428,37 @@ def test_gradient_matches_oracle_adjoint_edge_sizes(n, s0, kw):
     g = gpu.adjoint(1.0)
     scale = max(np.linalg.norm(g_ref), 1e-300)
     assert np.linalg.norm(g - g_ref) <= 1e-10 * scale + 1e-18, (np.linalg.norm(g - g_ref), scale)
+
+
+@pytest.mark.parametrize("prec,heating,kw", [
+    ("f32", "y0", {}),
+    ("f64", "z0", {"f_wall": 1}),
+    ("f16s", "y0", {"front_scheme": 1}),
+    ("bf16s", "z0", {}),
+])
+def test_gradient_is_independent_of_the_checkpoint_interval(prec, heating, kw):
+    """The recompute of every segment is the forward run bit for bit, and the
+    reverse steps are the same whatever the segmentation, so dJ/dT_h does not
+    depend on K: one segment (the sweep on one stream), and 7, 1, 2 and 13
+    steps per segment (two segment sets: each segment's recompute on a side
+    stream beside the reverse sweep of the one after it; ragged last
+    segments). A layer of cells melts during the 45 recorded steps."""
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, Sim
+    n = 24
+    sim = Sim(Config(n=n, ra=1e5, pr=1.0, ste=1.0, s0=4.4, t_c=0.1, t_m=0.1, heating=heating,
+                     precision=prec, **kw))
+    sim.set_hot_wall(hot_wall_field(n, seed=5))
+    sim.step(80)  # the first layer melts at about step 100
+    blob = sim.save_state()
+    melted0 = sim.diagnostics()["melted"]
+    grads, fls = [], []
+    for every in (45, 7, 1, 2, 13):
+        sim.load_state(blob)
+        fls.append(sim.forward_ckpt(45, every))
+        grads.append(sim.adjoint(1.0))
+    assert sim.diagnostics()["melted"] > melted0
+    assert np.linalg.norm(grads[0]) > 0
+    for fl, g in zip(fls[1:], grads[1:]):
+        assert fl == fls[0]
+        assert np.array_equal(g, grads[0])
