@@ -5,9 +5,10 @@
 //    (one 16-byte load and one 16-byte store per lane);
 //  * the bare access pattern of the fused step in the all-liquid state: for
 //    every cell the 19 + 7 pulled loads of the row-interleaved layout (the
-//    same source rows, x shifts and wall bounce-back address selects) and
-//    the 19 + 7 non-temporal stores, with the step kernel's launch shape and
-//    row order, and no arithmetic at all.
+//    same source rows, x shifts and wall bounce-back address selects, and
+//    off the y and z walls the fast path's uniform-base addressing) and the
+//    19 + 7 non-temporal stores, with the step kernel's launch shape and row
+//    order, and no arithmetic at all.
 //
 // Both move exactly the bytes they are credited with; the step kernel's
 // fraction of each tells how much of the gap to peak belongs to its access
@@ -55,6 +56,37 @@ __device__ __forceinline__ void move_pulled(const Ts* __restrict__ src, Ts* __re
   for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q], out + q * pitch + x);
 }
 
+// The same for a row off the y and z walls, addressed as the step kernel's
+// fast path does: one uniform base (the row block's first row, y - 1, z - 1)
+// and a 32-bit offset per lane and direction, the x-wall bounce-back an
+// offset select.
+template <int Q, typename Ts>
+__device__ __forceinline__ void move_pulled_interior(const Ts* __restrict__ src,
+                                                     Ts* __restrict__ dst, const KParams& P,
+                                                     int x, int y, int z) {
+  const int n = P.n;
+  const uint32_t pitch = P.pitch, un = (uint32_t)n;
+  const Ts* b = row_ptr<Q>(src, P, y - 1, z - 1);
+  auto row_ofs = [&](int dy, int dz) {  // row (y + dy, z + dz)
+    return ((uint32_t)(1 + dz) * un + (uint32_t)(1 + dy)) * ((uint32_t)Q * pitch);
+  };
+  Ts v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int ex = Q == 19 ? ex19(q) : ex7(q), ey = Q == 19 ? ey19(q) : ey7(q),
+              ez = Q == 19 ? ez19(q) : ez7(q), p = Q == 19 ? opp19(q) : opp7(q);
+    uint32_t i = row_ofs(-ey, -ez) + q * pitch + (uint32_t)(x - ex);
+    if (ex != 0) {
+      const bool wall = ex > 0 ? (x == 0) : (x == n - 1);
+      i = wall ? row_ofs(0, 0) + p * pitch + x : i;
+    }
+    v[q] = load_stream<Ts>(b, i);
+  }
+  Ts* out = row_ptr<Q>(dst, P, y, z);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q], out + q * pitch + x);
+}
+
 template <typename Ts>
 __global__ __launch_bounds__(512) void k_pull_pattern(const Ts* __restrict__ fs,
                                                       Ts* __restrict__ fd,
@@ -64,6 +96,11 @@ __global__ __launch_bounds__(512) void k_pull_pattern(const Ts* __restrict__ fs,
   int y, z;
   step_row<row_run<Ts>()>(P.n, y, z);
   if (x >= P.n) return;
+  if (y >= 1 && y <= P.n - 2 && z >= 1 && z <= P.n - 2) {  // uniform
+    move_pulled_interior<7>(gs, gd, P, x, y, z);
+    if (P.flow) move_pulled_interior<19>(fs, fd, P, x, y, z);
+    return;
+  }
   move_pulled<7>(gs, gd, P, x, y, z);
   if (P.flow) move_pulled<19>(fs, fd, P, x, y, z);
 }
