@@ -75,10 +75,9 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stream_collide_f32_256_counter
 
 
 def workload_config(n: int, precision: str, all_liquid: bool):
-    from paper_1604_03478_amd import Config
-    return Config(n=n, ra=1e5, pr=1.0, ste=0.1, t_h=1.0, t_c=0.0, t_m=0.0, ma=0.1,
-                  s0=float(n) if all_liquid else 1.0, heating="y0", flow=1,
-                  precision=precision)
+    """The side-heated convection workload (preset conv256) at n^3."""
+    from paper_1604_03478_amd import presets
+    return presets.conv256(precision, all_liquid, n=n).config
 
 
 def time_steps(sim, stream, steps: int):
@@ -132,12 +131,12 @@ def bottom_heated_512(stream, steps: int, warmup: int):
     adiabatic), Ra = 1e6, Pr = 1, Ste = 0.1, FP16 shifted storage with FP32
     collision and FP64 front and reductions.  Throughput of the all-liquid
     state (every cell moves 104 B) and of the initial melting state."""
-    from paper_1604_03478_amd import Config, Sim
+    from paper_1604_03478_amd import Sim, presets
     n = 512
     out = {"workload": "convection melting 512^3, bottom-heated (hot z=0), Ra=1e6, Pr=1, "
                        "Ste=0.1, fp16 shifted storage, fp32 collide, fp64 front"}
-    for key, s0 in (("all_liquid", float(n)), ("melting_state", 1.0)):
-        cfg = Config(n=n, ra=1e6, pr=1.0, ste=0.1, s0=s0, heating="z0", precision="f16s")
+    for key, liquid in (("all_liquid", True), ("melting_state", False)):
+        cfg = presets.bottom512("f16s", all_liquid=liquid, n=n).config
         sim = Sim(cfg, stream=stream)
         sim.step(warmup)
         ms = time_steps(sim, stream, steps)
@@ -160,8 +159,8 @@ def large_run(stream, n: int, steps: int, sample: int = 1000):
     104 B, a solid one the 28 B of g; the liquid share is f_l, sampled every
     `sample` steps outside the timed part."""
     import torch
-    from paper_1604_03478_amd import Config, Sim
-    cfg = Config(n=n, ra=1e6, pr=1.0, ste=0.1, s0=1.0, heating="z0", precision="f16s")
+    from paper_1604_03478_amd import Sim, presets
+    cfg = presets.bottom512("f16s", n=n).config
     sim = Sim(cfg, stream=stream)
     alpha = sim.lattice()["alpha"]
     done, t_gpu, nbytes, hist = 0, 0.0, 0.0, {}
@@ -230,9 +229,11 @@ def adjoint_timing(stream, n: int, steps: int, every: int):
     two gradients must agree bit for bit."""
     import numpy as np
     import torch
-    from paper_1604_03478_amd import Config, Sim
-    cfg = Config(n=n, ra=1e4 if n <= 64 else 1e5, pr=1.0, ste=0.1, s0=1.0, precision="f32")
-    th = 1.0 + 0.1 * np.random.default_rng(0).standard_normal((n, n))
+    from paper_1604_03478_amd import Sim, presets
+    # C4 at 64^3; the C3 physics (Ra = 1e5) at other sizes
+    p = presets.adj64("f32") if n == 64 else presets.conv256("f32", n=n)
+    cfg = p.config
+    th = 1.0 + 0.1 * np.random.default_rng(max(p.hot_wall_seed, 0)).standard_normal((n, n))
     sim = Sim(cfg, stream=stream)
     sim.set_hot_wall(th)
     blob = sim.save_state()
@@ -508,10 +509,9 @@ def main():
         return
 
     if args.mode == "profile":
-        from paper_1604_03478_amd import Config, Sim
+        from paper_1604_03478_amd import Sim, presets
         if args.case == "bottom512":  # the large configuration, hot wall z = 0
-            cfg = Config(n=args.n, ra=1e6, pr=1.0, ste=0.1, s0=1.0 if args.melting else
-                         float(args.n), heating="z0", precision=args.precision)
+            cfg = presets.bottom512(args.precision, all_liquid=not args.melting, n=args.n).config
         else:
             cfg = workload_config(args.n, args.precision, not args.melting)
         sim = Sim(cfg, stream=stream)

@@ -5,3 +5,4 @@ library ``liblbmmelt.so`` behind the C ABI of ``include/lbmmelt.h``; this
 package holds its sources (``csrc/``), its build and a thin ctypes binding.
 """
 from .binding import Config, LbmError, LiquidFraction, Sim, load_library  # noqa: F401
+from . import presets  # noqa: F401

@@ -145,11 +145,12 @@ def test_adjoint_at_the_64_configuration_matches_the_oracle(prec, dtype, tol):
     which moves f_l and the gradient far below these bars."""
     import torch
     from inputs import hot_wall_field
-    from paper_1604_03478_amd import Config, LiquidFraction
+    from paper_1604_03478_amd import LiquidFraction, presets
     fl_ref, g_ref = _golden_adj64()
-    cfg = Config(n=64, ra=1e4, pr=1.0, ste=0.1, s0=1.0, precision=prec)
-    th = torch.tensor(hot_wall_field(64, seed=0), dtype=getattr(torch, dtype), device="cuda",
-                      requires_grad=True)
+    p = presets.adj64(prec)
+    cfg = p.config
+    th = torch.tensor(hot_wall_field(64, seed=p.hot_wall_seed), dtype=getattr(torch, dtype),
+                      device="cuda", requires_grad=True)
     fl = LiquidFraction.apply(th, cfg, 100, 10)
     fl.backward()
     assert th.grad.dtype == th.dtype
@@ -171,18 +172,19 @@ def test_gradient_matches_finite_differences_64():
     <= 1e-3.  The gradient through torch.autograd is the library's."""
     import torch
     from inputs import hot_wall_field
-    from paper_1604_03478_amd import Config, LiquidFraction, Sim
-    n, steps = 64, 2000
-    cfg = Config(n=n, ra=1e4, pr=1.0, ste=0.1, s0=1.0, precision="f64")
-    th0 = hot_wall_field(n, seed=0)
+    from paper_1604_03478_amd import LiquidFraction, Sim, presets
+    p = presets.adj64("f64")
+    n, steps, every = p.config.n, p.steps, p.every_k
+    cfg = p.config
+    th0 = hot_wall_field(n, seed=p.hot_wall_seed)
     th = torch.tensor(th0, dtype=torch.float64, device="cuda", requires_grad=True)
-    fl = LiquidFraction.apply(th, cfg, steps, 100)
+    fl = LiquidFraction.apply(th, cfg, steps, every)
     fl.backward()
     grad_autograd = th.grad.detach().cpu().numpy()
 
     base = Sim(cfg)
     base.set_hot_wall(th0)
-    fl_base = base.forward_ckpt(steps, 100)
+    fl_base = base.forward_ckpt(steps, every)
     sched = base.schedule(steps)
     grad = base.adjoint(1.0)
     base.close()
@@ -221,8 +223,7 @@ def test_gradient_matches_finite_differences_64():
     # the same configuration in FP32 storage with an FP32 T_h tensor (its
     # own run and schedule): against the same central differences
     th32 = torch.tensor(th0, dtype=torch.float32, device="cuda", requires_grad=True)
-    fl32 = LiquidFraction.apply(th32, Config(n=n, ra=1e4, pr=1.0, ste=0.1, s0=1.0,
-                                             precision="f32"), steps, 100)
+    fl32 = LiquidFraction.apply(th32, presets.adj64("f32").config, steps, every)
     fl32.backward()
     g32 = th32.grad.detach().double().cpu().numpy()
     errs32 = [abs(fd - g32[c]) / abs(fd) for c, fd in zip(cols, fds[:len(cols)])]

@@ -235,9 +235,9 @@ def test_convection_melting_64_full_run(prec):
     steps) against the FP64 oracle's stored trajectory.  FP64 storage: round
     off.  FP32 storage: max|dT| <= 1e-5 and relative liquid-fraction error
     <= 1e-6."""
-    from paper_1604_03478_amd import Config, Sim
+    from paper_1604_03478_amd import Sim, presets
     fl, s, T, line = _golden_conv64()
-    g = Sim(Config(n=64, ra=1e4, pr=1.0, ste=0.1, s0=1.0, precision=prec))
+    g = Sim(presets.conv64(prec).config)
     worst_fl = 0.0
     done = 0
     for st in sorted(fl):
