@@ -208,6 +208,7 @@ void release_set(SegSet& s) {
 }
 
 void release_adjoint(AdjData& a) {
+  if (a.side) (void)hipStreamSynchronize(a.side);  // its recompute may still use the buffers
   free_all(a.ckf);
   free_all(a.ckg);
   free_all(a.cks);
@@ -914,6 +915,9 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
   const size_t fb = c->p.flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
   const int nck = (int)((nsteps + every_k - 1) / every_k);
   a.ready = false;
+  // a reverse sweep that failed part way may have left recompute work on the
+  // side stream; it uses the buffers resized below
+  if (a.side) HIP_TRY(hipStreamSynchronize(a.side));
   if (a.K != every_k) {  // the segment buffers are sized by every_k
     release_states(a.set[0]);
     release_states(a.set[1]);
@@ -1106,6 +1110,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   if (!a.ready || c->step != a.end)
     return fail(LBM_ESTATE, "lbm_adjoint needs lbm_forward_ckpt with no step, state change "
                 "or hot-wall change since");
+  if (a.side) HIP_TRY(hipStreamSynchronize(a.side));  // left over from a failed sweep
   const size_t nn = (size_t)c->p.n * c->p.n, nc = c->kp.ncell;
   const bool flow = c->p.flow != 0;
   // segment sets: a second one when the run has several segments and the set
