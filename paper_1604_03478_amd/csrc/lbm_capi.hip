@@ -544,18 +544,16 @@ namespace {
 // The kernels of one step from buffer parity (cur, scur) on stream st: the
 // same launches whether they run at once or are captured into a graph.
 // rec: schedule slot to record (or null).  step_ctr: the device step counter
-// to advance (graph replays, else null).  ev0/ev1 (or null):
-// events recorded around the stream-collide kernel.
+// to advance (graph replays, else null).  ev0/ev1 (or null): events the
+// stream-collide kernel's dispatch records at its start and end.
 hipError_t enqueue_step(lbm_ctx* c, const lbmk::KParams& k, int cur, int scur, int* rec,
                         uint32_t* step_ctr, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
   const int nx = cur ^ 1, sx = scur ^ 1;
   hipError_t e;
-  if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
   if ((e = lbmk::launch_stream_collide(c->kind, k, c->f[cur], c->f[nx], c->g[cur], c->g[nx],
-                                       c->cnt, c->cext, c->rowmax, c->s[scur], c->th,
-                                       c->flag, st)) != hipSuccess)
+                                       c->cnt, c->cext, c->rowmax, c->s[scur], c->th, c->flag,
+                                       st, ev0, ev1)) != hipSuccess)
     return e;
-  if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
   if (c->heat &&  // conservative front: heat of the streaming from the state g[cur]
       (e = lbmk::launch_front_heat(c->kind, k, c->g[cur], c->s[scur], c->cnt, c->heat, st)) !=
           hipSuccess)

@@ -63,10 +63,13 @@ inline bool uses_neighbourhood(int kind) { return store_bytes(kind) == 2; }
 // it the lattice rows whose stencils are all solid skip the per-cell phase
 // loads (the same results bit for bit).  s: front per column.  th: hot-wall
 // temperature per column.  flag: set to 1 when a non-finite value appears.
+// ev_start / ev_stop (or null): events the kernel's dispatch records at its
+// start and end (the kernel's own duration, with no separate event packets).
 hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, void* fd,
                                  const void* gs, void* gd, const int* cnt, const uint32_t* cext,
                                  const int* rowmax, const double* s, const double* th, int* flag,
-                                 hipStream_t st);
+                                 hipStream_t st, hipEvent_t ev_start = nullptr,
+                                 hipEvent_t ev_stop = nullptr);
 
 // Interface update (Eq. (6)) of every column from the post-collision g, then
 // the phase switch: s_new, cnt (in place), refill of f in newly liquid cells,

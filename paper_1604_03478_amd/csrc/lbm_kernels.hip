@@ -26,6 +26,7 @@
 //     per-lane address select, so all 26 loads of a cell are issued before
 //     the first wait.  Waves that touch the front or a y/z wall take the
 //     general path with per-link boundary handling.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -880,7 +881,8 @@ __global__ __launch_bounds__(kSumThreads) void k_sum(const double* __restrict__ 
 template <typename Ts>
 hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* gs, void* gd,
                        const int* cnt, const uint32_t* cext, const int* rowmax,
-                       const double* s, const double* th, int* flag, hipStream_t st) {
+                       const double* s, const double* th, int* flag, hipStream_t st,
+                       hipEvent_t ev_start, hipEvent_t ev_stop) {
   auto F = static_cast<const Ts*>(fs);
   auto Fd = static_cast<Ts*>(fd);
   auto G = static_cast<const Ts*>(gs);
@@ -896,14 +898,20 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
   const int bx = P.n >= bmax ? bmax : ((P.n + 63) / 64) * 64;
   dim3 block(bx, 1, 1);
   dim3 grid((P.n + bx - 1) / bx, P.n, P.n);
+#define LAUNCH_ONE(K, ...)                                                                      \
+  do {                                                                                          \
+    if (ev_start)  /* the dispatch itself records the kernel's start and end */                 \
+      hipExtLaunchKernelGGL(K, grid, block, 0, st, ev_start, ev_stop, 0, __VA_ARGS__);          \
+    else                                                                                        \
+      hipLaunchKernelGGL(K, grid, block, 0, st, __VA_ARGS__);                                   \
+  } while (0)
 #define LAUNCH(FLOW, MZ, FWALL)                                                                \
   do {                                                                                          \
     if constexpr (sizeof(Ts) == 2)                                                              \
-      hipLaunchKernelGGL((k_stream_collide_h<Ts, FLOW, MZ, FWALL>), grid, block, 0, st, F, Fd, \
-                         G, Gd, cnt, cext, rowmax, s, th, flag, P);                             \
+      LAUNCH_ONE((k_stream_collide_h<Ts, FLOW, MZ, FWALL>), F, Fd, G, Gd, cnt, cext, rowmax, s,  \
+                 th, flag, P);                                                                  \
     else                                                                                        \
-      hipLaunchKernelGGL((k_stream_collide<Ts, FLOW, MZ, FWALL>), grid, block, 0, st, F, Fd, G, \
-                         Gd, cnt, s, th, flag, P);                                              \
+      LAUNCH_ONE((k_stream_collide<Ts, FLOW, MZ, FWALL>), F, Fd, G, Gd, cnt, s, th, flag, P);    \
   } while (0)
   if (P.flow && P.f_wall) {
     if (P.melt_z) LAUNCH(true, true, true); else LAUNCH(true, false, true);
@@ -912,6 +920,7 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
   } else {
     if (P.melt_z) LAUNCH(false, true, false); else LAUNCH(false, false, false);
   }
+#undef LAUNCH_ONE
 #undef LAUNCH
   return hipGetLastError();
 }
@@ -1018,8 +1027,9 @@ size_t store_bytes(int kind) {
 hipError_t launch_stream_collide(int kind, const KParams& P, const void* fs, void* fd,
                                  const void* gs, void* gd, const int* cnt, const uint32_t* cext,
                                  const int* rowmax, const double* s, const double* th, int* flag,
-                                 hipStream_t st) {
-#define CALL(T) sc_dispatch<T>(P, fs, fd, gs, gd, cnt, cext, rowmax, s, th, flag, st)
+                                 hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
+#define CALL(T) \
+  sc_dispatch<T>(P, fs, fd, gs, gd, cnt, cext, rowmax, s, th, flag, st, ev_start, ev_stop)
   switch (kind) {
     case kF64: return CALL(double);
     case kF32: return CALL(float);
