@@ -276,11 +276,12 @@ int lbm_adjoint(lbm_ctx *ctx, double dJ_dfl, double *grad_th, int on_device);
 int lbm_get_schedule(lbm_ctx *ctx, int32_t *out, size_t count);
 int lbm_step_replay(lbm_ctx *ctx, const int32_t *schedule, int64_t nsteps);
 
-/* Kernel timing for measurement.  While enabled (enable != 0), every step
- * brackets its fused stream-collide kernel with a pair of HIP events on the
- * context stream.  lbm_kernel_time synchronizes, returns the summed duration
- * of those kernels in milliseconds and their count, and clears the record.
- * Enabling adds two event records per step; leave it off when timing whole
+/* Kernel timing for measurement.  While enabled (enable != 0), the dispatch
+ * of every step's fused stream-collide kernel records a pair of HIP events
+ * at the kernel's start and end (hipExtLaunchKernel, on the context stream).
+ * lbm_kernel_time synchronizes, returns the summed duration of those kernels
+ * in milliseconds and their count, and clears the record.  Steps are then
+ * launched one by one (no graph replays); leave it off when timing whole
  * steps. */
 int lbm_kernel_timing(lbm_ctx *ctx, int enable);
 int lbm_kernel_time(lbm_ctx *ctx, double *ms, int64_t *launches);
