@@ -125,6 +125,7 @@ struct StepGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int cur = -1, scur = -1;
+  int pair_rows = -1;  // the row order the graph's kernels were captured with
 };
 
 struct lbm_ctx {
@@ -166,6 +167,10 @@ struct lbm_ctx {
   size_t replay_cap = 0;
   bool unstable = false;  // a query saw the device flag; steps refused until load
   bool timing = false;
+  // the liquid fraction last known on the host (the seed front, then every
+  // query): picks the row order of the 16-bit step kernel at two workgroups
+  // per row (KParams::pair_rows), which changes no result
+  double fl_hint = 0.0;
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed kernels
   size_t ev_used = 0;
   // graph replays of the step loop (lbm_set_graph)
@@ -528,6 +533,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
     return bail(fail(LBM_EDEVICE, "init kernel launch failed"));
   if (hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(fail(LBM_EDEVICE, "initialisation failed on the device"));
+  c->fl_hint = std::min(std::max(params->s0, 0.0), (double)n) / n;
   *out = c;
   return LBM_OK;
 }
@@ -603,6 +609,7 @@ int build_step_graph(lbm_ctx* c) {
   c->sgraph.exec = x;
   c->sgraph.cur = c->cur;
   c->sgraph.scur = c->scur;
+  c->sgraph.pair_rows = c->kp.pair_rows;
   return LBM_OK;
 }
 
@@ -614,10 +621,12 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
   if (c->unstable) return fail(LBM_ESTATE, "state is unstable; restore it with lbm_load_state");
   lbmk::KParams& k = c->kp;
+  k.pair_rows = c->fl_hint > 0.5 ? 1 : 0;
   // whole chunks as graph replays (an even number of steps returns the
   // buffers to their parity, so one graph serves every chunk)
   if (c->graph_steps > 0 && !c->timing && c->rec_start < 0 && nsteps >= c->graph_steps) {
-    if (!c->sgraph.exec || c->sgraph.cur != c->cur || c->sgraph.scur != c->scur)
+    if (!c->sgraph.exec || c->sgraph.cur != c->cur || c->sgraph.scur != c->scur ||
+        c->sgraph.pair_rows != k.pair_rows)
       if ((rc = build_step_graph(c))) return rc;
     HIP_TRY(lbmk::launch_set_u32(c->step_dev, (uint32_t)c->step, c->stream));
     const int64_t reps = nsteps / c->graph_steps;
@@ -678,6 +687,7 @@ int lbm_liquid_fraction(lbm_ctx* c, double* fl) {
   HIP_TRY(hipMemcpyAsync(host, c->red, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if ((rc = check_unstable(c))) return rc;
   *fl = host[0] / ((double)nn * c->p.n);
+  c->fl_hint = *fl;
   return LBM_OK;
 }
 
@@ -769,6 +779,9 @@ int lbm_set_populations(lbm_ctx* c, const double* f, const double* g, const doub
       hipMemcpyAsync(c->s[c->scur], s, nn * sizeof(double), hipMemcpyHostToDevice, c->stream))
     return done(fail(LBM_EDEVICE, "upload of g or s failed"));
   if ((rc = refresh_masks(c))) return done(rc);
+  double sum = 0.0;
+  for (size_t i = 0; i < nn; ++i) sum += std::min(std::max(s[i], 0.0), (double)c->p.n);
+  c->fl_hint = sum / ((double)nn * c->p.n);
   return done(LBM_OK);
 }
 
@@ -809,6 +822,7 @@ int lbm_diagnostics(lbm_ctx* c, double out[5]) {
   HIP_TRY(hipMemcpyAsync(out, c->dpart + 5 * (size_t)lbmk::diag_blocks(c->p.n),
                          5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  c->fl_hint = out[2] / ((double)c->p.n * c->p.n * c->p.n);  // the front sum over n^3
   return check_unstable(c);
 }
 
@@ -891,6 +905,14 @@ int lbm_load_state(lbm_ctx* c, const void* host_buf, size_t bytes) {
   HIP_TRY(hipMemcpyAsync(c->g[c->cur], b, gb, hipMemcpyHostToDevice, c->stream));
   b += gb;
   HIP_TRY(hipMemcpyAsync(c->s[c->scur], b, nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  {
+    double sum = 0.0, v;
+    for (size_t i = 0; i < nn; ++i) {
+      memcpy(&v, b + i * sizeof(double), sizeof(double));
+      sum += std::min(std::max(v, 0.0), (double)c->p.n);
+    }
+    c->fl_hint = sum / ((double)nn * c->p.n);
+  }
   b += nn * sizeof(double);
   HIP_TRY(hipMemcpyAsync(c->melted, b, nn * sizeof(int), hipMemcpyHostToDevice, c->stream));
   b += nn * sizeof(int);

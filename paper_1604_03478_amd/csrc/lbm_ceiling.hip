@@ -92,9 +92,9 @@ __global__ __launch_bounds__(512) void k_pull_pattern(const Ts* __restrict__ fs,
                                                       Ts* __restrict__ fd,
                                                       const Ts* __restrict__ gs,
                                                       Ts* __restrict__ gd, KParams P) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  int y, z;
-  step_row<row_run<Ts>()>(P.n, y, z);
+  int y, z, xb;
+  step_row<row_run<Ts>()>(P.n, y, z, xb);
+  const int x = xb * blockDim.x + threadIdx.x;
   if (x >= P.n) return;
   if (y >= 1 && y <= P.n - 2 && z >= 1 && z <= P.n - 2) {  // uniform
     move_pulled_interior<7>(gs, gd, P, x, y, z);

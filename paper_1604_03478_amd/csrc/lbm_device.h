@@ -208,16 +208,37 @@ __host__ __device__ constexpr int step_block_max(size_t bytes) { return bytes ==
 // 290.9 us, melting 103.4 -> 103.8, reads 1.012x (FP16 with L = 4: +0.7 and
 // +1.5 %).
 //
+// Two workgroups per row (16-bit storage at n = 512), n a multiple of 8, in
+// the instantiation that asks for it (PAIR): workgroups w and w + 8 of every
+// block of 16 take the two halves of one row, so a row sits on one XCD as
+// well, and the same order follows.  The halves share the line where a
+// shifted direction row crosses from one to the other.  That pays in a
+// mostly liquid lattice (512^3 all-liquid FP16 2560 -> 2438 us) and costs in
+// a mostly solid one, whose g-only rows share no lines (melting state 720 ->
+// 773 us), so the host picks that instantiation from the liquid fraction it
+// last knew (KParams::pair_rows): any order gives the same results bit for
+// bit.  (A choice inside the kernel cost the melting state 2-21 %.)
+//
 // Otherwise (several workgroups per row, or other n): the 4n - 4 rows on the
 // y and z walls, which always take the general path, come first, and the
 // interior rows follow in z-major order.  In plane order the wall plane
 // z = n - 1 came last, and its slow rows formed a tail: at 256^3 the melting
 // step took 214 instead of 179 us (FP32), 167 instead of 141 us (FP16).
-template <int L>
-__device__ __forceinline__ void step_row(int n, int& y, int& z) {
-  const int r = blockIdx.z * n + blockIdx.y;
+template <int L, bool PAIR = false>
+__device__ __forceinline__ void step_row(int n, int& y, int& z, int& xb) {
+  int r = blockIdx.z * n + blockIdx.y;
+  xb = blockIdx.x;
+  bool xcd_order = gridDim.x == 1;
+  if (PAIR && gridDim.x == 2 && (n & 7) == 0) {
+    // two workgroups per row: workgroups w and w + 8 of each block of 16 take
+    // the two halves of row 8 (w / 16) + w mod 8, so both run on its XCD
+    const int w = (int)blockIdx.x + 2 * r;
+    r = 8 * (w >> 4) + (w & 7);
+    xb = (w >> 3) & 1;
+    xcd_order = true;
+  }
   const int run = L > 0 ? L : n >> 3;
-  if (gridDim.x == 1 && (n & 7) == 0 && ((n >> 3) % run) == 0) {
+  if (xcd_order && (n & 7) == 0 && ((n >> 3) % run) == 0) {
     if (r < 2 * n) {
       y = r < n ? r : r - n;
       z = r < n ? 0 : n - 1;

@@ -39,6 +39,9 @@ struct KParams {
   // Graph replays: the step counter in device memory, advanced by each step's
   // front kernel (launch_front's step_ctr); null: use step.
   const uint32_t* step_dev;
+  // 16-bit storage with two workgroups per row: 1 keeps both halves of a row
+  // on one XCD (the order for a mostly liquid lattice; results identical).
+  int pair_rows;
 };
 
 size_t store_bytes(int kind);

@@ -531,9 +531,9 @@ __global__ __launch_bounds__(512) void k_stream_collide(
     const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
     Ts* __restrict__ gd, const int* __restrict__ cnt, const double* __restrict__ s,
     const double* __restrict__ th, int* __restrict__ flag, KParams P) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  int y, z;
-  step_row<row_run<Ts>()>(P.n, y, z);
+  int y, z, xb;
+  step_row<row_run<Ts>()>(P.n, y, z, xb);
+  const int x = xb * blockDim.x + threadIdx.x;
   update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, nullptr, s, th, flag, P);
 }
 
@@ -548,7 +548,9 @@ __global__ __launch_bounds__(512) void k_stream_collide(
 // 304 us.  (For FP32 an 8-wave limit spills 60 bytes and costs 24 %.)
 template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 constexpr int kWaves16 = !FLOW ? 8 : 7;
-template <typename Ts, bool FLOW, bool MZ, bool FWALL>
+// PAIR: the row order that keeps both halves of a row on one XCD (two
+// workgroups per row; see step_row).
+template <typename Ts, bool FLOW, bool MZ, bool FWALL, bool PAIR>
 __global__ __launch_bounds__(512) __attribute__((
     amdgpu_waves_per_eu(kWaves16<Ts, FLOW, MZ, FWALL>, kWaves16<Ts, FLOW, MZ, FWALL>))) void
 k_stream_collide_h(const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
@@ -556,9 +558,9 @@ k_stream_collide_h(const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __r
                    const uint32_t* __restrict__ cext, const int* __restrict__ rowmax,
                    const double* __restrict__ s, const double* __restrict__ th,
                    int* __restrict__ flag, KParams P) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  int y, z;
-  step_row<row_run<Ts>()>(P.n, y, z);
+  int y, z, xb;
+  step_row<row_run<Ts>(), PAIR>(P.n, y, z, xb);
+  const int x = xb * blockDim.x + threadIdx.x;
   if (rowmax) {
     // rowmax[o]: the largest liquid count over the 3x3 neighbourhoods of the
     // columns with this other-lateral index, so every stencil of the row is
@@ -898,6 +900,8 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
   const int bx = P.n >= bmax ? bmax : ((P.n + 63) / 64) * 64;
   dim3 block(bx, 1, 1);
   dim3 grid((P.n + bx - 1) / bx, P.n, P.n);
+  // the paired row order applies at two workgroups per row only
+  const bool pair = P.pair_rows != 0 && grid.x == 2 && (P.n & 7) == 0;
 #define LAUNCH_ONE(K, ...)                                                                      \
   do {                                                                                          \
     if (ev_start)  /* the dispatch itself records the kernel's start and end */                 \
@@ -907,10 +911,14 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
   } while (0)
 #define LAUNCH(FLOW, MZ, FWALL)                                                                \
   do {                                                                                          \
-    if constexpr (sizeof(Ts) == 2)                                                              \
-      LAUNCH_ONE((k_stream_collide_h<Ts, FLOW, MZ, FWALL>), F, Fd, G, Gd, cnt, cext, rowmax, s,  \
-                 th, flag, P);                                                                  \
-    else                                                                                        \
+    if constexpr (sizeof(Ts) == 2) {                                                            \
+      if (pair)                                                                                 \
+        LAUNCH_ONE((k_stream_collide_h<Ts, FLOW, MZ, FWALL, true>), F, Fd, G, Gd, cnt, cext,     \
+                   rowmax, s, th, flag, P);                                                     \
+      else                                                                                      \
+        LAUNCH_ONE((k_stream_collide_h<Ts, FLOW, MZ, FWALL, false>), F, Fd, G, Gd, cnt, cext,    \
+                   rowmax, s, th, flag, P);                                                     \
+    } else                                                                                      \
       LAUNCH_ONE((k_stream_collide<Ts, FLOW, MZ, FWALL>), F, Fd, G, Gd, cnt, s, th, flag, P);    \
   } while (0)
   if (P.flow && P.f_wall) {
