@@ -343,6 +343,21 @@ def test_one_step_random_state_256(prec):
     assert d["s"] <= ONE_STEP_TOL_S[prec], d
 
 
+@pytest.mark.parametrize("prec", ["f16s", "bf16s"])
+@pytest.mark.parametrize("front", [(100.0, 101.8), (170.0, 171.8)], ids=["mostly_solid", "mostly_liquid"])
+def test_one_step_random_state_264_two_workgroups_per_row(prec, front):
+    """16-bit storage runs a row of up to 256 cells in one workgroup, so at
+    264^3 every row takes two, the second with 8 live lanes.  The host picks
+    the row order from the liquid fraction: above one half (front at ~0.65 n)
+    both halves of a row go to one XCD, below it (~0.38 n) the halves are
+    dispatched as separate row blocks.  Both orders, every cell, one step from
+    a random state, at the one-step bars."""
+    d = _one_step_random(264, prec, seed=13, heating="z0", front=front)
+    tol = ONE_STEP_TOL[prec]
+    assert d["g"] <= tol and d["f"] <= tol, d
+    assert d["s"] <= ONE_STEP_TOL_S[prec], d
+
+
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 1e-7), ("f16s", 1e-3),
                                       ("bf16s", 8e-3)])
 @pytest.mark.parametrize("heating", ["y0", "z0"])
