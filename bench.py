@@ -148,6 +148,13 @@ def bottom_heated_512(stream, steps: int, warmup: int):
         if key == "all_liquid":
             d["achieved_GBps"] = round(BYTES_PER_CELL["f16s"] * n ** 3 / (kms * 1e-3) / 1e9, 1)
         out[key] = d
+    # the bare access pattern of the all-liquid step at this size (launch shape
+    # and row order of the step kernel in that state)
+    from paper_1604_03478_amd.binding import bandwidth_ceiling
+    pms, nbytes = bandwidth_ceiling("pattern", n, "f16s", 1, 10, stream=stream)
+    pat = nbytes / (pms * 1e-3) / 1e9
+    out["all_liquid"]["pattern_ceiling_GBps"] = round(pat, 1)
+    out["all_liquid"]["frac_of_pattern"] = round(out["all_liquid"]["achieved_GBps"] / pat, 4)
     return out
 
 

@@ -7,8 +7,8 @@
 //    every cell the 19 + 7 pulled loads of the row-interleaved layout (the
 //    same source rows, x shifts and wall bounce-back address selects, and
 //    off the y and z walls the fast path's uniform-base addressing) and the
-//    19 + 7 non-temporal stores, with the step kernel's launch shape and row
-//    order, and no arithmetic at all.
+//    19 + 7 non-temporal stores, with the step kernel's launch shape and the
+//    row order it takes in that state, and no arithmetic at all.
 //
 // Both move exactly the bytes they are credited with; the step kernel's
 // fraction of each tells how much of the gap to peak belongs to its access
@@ -87,13 +87,13 @@ __device__ __forceinline__ void move_pulled_interior(const Ts* __restrict__ src,
   for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q], out + q * pitch + x);
 }
 
-template <typename Ts>
+template <typename Ts, bool PAIR>
 __global__ __launch_bounds__(512) void k_pull_pattern(const Ts* __restrict__ fs,
                                                       Ts* __restrict__ fd,
                                                       const Ts* __restrict__ gs,
                                                       Ts* __restrict__ gd, KParams P) {
   int y, z, xb;
-  step_row<row_run<Ts>()>(P.n, y, z, xb);
+  step_row<row_run<Ts>(), PAIR>(P.n, y, z, xb);
   const int x = xb * blockDim.x + threadIdx.x;
   if (x >= P.n) return;
   if (y >= 1 && y <= P.n - 2 && z >= 1 && z <= P.n - 2) {  // uniform
@@ -109,12 +109,20 @@ template <typename Ts>
 hipError_t pattern_dispatch(const KParams& P, const void* fs, void* fd, const void* gs, void* gd,
                             hipStream_t st) {
   // the step kernel's launch: one x row per workgroup, split as the step
-  // kernel splits it
+  // kernel splits it, and for 16-bit storage at two workgroups per row the
+  // order the host picks for a mostly liquid lattice (both halves of a row
+  // on one XCD)
   const int bmax = step_block_max(sizeof(Ts));
   const int bx = P.n >= bmax ? bmax : ((P.n + 63) / 64) * 64;
-  hipLaunchKernelGGL(k_pull_pattern<Ts>, dim3((P.n + bx - 1) / bx, P.n, P.n), dim3(bx), 0, st,
-                     static_cast<const Ts*>(fs), static_cast<Ts*>(fd),
-                     static_cast<const Ts*>(gs), static_cast<Ts*>(gd), P);
+  const dim3 grid((P.n + bx - 1) / bx, P.n, P.n);
+  const bool pair = sizeof(Ts) == 2 && grid.x == 2 && (P.n & 7) == 0;
+  if (pair)
+    hipLaunchKernelGGL((k_pull_pattern<Ts, true>), grid, dim3(bx), 0, st, static_cast<const Ts*>(fs),
+                       static_cast<Ts*>(fd), static_cast<const Ts*>(gs), static_cast<Ts*>(gd), P);
+  else
+    hipLaunchKernelGGL((k_pull_pattern<Ts, false>), grid, dim3(bx), 0, st,
+                       static_cast<const Ts*>(fs), static_cast<Ts*>(fd),
+                       static_cast<const Ts*>(gs), static_cast<Ts*>(gd), P);
   return hipGetLastError();
 }
 

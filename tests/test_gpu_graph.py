@@ -134,3 +134,33 @@ def test_graph_setting_leaves_the_adjoint_unchanged():
     assert out[0][0] == out[1][0]
     assert np.array_equal(out[0][1], out[1][1])
     assert np.linalg.norm(out[0][1]) > 0
+
+
+def test_graph_follows_the_row_order_the_liquid_fraction_picks():
+    """16-bit storage at 264^3 runs every row in two workgroups, and the host
+    picks their order from the last known liquid fraction (both halves of a
+    row on one XCD above one half, separate row blocks below).  A context with
+    graphs captures in the order of its state, and a state handed over with
+    the fraction on the other side of one half is replayed in the other order:
+    the same states bit for bit as kernel-by-kernel launches throughout."""
+    from inputs import random_state
+    from paper_1604_03478_amd import Config, Sim
+    n = 264
+    cfg = Config(n=n, ra=1e5, pr=1.0, ste=0.1, s0=200.0, heating="z0", precision="f16s")
+    a = Sim(cfg)
+    b = Sim(cfg)
+    b.set_graph(4)
+    a.step(9)  # mostly liquid (f_l 0.76): paired order, two replays and one launch
+    b.step(9)
+    assert states_equal(_state(a), _state(b), "z0")
+    for seed, front in ((3, (100.0, 101.8)), (4, (190.0, 191.8))):  # f_l 0.38, then 0.72
+        f, g, s = random_state(n, seed, front=front)
+        a.set_populations(f, g, s)
+        b.set_populations(f, g, s)
+        del f, g, s
+        a.step(8)
+        b.step(8)
+        assert a.steps == b.steps
+        assert states_equal(_state(a), _state(b), "z0")
+    a.close()
+    b.close()
