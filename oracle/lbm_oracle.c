@@ -24,7 +24,8 @@
  * Parity unpinned (no value in the paper or closed form fixes them; the
  * GPU-oracle comparison is their only quantitative check): the convection
  * results themselves (the paper's figures are not available), the values of
- * the non-hydrodynamic rates of Eq. (2) and the rate q_e of Eq. (4).  Every
+ * the non-hydrodynamic rates of Eq. (2) and the rate q_e of Eq. (4) (which
+ * moment each rate relaxes is pinned with random distinct rates).  Every
  * other function is pinned by tests against the paper's tables, closed forms
  * (Neumann, Guo forcing moments, BGK limit, diffusion decay rates),
  * invariants and finite differences (the reverse sweep).

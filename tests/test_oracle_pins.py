@@ -139,6 +139,91 @@ def test_equal_rates_reduce_to_bgk_with_guo_forcing(tables):
         np.testing.assert_allclose(out, bgk, atol=1e-15)
 
 
+def _uniform_collision_errors(tables, library=None):
+    """Largest deviations of f and g from the collision of Eq. (2) and
+    Eq. (4) with random distinct rates, after one oracle step of a lattice
+    whose populations are the same in every cell: an interior cell pulls
+    the same populations it holds, so it is left with the collision alone.
+    Its moments must be m - S (m - m_eq) + (I - S/2) M F for f, with the
+    equilibrium and the forcing of the textbook BGK and Guo forms projected
+    by M, and n - Q (n - n_eq) for g with the D3Q7 equilibrium
+    w_q T (1 + 4 e_q . u), u = j + F/2."""
+    n = 6
+    sim = OracleSim(n, ra=1e4, pr=1.0, ste=0.1, s0=float(n), flow=1, library=library)
+    d = sim.derived()
+    rng = np.random.default_rng(11)
+    S = rng.uniform(0.6, 1.9, 19)
+    Qr = rng.uniform(0.6, 1.9, 7)
+    sim.set_rates(S=S, Q=Qr)
+    M, N = tables["M"], tables["N"]
+    w, w7 = tables["w19"], tables["w7"]
+    e19, e7 = tables["e19"].astype(float), tables["e7"].astype(float)
+    fin = w * (1 + 0.02 * rng.standard_normal(19))
+    gin = w7 * 0.7 * (1 + 0.3 * rng.uniform(-1, 1, 7))
+    sim.f[:] = fin[:, None, None, None]
+    sim.g[:] = gin[:, None, None, None]
+    sim.step(1)
+
+    rho, T = fin.sum(), gin.sum()
+    F = np.array([0.0, 0.0, d.gbeta * (T - d.t0)])
+    u = e19.T @ fin + 0.5 * F
+    feq = _feq_incompressible(w, e19, rho, u)
+    eu = e19 @ u
+    Fq = w * (3 * ((e19 - u) @ F) + 9 * eu * (e19 @ F))
+    m = M @ fin
+    f_exp = np.linalg.solve(M, m - S * (m - M @ feq) + (1 - 0.5 * S) * (M @ Fq))
+    nn = N @ gin
+    n_eq = N @ (w7 * T * (1 + 4 * (e7 @ u)))
+    g_exp = np.linalg.solve(N, nn - Qr * (nn - n_eq))
+    # the rates matter: the collision moves both distributions well above round-off
+    assert np.abs(f_exp - fin).max() > 1e-5 and np.abs(g_exp - gin).max() > 1e-3
+
+    inner = (slice(None), slice(1, n - 1), slice(1, n - 1), slice(1, n - 1))
+    ef = float(np.abs(sim.f[inner] - f_exp[:, None, None, None]).max())
+    eg = float(np.abs(sim.g[inner] - g_exp[:, None, None, None]).max())
+    return ef, eg
+
+
+def test_distinct_rates_relax_each_moment_by_its_own_rate(tables):
+    """Eq. (2) and Eq. (4) with every rate different (the collision alone,
+    above): round-off at every interior cell, within 20 ulps of the largest
+    population (about 1/3) after the dense 19 x 19 transforms."""
+    ef, eg = _uniform_collision_errors(tables)
+    assert ef <= 1e-15 and eg <= 1e-15, (ef, eg)
+
+
+# Planted mistakes for the pin above: (name, text in the oracle source,
+# replacement).  Each text occurs exactly once in the step's collision.
+COLLISION_MISTAKES = [
+    ("rate of the next moment applied to each moment of f",
+     "      ms[k] = m[k] - S->S[k] * (m[k] - me[k]) + (1.0 - 0.5 * S->S[k]) * Fm[k];\n",
+     "      ms[k] = m[k] - S->S[(k + 1) % Q19] * (m[k] - me[k]) + (1.0 - 0.5 * S->S[k]) * Fm[k];\n"),
+    ("forcing without the (I - S/2) factor",
+     "      ms[k] = m[k] - S->S[k] * (m[k] - me[k]) + (1.0 - 0.5 * S->S[k]) * Fm[k];\n",
+     "      ms[k] = m[k] - S->S[k] * (m[k] - me[k]) + Fm[k];\n"),
+    ("velocity without the half force",
+     "    uz = (jz + 0.5 * Fz) / rho0;\n",
+     "    uz = jz / rho0;\n"),
+    ("rates of g shifted by one moment",
+     "  for (int k = 0; k < Q7; ++k) ns[k] = nm[k] - QR[k] * (nm[k] - ne[k]);\n",
+     "  for (int k = 0; k < Q7; ++k) ns[k] = nm[k] - QR[(k + 1) % Q7] * (nm[k] - ne[k]);\n"),
+]
+
+
+def test_distinct_rates_pin_catches_planted_mistakes(tables, tmp_path):
+    import os
+    from oracle.oracle import _SRC, compile_oracle
+    src = open(_SRC).read()
+    for k, (name, old, new) in enumerate(COLLISION_MISTAKES):
+        assert src.count(old) == 1, name
+        path = os.path.join(tmp_path, f"mut{k}.c")
+        with open(path, "w") as fh:
+            fh.write(src.replace(old, new))
+        lib = compile_oracle(path, os.path.join(tmp_path, f"libmut{k}.so"))
+        ef, eg = _uniform_collision_errors(tables, library=lib)
+        assert max(ef, eg) > 1e-8, (name, ef, eg)
+
+
 def test_collision_conserves_mass_and_adds_force_momentum(tables):
     sim = OracleSim(8, ra=1e4, pr=1.0, flow=1)
     d = sim.derived()
