@@ -244,10 +244,12 @@ int lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
  * steps (ceil(nsteps/every_k) states); *fl (may be NULL) receives the liquid
  * fraction at the end.  lbm_adjoint then writes grad_th[c] = dJ/dT_h(c) for
  * J = dJ_dfl * f_l at the end of that run: it recomputes each segment of
- * every_k steps from its checkpoint (holding every_k + 1 states in device
- * memory) and applies the transposed step in reverse order.  When the run has
- * several segments and free device memory holds a second set of every_k + 1
- * states with a quarter and 4 GB to spare, lbm_adjoint allocates it (kept
+ * every_k steps from its checkpoint (holding the populations of every_k
+ * states in device memory, the first state of a segment being its
+ * checkpoint, read in place) and applies the transposed step in reverse
+ * order.  When the run has several segments and free device memory holds a
+ * second set of every_k states with a quarter and 4 GB to spare,
+ * lbm_adjoint allocates it (kept
  * with the context, like the first) and recomputes each segment on a stream
  * of its own while the context's stream reverses the segment after it; the
  * gradient is the same bit for bit either way, and for every every_k.  The phase

@@ -21,10 +21,10 @@
 //                       adjoint of f is kept only where the cell is liquid
 //                       on both sides of a step); k_adj_front_heat instead
 //                       for the conservative front update
-//   k_adj_collide       per cell of the rows near the front and the walls:
+//   k_adj_collide       per cell of the rows that hold a liquid cell:
 //                       recomputes the pulled populations and applies the
 //                       transposed collision Jacobian; k_adj_collide_solid
-//                       the same for the bulk-solid rows, g only and
+//                       the same for the all-solid rows, g only and
 //                       without the state (linear at rest)
 //   k_adj_stream        per cell: transposed streaming as a gather over every
 //                       reader of each stored population (no atomics), on
@@ -265,7 +265,7 @@ struct Macro {
   }
 };
 
-// Row partition of the reverse collision and streaming.  With A = min(n - 1,
+// Row partition of the reverse streaming.  With A = min(n - 1,
 // max liquid count + 2), a row (height a along the melt axis, o across it)
 // with A <= a < n - 1 and 0 < o < n - 1 is away from the walls and every
 // cell within two columns and two heights of it is solid: the fast path
@@ -293,6 +293,13 @@ __device__ __forceinline__ void front_row(int r, int A, int n, int& a, int& o) {
 // The bound A of the row partition from the largest liquid count m of the
 // lattice.
 __device__ __forceinline__ int row_bound(int m, int n) { return m + 2 < n - 1 ? m + 2 : n - 1; }
+
+// The reverse collision needs no such margin: it is local to a cell, and a
+// solid cell's needs no state (at rest the heat collision is linear in g).
+// So every row at a height a >= m, all of whose cells are solid, takes the
+// g-only kernel, wall rows included; the m n rows below (heights a < m,
+// every o) take the full one.
+__device__ __forceinline__ bool solid_collide_row(int a, int m) { return a >= m; }
 
 // Phase bookkeeping of the states of a segment, one state per grid plane z
 // (state s[z]), in one pass over its columns: the liquid count of each column
@@ -817,9 +824,9 @@ __device__ __forceinline__ void adj_collide_cell(
   for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = (Lam)lgl[q];
 }
 
-// The rows outside the bulk solid, front_rows(A, n) of them, visited by a
-// grid of gridDim.y row slots (this kernel needs many registers, so its
-// waves are not spent on rows it would skip).
+// The rows with a liquid cell, the m n rows at heights below the largest
+// liquid count m, visited by a grid of gridDim.y row slots (this kernel
+// needs many registers, so its waves are not spent on rows it would skip).
 template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
 __device__ __forceinline__ void adj_collide_rows(
     int slot, int nslots, int x, const Ts* __restrict__ f0, const Ts* __restrict__ g0,
@@ -828,10 +835,9 @@ __device__ __forceinline__ void adj_collide_rows(
     const int* __restrict__ rowb, const Lam* __restrict__ lf1, const Lam* __restrict__ lg1,
     Lam* __restrict__ lfh, Lam* __restrict__ lgh, const KParams& P) {
   const int n = P.n;
-  const int A = row_bound(rowb[0], n), R = front_rows(A, n);
+  const int R = rowb[0] * n;
   for (int r = slot; r < R; r += nslots) {
-    int a, o;
-    front_row(r, A, n, a, o);
+    const int a = r / n, o = r - a * n;
     if (x < n)
       adj_collide_cell<Ts, Lam, FLOW, MZ, EXT>(f0, g0, s0, s1, th, cnt, cmin2, cmax2, lf1, lg1,
                                                lfh, lgh, P, x, MZ ? o : a, MZ ? a : o);
@@ -850,7 +856,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(
                                            th, cnt, cmin2, cmax2, rowb, lf1, lg1, lfh, lgh, P);
 }
 
-// The bulk solid rows k_adj_collide leaves out: only the energy distribution
+// The all-solid rows k_adj_collide leaves out: only the energy distribution
 // is reversed, with few registers, so these rows (most of a melting state)
 // run at full occupancy.  A solid cell is at rest, and at u = 0 the heat
 // collision is linear in g: its transpose needs no state, so the kernel reads
@@ -861,7 +867,7 @@ __device__ __forceinline__ void adj_collide_solid_row(int x, int y, int z,
                                                       const Lam* __restrict__ lg1,
                                                       Lam* __restrict__ lgh, const KParams& P) {
   const int n = P.n;
-  if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, row_bound(rowb[0], n), n)) return;
+  if (x >= n || !solid_collide_row(melt_of<MZ>(y, z), rowb[0])) return;
   const size_t nc = P.ncell;
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
   const Macro M;  // T enters only the flow part, which a solid cell skips
@@ -1322,8 +1328,8 @@ __global__ __launch_bounds__(64) void k_adj_interface(
 // independent kernels share a launch, each workgroup taking one role by its
 // index, so their latencies overlap instead of adding up.  The same cell and
 // column functions as the separate kernels: the same results bit for bit.
-// Collision: row slots of the rows outside the bulk solid first (the longer
-// chain), then the bulk-solid rows.
+// Collision: row slots of the rows with a liquid cell first (the longer
+// chain), then the all-solid rows.
 template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
 __global__ __launch_bounds__(256) void k_adj_collide_all(
     const Ts* __restrict__ f0, const Ts* __restrict__ g0, const double* __restrict__ s0,

@@ -86,7 +86,10 @@ double two_phase_constant(double ste_l, double ste_s, double kappa) {
 // The recomputed states of one segment (0..K) and their phase bookkeeping
 // (launch_adj_partition), for up to pcap states: counts, their 5x5 extremes
 // (pcap n^2 each), the largest count of each state, and the device array of
-// their fronts.
+// their fronts.  State 0 is the segment's checkpoint: its populations are
+// read in place (sf[0] and sg[0] stay null), its front is copied into ss[0]
+// so that the device array of fronts does not change from segment to
+// segment.
 struct SegSet {
   std::vector<void*> sf, sg;
   std::vector<double*> ss;
@@ -1006,11 +1009,12 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
 
 namespace {
 
-// Device bytes of one segment set: K + 1 states and the bookkeeping of K.
+// Device bytes of one segment set: the populations of K states, the fronts
+// of K + 1 and the bookkeeping of K.
 size_t segset_bytes(const lbm_ctx* c, int K) {
   const size_t nn = (size_t)c->p.n * c->p.n;
   const size_t fb = c->p.flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
-  return (size_t)(K + 1) * (fb + gb + nn * sizeof(double)) +
+  return (size_t)K * (fb + gb) + (size_t)(K + 1) * nn * sizeof(double) +
          (size_t)K * (3 * nn * sizeof(int) + sizeof(int) + sizeof(double*));
 }
 
@@ -1021,7 +1025,9 @@ int alloc_segset(lbm_ctx* c, SegSet& S, int K) {
   while ((int)S.sg.size() < K + 1) {
     void *f = nullptr, *g = nullptr;
     double* sp = nullptr;
-    if ((fb && hipMalloc(&f, fb) != hipSuccess) || hipMalloc(&g, gb) != hipSuccess ||
+    const bool pops = !S.sg.empty();  // state 0: the checkpoint's populations
+    if ((pops && fb && hipMalloc(&f, fb) != hipSuccess) ||
+        (pops && hipMalloc(&g, gb) != hipSuccess) ||
         hipMalloc((void**)&sp, nn * sizeof(double)) != hipSuccess) {
       if (f) (void)hipFree(f);
       if (g) (void)hipFree(g);
@@ -1054,23 +1060,22 @@ int alloc_segset(lbm_ctx* c, SegSet& S, int K) {
 int enqueue_recompute(lbm_ctx* c, int i, SegSet& S, hipStream_t st) {
   AdjData& a = c->adj;
   const size_t nn = (size_t)c->p.n * c->p.n;
-  const size_t fb = c->p.flow ? dist_bytes(c, 19) : 0, gb = dist_bytes(c, 7);
   const int64_t len = std::min<int64_t>(a.K, a.nsteps - (int64_t)i * a.K);
   lbmk::KParams k = c->kp;
-  if (fb) HIP_TRY(hipMemcpyAsync(S.sf[0], a.ckf[i], fb, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(hipMemcpyAsync(S.sg[0], a.ckg[i], gb, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(S.ss[0], a.cks[i], nn * sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int64_t t = 0; t < len; ++t) {
+    const void* fs = t == 0 ? a.ckf[i] : S.sf[t];  // state 0: the checkpoint, in place
+    const void* gs = t == 0 ? a.ckg[i] : S.sg[t];
     k.step = (uint32_t)(a.start + (int64_t)i * a.K + t);
     // the front kernel leaves the counts of the next state behind
     if (t == 0) HIP_TRY(lbmk::launch_counts(k, S.ss[t], a.cnt, st));
     if (lbmk::uses_neighbourhood(c->kind))
       HIP_TRY(lbmk::launch_neighbourhood(k, a.cnt, a.cext, nullptr, st));
     // the one-cell path throughout (no row maxima): bit for bit the forward run
-    HIP_TRY(lbmk::launch_stream_collide(c->kind, k, S.sf[t], S.sf[t + 1], S.sg[t], S.sg[t + 1],
-                                        a.cnt, a.cext, nullptr, S.ss[t], c->th, a.flag, st));
-    if (c->heat)  // conservative front: heat of the streaming from the state sg[t]
-      HIP_TRY(lbmk::launch_front_heat(c->kind, k, S.sg[t], S.ss[t], a.cnt, a.heat_rc, st));
+    HIP_TRY(lbmk::launch_stream_collide(c->kind, k, fs, S.sf[t + 1], gs, S.sg[t + 1], a.cnt,
+                                        a.cext, nullptr, S.ss[t], c->th, a.flag, st));
+    if (c->heat)  // conservative front: heat of the streaming from the state gs
+      HIP_TRY(lbmk::launch_front_heat(c->kind, k, gs, S.ss[t], a.cnt, a.heat_rc, st));
     HIP_TRY(lbmk::launch_front(c->kind, k, S.ss[t], S.ss[t + 1], a.cnt, S.sg[t + 1],
                                S.sf[t + 1], c->th, a.melted, a.frozen, a.flag, nullptr, nullptr,
                                nullptr, c->heat ? a.heat_rc : nullptr, nullptr, st));
@@ -1088,11 +1093,12 @@ int enqueue_reverse(lbm_ctx* c, int i, SegSet& S, int& cur, hipStream_t st) {
   const int64_t len = std::min<int64_t>(a.K, a.nsteps - (int64_t)i * a.K);
   for (int64_t t = len - 1; t >= 0; --t) {
     const int* cnt_t = S.cnt2 + (size_t)t * nn;
+    const void* g0 = t == 0 ? a.ckg[i] : S.sg[t];  // state 0: the checkpoint, in place
     if (c->heat)  // the interface heat of state t, for the reverse of the front update
-      HIP_TRY(lbmk::launch_front_heat(c->kind, c->kp, S.sg[t], S.ss[t], cnt_t, c->heat, st));
+      HIP_TRY(lbmk::launch_front_heat(c->kind, c->kp, g0, S.ss[t], cnt_t, c->heat, st));
     lbmk::AdjointStep A;
-    A.f0 = S.sf[t];
-    A.g0 = S.sg[t];
+    A.f0 = t == 0 ? a.ckf[i] : S.sf[t];
+    A.g0 = g0;
     A.s0 = S.ss[t];
     A.g1 = S.sg[t + 1];
     A.s1 = S.ss[t + 1];
