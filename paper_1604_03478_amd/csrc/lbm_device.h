@@ -208,7 +208,7 @@ __host__ __device__ constexpr int step_block_max(size_t bytes) { return bytes ==
 // 290.9 us, melting 103.4 -> 103.8, reads 1.012x (FP16 with L = 4: +0.7 and
 // +1.5 %).
 //
-// Two workgroups per row (16-bit storage at n = 512), n a multiple of 8, in
+// Two workgroups per row (16-bit storage at 256 < n <= 512), n a multiple of 8, in
 // the instantiation that asks for it (PAIR): workgroups w and w + 8 of every
 // block of 16 take the two halves of one row, so a row sits on one XCD as
 // well, and the same order follows.  The halves share the line where a
