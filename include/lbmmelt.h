@@ -240,9 +240,12 @@ int lbm_load_state(lbm_ctx *ctx, const void *host_buf, size_t bytes);
 /* Gradient of the liquid fraction with respect to the hot-wall temperatures
  * (reverse mode; not part of the paper, which runs the forward method only).
  * lbm_forward_ckpt runs nsteps >= 1 steps from the current state exactly as
- * lbm_step does and keeps a device copy of the state every every_k >= 1
- * steps (ceil(nsteps/every_k) states); *fl (may be NULL) receives the liquid
- * fraction at the end.  lbm_adjoint then writes grad_th[c] = dJ/dT_h(c) for
+ * lbm_step does and keeps the state every every_k >= 1 steps
+ * (ceil(nsteps/every_k) states; the checkpoints take over the context's
+ * population buffers of those states instead of copying them, and the
+ * context continues in buffers of the same size, so a step graph captured
+ * before is captured again at the next replay); *fl (may be NULL) receives
+ * the liquid fraction at the end.  lbm_adjoint then writes grad_th[c] = dJ/dT_h(c) for
  * J = dJ_dfl * f_l at the end of that run: it recomputes each segment of
  * every_k steps from its checkpoint (holding the populations of every_k
  * states in device memory, the first state of a segment being its

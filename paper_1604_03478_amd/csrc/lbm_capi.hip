@@ -979,15 +979,37 @@ int lbm_forward_ckpt(lbm_ctx* c, int64_t nsteps, int32_t every_k, double* fl) {
     if ((rc = dalloc(&c->sched, need))) return rc;
     c->sched_cap = need;
   }
+  // The checkpoints take the population buffers themselves instead of copies:
+  // at the start of segment i the buffers that hold the current populations
+  // become checkpoint i, the segment's first step reads them there and writes
+  // the other buffers as usual, and checkpoint i's previous buffers (same
+  // sizes) then take their place in the context.  Only the fronts are
+  // copied.  A captured step graph addresses the old buffers: it goes.
+  if (c->sgraph.exec) {
+    HIP_TRY(hipStreamSynchronize(c->stream));  // no replay of it is pending
+    release_graph(c->sgraph);
+  }
   c->rec_start = c->step;
   c->sched_steps = 0;
   for (int i = 0; i < nck; ++i) {
-    if (fb) HIP_TRY(hipMemcpyAsync(a.ckf[i], c->f[c->cur], fb, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(a.ckg[i], c->g[c->cur], gb, hipMemcpyDeviceToDevice, c->stream));
+    const int cur = c->cur;
+    void* spare_f = a.ckf[i];
+    void* spare_g = a.ckg[i];
+    a.ckf[i] = c->f[cur];
+    a.ckg[i] = c->g[cur];
     HIP_TRY(hipMemcpyAsync(a.cks[i], c->s[c->scur], nn * sizeof(double), hipMemcpyDeviceToDevice,
                            c->stream));
     const int64_t len = std::min<int64_t>(every_k, nsteps - (int64_t)i * every_k);
-    if ((rc = lbm_step(c, len))) {
+    rc = lbm_step(c, 1);
+    if (c->cur != cur) {  // the step was enqueued: the state lives on in the other buffers
+      c->f[cur] = spare_f;
+      c->g[cur] = spare_g;
+    } else {  // it was not: the context keeps its buffers, the checkpoint its own
+      a.ckf[i] = spare_f;
+      a.ckg[i] = spare_g;
+    }
+    if (!rc && len > 1) rc = lbm_step(c, len - 1);
+    if (rc) {
       c->rec_start = -1;
       return rc;
     }

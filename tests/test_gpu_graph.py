@@ -118,11 +118,14 @@ def test_graph_setting_leaves_the_adjoint_unchanged():
     """lbm_forward_ckpt records every step and lbm_adjoint recomputes them,
     so both launch kernel by kernel whatever the graph setting; steps taken
     as replays before the recorded run reach the same state.  The gradient
-    and the liquid fraction equal a context's without graphs bit for bit."""
+    and the liquid fraction equal a context's without graphs bit for bit.
+    The recorded run hands the context's population buffers to its
+    checkpoints, so the replays after it capture a new graph: the states
+    stay equal through them, and through a second recorded run."""
     from inputs import hot_wall_field
     from paper_1604_03478_amd import Sim
     cfg = _cfg("f32", "y0", 0, 0)
-    out = []
+    out, sims = [], []
     for chunk in (0, 6):
         sim = Sim(cfg)
         sim.set_graph(chunk)
@@ -130,10 +133,24 @@ def test_graph_setting_leaves_the_adjoint_unchanged():
         sim.step(48)
         fl = sim.forward_ckpt(30, 7)
         out.append((fl, sim.adjoint(1.0)))
-        sim.close()
+        sims.append(sim)
     assert out[0][0] == out[1][0]
     assert np.array_equal(out[0][1], out[1][1])
     assert np.linalg.norm(out[0][1]) > 0
+    a, b = sims
+    for k in (24, 13):
+        a.step(k)
+        b.step(k)
+        assert states_equal(_state(a), _state(b), "y0")
+    fa, fb = a.forward_ckpt(12, 5), b.forward_ckpt(12, 5)
+    assert fa == fb
+    assert np.array_equal(a.adjoint(1.0), b.adjoint(1.0))
+    a.step(18)
+    b.step(18)
+    assert a.steps == b.steps
+    assert states_equal(_state(a), _state(b), "y0")
+    a.close()
+    b.close()
 
 
 def test_graph_follows_the_row_order_the_liquid_fraction_picks():
