@@ -147,12 +147,13 @@ int lbm_step(lbm_ctx *ctx, int64_t nsteps);
  * while a chunk runs, so the results are the same bit for bit either way.
  * Replays are not used while kernel timing is on or inside lbm_forward_ckpt,
  * lbm_step_replay and lbm_adjoint.  The graph holds pointers into the
- * context only; it lives until the next lbm_set_graph or lbm_destroy.  Costs
- * 4 bytes of device memory and one capture stream.  Synchronizes the
+ * context only; it lives until the next lbm_set_graph, lbm_forward_ckpt
+ * (which moves the populations to other buffers, see there) or lbm_destroy.
+ * Costs 4 bytes of device memory and one capture stream.  Synchronizes the
  * context's stream when the setting changes.  Callers that capture the
  * context's stream into a graph of their own leave the setting at 0 (lbm_step
  * then only launches kernels, with no memory operations, and can be
- * captured).
+ * captured) and capture again after an lbm_forward_ckpt.
  * Errors: LBM_EINVAL (steps odd, negative or above 4096), LBM_ENOMEM,
  * LBM_EDEVICE (capture failures are reported by the lbm_step that captures). */
 int lbm_set_graph(lbm_ctx *ctx, int32_t steps);
