@@ -93,7 +93,7 @@ __global__ __launch_bounds__(512) void k_pull_pattern(const Ts* __restrict__ fs,
                                                       const Ts* __restrict__ gs,
                                                       Ts* __restrict__ gd, KParams P) {
   int y, z, xb;
-  step_row<row_run<Ts>(), PAIR>(P.n, y, z, xb);
+  step_row<row_run<Ts>(), PAIR>(P, y, z, xb);
   const int x = xb * blockDim.x + threadIdx.x;
   if (x >= P.n) return;
   if (y >= 1 && y <= P.n - 2 && z >= 1 && z <= P.n - 2) {  // uniform

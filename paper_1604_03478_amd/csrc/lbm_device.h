@@ -225,34 +225,40 @@ __host__ __device__ constexpr int step_block_max(size_t bytes) { return bytes ==
 // z = n - 1 came last, and its slow rows formed a tail: at 256^3 the melting
 // step took 214 instead of 179 us (FP32), 167 instead of 141 us (FP16).
 template <int L, bool PAIR = false>
-__device__ __forceinline__ void step_row(int n, int& y, int& z, int& xb) {
-  int r = blockIdx.z * n + blockIdx.y;
-  xb = blockIdx.x;
+__device__ __forceinline__ void step_row(const KParams& P, int& y, int& z, int& xb) {
+  // No integer divisions: the grid is (row workgroups, n, n), so blockIdx.z
+  // is the plane of row r = blockIdx.z n + blockIdx.y and blockIdx.y its
+  // position j in the plane (the remapped r of the paired order stays in
+  // plane blockIdx.z when n is a multiple of 8), and the walls-first order
+  // divides by n - 2 with the host's reciprocal.
+  const int n = P.n, bz = (int)blockIdx.z;
+  int j = (int)blockIdx.y;
+  xb = (int)blockIdx.x;
   bool xcd_order = gridDim.x == 1;
   if (PAIR && gridDim.x == 2 && (n & 7) == 0) {
-    // two workgroups per row: workgroups w and w + 8 of each block of 16 take
-    // the two halves of row 8 (w / 16) + w mod 8, so both run on its XCD
-    const int w = (int)blockIdx.x + 2 * r;
-    r = 8 * (w >> 4) + (w & 7);
-    xb = (w >> 3) & 1;
+    // two workgroups per row: workgroups w and w + 8 of each block of 16
+    // (w = blockIdx.x + 2 r) take the two halves of row 8 (w / 16) + w mod 8,
+    // so both run on its XCD; with 2 n a multiple of 16 that row is row
+    // 8 (v / 16) + v mod 8 of plane blockIdx.z, v = blockIdx.x + 2 j
+    const int v = (int)blockIdx.x + 2 * j;
+    j = 8 * (v >> 4) + (v & 7);
+    xb = (v >> 3) & 1;
     xcd_order = true;
   }
-  const int run = L > 0 ? L : n >> 3;
-  if (xcd_order && (n & 7) == 0 && ((n >> 3) % run) == 0) {
-    if (r < 2 * n) {
-      y = r < n ? r : r - n;
-      z = r < n ? 0 : n - 1;
+  if (xcd_order && (n & 7) == 0 && (L == 0 || ((n >> 3) % (L > 0 ? L : 1)) == 0)) {
+    if (bz < 2) {  // the z-wall planes
+      y = j;
+      z = bz == 0 ? 0 : n - 1;
       return;
     }
-    const int k = r - 2 * n;
-    z = 1 + k / n;
-    const int j = k - (z - 1) * n;            // position in the plane; XCD j mod 8
-    const int c = ((j & 7) + (z >> 3)) & 7;   // the XCD's run in this plane
+    z = bz - 1;
+    const int c = ((j & 7) + (z >> 3)) & 7;  // the XCD's run in this plane
     const int m = j >> 3;
-    y = (m / run) * (run << 3) + c * run + (m - (m / run) * run);
+    // L = 0: one run of n / 8 rows per XCD, and m < n / 8
+    y = L > 0 ? (m / L) * (L << 3) + c * L + (m % L) : c * (n >> 3) + m;
     return;
   }
-  const int nw = 4 * n - 4;
+  const int r = bz * n + j, nw = 4 * n - 4;
   if (r < n) {
     y = r;
     z = 0;
@@ -264,9 +270,11 @@ __device__ __forceinline__ void step_row(int n, int& y, int& z, int& xb) {
     z = 1 + (k >> 1);
     y = (k & 1) ? n - 1 : 0;
   } else {
-    const int k = r - nw;
-    z = 1 + k / (n - 2);
-    y = 1 + (k - (z - 1) * (n - 2));
+    const uint32_t k = (uint32_t)(r - nw), d = (uint32_t)(n - 2);
+    uint32_t q = __umulhi(k, P.inv_nm2);  // floor(k / d) or one more
+    q -= q * d > k ? 1u : 0u;
+    z = 1 + (int)q;
+    y = 1 + (int)(k - q * d);
   }
 }
 

@@ -42,7 +42,13 @@ struct KParams {
   // 16-bit storage with two workgroups per row: 1 keeps both halves of a row
   // on one XCD (the order for a mostly liquid lattice; results identical).
   int pair_rows;
+  // ceil(2^32 / (n - 2)): the interior rows of the walls-first row order are
+  // numbered without an integer division (recip32)
+  uint32_t inv_nm2;
 };
+
+// ceil(2^32 / d) for 2 <= d < 2^32.
+inline uint32_t recip32(uint32_t d) { return (uint32_t)((0xFFFFFFFFull + d) / d); }
 
 size_t store_bytes(int kind);
 

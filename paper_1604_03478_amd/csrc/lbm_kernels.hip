@@ -532,7 +532,7 @@ __global__ __launch_bounds__(512) void k_stream_collide(
     Ts* __restrict__ gd, const int* __restrict__ cnt, const double* __restrict__ s,
     const double* __restrict__ th, int* __restrict__ flag, KParams P) {
   int y, z, xb;
-  step_row<row_run<Ts>()>(P.n, y, z, xb);
+  step_row<row_run<Ts>()>(P, y, z, xb);
   const int x = xb * blockDim.x + threadIdx.x;
   update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, nullptr, s, th, flag, P);
 }
@@ -559,7 +559,7 @@ k_stream_collide_h(const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __r
                    const double* __restrict__ s, const double* __restrict__ th,
                    int* __restrict__ flag, KParams P) {
   int y, z, xb;
-  step_row<row_run<Ts>(), PAIR>(P.n, y, z, xb);
+  step_row<row_run<Ts>(), PAIR>(P, y, z, xb);
   const int x = xb * blockDim.x + threadIdx.x;
   if (rowmax) {
     // rowmax[o]: the largest liquid count over the 3x3 neighbourhoods of the
