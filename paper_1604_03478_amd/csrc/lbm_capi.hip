@@ -457,6 +457,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   k.alpha = L.alpha;
   k.ste = params->ste;
   k.dT = params->t_h - params->t_m;
+  lbmk::set_f32_params(k);
 
   auto bail = [&](int code) {
     release(c);

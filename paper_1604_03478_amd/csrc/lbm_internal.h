@@ -45,7 +45,22 @@ struct KParams {
   // ceil(2^32 / (n - 2)): the interior rows of the walls-first row order are
   // numbered without an integer division (recip32)
   uint32_t inv_nm2;
+  // s_nu, gbeta, q_j, q_e, q_js, q_es, tref and tref - t0 rounded to FP32 on
+  // the host (set_f32_params), for the kernels that collide in FP32: the
+  // values a conversion in every wave would give
+  float s_nu_f, gbeta_f, q_j_f, q_e_f, q_js_f, q_es_f, tref_f, dbuoy_f;
 };
+
+inline void set_f32_params(KParams& k) {
+  k.s_nu_f = (float)k.s_nu;
+  k.gbeta_f = (float)k.gbeta;
+  k.q_j_f = (float)k.q_j;
+  k.q_e_f = (float)k.q_e;
+  k.q_js_f = (float)k.q_js;
+  k.q_es_f = (float)k.q_es;
+  k.tref_f = (float)k.tref;
+  k.dbuoy_f = (float)(k.tref - k.t0);
+}
 
 // ceil(2^32 / d) for 2 <= d < 2^32.
 inline uint32_t recip32(uint32_t d) { return (uint32_t)((0xFFFFFFFFull + d) / d); }

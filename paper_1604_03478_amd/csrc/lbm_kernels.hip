@@ -47,17 +47,25 @@ struct Rates {
   G dbuoy;   // tref - t0, so that T - t0 = (T - tref) + dbuoy
 };
 
+// A parameter in the collision's type: the host's FP32 rounding of it for
+// FP32 arithmetic (no conversion in every wave), else the FP64 value.
+template <typename T>
+__device__ __forceinline__ T param_as(double d, float f) {
+  if constexpr (sizeof(T) == 4) return f;
+  else return (T)d;
+}
+
 template <typename C, typename G>
 __device__ __forceinline__ Rates<C, G> make_rates(const KParams& P) {
   Rates<C, G> r;
-  r.sv = (C)P.s_nu;
-  r.gb = (C)P.gbeta;
-  r.qj = (G)P.q_j;
-  r.qe = (G)P.q_e;
-  r.qjs = (G)P.q_js;
-  r.qes = (G)P.q_es;
-  r.tref = (G)P.tref;
-  r.dbuoy = (G)(P.tref - P.t0);
+  r.sv = param_as<C>(P.s_nu, P.s_nu_f);
+  r.gb = param_as<C>(P.gbeta, P.gbeta_f);
+  r.qj = param_as<G>(P.q_j, P.q_j_f);
+  r.qe = param_as<G>(P.q_e, P.q_e_f);
+  r.qjs = param_as<G>(P.q_js, P.q_js_f);
+  r.qes = param_as<G>(P.q_es, P.q_es_f);
+  r.tref = param_as<G>(P.tref, P.tref_f);
+  r.dbuoy = param_as<G>(P.tref - P.t0, P.dbuoy_f);
   return r;
 }
 
