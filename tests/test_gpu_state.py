@@ -136,3 +136,41 @@ def test_adjoint_refuses_a_recorded_run_changed_underneath():
         sim.forward_ckpt(6, 2)
         assert np.array_equal(sim.adjoint(1.0), g_ok)
     sim.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s", "bf16s"])
+def test_forward_ckpt_continues_as_plain_steps(prec):
+    """lbm_forward_ckpt hands the population buffers of each checkpointed
+    state to its checkpoint and continues in others: the run it records, and
+    every step after it, must equal plain lbm_step calls bit for bit (a
+    segment length that does not divide the run, then a single segment, then
+    a saved and reloaded state)."""
+    from live_state import states_equal
+    from paper_1604_03478_amd import Config, Sim
+    cfg = Config(n=24, ra=1e5, pr=1.0, ste=1.0, s0=3.4, t_c=0.1, t_m=0.1, heating="z0",
+                 precision=prec)
+    a, b = Sim(cfg), Sim(cfg)
+    a.step(10)
+    b.step(10)
+    fa = a.forward_ckpt(23, 5)
+    b.step(23)
+    assert fa == b.liquid_fraction()
+    assert states_equal(a.get_populations(), b.get_populations(), "z0")
+    a.step(7)
+    b.step(7)
+    assert states_equal(a.get_populations(), b.get_populations(), "z0")
+    fa = a.forward_ckpt(4, 9)
+    b.step(4)
+    assert fa == b.liquid_fraction()
+    g1 = a.adjoint(1.0)
+    assert np.isfinite(g1).all()
+    blob = a.save_state()
+    a.step(5)
+    b.step(5)
+    assert states_equal(a.get_populations(), b.get_populations(), "z0")
+    a.load_state(blob)
+    a.step(5)
+    assert a.steps == b.steps
+    assert states_equal(a.get_populations(), b.get_populations(), "z0")
+    a.close()
+    b.close()
