@@ -186,8 +186,8 @@ __device__ __forceinline__ bool liquid_at(const int* cnt, int x, int y, int z, i
   return melt_of<MZ>(y, z) < cnt[col_of<MZ>(x, y, z, n)];
 }
 template <bool MZ>
-__device__ __forceinline__ uint32_t cell_in_column(int c, int a, int n) {
-  const int x = c % n, o = c / n;
+__device__ __forceinline__ uint32_t cell_in_column(int c, int a, const KParams& P) {
+  const int n = P.n, o = (int)div_n((uint32_t)c, P), x = c - o * n;
   return MZ ? ((uint32_t)a * n + o) * n + x : ((uint32_t)o * n + a) * n + x;
 }
 
@@ -235,7 +235,7 @@ __device__ __forceinline__ double frac19(const double* s, int x, int y, int z, i
 // row-interleaved layout of a distribution with Q directions)
 template <int Q, typename Ts>
 __device__ __forceinline__ double sv(const Ts* a, const KParams& P, int q, uint32_t i) {
-  const uint32_t n = (uint32_t)P.n, x = i % n, row = i / n;
+  const uint32_t row = div_n(i, P), x = i - row * (uint32_t)P.n;
   return (double)static_cast<typename Compute<Ts>::type>(
       a[((uint64_t)row * Q + q) * P.pitch + x]);
 }
@@ -276,9 +276,10 @@ __device__ __forceinline__ bool bulk_solid_row(int a, int o, int A, int n) {
   return (a >= A) & (a < n - 1) & (o > 0) & (o < n - 1);
 }
 __device__ __forceinline__ int front_rows(int A, int n) { return A * n + n + 2 * (n - 1 - A); }
-__device__ __forceinline__ void front_row(int r, int A, int n, int& a, int& o) {
+__device__ __forceinline__ void front_row(int r, int A, const KParams& P, int& a, int& o) {
+  const int n = P.n;
   if (r < A * n) {
-    a = r / n;
+    a = (int)div_n((uint32_t)r, P);
     o = r - a * n;
   } else if (r < A * n + n) {
     a = n - 1;
@@ -607,7 +608,7 @@ __device__ __forceinline__ void front_der(const Ts* g1, const double* s, const d
   const double sc = s[c];
   // front slopes by central differences, mirrored at the walls, and the
   // hot-wall temperature: loads that depend on nothing else, issued first
-  const int x = c % n, o = c / n;
+  const int o = (int)div_n((uint32_t)c, P), x = c - o * n;
   const int cxp = o * n + (x + 1 < n ? x + 1 : x), cxm = o * n + (x > 0 ? x - 1 : x);
   const int cop = (o + 1 < n ? o + 1 : o) * n + x, com = (o > 0 ? o - 1 : o) * n + x;
   const double dsx = 0.5 * (s[cxp] - s[cxm]), dso = 0.5 * (s[cop] - s[com]);
@@ -629,7 +630,7 @@ __device__ __forceinline__ void front_der(const Ts* g1, const double* s, const d
   int ab = cnt;
   if (ab < n && (ab + 0.5) - sc < 0.5) ++ab;
   auto cell_at = [&](int a) {
-    return cell_in_column<MZ>(c, a < 0 ? 0 : (a > n - 1 ? n - 1 : a), n);
+    return cell_in_column<MZ>(c, a < 0 ? 0 : (a > n - 1 ? n - 1 : a), P);
   };
   const uint32_t cl0 = cell_at(at), cl1 = cell_at(at - 1), cs0 = cell_at(ab), cs1 = cell_at(ab + 1);
   const double Tl0 = Tcell(cl0), Tl1 = Tcell(cl1), Ts0 = Tcell(cs0), Ts1 = Tcell(cs1);
@@ -837,7 +838,7 @@ __device__ __forceinline__ void adj_collide_rows(
   const int n = P.n;
   const int R = rowb[0] * n;
   for (int r = slot; r < R; r += nslots) {
-    const int a = r / n, o = r - a * n;
+    const int a = (int)div_n((uint32_t)r, P), o = r - a * n;
     if (x < n)
       adj_collide_cell<Ts, Lam, FLOW, MZ, EXT>(f0, g0, s0, s1, th, cnt, cmin2, cmax2, lf1, lg1,
                                                lfh, lgh, P, x, MZ ? o : a, MZ ? a : o);
@@ -1078,7 +1079,7 @@ __device__ __forceinline__ void adj_stream_rows(
   const int A = row_bound(rowb[0], n), R = front_rows(A, n);
   for (int r = slot; r < R; r += nslots) {
     int a, o;
-    front_row(r, A, n, a, o);
+    front_row(r, A, P, a, o);
     if (x < n)
       adj_stream_cell<Ts, Lam, FLOW, MZ, EXT>(s0, cnt, cmin2, cmax2, lfh, lgh, lf0, lg0, wq, P, x,
                                               MZ ? o : a, MZ ? a : o);
@@ -1233,7 +1234,7 @@ __device__ __forceinline__ void adj_interface_column(
   // hot-wall anti-bounce-back of the cell next to the heated wall:
   // g_in = -g_out + 2 w (T_h - tref)
   {
-    const uint32_t i = cell_in_column<MZ>(c, 0, n);
+    const uint32_t i = cell_in_column<MZ>(c, 0, P);
     const int qin = MZ ? 5 : 3;  // +z or +y: pulled from the heated wall
     lth[c] += 2.0 * 0.125 * (double)lgh[(size_t)qin * nc + i];
   }
@@ -1343,7 +1344,8 @@ __global__ __launch_bounds__(256) void k_adj_collide_all(
                                              rowb, lf1, lg1, lfh, lgh, P);
   } else {
     const int r = b - nslots;  // row (y, z) = (r mod n, r / n)
-    adj_collide_solid_row<Lam, MZ>(x, r % P.n, r / P.n, rowb, lg1, lgh, P);
+    const int rz = (int)div_n((uint32_t)r, P);
+    adj_collide_solid_row<Lam, MZ>(x, r - rz * P.n, rz, rowb, lg1, lgh, P);
   }
 }
 
@@ -1369,7 +1371,8 @@ __global__ __launch_bounds__(64) void k_adj_stream_all(
                                             lf0, lg0, wq, P);
   } else {
     b -= nslots;
-    adj_stream_solid_row<Lam, MZ>(x, b % n, b / n, rowb, lgh, lg0, P);
+    const int bz = (int)div_n((uint32_t)b, P);
+    adj_stream_solid_row<Lam, MZ>(x, b - bz * n, bz, rowb, lgh, lg0, P);
   }
 }
 

@@ -436,6 +436,7 @@ int lbm_init(const lbm_params* params, void* hip_stream, lbm_ctx** out) {
   k.ncell = (uint32_t)nc;
   k.pitch = lbmk::row_pitch(n, c->kind);
   k.inv_nm2 = lbmk::recip32((uint32_t)(n - 2));
+  k.inv_n = lbmk::recip32((uint32_t)n);
   k.melt_z = params->heating == LBM_HEAT_Z0;
   k.flow = params->flow;
   k.t0 = L.t0;
@@ -1372,6 +1373,7 @@ int lbm_bandwidth_ceiling(int32_t which, int32_t n, int32_t precision, int32_t f
   k.ncell = (uint32_t)((size_t)n * n * n);
   k.pitch = lbmk::row_pitch(n, precision);
   k.inv_nm2 = lbmk::recip32((uint32_t)(n - 2));
+  k.inv_n = lbmk::recip32((uint32_t)n);
   k.flow = flow;
   const size_t esz = lbmk::store_bytes(precision), nn = (size_t)n * n;
   const size_t fb = flow ? 19 * (size_t)k.pitch * nn * esz : 0, gb = 7 * (size_t)k.pitch * nn * esz;

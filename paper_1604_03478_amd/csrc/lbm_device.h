@@ -64,6 +64,14 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 __device__ __forceinline__ uint32_t step_of(const KParams& P) {
   return P.step_dev ? *P.step_dev : P.step;
 }
+// floor(k / n) for k < 2^30 (indices of cells, rows and columns) with the
+// host's reciprocal ceil(2^32 / n): the multiply-high gives the quotient or
+// one more, and one comparison corrects it.
+__device__ __forceinline__ uint32_t div_n(uint32_t k, const KParams& P) {
+  const uint32_t q = __umulhi(k, P.inv_n);
+  return q - (q * (uint32_t)P.n > k ? 1u : 0u);
+}
+
 __device__ __forceinline__ uint32_t next_rand(uint32_t& st) {
   st += 0x9e3779b9u;
   return st;

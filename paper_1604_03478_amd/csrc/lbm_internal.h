@@ -45,6 +45,9 @@ struct KParams {
   // ceil(2^32 / (n - 2)): the interior rows of the walls-first row order are
   // numbered without an integer division (recip32)
   uint32_t inv_nm2;
+  // ceil(2^32 / n): cell, row and column indices split without an integer
+  // division (div_n)
+  uint32_t inv_n;
   // s_nu, gbeta, q_j, q_e, q_js, q_es, tref and tref - t0 rounded to FP32 on
   // the host (set_f32_params), for the kernels that collide in FP32: the
   // values a conversion in every wave would give
