@@ -234,6 +234,11 @@ __device__ __forceinline__ double frac19(const double* s, int x, int y, int z, i
 // stored population q of linear cell i = (z n + y) n + x, in FP64 (the
 // row-interleaved layout of a distribution with Q directions)
 template <int Q, typename Ts>
+__device__ __forceinline__ double sv3(const Ts* a, const KParams& P, int q, int x, int y, int z) {
+  return (double)static_cast<typename Compute<Ts>::type>(
+      a[(((uint64_t)z * (uint32_t)P.n + (uint32_t)y) * Q + q) * P.pitch + (uint32_t)x]);
+}
+template <int Q, typename Ts>
 __device__ __forceinline__ double sv(const Ts* a, const KParams& P, int q, uint32_t i) {
   const uint32_t row = div_n(i, P), x = i - row * (uint32_t)P.n;
   return (double)static_cast<typename Compute<Ts>::type>(
@@ -436,32 +441,54 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
   auto liq = [&](int X, int Y, int Z) -> bool {
     return melt_of<MZ>(Y, Z) < nbc[((MZ ? Y : Z) - o + 1) * 3 + (X - x) + 1];
   };
+  // Every value the terms of g below may read is loaded first, for the seven
+  // directions together (positions clamped into the box), so the loads are
+  // in flight at once instead of one direction's after the other's: the
+  // cell's own populations, the pulled one, the one of the cell behind, the
+  // front of the column across a lateral link, the hot-wall temperature.
+  const int col = col_of<MZ>(x, y, z, n);
+  const double s_c = s[col], th_c = th[col];
+  auto cl = [&](int v) { return v < 0 ? 0 : (v > n - 1 ? n - 1 : v); };
+  double own[7], src[7], beh[7], sn[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const int ex = ex7(q), ey = ey7(q), ez = ez7(q), p = opp7(q);
+    own[q] = sv3<7>(g, P, q, x, y, z);
+    src[q] = q == 0 ? 0.0 : sv3<7>(g, P, q, cl(x - ex), cl(y - ey), cl(z - ez));
+    beh[q] = q == 0 ? 0.0 : sv3<7>(g, P, p, cl(x + ex), cl(y + ey), cl(z + ez));
+    const bool along = MZ ? (ez != 0) : (ey != 0);
+    sn[q] = (q == 0 || along) ? s_c : s[col_of<MZ>(cl(x - ex), cl(y - ey), cl(z - ez), n)];
+  }
+  const double a0 = melt_of<MZ>(y, z) + 0.5;
 #pragma unroll
   for (int q = 0; q < 7; ++q) {
     const int ex = ex7(q), ey = ey7(q), ez = ez7(q), p = opp7(q);
     const int sx = x - ex, sy = y - ey, sz = z - ez;
     double v;
-    if (!G.in(sx, sy, sz)) {
+    if (q == 0) {
+      v = own[0];  // the rest population stays in its cell
+    } else if (!G.in(sx, sy, sz)) {
       const int sa = melt_of<MZ>(sy, sz);
-      const double gp = sv<7>(g, P, p, i);
+      const double gp = own[p];
       if (sa < 0)
-        v = -gp + 2.0 * w * (th[col_of<MZ>(x, y, z, n)] - P.tref);
+        v = -gp + 2.0 * w * (th_c - P.tref);
       else if (!MZ && sa >= n)
         v = -gp + 2.0 * w * (P.t_c - P.tref);
       else
         v = gp;
     } else if (liq(sx, sy, sz) == liquid) {
-      v = sv<7>(g, P, q, G.cell(sx, sy, sz));
+      v = src[q];
     } else {
-      const double d = link_delta<MZ>(s, x, y, z, -ex, -ey, -ez, n);
-      const double gp = sv<7>(g, P, p, i);
+      // link_delta, term for term
+      const bool along = MZ ? (ez != 0) : (ey != 0);
+      const double d = along ? fabs(s_c - a0) : (a0 - s_c) / (sn[q] - s_c);
+      const double gp = own[p];
       if (d < 0.5) {
         const int bx = x + ex, by = y + ey, bz = z + ez;
         const bool behind = G.in(bx, by, bz) && liq(bx, by, bz) == liquid;
-        v = behind ? -(2.0 * d * gp + (1.0 - 2.0 * d) * sv<7>(g, P, p, G.cell(bx, by, bz))) + 2.0 * wTm
-                   : -gp + 2.0 * wTm;
+        v = behind ? -(2.0 * d * gp + (1.0 - 2.0 * d) * beh[q]) + 2.0 * wTm : -gp + 2.0 * wTm;
       } else {
-        v = -gp / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * sv<7>(g, P, q, i) + wTm / d;
+        v = -gp / (2.0 * d) + (2.0 * d - 1.0) / (2.0 * d) * own[q] + wTm / d;
       }
     }
     M.add_g(v);
