@@ -499,7 +499,9 @@ __device__ void pull_cell(const Ts* f, const Ts* g, const double* s, const doubl
       const int sx = x - ex19(q), sy = y - ey19(q), sz = z - ez19(q);
       const bool inb = G.in(sx, sy, sz);
       const bool ok = inb && liq(sx, sy, sz);
-      double v = ok ? sv<19>(f, P, q, G.cell(sx, sy, sz)) : sv<19>(f, P, opp19(q), i);
+      // the pulled population or the bounce-back of the cell's own: one load
+      // from the selected position, not a branch per direction
+      double v = sv3<19>(f, P, ok ? q : opp19(q), ok ? sx : x, ok ? sy : y, ok ? sz : z);
       if (EXT && P.f_wall && inb && !ok) {  // interpolated no-slip at the front
         double num, den;
         const double d = frac19<MZ>(s, x, y, z, q, n, num, den);
