@@ -233,8 +233,7 @@ __device__ __forceinline__ bool collide(C (&f)[19], G (&g)[7], bool liquid, cons
 // per-lane offset q * pitch + x.  FWALL: no-slip of f at the front
 // interpolated to the link fraction (a separate instantiation, so that the
 // default halfway rule compiles to the same code as without the option).
-// PRIO: the fast path's load priority for all-solid waves (below).
-template <typename Ts, bool FLOW, bool MZ, bool FWALL, bool PRIO = false>
+template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 __device__ __forceinline__ void update_cell(
     int x, int y, int z, const Ts* __restrict__ fs, Ts* __restrict__ fd,
     const Ts* __restrict__ gs, Ts* __restrict__ gd, const int* __restrict__ cnt,
@@ -320,15 +319,6 @@ __device__ __forceinline__ void update_cell(
   if (__all(fast)) {
     // ---------- fast path: one phase, only x walls possible ----------
     if constexpr (sizeof(Ts) == 2) liquid = all_liq;  // a + 1 < lo <= cc, or a - 1 >= hi >= cc
-    // PRIO (FP32 storage from 128^3 up, the host's choice): a wave whose
-    // cells are all solid (g alone, 7 loads, little arithmetic) issues its
-    // loads at raised priority, so the SIMD favours waves starting their
-    // loads over waves in their arithmetic and stores.  Scheduling only; the
-    // kernel also compiles to 65 instead of 76 VGPRs (7 waves per SIMD).
-    // 256^3 melting state 171.5 -> 163.1 us, all-liquid 603.0 -> 600.5 us; at
-    // 64^3 the same code cost 4 %, and the 16-bit kernels gained nothing.
-    const bool prio = PRIO && __all(!liquid);
-    if (prio) __builtin_amdgcn_s_setprio(2);
     // Every source row lies in the 3x3 block of rows around (y, z).  Offsets
     // are counted from the block's first row (y - 1, z - 1), so all loads of
     // a distribution share one uniform base and differ by a 32-bit lane
@@ -362,7 +352,12 @@ __device__ __forceinline__ void update_cell(
         f[q] = load_stream<C>(fb, i);
       }
     }
-    if (prio) __builtin_amdgcn_s_setprio(0);
+    // FP32 storage: no instruction moves across this point, so the
+    // collision is not scheduled among the loads.  The kernel then needs 64
+    // instead of 76 VGPRs: 8 instead of 6 waves per SIMD, the loads of more
+    // cells in flight (256^3 melting state 171.6 -> 163.3 us, all-liquid
+    // 607.2 -> 599.4 us, 64^3 unchanged; the same results bit for bit).
+    if constexpr (sizeof(Ts) == 4) __builtin_amdgcn_sched_barrier(0);
   } else {
     // ---------- general path: walls and the front, link by link ----------
     if constexpr (sizeof(Ts) == 2) {
@@ -545,7 +540,7 @@ __device__ __forceinline__ void solid_cell(int x, int y, int z, const Ts* __rest
   for (int q = 0; q < 7; ++q) store_stream(gr, q * pitch + x, g[q], rs);
 }
 
-template <typename Ts, bool FLOW, bool MZ, bool FWALL, bool PRIO>
+template <typename Ts, bool FLOW, bool MZ, bool FWALL>
 __global__ __launch_bounds__(512) void k_stream_collide(
     const Ts* __restrict__ fs, Ts* __restrict__ fd, const Ts* __restrict__ gs,
     Ts* __restrict__ gd, const int* __restrict__ cnt, const double* __restrict__ s,
@@ -553,7 +548,7 @@ __global__ __launch_bounds__(512) void k_stream_collide(
   int y, z, xb;
   step_row<row_run<Ts>()>(P, y, z, xb);
   const int x = xb * blockDim.x + threadIdx.x;
-  update_cell<Ts, FLOW, MZ, FWALL, PRIO>(x, y, z, fs, fd, gs, gd, cnt, nullptr, s, th, flag, P);
+  update_cell<Ts, FLOW, MZ, FWALL>(x, y, z, fs, fd, gs, gd, cnt, nullptr, s, th, flag, P);
 }
 
 // The same for 16-bit storage, held to 7 or 8 resident waves per SIMD.  Its
@@ -921,8 +916,6 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
   dim3 grid((P.n + bx - 1) / bx, P.n, P.n);
   // the paired row order applies at two workgroups per row only
   const bool pair = P.pair_rows != 0 && grid.x == 2 && (P.n & 7) == 0;
-  // the FP32 kernel's load priority for all-solid waves, from 128^3 up
-  const bool prio = P.n >= 128;
 #define LAUNCH_ONE(K, ...)                                                                      \
   do {                                                                                          \
     if (ev_start)  /* the dispatch itself records the kernel's start and end */                 \
@@ -939,16 +932,8 @@ hipError_t sc_dispatch(const KParams& P, const void* fs, void* fd, const void* g
       else                                                                                      \
         LAUNCH_ONE((k_stream_collide_h<Ts, FLOW, MZ, FWALL, false>), F, Fd, G, Gd, cnt, cext,    \
                    rowmax, s, th, flag, P);                                                     \
-    } else if constexpr (sizeof(Ts) == 4) {                                                    \
-      if (prio)                                                                                 \
-        LAUNCH_ONE((k_stream_collide<Ts, FLOW, MZ, FWALL, true>), F, Fd, G, Gd, cnt, s, th, flag, \
-                   P);                                                                          \
-      else                                                                                      \
-        LAUNCH_ONE((k_stream_collide<Ts, FLOW, MZ, FWALL, false>), F, Fd, G, Gd, cnt, s, th,     \
-                   flag, P);                                                                    \
     } else                                                                                      \
-      LAUNCH_ONE((k_stream_collide<Ts, FLOW, MZ, FWALL, false>), F, Fd, G, Gd, cnt, s, th, flag, \
-                 P);                                                                            \
+      LAUNCH_ONE((k_stream_collide<Ts, FLOW, MZ, FWALL>), F, Fd, G, Gd, cnt, s, th, flag, P);    \
   } while (0)
   if (P.flow && P.f_wall) {
     if (P.melt_z) LAUNCH(true, true, true); else LAUNCH(true, false, true);
