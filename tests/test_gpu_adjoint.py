@@ -443,7 +443,8 @@ def test_gradient_is_independent_of_the_checkpoint_interval(prec, heating, kw):
     depend on K: one segment (the sweep on one stream), and 7, 1, 2 and 13
     steps per segment (two segment sets: each segment's recompute on a side
     stream beside the reverse sweep of the one after it; ragged last
-    segments). A layer of cells melts during the 45 recorded steps."""
+    segments), then 6 (twice: the segment sets kept from the first call)
+    and 10. A layer of cells melts during the 45 recorded steps."""
     from inputs import hot_wall_field
     from paper_1604_03478_amd import Config, Sim
     n = 24
@@ -454,7 +455,7 @@ def test_gradient_is_independent_of_the_checkpoint_interval(prec, heating, kw):
     blob = sim.save_state()
     melted0 = sim.diagnostics()["melted"]
     grads, fls = [], []
-    for every in (45, 7, 1, 2, 13):
+    for every in (45, 7, 1, 2, 13, 6, 6, 10):
         sim.load_state(blob)
         fls.append(sim.forward_ckpt(45, every))
         grads.append(sim.adjoint(1.0))
