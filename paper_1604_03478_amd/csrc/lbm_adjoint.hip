@@ -840,14 +840,19 @@ __device__ __forceinline__ void adj_collide_cell(
   // f of a cell that is solid after the step is dead data (never read; a
   // melting cell is refilled), so its adjoint is zero and is not stored
   const bool live1 = liquid && melt_of<MZ>(y, z) < count_liquid(s1[col_of<MZ>(x, y, z, n)], n);
+  // the adjoints after the step are loaded before the state pull, so the two
+  // round trips overlap
+  Lam lfr[19], lgr[7];
+  for (int q = 0; q < 19; ++q) lfr[q] = (FLOW && live1) ? lf1[(size_t)q * nc + i] : Lam(0);
+  for (int q = 0; q < 7; ++q) lgr[q] = lg1[(size_t)q * nc + i];
   Macro M;
   if (__all(adj_fast<MZ>(cmin2, cmax2, x, y, z, n)))
     pull_fast<Ts, FLOW>(f0, g0, x, y, z, liquid, P, M);
   else
     pull_cell<Ts, FLOW, MZ, EXT>(f0, g0, s0, th, cnt, x, y, z, liquid, P, M);
   double lfo[19], lgo[7], lfl[19], lgl[7];
-  for (int q = 0; q < 19; ++q) lfo[q] = (FLOW && live1) ? (double)lf1[(size_t)q * nc + i] : 0.0;
-  for (int q = 0; q < 7; ++q) lgo[q] = (double)lg1[(size_t)q * nc + i];
+  for (int q = 0; q < 19; ++q) lfo[q] = (double)lfr[q];
+  for (int q = 0; q < 7; ++q) lgo[q] = (double)lgr[q];
   collide_adjoint<FLOW>(M, liquid, P, lfo, lgo, lfl, lgl);
   if (FLOW && liquid)  // read only at liquid cells
     for (int q = 0; q < 19; ++q) lfh[(size_t)q * nc + i] = (Lam)lfl[q];
