@@ -630,9 +630,10 @@ __device__ __forceinline__ double slope_der(int k, double xi0, double xi1, doubl
   return 0.0;
 }
 
-template <typename Ts, bool MZ>
+template <typename Ts, typename Lam, bool MZ>
 __device__ __forceinline__ void front_der(const Ts* g1, const double* s, const double* th, int c,
-                                          const KParams& P, VDer& d) {
+                                          const KParams& P, VDer& d, const Lam* lg1,
+                                          Lam (&old)[4][7]) {
   const int n = P.n;
   const double sc = s[c];
   // front slopes by central differences, mirrored at the walls, and the
@@ -662,6 +663,13 @@ __device__ __forceinline__ void front_der(const Ts* g1, const double* s, const d
     return cell_in_column<MZ>(c, a < 0 ? 0 : (a > n - 1 ? n - 1 : a), P);
   };
   const uint32_t cl0 = cell_at(at), cl1 = cell_at(at - 1), cs0 = cell_at(ab), cs1 = cell_at(ab + 1);
+  // the adjoints at the same four cells, which the caller updates: a node
+  // that is used is one of these candidates
+  const uint32_t cand[4] = {cl0, cl1, cs0, cs1};
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int q = 0; q < 7; ++q) old[k][q] = lg1[(size_t)q * P.ncell + cand[k]];
   const double Tl0 = Tcell(cl0), Tl1 = Tcell(cl1), Ts0 = Tcell(cs0), Ts1 = Tcell(cs1);
 
   // liquid side: those nodes toward the heated wall, then the wall itself
@@ -761,7 +769,8 @@ __global__ __launch_bounds__(64) void k_adj_front(const double* __restrict__ s0,
   const int c = o * n + x;
   const size_t nc = P.ncell, nn = (size_t)n * n;
   VDer d;
-  front_der<Ts, MZ>(g1, s0, th, c, P, d);
+  Lam old[4][7];
+  front_der<Ts, Lam, MZ>(g1, s0, th, c, P, d, lg1, old);
   const double v = s0[c] + d.V;  // the unclamped update, recomputed as the step did
   const double l = ls1[c];
   if (v < 0.0 || v > (double)n) {  // clamped: no dependence
@@ -771,14 +780,9 @@ __global__ __launch_bounds__(64) void k_adj_front(const double* __restrict__ s0,
   }
   own[c] = l;
   // The 28 updated values are distinct (other direction or other cell of this
-  // column, and no other column touches these cells): all loads are issued
-  // before the first store, instead of one load-add-store round trip each.
-  // An unused slot loads cell 0 (its node index stays 0) and stores nothing.
-  Lam old[4][7];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int q = 0; q < 7; ++q) old[k][q] = lg1[(size_t)q * nc + d.node[k]];
+  // column, and no other column touches these cells), so their loads were
+  // issued with the node temperatures, before the first store.  An unused
+  // slot stores nothing.
 #pragma unroll
   for (int k = 0; k < 4; ++k)
     if (d.use[k])
