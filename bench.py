@@ -62,12 +62,18 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_CELL = {"f32": 208, "f16s": 104, "bf16s": 104, "f64": 416}
-# one reverse step, FP32 storage and FP32 per-cell adjoints: transposed
-# collision (state 104 B + adjoint 104 B read, 104 B written) and transposed
-# streaming (104 B read, 104 B written) in a liquid cell; a solid cell moves
-# only g and its adjoint (28 + 28 B read, 28 B written; 28 B read, 28 B written)
+# Algorithmic bytes per cell, FP32 storage and FP32 per-cell adjoints.  A
+# forward step moves 208 B in a liquid cell and 56 B (g alone) in a solid one.
+# A reverse step in a liquid cell: transposed collision (state 104 B and
+# adjoint 104 B read, 104 B written) and transposed streaming (104 B read,
+# 104 B written); in a solid cell only the g adjoint, 28 B read and 28 B
+# written by each of the two, or 28 + 28 B in all where the streaming is
+# paired with the next reverse collision (the bulk-solid rows of lattices
+# above 128^3, in every step of a segment but its last).
+FWD_BYTES_LIQUID, FWD_BYTES_SOLID = 208, 56
 ADJ_BYTES_LIQUID = 312 + 208
-ADJ_BYTES_SOLID = 84 + 56
+ADJ_BYTES_SOLID, ADJ_BYTES_SOLID_PAIRED = 56 + 56, 28 + 28
+ADJ_PAIR_MIN_N = 129
 # sources the stream-collide kernel is compiled from
 KERNEL_SRC = [os.path.join(ROOT, "paper_1604_03478_amd", "csrc", f)
               for f in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h")]
@@ -262,16 +268,21 @@ def adjoint_timing(stream, n: int, steps: int, every: int):
     fl = sim.liquid_fraction()
     sim.close()
     fwd, adj = times[1][0], times[1][1]
-    rev = max(adj - plain * steps, 0.0) / steps
-    # algorithmic bytes of a reverse step at the final liquid fraction
-    rev_bytes = n ** 3 * (fl * ADJ_BYTES_LIQUID + (1.0 - fl) * ADJ_BYTES_SOLID)
+    # algorithmic bytes of the sweep, one recomputed forward step and one
+    # reverse step per step, at the final (largest) liquid fraction; the
+    # recompute runs beside the reverse steps, so only the sum is timed
+    solid_rev = ADJ_BYTES_SOLID
+    if n >= ADJ_PAIR_MIN_N:
+        solid_rev = (ADJ_BYTES_SOLID_PAIRED * (every - 1) + ADJ_BYTES_SOLID) / every
+    sweep_bytes = steps * n ** 3 * (fl * (FWD_BYTES_LIQUID + ADJ_BYTES_LIQUID)
+                                    + (1.0 - fl) * (FWD_BYTES_SOLID + solid_rev))
     return {"n": n, "steps": steps, "every_k": every, "liquid_fraction": round(fl, 6),
             "plain_ms_per_step": round(plain, 4), "forward_ckpt_ms": round(fwd, 2),
             "adjoint_ms": round(adj, 2), "adjoint_over_forward": round(adj / (plain * steps), 2),
             "first_call": {"forward_ckpt_ms": round(times[0][0], 2),
                            "adjoint_ms": round(times[0][1], 2)},
-            "reverse_ms_per_step_est": round(rev, 4),
-            "reverse_GBps_est": round(rev_bytes / (rev * 1e-3) / 1e9, 1) if rev > 0 else None,
+            "sweep_ms_per_step": round(adj / steps, 4),
+            "sweep_GBps_est": round(sweep_bytes / (adj * 1e-3) / 1e9, 1),
             "grad_norm": float(torch.linalg.norm(grad).item())}
 
 

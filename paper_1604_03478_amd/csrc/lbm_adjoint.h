@@ -34,6 +34,16 @@ struct AdjointStep {
   double* ls0;
   void* lfh;
   void* lgh;         // per-cell adjoint of the pulled populations
+  // Pairing of the bulk-solid rows (lattices above the shared-launch size):
+  // rowb_prev is state t+1's largest liquid count when the step after this
+  // one in time (reversed just before) left the transposed streaming of the
+  // paired rows to this step, whose reverse collision then gathers from
+  // lgh_prev, that step's lgh; rowb_next is state t-1's when the step reversed
+  // next pairs with this one (this step then skips the paired rows'
+  // streaming).  NULL when there is no such pairing.
+  const int* rowb_prev;
+  const int* rowb_next;
+  const void* lgh_prev;
   double* out5;
   double* own;       // per-column scratch of the front adjoint
   double* lth;
@@ -42,6 +52,9 @@ struct AdjointStep {
   const double* heat;
   double* wq;
 };
+// Largest lattice whose reverse step uses the two shared launches; above it
+// the bulk-solid rows of consecutive reverse steps are paired.
+constexpr int kAdjFuseMaxN = 128;
 hipError_t launch_adjoint_step(int kind, const KParams& P, const AdjointStep& A, hipStream_t st);
 // For each of `count` states (device array `states` of their fronts, n^2
 // values each): the liquid counts (cnt), their min / max over the 5x5 columns

@@ -307,6 +307,17 @@ __device__ __forceinline__ int row_bound(int m, int n) { return m + 2 < n - 1 ? 
 // every o) take the full one.
 __device__ __forceinline__ bool solid_collide_row(int a, int m) { return a >= m; }
 
+// Pairing of two consecutive reverse steps (lattices above the shared-launch
+// size).  A row that is bulk-solid for the transposed streaming of state t+1
+// (largest liquid count ms) and at least three heights above the largest
+// liquid count mc of state t, so that no node of state t's front adjoint lies
+// in it, skips that streaming: the reverse collision of state t gathers the
+// seven values from the neighbours' adjoints itself, the values the
+// streaming would have stored.  56 instead of 112 bytes per cell in FP32.
+__device__ __forceinline__ bool paired_row(int a, int o, int ms, int mc, int n) {
+  return bulk_solid_row(a, o, row_bound(ms, n), n) && a >= mc + 3;
+}
+
 // Phase bookkeeping of the states of a segment, one state per grid plane z
 // (state s[z]), in one pass over its columns: the liquid count of each column
 // (from its front), the minimum and maximum count over the 5x5 columns around
@@ -903,25 +914,43 @@ __global__ __launch_bounds__(256) void k_adj_collide(
 template <typename Lam, bool MZ>
 __device__ __forceinline__ void adj_collide_solid_row(int x, int y, int z,
                                                       const int* __restrict__ rowb,
+                                                      const int* __restrict__ rowb_prev,
                                                       const Lam* __restrict__ lg1,
+                                                      const Lam* __restrict__ lgh_prev,
                                                       Lam* __restrict__ lgh, const KParams& P) {
-  const int n = P.n;
-  if (x >= n || !solid_collide_row(melt_of<MZ>(y, z), rowb[0])) return;
+  const int n = P.n, a = melt_of<MZ>(y, z);
+  if (x >= n || !solid_collide_row(a, rowb[0])) return;
   const size_t nc = P.ncell;
   const uint32_t i = ((uint32_t)z * n + y) * n + x;
   const Macro M;  // T enters only the flow part, which a solid cell skips
   double lfo[19] = {}, lgo[7], lfl[19], lgl[7];
-  for (int q = 0; q < 7; ++q) lgo[q] = (double)lg1[(size_t)q * nc + i];
+  if (rowb_prev && paired_row(a, MZ ? y : z, rowb_prev[0], rowb[0], n)) {
+    // the transposed streaming of state t+1 (push_fast's gather), in place of
+    // its stored result
+    const Geo G{n, (uint32_t)n * (uint32_t)n};
+    Lam v[7];
+#pragma unroll
+    for (int p = 0; p < 7; ++p) {
+      const int ex = ex7(p), ey = ey7(p), ez = ez7(p);
+      const bool in = (unsigned)(x + ex) < (unsigned)n;
+      v[p] = lgh_prev[in ? (size_t)p * nc + G.cell(x + ex, y + ey, z + ez)
+                         : (size_t)opp7(p) * nc + i];
+    }
+#pragma unroll
+    for (int p = 0; p < 7; ++p) lgo[p] = (double)v[p];
+  } else {
+    for (int q = 0; q < 7; ++q) lgo[q] = (double)lg1[(size_t)q * nc + i];
+  }
   collide_adjoint<false>(M, false, P, lfo, lgo, lfl, lgl);
   for (int q = 0; q < 7; ++q) lgh[(size_t)q * nc + i] = (Lam)lgl[q];
 }
 
 template <typename Lam, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_collide_solid(
-    const int* __restrict__ rowb, const Lam* __restrict__ lg1, Lam* __restrict__ lgh,
-    KParams P) {
+    const int* __restrict__ rowb, const int* __restrict__ rowb_prev, const Lam* __restrict__ lg1,
+    const Lam* __restrict__ lgh_prev, Lam* __restrict__ lgh, KParams P) {
   adj_collide_solid_row<Lam, MZ>(blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, blockIdx.z,
-                                 rowb, lg1, lgh, P);
+                                 rowb, rowb_prev, lg1, lgh_prev, lgh, P);
 }
 
 // Transposed streaming of one cell outside the bulk-solid rows.
@@ -1140,20 +1169,23 @@ __global__ __launch_bounds__(256) void k_adj_stream(
 template <typename Lam, bool MZ>
 __device__ __forceinline__ void adj_stream_solid_row(int x, int y, int z,
                                                      const int* __restrict__ rowb,
+                                                     const int* __restrict__ rowb_next,
                                                      const Lam* __restrict__ lgh,
                                                      Lam* __restrict__ lg0, const KParams& P) {
-  const int n = P.n;
-  if (x >= n || !bulk_solid_row(melt_of<MZ>(y, z), MZ ? y : z, row_bound(rowb[0], n), n)) return;
+  const int n = P.n, a = melt_of<MZ>(y, z);
+  if (x >= n || !bulk_solid_row(a, MZ ? y : z, row_bound(rowb[0], n), n)) return;
+  if (rowb_next && a >= rowb_next[0] + 3) return;  // paired: see paired_row
   const Geo G{n, (uint32_t)n * (uint32_t)n};
   push_fast<7>(lgh, lg0, G, P.ncell, x, y, z, G.cell(x, y, z));
 }
 
 template <typename Lam, bool MZ>
 __global__ __launch_bounds__(256) void k_adj_stream_solid(const int* __restrict__ rowb,
+                                                          const int* __restrict__ rowb_next,
                                                           const Lam* __restrict__ lgh,
                                                           Lam* __restrict__ lg0, KParams P) {
   adj_stream_solid_row<Lam, MZ>(blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, blockIdx.z,
-                                rowb, lgh, lg0, P);
+                                rowb, rowb_next, lgh, lg0, P);
 }
 
 // derivative of the pulled population of an interface link with respect to
@@ -1383,7 +1415,7 @@ __global__ __launch_bounds__(256) void k_adj_collide_all(
   } else {
     const int r = b - nslots;  // row (y, z) = (r mod n, r / n)
     const int rz = (int)div_n((uint32_t)r, P);
-    adj_collide_solid_row<Lam, MZ>(x, r - rz * P.n, rz, rowb, lg1, lgh, P);
+    adj_collide_solid_row<Lam, MZ>(x, r - rz * P.n, rz, rowb, nullptr, lg1, nullptr, lgh, P);
   }
 }
 
@@ -1410,7 +1442,7 @@ __global__ __launch_bounds__(64) void k_adj_stream_all(
   } else {
     b -= nslots;
     const int bz = (int)div_n((uint32_t)b, P);
-    adj_stream_solid_row<Lam, MZ>(x, b - bz * n, bz, rowb, lgh, lg0, P);
+    adj_stream_solid_row<Lam, MZ>(x, b - bz * n, bz, rowb, nullptr, lgh, lg0, P);
   }
 }
 
@@ -1431,9 +1463,6 @@ hipError_t fill_t(V* v, size_t count, double value, hipStream_t st) {
 
 // EXT: the interpolated no-slip of f or the conservative front update is on
 // (a separate instantiation, so that the default one compiles without them)
-// Largest lattice whose reverse step uses the two shared launches.
-constexpr int kAdjFuseMaxN = 128;
-
 template <typename Ts, typename Lam, bool FLOW, bool MZ, bool EXT>
 hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st) {
   const int n = P.n;
@@ -1474,10 +1503,14 @@ hipError_t adjoint_step_t(const KParams& P, const AdjointStep& A, hipStream_t st
   const dim3 gfront((n + bx - 1) / bx, (unsigned)nslots, 1);
   hipLaunchKernelGGL((k_adj_collide<Ts, Lam, FLOW, MZ, EXT>), gfront, bcell, 0, st, f0, g0, A.s0,
                      A.s1, A.th, A.cnt, A.cmin2, A.cmax2, A.rowb, lf1, lg1, lfh, lgh, P);
-  hipLaunchKernelGGL((k_adj_collide_solid<Lam, MZ>), gcell, bcell, 0, st, A.rowb, lg1, lgh, P);
+  const Lam* lghp = static_cast<const Lam*>(A.lgh_prev);
+  if (A.rowb_prev && (!lghp || lghp == lgh)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_adj_collide_solid<Lam, MZ>), gcell, bcell, 0, st, A.rowb, A.rowb_prev,
+                     lg1, lghp, lgh, P);
   hipLaunchKernelGGL((k_adj_stream<Ts, Lam, FLOW, MZ, EXT>), gfront, bcell, 0, st, A.s0, A.cnt,
                      A.cmin2, A.cmax2, A.rowb, lfh, lgh, lf0, lg0, wq, P);
-  hipLaunchKernelGGL((k_adj_stream_solid<Lam, MZ>), gcell, bcell, 0, st, A.rowb, lgh, lg0, P);
+  hipLaunchKernelGGL((k_adj_stream_solid<Lam, MZ>), gcell, bcell, 0, st, A.rowb, A.rowb_next,
+                     lgh, lg0, P);
   hipLaunchKernelGGL((k_adj_interface<Ts, Lam, MZ, EXT>), gcol, bcol, 0, st, g0, A.s0, A.cnt, lgh, f0,
                      lfh, wq, A.own, A.out5, A.ls0, A.lth, P);
   return hipGetLastError();

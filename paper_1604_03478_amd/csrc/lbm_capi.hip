@@ -118,6 +118,9 @@ struct AdjData {
   double* wq = nullptr;  // per-column weight of the interface heat (front scheme 1)
   void *lf[2] = {nullptr, nullptr}, *lg[2] = {nullptr, nullptr};  // per-cell adjoints
   void *lfh = nullptr, *lgh = nullptr;
+  // above the shared-launch size: the second buffer of the pulled adjoints,
+  // alternating with lgh step by step (paired bulk-solid rows)
+  void* lgh_b = nullptr;
   double *ls[2] = {nullptr, nullptr};
   double *out5 = nullptr, *own = nullptr, *lth = nullptr;
 };
@@ -224,7 +227,7 @@ void release_adjoint(AdjData& a) {
   release_set(a.set[1]);
   void* ptrs[] = {a.cnt,   a.cext,  a.heat_rc, a.melted, a.frozen, a.flag, a.lf[0], a.lf[1],
                   a.lg[0], a.lg[1], a.ls[0],   a.ls[1],  a.lfh,    a.lgh,  a.out5,  a.own,
-                  a.lth,   a.wq};
+                  a.lth,   a.wq,    a.lgh_b};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   hipEvent_t evs[] = {a.ev_start, a.ev_rc[0], a.ev_rc[1], a.ev_rv[0], a.ev_rv[1]};
@@ -1139,7 +1142,14 @@ int enqueue_reverse(lbm_ctx* c, int i, SegSet& S, int& cur, hipStream_t st) {
     A.lg0 = a.lg[1 - cur];
     A.ls0 = a.ls[1 - cur];
     A.lfh = a.lfh;
-    A.lgh = a.lgh;
+    // paired bulk-solid rows: this step's pulled adjoints alternate between
+    // two buffers, and the step reversed just before (state t+1, same
+    // segment) left those rows' transposed streaming to this one
+    const bool pair = c->p.n > lbmk::kAdjFuseMaxN;
+    A.lgh = pair && cur ? a.lgh_b : a.lgh;
+    A.lgh_prev = pair ? (cur ? a.lgh : a.lgh_b) : nullptr;
+    A.rowb_prev = pair && t + 1 < len ? S.rowb + t + 1 : nullptr;
+    A.rowb_next = pair && t >= 1 ? S.rowb + t - 1 : nullptr;
     A.out5 = a.out5;
     A.own = a.own;
     A.lth = a.lth;
@@ -1193,6 +1203,7 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
         (rc = dalloc(&a.own, nn)) || (rc = dalloc(&a.lth, nn)) || (rc = dalloc(&a.wq, nn)) ||
         (c->heat && (rc = dalloc(&a.heat_rc, nn))))
       return rc;
+    if (c->p.n > lbmk::kAdjFuseMaxN && (rc = dalloc_bytes(&a.lgh_b, 7 * nc * lb))) return rc;
     if (flow && ((rc = dalloc_bytes(&a.lf[0], 19 * nc * lb)) ||
                  (rc = dalloc_bytes(&a.lf[1], 19 * nc * lb)) ||
                  (rc = dalloc_bytes(&a.lfh, 19 * nc * lb))))
