@@ -464,3 +464,57 @@ def test_gradient_is_independent_of_the_checkpoint_interval(prec, heating, kw):
     for fl, g in zip(fls[1:], grads[1:]):
         assert fl == fls[0]
         assert np.array_equal(g, grads[0])
+
+
+def test_gradient_above_the_shared_launch_size_matches_the_oracle():
+    """Above 128^3 the reverse step runs in separate kernels (reverse
+    collision of the rows near the front and of the all-solid rows,
+    transposed streaming of both, interface adjoint) and pairs the
+    bulk-solid rows of consecutive steps of a segment.  132^3, FP64, against
+    the oracle's reverse sweep: 12 steps with a checkpoint every 5 (segments
+    of 5, 5 and 2 steps), the front seeded 0.03 cells short of the next cell
+    centre, so that the largest liquid count changes between states of the
+    run."""
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, Sim
+    n = 132
+    base = dict(ra=1e5, pr=1.0, ste=1.0, s0=4.47, flow=1)
+    print(f"adjoint vs oracle n={n} FP64, 12 steps, every 5", flush=True)
+    orc = OracleSim(n, heating=0, **base)
+    gpu = Sim(Config(n=n, heating="y0", precision="f64", **base))
+    th = hot_wall_field(n, seed=11)
+    orc.th[:] = th
+    gpu.set_hot_wall(th)
+    orc.record(12)
+    *_, g_ref = orc.adjoint()
+    gpu.forward_ckpt(12, 5)
+    g = gpu.adjoint(1.0)
+    scale = np.linalg.norm(g_ref)
+    assert scale > 0
+    assert np.linalg.norm(g - g_ref) <= 1e-10 * scale, (np.linalg.norm(g - g_ref), scale)
+
+
+@pytest.mark.parametrize("prec,heating", [("f32", "y0"), ("f16s", "z0")])
+def test_paired_bulk_solid_rows_equal_unpaired_steps(prec, heating):
+    """With one step per segment no step is paired with the next (the last
+    step of a segment never is); with longer segments the bulk-solid rows of
+    consecutive steps are.  The gradients must agree bit for bit, at 136^3,
+    while the front melts a layer of cells during the 40 recorded steps (the
+    largest liquid count, which bounds the paired rows, changes)."""
+    from inputs import hot_wall_field
+    from paper_1604_03478_amd import Config, Sim
+    n = 136
+    print(f"paired rows n={n} {prec} {heating}", flush=True)
+    sim = Sim(Config(n=n, ra=1e5, pr=1.0, ste=1.0, s0=4.45, heating=heating, precision=prec))
+    sim.set_hot_wall(hot_wall_field(n, seed=3))
+    blob = sim.save_state()
+    melted0 = sim.diagnostics()["melted"]
+    grads = []
+    for every in (1, 40, 8, 13):
+        sim.load_state(blob)
+        sim.forward_ckpt(40, every)
+        grads.append(sim.adjoint(1.0))
+    assert sim.diagnostics()["melted"] > melted0
+    assert np.linalg.norm(grads[0]) > 0
+    for g in grads[1:]:
+        assert np.array_equal(g, grads[0])
