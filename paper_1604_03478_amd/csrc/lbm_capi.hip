@@ -1195,19 +1195,29 @@ int lbm_adjoint(lbm_ctx* c, double dJ_dfl, double* grad_th, int on_device) {
   const int nsets = a.nck > 1 && !a.set[1].sg.empty() ? 2 : 1;
   const size_t lb = lbmk::lambda_bytes(c->kind);  // bytes of one per-cell adjoint value
   if (!a.lg[0]) {
+    // all or nothing (lg[0] marks the set as allocated): after a failure
+    // here the next call allocates afresh
     if ((rc = dalloc(&a.cnt, nn)) || (rc = dalloc(&a.cext, nn)) ||
         (rc = dalloc(&a.melted, nn)) || (rc = dalloc(&a.frozen, nn)) || (rc = dalloc(&a.flag, 1)) ||
         (rc = dalloc_bytes(&a.lg[0], 7 * nc * lb)) || (rc = dalloc_bytes(&a.lg[1], 7 * nc * lb)) ||
         (rc = dalloc(&a.ls[0], nn)) || (rc = dalloc(&a.ls[1], nn)) ||
         (rc = dalloc_bytes(&a.lgh, 7 * nc * lb)) || (rc = dalloc(&a.out5, 5 * nn)) ||
         (rc = dalloc(&a.own, nn)) || (rc = dalloc(&a.lth, nn)) || (rc = dalloc(&a.wq, nn)) ||
-        (c->heat && (rc = dalloc(&a.heat_rc, nn))))
+        (c->heat && (rc = dalloc(&a.heat_rc, nn))) ||
+        (c->p.n > lbmk::kAdjFuseMaxN && (rc = dalloc_bytes(&a.lgh_b, 7 * nc * lb))) ||
+        (flow && ((rc = dalloc_bytes(&a.lf[0], 19 * nc * lb)) ||
+                  (rc = dalloc_bytes(&a.lf[1], 19 * nc * lb)) ||
+                  (rc = dalloc_bytes(&a.lfh, 19 * nc * lb))))) {
+      auto drop = [](auto*& p) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+      };
+      drop(a.cnt), drop(a.cext), drop(a.melted), drop(a.frozen), drop(a.flag);
+      drop(a.lg[0]), drop(a.lg[1]), drop(a.ls[0]), drop(a.ls[1]), drop(a.lgh), drop(a.out5);
+      drop(a.own), drop(a.lth), drop(a.wq), drop(a.heat_rc), drop(a.lgh_b);
+      drop(a.lf[0]), drop(a.lf[1]), drop(a.lfh);
       return rc;
-    if (c->p.n > lbmk::kAdjFuseMaxN && (rc = dalloc_bytes(&a.lgh_b, 7 * nc * lb))) return rc;
-    if (flow && ((rc = dalloc_bytes(&a.lf[0], 19 * nc * lb)) ||
-                 (rc = dalloc_bytes(&a.lf[1], 19 * nc * lb)) ||
-                 (rc = dalloc_bytes(&a.lfh, 19 * nc * lb))))
-      return rc;
+    }
   }
   const bool two = nsets == 2;
   if (two && !a.side) {
